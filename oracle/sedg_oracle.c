@@ -1,0 +1,1213 @@
+/*
+ * Oracle: plain FP64 CPU definition of the sub-element adaptive blended DG/FV
+ * semi-discretisation (arXiv:2011.03338) and its SSP-RK3 time stepping.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the CPU
+ * baseline of the benchmark.  It shares nothing with the HIP library.  Every
+ * step follows the paper's definitions literally, element by element, with no
+ * blocking or fusion; operator tables are built here in long double and rounded
+ * once.  Built with -O2 -ffp-contract=off.
+ *
+ * Where the paper leaves a detail open, the reading taken is stated at the
+ * function that implements it.  Parity of those readings against the paper is
+ * pinned only through their limits, conservation and reductions (see the tests).
+ */
+#include "sedg_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXK 8
+#define MAXV 5
+#define MAXLEV 4 /* levels 8, 4, 2 plus room */
+
+/* ------------------------------------------------------------------------- */
+/* Operator tables (Sec. 2.1-2.4, 2.6; App. 3D extension)                    */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int n;
+    double xi[MAXK], w[MAXK];       /* collocation nodes on [-1/2,1/2], weights sum to 1 */
+    double Dcal[MAXK * MAXK];       /* derivative matrix: Dcal[i][j] = l_j'(xi_i) */
+    double D[MAXK * MAXK];          /* volume operator M^-1 Dcal^T M */
+    double bm[MAXK], bp[MAXK];      /* boundary interpolation l_j(-1/2), l_j(+1/2) */
+    double P[MAXK * MAXK];          /* projection nodal -> subcell means */
+    double R[MAXK * MAXK];          /* reconstruction R = P^-1 */
+    double Dhat[MAXK * MAXK];       /* P D */
+    double Bhl[MAXK], Bhr[MAXK];    /* nonzero first / last columns of P B^(0) */
+    double Ip[MAXK * MAXK];         /* Ip[i][j] = l_j(mu_{i+1/2}) */
+    double Im[MAXK * MAXK];         /* Im[i][j] = l_j(mu_{i-1/2}) */
+} lvl_t;
+
+typedef long double ld;
+
+/* Legendre polynomial P_m(x) and its derivative on [-1,1] by the three-term recurrence. */
+static void legendre(int m, ld x, ld *pm, ld *dpm)
+{
+    ld p0 = 1.0L, p1 = x;
+    if (m == 0) { *pm = 1.0L; *dpm = 0.0L; return; }
+    for (int k = 2; k <= m; k++) {
+        ld p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / (ld)k;
+        p0 = p1;
+        p1 = p2;
+    }
+    *pm = p1;
+    *dpm = (ld)m * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+/* Gauss-Legendre nodes/weights mapped to [-1/2,1/2] (weights sum to 1). */
+static void gauss_nodes(int n, ld *x, ld *w)
+{
+    for (int i = 0; i < n; i++) {
+        ld t = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+        for (int it = 0; it < 100; it++) {
+            ld pm, dpm;
+            legendre(n, t, &pm, &dpm);
+            ld dt = pm / dpm;
+            t -= dt;
+            if (fabsl(dt) < 1e-30L) break;
+        }
+        ld pm, dpm;
+        legendre(n, t, &pm, &dpm);
+        /* ascending order */
+        x[n - 1 - i] = 0.5L * t;
+        w[n - 1 - i] = 0.5L * 2.0L / ((1.0L - t * t) * dpm * dpm);
+    }
+}
+
+/* Legendre-Gauss-Lobatto nodes/weights mapped to [-1/2,1/2]. */
+static void lgl_nodes(int n, ld *x, ld *w)
+{
+    int N = n - 1;
+    x[0] = -0.5L;
+    x[n - 1] = 0.5L;
+    for (int i = 1; i < N; i++) {
+        ld t = -cosl(3.14159265358979323846264338327950288L * i / N);
+        for (int it = 0; it < 100; it++) {
+            ld pm, dpm;
+            legendre(N, t, &pm, &dpm);
+            ld d2 = (2.0L * t * dpm - N * (N + 1.0L) * pm) / (1.0L - t * t);
+            ld dt = dpm / d2;
+            t -= dt;
+            if (fabsl(dt) < 1e-30L) break;
+        }
+        x[i] = 0.5L * t;
+    }
+    for (int i = 0; i < n; i++) {
+        ld pm, dpm;
+        legendre(N, 2.0L * x[i], &pm, &dpm);
+        w[i] = 0.5L * 2.0L / (N * (N + 1.0L) * pm * pm);
+    }
+}
+
+/* Lagrange basis function l_j at t (eq. lagrange-function). */
+static ld lagr(int n, const ld *x, int j, ld t)
+{
+    ld v = 1.0L;
+    for (int k = 0; k < n; k++)
+        if (k != j) v *= (t - x[k]) / (x[j] - x[k]);
+    return v;
+}
+
+/* Derivative of l_j at t by the product rule. */
+static ld lagr_d(int n, const ld *x, int j, ld t)
+{
+    ld s = 0.0L;
+    for (int m = 0; m < n; m++) {
+        if (m == j) continue;
+        ld v = 1.0L / (x[j] - x[m]);
+        for (int k = 0; k < n; k++)
+            if (k != j && k != m) v *= (t - x[k]) / (x[j] - x[k]);
+        s += v;
+    }
+    return s;
+}
+
+/* Gauss-Jordan inverse with partial pivoting, long double. */
+static int invert(int n, const ld *A, ld *Ainv)
+{
+    ld a[MAXK][2 * MAXK];
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < 2 * n; j++)
+            a[i][j] = (j < n) ? A[i * n + j] : (j - n == i ? 1.0L : 0.0L);
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int r = c + 1; r < n; r++)
+            if (fabsl(a[r][c]) > fabsl(a[piv][c])) piv = r;
+        if (a[piv][c] == 0.0L) return -1;
+        if (piv != c)
+            for (int j = 0; j < 2 * n; j++) { ld t = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = t; }
+        ld d = a[c][c];
+        for (int j = 0; j < 2 * n; j++) a[c][j] /= d;
+        for (int r = 0; r < n; r++) {
+            if (r == c) continue;
+            ld f = a[r][c];
+            for (int j = 0; j < 2 * n; j++) a[r][j] -= f * a[c][j];
+        }
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) Ainv[i * n + j] = a[i][j + n];
+    return 0;
+}
+
+static int build_level(int n, int fam, lvl_t *L)
+{
+    if (n < 2 || n > MAXK) return -1;
+    ld x[MAXK], w[MAXK];
+    if (fam == OR_LGL) lgl_nodes(n, x, w);
+    else gauss_nodes(n, x, w);
+    /* Gauss rule used to integrate the basis exactly over subcells (degree n-1). */
+    ld gx[MAXK], gw[MAXK];
+    gauss_nodes(n, gx, gw);
+
+    ld Dc[MAXK * MAXK], Pm[MAXK * MAXK], Rm[MAXK * MAXK], Dv[MAXK * MAXK];
+    L->n = n;
+    for (int i = 0; i < n; i++) {
+        L->xi[i] = (double)x[i];
+        L->w[i] = (double)w[i];
+        L->bm[i] = (double)lagr(n, x, i, -0.5L);
+        L->bp[i] = (double)lagr(n, x, i, 0.5L);
+    }
+    /* Dcal_ij = l_j'(xi_i) (Sec. 2.2) */
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) Dc[i * n + j] = lagr_d(n, x, j, x[i]);
+    /* D = M^-1 Dcal^T M, i.e. D_ij = Dcal_ji w_j / w_i (eq. semi-discrete-dg) */
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) Dv[i * n + j] = Dc[j * n + i] * w[j] / w[i];
+    /* P_ij = n * integral of l_j over subcell i (Sec. 2.3), subcell i = [-1/2 + i/n, -1/2 + (i+1)/n] */
+    for (int i = 0; i < n; i++) {
+        ld a = -0.5L + (ld)i / n, b = -0.5L + (ld)(i + 1) / n;
+        for (int j = 0; j < n; j++) {
+            ld s = 0.0L;
+            for (int q = 0; q < n; q++) s += (b - a) * gw[q] * lagr(n, x, j, 0.5L * (a + b) + (b - a) * gx[q]);
+            Pm[i * n + j] = (ld)n * s;
+        }
+    }
+    if (invert(n, Pm, Rm)) return -1;
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            L->Dcal[i * n + j] = (double)Dc[i * n + j];
+            L->D[i * n + j] = (double)Dv[i * n + j];
+            L->P[i * n + j] = (double)Pm[i * n + j];
+            L->R[i * n + j] = (double)Rm[i * n + j];
+            ld s = 0.0L;
+            for (int k = 0; k < n; k++) s += Pm[i * n + k] * Dv[k * n + j];
+            L->Dhat[i * n + j] = (double)s;
+            /* subcell interfaces mu_{i+1/2} = -1/2 + (i+1)/n, mu_{i-1/2} = -1/2 + i/n (eq. subcell-grid) */
+            L->Ip[i * n + j] = (double)lagr(n, x, j, -0.5L + (ld)(i + 1) / n);
+            L->Im[i * n + j] = (double)lagr(n, x, j, -0.5L + (ld)i / n);
+        }
+    /* B^(0) has nonzero columns -l_i(-1/2)/w_i (first) and l_i(1/2)/w_i (last)
+       (eq. boundary-evalution-matrix, tweak-boundary-evaluation-matrix); Bhat = P B^(0). */
+    for (int i = 0; i < n; i++) {
+        ld sl = 0.0L, sr = 0.0L;
+        for (int k = 0; k < n; k++) {
+            sl += Pm[i * n + k] * (-lagr(n, x, k, -0.5L) / w[k]);
+            sr += Pm[i * n + k] * (lagr(n, x, k, 0.5L) / w[k]);
+        }
+        L->Bhl[i] = (double)sl;
+        L->Bhr[i] = (double)sr;
+    }
+    return 0;
+}
+
+int or_tables(int n, int fam, double *out, int cap)
+{
+    lvl_t L;
+    if (build_level(n, fam, &L)) return OR_EINVAL;
+    int need = 2 * n + 2 * n * n + 2 * n + 3 * n * n + 2 * n + 2 * n * n;
+    if (cap < need) return OR_EINVAL;
+    double *o = out;
+#define PUT(arr, cnt) do { memcpy(o, arr, sizeof(double) * (cnt)); o += (cnt); } while (0)
+    PUT(L.xi, n); PUT(L.w, n); PUT(L.Dcal, n * n); PUT(L.D, n * n);
+    PUT(L.bm, n); PUT(L.bp, n); PUT(L.P, n * n); PUT(L.R, n * n); PUT(L.Dhat, n * n);
+    PUT(L.Bhl, n); PUT(L.Bhr, n); PUT(L.Ip, n * n); PUT(L.Im, n * n);
+#undef PUT
+    return (int)(o - out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Compressible Euler physics (Sec. 3.1)                                      */
+/* ------------------------------------------------------------------------- */
+
+/* Perfect-gas pressure (eq. equation-of-state); -inf when rho <= 0 so that
+   such a point forces the squeeze parameter to zero. */
+static double pressure(int dim, double g, const double *u)
+{
+    if (!(u[0] > 0.0)) return -INFINITY;
+    double m2 = 0.0;
+    for (int a = 0; a < dim; a++) m2 += u[1 + a] * u[1 + a];
+    return (g - 1.0) * (u[dim + 1] - 0.5 * m2 / u[0]);
+}
+
+static int permissible(int dim, double g, const double *u)
+{
+    if (!(u[0] > 0.0)) return 0;
+    double p = pressure(dim, g, u);
+    return p > 0.0;
+}
+
+/* Physical flux along axis a (eqn. comp-euler-conservative). */
+static void euler_flux(int dim, double g, int a, const double *u, double *f)
+{
+    double p = pressure(dim, g, u);
+    double va = u[1 + a] / u[0];
+    f[0] = u[1 + a];
+    for (int b = 0; b < dim; b++) f[1 + b] = u[1 + b] * va + (a == b ? p : 0.0);
+    f[dim + 1] = va * (u[dim + 1] + p);
+}
+
+/* HLL flux with Einfeldt signal speeds from Roe averages (cited in Sec. 3; the
+   formulas are the textbook ones):  S_L = min(v_L - c_L, v~ - c~),
+   S_R = max(v_R + c_R, v~ + c~),
+   f* = (S_R+ f_L - S_L- f_R + S_L- S_R+ (u_R - u_L)) / (S_R+ - S_L-). */
+static void hlle(int dim, double g, int a, const double *uL, const double *uR, double *fs)
+{
+    int nv = dim + 2;
+    double fL[MAXV], fR[MAXV];
+    euler_flux(dim, g, a, uL, fL);
+    euler_flux(dim, g, a, uR, fR);
+    double pL = pressure(dim, g, uL), pR = pressure(dim, g, uR);
+    double vL = uL[1 + a] / uL[0], vR = uR[1 + a] / uR[0];
+    double cL = sqrt(g * pL / uL[0]), cR = sqrt(g * pR / uR[0]);
+    double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
+    double HL = (uL[dim + 1] + pL) / uL[0], HR = (uR[dim + 1] + pR) / uR[0];
+    double vt2 = 0.0, vtn = 0.0;
+    for (int b = 0; b < dim; b++) {
+        double vb = (sqL * (uL[1 + b] / uL[0]) + sqR * (uR[1 + b] / uR[0])) / (sqL + sqR);
+        vt2 += vb * vb;
+        if (b == a) vtn = vb;
+    }
+    double Ht = (sqL * HL + sqR * HR) / (sqL + sqR);
+    double ct = sqrt((g - 1.0) * (Ht - 0.5 * vt2));
+    double SL = fmin(vL - cL, vtn - ct);
+    double SR = fmax(vR + cR, vtn + ct);
+    double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
+    double inv = 1.0 / (SRp - SLm);
+    for (int v = 0; v < nv; v++)
+        fs[v] = (SRp * fL[v] - SLm * fR[v] + SLm * SRp * (uR[v] - uL[v])) * inv;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tensor helpers (App. N-mode product)                                       */
+/* ------------------------------------------------------------------------- */
+
+/* out = in x_a A : A is rows x ext[a] (row-major); extent along a becomes rows. */
+static void mode_product(const double *in, const int ext[3], int a, const double *A, int rows, double *out)
+{
+    int eo[3] = {ext[0], ext[1], ext[2]};
+    eo[a] = rows;
+    for (int k = 0; k < eo[2]; k++)
+        for (int j = 0; j < eo[1]; j++)
+            for (int i = 0; i < eo[0]; i++) {
+                int o[3] = {i, j, k};
+                double s = 0.0;
+                for (int c = 0; c < ext[a]; c++) {
+                    int ii[3] = {i, j, k};
+                    ii[a] = c;
+                    s += A[o[a] * ext[a] + c] * in[ii[0] + ext[0] * (ii[1] + ext[1] * ii[2])];
+                }
+                out[i + eo[0] * (j + eo[1] * k)] = s;
+            }
+}
+
+/* Apply the n x n matrix M along every axis b < dim except 'skip' (skip = -1: all). */
+static void apply_all(double *t, double *tmp, int dim, int n, const double *M, int skip)
+{
+    int ext[3] = {n, dim > 1 ? n : 1, dim > 2 ? n : 1};
+    int cnt = ext[0] * ext[1] * ext[2];
+    for (int b = 0; b < dim; b++) {
+        if (b == skip) continue;
+        mode_product(t, ext, b, M, n, tmp);
+        memcpy(t, tmp, sizeof(double) * cnt);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    or_mesh m;
+    or_params p;
+    int dim, K, nv;
+    int G[3];          /* global subcell extents */
+    long dof;          /* subcells */
+    int nel;           /* elements */
+    int Kd;            /* K^dim */
+    int nlev;          /* DG levels (top .. 2) */
+    int lev_n[MAXLEV];
+    int lev_off[MAXLEV];
+    int A;             /* blending factors per element */
+    lvl_t L[MAXLEV];   /* tables per DG level index */
+    lvl_t Lhalf[MAXLEV];   /* tables of level n/2 (for the indicator), n >= 4 */
+    double dx[3];
+} ctx_t;
+
+static int ilog2(int n) { int r = 0; while ((1 << r) < n) r++; return r; }
+
+static int make_ctx(const or_mesh *m, const or_params *p, ctx_t *c)
+{
+    memset(c, 0, sizeof(*c));
+    if (m->dim < 1 || m->dim > 3) return OR_EINVAL;
+    if (m->K != 2 && m->K != 4 && m->K != 8) return OR_EINVAL;
+    c->m = *m;
+    c->p = *p;
+    c->dim = m->dim;
+    c->K = m->K;
+    c->nv = m->dim + 2;
+    c->nel = 1;
+    c->dof = 1;
+    c->Kd = 1;
+    for (int a = 0; a < 3; a++) {
+        if (a < m->dim) {
+            if (m->nelem[a] < 1) return OR_EINVAL;
+            c->G[a] = m->nelem[a] * m->K;
+            c->nel *= m->nelem[a];
+            c->Kd *= m->K;
+            c->dx[a] = (m->hi[a] - m->lo[a]) / m->nelem[a];
+        } else {
+            c->G[a] = 1;
+            c->dx[a] = 1.0;
+        }
+        c->dof *= c->G[a];
+    }
+    int top = p->top_level > 0 ? p->top_level : m->K;
+    if (top > m->K || (top & (top - 1))) return OR_EINVAL;
+    c->nlev = 0;
+    int off = 0;
+    for (int n = top; n >= 2; n /= 2) {
+        int li = c->nlev++;
+        c->lev_n[li] = n;
+        c->lev_off[li] = off;
+        int per = 1;
+        for (int a = 0; a < m->dim; a++) per *= m->K / n;
+        off += per;
+        if (build_level(n, m->family, &c->L[li])) return OR_EINVAL;
+        if (n >= 4 && build_level(n / 2, m->family, &c->Lhalf[li])) return OR_EINVAL;
+    }
+    c->A = off;
+    return OR_OK;
+}
+
+int or_alpha_len(const or_mesh *m, const or_params *p)
+{
+    ctx_t c;
+    if (make_ctx(m, p, &c)) return OR_EINVAL;
+    return c.A;
+}
+
+static int level_enabled(const ctx_t *c, int li)
+{
+    if (c->p.level_mask == 0) return 1;
+    return (c->p.level_mask >> ilog2(c->lev_n[li])) & 1u;
+}
+
+/* Element coordinates and global index of local subcell (i,j,k). */
+static long gidx(const ctx_t *c, const int e3[3], int i, int j, int k)
+{
+    long gx = (long)e3[0] * c->K + i;
+    long gy = c->dim > 1 ? (long)e3[1] * c->K + j : 0;
+    long gz = c->dim > 2 ? (long)e3[2] * c->K + k : 0;
+    return gx + c->G[0] * (gy + (long)c->G[1] * gz);
+}
+
+static void elem_coords(const ctx_t *c, int e, int e3[3])
+{
+    e3[0] = e % c->m.nelem[0];
+    int r = e / c->m.nelem[0];
+    e3[1] = c->dim > 1 ? r % c->m.nelem[1] : 0;
+    e3[2] = c->dim > 2 ? r / c->m.nelem[1] : 0;
+}
+
+/* Gather element data ub[v][Kd] (local index i + K(j + K k)). */
+static void gather_elem(const ctx_t *c, const double *u, int e, double *ub)
+{
+    int e3[3];
+    elem_coords(c, e, e3);
+    int K = c->K, ky = c->dim > 1 ? K : 1, kz = c->dim > 2 ? K : 1;
+    for (int v = 0; v < c->nv; v++)
+        for (int k = 0; k < kz; k++)
+            for (int j = 0; j < ky; j++)
+                for (int i = 0; i < K; i++)
+                    ub[v * c->Kd + i + K * (j + K * k)] = u[v * c->dof + gidx(c, e3, i, j, k)];
+}
+
+/* Gather sub-element (block of n^dim subcells starting at local (i0,j0,k0)) of ub. */
+static void gather_sub(const ctx_t *c, const double *ub, int n, int i0, int j0, int k0, double *us)
+{
+    int K = c->K, ny = c->dim > 1 ? n : 1, nz = c->dim > 2 ? n : 1, nd = n * ny * nz;
+    for (int v = 0; v < c->nv; v++)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < n; i++)
+                    us[v * nd + i + n * (j + n * k)] = ub[v * c->Kd + (i0 + i) + K * ((j0 + j) + K * (k0 + k))];
+}
+
+/* Nodal reconstruction of every variable: ut = us x_1 R x_2 R x_3 R (eq. reco-*, 3D-nodal-reconstruction). */
+static void reconstruct(const ctx_t *c, const lvl_t *L, const double *us, double *ut)
+{
+    int n = L->n, nd = 1;
+    for (int a = 0; a < c->dim; a++) nd *= n;
+    double tmp[MAXK * MAXK * MAXK];
+    for (int v = 0; v < c->nv; v++) {
+        memcpy(ut + v * nd, us + v * nd, sizeof(double) * nd);
+        apply_all(ut + v * nd, tmp, c->dim, n, L->R, -1);
+    }
+}
+
+/* Squeezing parameter beta (eq. positivity-limiter-2, calc-squeezing-parameter).
+   Check set: nodal values and, per axis, both boundary traces at the face nodes.
+   Readings: <p> = p(<u>); a ratio whose denominator is not positive is 1; a point
+   with rho <= 0 has p = -inf and so gives beta = 0. */
+static double squeeze_beta(const ctx_t *c, const lvl_t *L, const double *us, const double *ut, double *mean)
+{
+    int n = L->n, dim = c->dim, nv = c->nv;
+    int nd = 1;
+    for (int a = 0; a < dim; a++) nd *= n;
+    for (int v = 0; v < nv; v++) {
+        double s = 0.0;
+        for (int q = 0; q < nd; q++) s += us[v * nd + q];
+        mean[v] = s / nd;
+    }
+    double g = c->m.gamma;
+    double rmean = mean[0], pmean = pressure(dim, g, mean);
+    double rmin = INFINITY, pmin = INFINITY;
+    int ok = 1;
+    double pt[MAXV];
+    for (int q = 0; q < nd; q++) {
+        for (int v = 0; v < nv; v++) pt[v] = ut[v * nd + q];
+        double pp = pressure(dim, g, pt);
+        if (!(pt[0] > 0.0 && pp > 0.0)) ok = 0;
+        rmin = fmin(rmin, pt[0]);
+        pmin = fmin(pmin, pp);
+    }
+    int ext[3] = {n, dim > 1 ? n : 1, dim > 2 ? n : 1};
+    double tr[MAXV][MAXK * MAXK];
+    for (int a = 0; a < dim; a++)
+        for (int side = 0; side < 2; side++) {
+            const double *b = side ? L->bp : L->bm;
+            for (int v = 0; v < nv; v++) mode_product(ut + v * nd, ext, a, b, 1, tr[v]);
+            int nf = nd / n;
+            for (int q = 0; q < nf; q++) {
+                for (int v = 0; v < nv; v++) pt[v] = tr[v][q];
+                double pp = pressure(dim, g, pt);
+                if (!(pt[0] > 0.0 && pp > 0.0)) ok = 0;
+                rmin = fmin(rmin, pt[0]);
+                pmin = fmin(pmin, pp);
+            }
+        }
+    if (ok) return 1.0;
+    double eps = fmin(1e-20, fmin(rmean, pmean));
+    double br = (rmean - rmin > 0.0) ? (rmean - eps) / (rmean - rmin) : 1.0;
+    double bq = (pmean - pmin > 0.0) ? (pmean - eps) / (pmean - pmin) : 1.0;
+    double beta = fmin(fmin(br, bq), 1.0);
+    return beta;
+}
+
+/* Primitive variables (rho, v_1..v_dim, p) of a conserved state. */
+static void primitives(int dim, double g, const double *u, double *w)
+{
+    w[0] = u[0];
+    for (int a = 0; a < dim; a++) w[1 + a] = u[1 + a] / u[0];
+    w[dim + 1] = pressure(dim, g, u);
+}
+
+/* Smoothness measure of one scalar nodal field (Sec. 2.7, eq. L1-norm-slope):
+   the sum over axes of the L1 norm of the first derivative on [-1/2,1/2]^dim,
+   by the tensor n-point rule on the collocation nodes. */
+static double sigma_field(const ctx_t *c, const lvl_t *L, const double *phi)
+{
+    int n = L->n, dim = c->dim;
+    int ext[3] = {n, dim > 1 ? n : 1, dim > 2 ? n : 1};
+    double der[MAXK * MAXK * MAXK];
+    double s = 0.0;
+    for (int a = 0; a < dim; a++) {
+        mode_product(phi, ext, a, L->Dcal, n, der);
+        for (int k = 0; k < ext[2]; k++)
+            for (int j = 0; j < ext[1]; j++)
+                for (int i = 0; i < ext[0]; i++) {
+                    double wq = L->w[i] * (dim > 1 ? L->w[j] : 1.0) * (dim > 2 ? L->w[k] : 1.0);
+                    s += wq * fabs(der[i + ext[0] * (j + ext[1] * k)]);
+                }
+    }
+    return s;
+}
+
+/* Blending factor of one level-n sub-element (eq. calc-blending-factor).
+   sigma_n is measured on the sub-element's own reference cube; sigma_{n/2} is
+   the sum over its 2^dim children, each child's own-cube measure scaled by
+   2^(1-dim) to the parent's coordinates.  The factor is the minimum over the
+   primitive variables.  If any node of either reconstruction has rho <= 0 or
+   a non-finite value appears, the factor is 0.  Returns alpha; *xr gets the
+   largest pre-clamp value tau_A (r - tau_S). */
+static double indicator(const ctx_t *c, int li, const double *us, const double *ut, double *xr)
+{
+    const lvl_t *L = &c->L[li], *H = &c->Lhalf[li];
+    int n = L->n, h = n / 2, dim = c->dim, nv = c->nv;
+    double g = c->m.gamma;
+    int nd = 1, hd = 1;
+    for (int a = 0; a < dim; a++) { nd *= n; hd *= h; }
+    double phi[MAXV][MAXK * MAXK * MAXK];
+    double pt[MAXV], w[MAXV];
+    *xr = NAN;
+    for (int q = 0; q < nd; q++) {
+        for (int v = 0; v < nv; v++) pt[v] = ut[v * nd + q];
+        if (!(pt[0] > 0.0)) return 0.0;
+        primitives(dim, g, pt, w);
+        for (int v = 0; v < nv; v++) phi[v][q] = w[v];
+    }
+    double sig_n[MAXV], sig_h[MAXV];
+    for (int v = 0; v < nv; v++) { sig_n[v] = sigma_field(c, L, phi[v]); sig_h[v] = 0.0; }
+    /* children */
+    int nch = 1 << dim;
+    double cs[MAXV * MAXK * MAXK * MAXK], ct[MAXV * MAXK * MAXK * MAXK];
+    double cphi[MAXK * MAXK * MAXK];
+    double scale = 1.0;
+    for (int a = 1; a < dim; a++) scale *= 0.5;
+    for (int ch = 0; ch < nch; ch++) {
+        int ci = (ch & 1) * h, cj = ((ch >> 1) & 1) * h, ck = ((ch >> 2) & 1) * h;
+        /* gather child means from the parent block us (extent n) */
+        int hy = dim > 1 ? h : 1, hz = dim > 2 ? h : 1;
+        for (int v = 0; v < nv; v++)
+            for (int k = 0; k < hz; k++)
+                for (int j = 0; j < hy; j++)
+                    for (int i = 0; i < h; i++)
+                        cs[v * hd + i + h * (j + h * k)] =
+                            us[v * nd + (ci + i) + n * ((cj + j) + n * (ck + k))];
+        for (int v = 0; v < nv; v++) {
+            memcpy(ct + v * hd, cs + v * hd, sizeof(double) * hd);
+            double tmp[MAXK * MAXK * MAXK];
+            apply_all(ct + v * hd, tmp, dim, h, H->R, -1);
+        }
+        double cw[MAXV][MAXK * MAXK * MAXK];
+        for (int q = 0; q < hd; q++) {
+            for (int v = 0; v < nv; v++) pt[v] = ct[v * hd + q];
+            if (!(pt[0] > 0.0)) return 0.0;
+            primitives(dim, g, pt, w);
+            for (int v = 0; v < nv; v++) cw[v][q] = w[v];
+        }
+        for (int v = 0; v < nv; v++) {
+            memcpy(cphi, cw[v], sizeof(double) * hd);
+            sig_h[v] += scale * sigma_field(c, H, cphi);
+        }
+    }
+    double alpha = 1.0, xmax = -INFINITY;
+    for (int v = 0; v < nv; v++) {
+        double den = fmax(fmax(sig_h[v], sig_n[v]), 1.0);
+        double r = fabs(sig_n[v] - sig_h[v]) / den;
+        double x = c->p.tau_A * (r - c->p.tau_S);
+        if (!isfinite(x)) { *xr = NAN; return 0.0; }
+        double cut = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+        double a_v = 1.0 - cut;
+        if (a_v < alpha) alpha = a_v;
+        if (x > xmax) xmax = x;
+    }
+    *xr = xmax;
+    return alpha;
+}
+
+/* Per element: squeeze parameters of every level, blending factors by the
+   multi-level algorithm (App. sketch of the algorithm, multi-level):
+   levels from the top down; beta < beta_L gives alpha = 0, level 2 takes
+   alpha = beta, higher levels use the indicator on the unlimited data; if every
+   factor of a level exceeds alpha_H they are set to 1 and lower levels are not
+   visited; if every factor is below alpha_L they are set to 0. */
+static void analyse_element(const ctx_t *c, const double *u, int e, double *alpha, double *beta,
+                            const double *alpha_in, double *xraw, double *araw)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    double ub[MAXV * MAXK * MAXK * MAXK];
+    double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK];
+    double mean[MAXV];
+    gather_elem(c, u, e, ub);
+    for (int q = 0; q < c->A; q++) { xraw[q] = NAN; araw[q] = NAN; }
+    for (int li = 0; li < c->nlev; li++) {
+        int n = c->lev_n[li], ns = K / n;
+        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+        for (int s3 = 0; s3 < sz; s3++)
+            for (int s2 = 0; s2 < sy; s2++)
+                for (int s1 = 0; s1 < ns; s1++) {
+                    int s = s1 + ns * (s2 + ns * s3);
+                    gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                    reconstruct(c, &c->L[li], us, ut);
+                    beta[c->lev_off[li] + s] = squeeze_beta(c, &c->L[li], us, ut, mean);
+                }
+    }
+    if (c->p.mode == OR_EXTERNAL) {
+        for (int q = 0; q < c->A; q++) alpha[q] = alpha_in[q];
+        return;
+    }
+    for (int q = 0; q < c->A; q++) alpha[q] = 0.0;
+    if (c->p.mode == OR_FORCE_FV) return;
+    if (c->p.mode == OR_FORCE_DG) { alpha[0] = 1.0; return; }
+    int broke = 0;
+    for (int li = 0; li < c->nlev && !broke; li++) {
+        if (!level_enabled(c, li)) continue;
+        int n = c->lev_n[li], ns = K / n;
+        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+        int cnt = ns * sy * sz, nhi = 0, nlo = 0;
+        double *al = alpha + c->lev_off[li];
+        for (int s3 = 0; s3 < sz; s3++)
+            for (int s2 = 0; s2 < sy; s2++)
+                for (int s1 = 0; s1 < ns; s1++) {
+                    int s = s1 + ns * (s2 + ns * s3);
+                    double b = beta[c->lev_off[li] + s];
+                    double a;
+                    if (b < c->p.beta_L) a = 0.0;
+                    else if (n == 2) a = b;
+                    else {
+                        gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                        reconstruct(c, &c->L[li], us, ut);
+                        a = indicator(c, li, us, ut, &xraw[c->lev_off[li] + s]);
+                    }
+                    al[s] = a;
+                    araw[c->lev_off[li] + s] = a;
+                    if (a > c->p.alpha_H) nhi++;
+                    if (a < c->p.alpha_L) nlo++;
+                }
+        if (nhi == cnt) {
+            for (int s = 0; s < cnt; s++) al[s] = 1.0;
+            broke = 1;
+        } else if (nlo == cnt) {
+            for (int s = 0; s < cnt; s++) al[s] = 0.0;
+        }
+    }
+    (void)nv;
+}
+
+/* Blending weights of local subcell (i,j,k) (eq. blending-weights):
+   th[0] = FV weight, th[1+li] = weight of DG level index li. */
+static void theta_cell(const ctx_t *c, const double *alpha, int i, int j, int k, double *th)
+{
+    double prod = 1.0;
+    for (int li = 0; li < c->nlev; li++) {
+        int n = c->lev_n[li], ns = c->K / n;
+        int s = i / n + ns * ((c->dim > 1 ? j / n : 0) + ns * (c->dim > 2 ? k / n : 0));
+        double a = alpha[c->lev_off[li] + s];
+        th[1 + li] = a * prod;
+        prod *= (1.0 - a);
+    }
+    th[0] = prod;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Right-hand side                                                            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double *alpha, *beta;   /* nel * A */
+    double *theta;          /* (nlev+1) * dof, global subcell order */
+    double *side;           /* [axis][side][v][dof] blended interface states */
+    double *flux;           /* [axis] -> (G_a+1) * trans * nv, see flux_index */
+    long flux_off[3];
+} work_t;
+
+/* Flux array index: face f along axis a (0..G_a), transverse global cell t, variable v. */
+static long flux_index(const ctx_t *c, int a, long f, long t, int v)
+{
+    long trans = c->dof / c->G[a];
+    return ((long)v * (c->G[a] + 1) + f) * trans + t;
+}
+
+/* Transverse index of global cell (gx,gy,gz) for axis a. */
+static long trans_index(const ctx_t *c, int a, const long g[3])
+{
+    if (a == 0) return g[1] + (long)c->G[1] * g[2];
+    if (a == 1) return g[0] + (long)c->G[0] * g[2];
+    return g[0] + (long)c->G[0] * g[1];
+}
+
+/* Pass 1, per element: blending factors, weights and the blended interface
+   states of every subcell on both sides along every axis (Sec. 2.6 interface
+   values, App. eq. 3D-prolongation): side = theta_FV * mean +
+   sum_n theta_n * (face mean of the trace of the squeezed level-n polynomial at
+   that subcell face). */
+static void pass1_element(const ctx_t *c, const double *u, int e, work_t *W, const double *alpha_in,
+                          double *xraw, double *araw)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    double *alpha = W->alpha + (long)e * c->A, *beta = W->beta + (long)e * c->A;
+    analyse_element(c, u, e, alpha, beta, alpha_in ? alpha_in + (long)e * c->A : NULL,
+                    xraw + (long)e * c->A, araw + (long)e * c->A);
+    int e3[3];
+    elem_coords(c, e, e3);
+    int ky = dim > 1 ? K : 1, kz = dim > 2 ? K : 1;
+    double ub[MAXV * MAXK * MAXK * MAXK];
+    gather_elem(c, u, e, ub);
+    /* weights */
+    double th[MAXLEV + 1];
+    for (int k = 0; k < kz; k++)
+        for (int j = 0; j < ky; j++)
+            for (int i = 0; i < K; i++) {
+                theta_cell(c, alpha, i, j, k, th);
+                long gi = gidx(c, e3, i, j, k);
+                for (int l = 0; l <= c->nlev; l++) W->theta[l * c->dof + gi] = th[l];
+            }
+    /* start the side states with the FV part */
+    for (int a = 0; a < dim; a++)
+        for (int sd = 0; sd < 2; sd++)
+            for (int v = 0; v < nv; v++)
+                for (int k = 0; k < kz; k++)
+                    for (int j = 0; j < ky; j++)
+                        for (int i = 0; i < K; i++) {
+                            long gi = gidx(c, e3, i, j, k);
+                            W->side[(((long)a * 2 + sd) * nv + v) * c->dof + gi] =
+                                W->theta[gi] * ub[v * c->Kd + i + K * (j + K * k)];
+                        }
+    /* add the DG levels */
+    double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK], mean[MAXV];
+    double tr[MAXK * MAXK * MAXK], tmp[MAXK * MAXK * MAXK];
+    for (int li = 0; li < c->nlev; li++) {
+        const lvl_t *L = &c->L[li];
+        int n = L->n, ns = K / n;
+        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+        int ny = dim > 1 ? n : 1, nz = dim > 2 ? n : 1, nd = n * ny * nz;
+        for (int s3 = 0; s3 < sz; s3++)
+            for (int s2 = 0; s2 < sy; s2++)
+                for (int s1 = 0; s1 < ns; s1++) {
+                    long g0 = gidx(c, e3, s1 * n, s2 * n, s3 * n);
+                    double thn = W->theta[(1 + li) * c->dof + g0];
+                    if (thn == 0.0) continue;
+                    int s = s1 + ns * (s2 + ns * s3);
+                    double b = beta[c->lev_off[li] + s];
+                    gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                    reconstruct(c, L, us, ut);
+                    for (int v = 0; v < nv; v++) {
+                        double sum = 0.0;
+                        for (int q = 0; q < nd; q++) sum += us[v * nd + q];
+                        mean[v] = sum / nd;
+                    }
+                    /* squeezed nodal values (eq. positivity-limiter-applied) */
+                    for (int v = 0; v < nv; v++)
+                        for (int q = 0; q < nd; q++) ut[v * nd + q] = (1.0 - b) * mean[v] + b * ut[v * nd + q];
+                    int ext[3] = {n, ny, nz};
+                    for (int a = 0; a < dim; a++)
+                        for (int sd = 0; sd < 2; sd++) {
+                            const double *I = sd ? L->Ip : L->Im;
+                            for (int v = 0; v < nv; v++) {
+                                /* trace at every subcell interface along a, then face means along the other axes */
+                                mode_product(ut + v * nd, ext, a, I, n, tr);
+                                apply_all(tr, tmp, dim, n, L->P, a);
+                                for (int k = 0; k < nz; k++)
+                                    for (int j = 0; j < ny; j++)
+                                        for (int i = 0; i < n; i++) {
+                                            long gi = gidx(c, e3, s1 * n + i, s2 * n + j, s3 * n + k);
+                                            W->side[(((long)a * 2 + sd) * nv + v) * c->dof + gi] +=
+                                                thn * tr[i + n * (j + n * k)];
+                                        }
+                            }
+                        }
+                }
+    }
+}
+
+/* Pass 2: the unique common flux at one face subcell (Sec. 2.6 common surface
+   flux; App. eq. 3D-interface-fluxes and 3D-blend-interface-fluxes, extended to
+   several levels):
+     F* = thFV * HLLE(uL, uR) + sum_{n in L(f)} thbar_n * [P_perp HLLE(R_perp uL, R_perp uR)]
+   where L(f) holds the DG levels whose sub-element boundary contains the face,
+   thbar_n is the mean of the level-n weights of the two adjacent subcells,
+   R_perp / P_perp act along the face over the level-n face segment, and
+   thFV = 1 - sum thbar_n.  Interface safety: an FV input that is not permissible
+   is replaced by that side's subcell mean; a DG candidate whose face-node states
+   are not all permissible hands its weight to the FV candidate. */
+static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, long f, const long gt[3],
+                      double *F, long *nfb)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    double g = c->m.gamma;
+    int Ga = c->G[a];
+    int periodic = c->m.bc[a] == OR_PERIODIC;
+    /* adjacent cells along a; gt holds the transverse coordinates */
+    long gl[3] = {gt[0], gt[1], gt[2]}, gr[3] = {gt[0], gt[1], gt[2]};
+    int haveL = 1, haveR = 1;
+    if (f == 0) { if (periodic) gl[a] = Ga - 1; else haveL = 0; }
+    else gl[a] = f - 1;
+    if (f == Ga) { if (periodic) gr[a] = 0; else haveR = 0; }
+    else gr[a] = f;
+    if (!haveL) gl[a] = gr[a];
+    if (!haveR) gr[a] = gl[a];
+    long il = gl[0] + c->G[0] * (gl[1] + (long)c->G[1] * gl[2]);
+    long ir = gr[0] + c->G[0] * (gr[1] + (long)c->G[1] * gr[2]);
+    /* states: outflow mirrors the interior side (state and weights) */
+    double uL[MAXV], uR[MAXV];
+    for (int v = 0; v < nv; v++) {
+        uL[v] = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il] : W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir];
+        uR[v] = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir] : W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il];
+    }
+    int k = (int)(f % K);
+    double thFV = 1.0;
+    double Fdg[MAXLEV][MAXV];
+    double wdg[MAXLEV];
+    for (int li = 0; li < c->nlev; li++) {
+        wdg[li] = 0.0;
+        int n = c->lev_n[li];
+        if (k % n != 0) continue;
+        double tb = 0.5 * (W->theta[(1 + li) * c->dof + il] + W->theta[(1 + li) * c->dof + ir]);
+        if (tb == 0.0) continue;
+        /* level-n face segment: the n^(dim-1) face subcells of the sub-element face */
+        int tax[2], nt = 0;
+        for (int b = 0; b < dim; b++) if (b != a) tax[nt++] = b;
+        long base[3] = {gt[0], gt[1], gt[2]};
+        int pos[2] = {0, 0};
+        for (int q = 0; q < nt; q++) {
+            long gb = gt[tax[q]];
+            long loc = gb % K;
+            base[tax[q]] = gb - loc + (loc / n) * n;
+            pos[q] = (int)(loc % n);
+        }
+        int ext[3] = {n, nt > 1 ? n : 1, 1};
+        if (nt == 0) ext[0] = 1;
+        int nf = ext[0] * ext[1];
+        double sL[MAXV][MAXK * MAXK], sR[MAXV][MAXK * MAXK];
+        for (int q1 = 0; q1 < ext[1]; q1++)
+            for (int q0 = 0; q0 < ext[0]; q0++) {
+                long cl[3] = {gl[0], gl[1], gl[2]}, cr[3] = {gr[0], gr[1], gr[2]};
+                if (nt > 0) { cl[tax[0]] = base[tax[0]] + q0; cr[tax[0]] = base[tax[0]] + q0; }
+                if (nt > 1) { cl[tax[1]] = base[tax[1]] + q1; cr[tax[1]] = base[tax[1]] + q1; }
+                long jl = cl[0] + c->G[0] * (cl[1] + (long)c->G[1] * cl[2]);
+                long jr = cr[0] + c->G[0] * (cr[1] + (long)c->G[1] * cr[2]);
+                for (int v = 0; v < nv; v++) {
+                    double vl = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + jl] : W->side[(((long)a * 2 + 0) * nv + v) * c->dof + jr];
+                    double vr = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + jr] : W->side[(((long)a * 2 + 1) * nv + v) * c->dof + jl];
+                    sL[v][q0 + ext[0] * q1] = vl;
+                    sR[v][q0 + ext[0] * q1] = vr;
+                }
+            }
+        /* nodal face states R_perp s */
+        double tmp[MAXK * MAXK];
+        for (int v = 0; v < nv; v++)
+            for (int q = 0; q < nt; q++) {
+                mode_product(sL[v], ext, q, c->L[li].R, n, tmp);
+                memcpy(sL[v], tmp, sizeof(double) * nf);
+                mode_product(sR[v], ext, q, c->L[li].R, n, tmp);
+                memcpy(sR[v], tmp, sizeof(double) * nf);
+            }
+        int ok = 1;
+        double pl[MAXV], pr[MAXV];
+        for (int q = 0; q < nf && ok; q++) {
+            for (int v = 0; v < nv; v++) { pl[v] = sL[v][q]; pr[v] = sR[v][q]; }
+            if (!permissible(dim, g, pl) || !permissible(dim, g, pr)) ok = 0;
+        }
+        if (!ok) { if (nfb) (*nfb)++; continue; }
+        double fn[MAXV][MAXK * MAXK], fs[MAXV];
+        for (int q = 0; q < nf; q++) {
+            for (int v = 0; v < nv; v++) { pl[v] = sL[v][q]; pr[v] = sR[v][q]; }
+            hlle(dim, g, a, pl, pr, fs);
+            for (int v = 0; v < nv; v++) fn[v][q] = fs[v];
+        }
+        for (int v = 0; v < nv; v++) {
+            for (int q = 0; q < nt; q++) {
+                mode_product(fn[v], ext, q, c->L[li].P, n, tmp);
+                memcpy(fn[v], tmp, sizeof(double) * nf);
+            }
+            Fdg[li][v] = fn[v][pos[0] + ext[0] * pos[1]];
+        }
+        wdg[li] = tb;
+        thFV -= tb;
+    }
+    for (int v = 0; v < nv; v++) F[v] = 0.0;
+    if (thFV != 0.0) {
+        double aL[MAXV], aR[MAXV], fs[MAXV];
+        memcpy(aL, uL, sizeof(aL));
+        memcpy(aR, uR, sizeof(aR));
+        if (!permissible(dim, g, aL)) {
+            for (int v = 0; v < nv; v++) aL[v] = u[v * c->dof + il];
+            if (nfb) (*nfb)++;
+        }
+        if (!permissible(dim, g, aR)) {
+            for (int v = 0; v < nv; v++) aR[v] = u[v * c->dof + ir];
+            if (nfb) (*nfb)++;
+        }
+        hlle(dim, g, a, aL, aR, fs);
+        for (int v = 0; v < nv; v++) F[v] = thFV * fs[v];
+    }
+    for (int li = 0; li < c->nlev; li++)
+        if (wdg[li] != 0.0)
+            for (int v = 0; v < nv; v++) F[v] += wdg[li] * Fdg[li][v];
+}
+
+/* Pass 3, per element: level right-hand sides and their blend
+   (eq. multilevel-blending-scheme, dgfv-scheme-3d, blending-weights):
+   FV:  -(K/dx_a) F*_a x_a Delta
+   DG level n on a sub-element:  (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat). */
+static void pass3_element(const ctx_t *c, const double *u, int e, const work_t *W, double *dudt)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    double g = c->m.gamma;
+    int e3[3];
+    elem_coords(c, e, e3);
+    int ky = dim > 1 ? K : 1, kz = dim > 2 ? K : 1;
+    double out[MAXV * MAXK * MAXK * MAXK];
+    memset(out, 0, sizeof(double) * nv * c->Kd);
+    const double *beta = W->beta + (long)e * c->A;
+    /* FV level */
+    for (int k = 0; k < kz; k++)
+        for (int j = 0; j < ky; j++)
+            for (int i = 0; i < K; i++) {
+                long gi = gidx(c, e3, i, j, k);
+                double t1 = W->theta[gi];
+                if (t1 == 0.0) continue;
+                long gg[3] = {(long)e3[0] * K + i, dim > 1 ? (long)e3[1] * K + j : 0, dim > 2 ? (long)e3[2] * K + k : 0};
+                for (int v = 0; v < nv; v++) {
+                    double r = 0.0;
+                    for (int a = 0; a < dim; a++) {
+                        long t = trans_index(c, a, gg);
+                        r -= (K / c->dx[a]) * (W->flux[W->flux_off[a] + flux_index(c, a, gg[a] + 1, t, v)] -
+                                               W->flux[W->flux_off[a] + flux_index(c, a, gg[a], t, v)]);
+                    }
+                    out[v * c->Kd + i + K * (j + K * k)] += t1 * r;
+                }
+            }
+    /* DG levels */
+    double ub[MAXV * MAXK * MAXK * MAXK];
+    gather_elem(c, u, e, ub);
+    double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK], mean[MAXV];
+    double fl[MAXV][MAXK * MAXK * MAXK], vol[MAXK * MAXK * MAXK], tmp[MAXK * MAXK * MAXK];
+    double lr[MAXV * MAXK * MAXK * MAXK];
+    for (int li = 0; li < c->nlev; li++) {
+        const lvl_t *L = &c->L[li];
+        int n = L->n, ns = K / n;
+        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+        int ny = dim > 1 ? n : 1, nz = dim > 2 ? n : 1, nd = n * ny * nz;
+        int ext[3] = {n, ny, nz};
+        for (int s3 = 0; s3 < sz; s3++)
+            for (int s2 = 0; s2 < sy; s2++)
+                for (int s1 = 0; s1 < ns; s1++) {
+                    long g0 = gidx(c, e3, s1 * n, s2 * n, s3 * n);
+                    double thn = W->theta[(1 + li) * c->dof + g0];
+                    if (thn == 0.0) continue;
+                    int s = s1 + ns * (s2 + ns * s3);
+                    double b = beta[c->lev_off[li] + s];
+                    gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                    reconstruct(c, L, us, ut);
+                    for (int v = 0; v < nv; v++) {
+                        double sum = 0.0;
+                        for (int q = 0; q < nd; q++) sum += us[v * nd + q];
+                        mean[v] = sum / nd;
+                    }
+                    for (int v = 0; v < nv; v++)
+                        for (int q = 0; q < nd; q++) ut[v * nd + q] = (1.0 - b) * mean[v] + b * ut[v * nd + q];
+                    memset(lr, 0, sizeof(double) * nv * nd);
+                    for (int a = 0; a < dim; a++) {
+                        double pt[MAXV], fp[MAXV];
+                        for (int q = 0; q < nd; q++) {
+                            for (int v = 0; v < nv; v++) pt[v] = ut[v * nd + q];
+                            euler_flux(dim, g, a, pt, fp);
+                            for (int v = 0; v < nv; v++) fl[v][q] = fp[v];
+                        }
+                        double sc = K / (n * c->dx[a]);
+                        for (int v = 0; v < nv; v++) {
+                            mode_product(fl[v], ext, a, L->Dhat, n, vol);
+                            apply_all(vol, tmp, dim, n, L->P, a);
+                            for (int kk = 0; kk < nz; kk++)
+                                for (int jj = 0; jj < ny; jj++)
+                                    for (int ii = 0; ii < n; ii++) {
+                                        int loc[3] = {ii, jj, kk};
+                                        long gg[3] = {(long)e3[0] * K + s1 * n + ii,
+                                                      dim > 1 ? (long)e3[1] * K + s2 * n + jj : 0,
+                                                      dim > 2 ? (long)e3[2] * K + s3 * n + kk : 0};
+                                        long t = trans_index(c, a, gg);
+                                        long fL = gg[a] - loc[a], fR = gg[a] - loc[a] + n;
+                                        double surf = L->Bhl[loc[a]] * W->flux[W->flux_off[a] + flux_index(c, a, fL, t, v)] +
+                                                      L->Bhr[loc[a]] * W->flux[W->flux_off[a] + flux_index(c, a, fR, t, v)];
+                                        int q = ii + n * (jj + n * kk);
+                                        lr[v * nd + q] += sc * (vol[q] - surf);
+                                    }
+                        }
+                    }
+                    for (int v = 0; v < nv; v++)
+                        for (int kk = 0; kk < nz; kk++)
+                            for (int jj = 0; jj < ny; jj++)
+                                for (int ii = 0; ii < n; ii++) {
+                                    int q = ii + n * (jj + n * kk);
+                                    int li2 = (s1 * n + ii) + K * ((s2 * n + jj) + K * (s3 * n + kk));
+                                    out[v * c->Kd + li2] += thn * lr[v * nd + q];
+                                }
+                }
+    }
+    for (int v = 0; v < nv; v++)
+        for (int k = 0; k < kz; k++)
+            for (int j = 0; j < ky; j++)
+                for (int i = 0; i < K; i++)
+                    dudt[v * c->dof + gidx(c, e3, i, j, k)] = out[v * c->Kd + i + K * (j + K * k)];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Drivers                                                                    */
+/* ------------------------------------------------------------------------- */
+
+static int check_state(const ctx_t *c, const double *u)
+{
+    int bad = 0;
+#pragma omp parallel for reduction(| : bad)
+    for (long gi = 0; gi < c->dof; gi++) {
+        double pt[MAXV];
+        for (int v = 0; v < c->nv; v++) pt[v] = u[v * c->dof + gi];
+        int fin = 1;
+        for (int v = 0; v < c->nv; v++) fin &= isfinite(pt[v]) ? 1 : 0;
+        if (!fin || !permissible(c->dim, c->m.gamma, pt)) bad |= 1;
+    }
+    return bad ? OR_ESTATE : OR_OK;
+}
+
+static int alloc_work(const ctx_t *c, work_t *W)
+{
+    memset(W, 0, sizeof(*W));
+    W->alpha = malloc(sizeof(double) * (size_t)c->nel * c->A);
+    W->beta = malloc(sizeof(double) * (size_t)c->nel * c->A);
+    W->theta = malloc(sizeof(double) * (size_t)(c->nlev + 1) * c->dof);
+    W->side = malloc(sizeof(double) * (size_t)c->dim * 2 * c->nv * c->dof);
+    long tot = 0;
+    for (int a = 0; a < c->dim; a++) {
+        W->flux_off[a] = tot;
+        tot += (long)c->nv * (c->G[a] + 1) * (c->dof / c->G[a]);
+    }
+    W->flux = malloc(sizeof(double) * (size_t)tot);
+    if (!W->alpha || !W->beta || !W->theta || !W->side || !W->flux) return -1;
+    return 0;
+}
+
+static void free_work(work_t *W)
+{
+    free(W->alpha); free(W->beta); free(W->theta); free(W->side); free(W->flux);
+}
+
+static int rhs_ctx(const ctx_t *c, const double *u, double *dudt, double *alpha_out, double *beta_out,
+                   const double *alpha_in, double *xraw_out, double *araw_out, long *nfallback)
+{
+    int rc = check_state(c, u);
+    if (rc) return rc;
+    if (c->p.mode == OR_EXTERNAL && !alpha_in) return OR_EINVAL;
+    work_t W;
+    if (alloc_work(c, &W)) { free_work(&W); return OR_EINVAL; }
+    double *xraw = malloc(sizeof(double) * (size_t)c->nel * c->A);
+    double *araw = malloc(sizeof(double) * (size_t)c->nel * c->A);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int e = 0; e < c->nel; e++) pass1_element(c, u, e, &W, alpha_in, xraw, araw);
+    long nfb = 0;
+    for (int a = 0; a < c->dim; a++) {
+        long trans = c->dof / c->G[a];
+        long nfaces = (long)c->G[a] + 1;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nfb)
+        for (long idx = 0; idx < nfaces * trans; idx++) {
+            long f = idx / trans, t = idx % trans;
+            long gt[3];
+            /* transverse coordinates from t */
+            if (a == 0) { gt[0] = 0; gt[1] = t % c->G[1]; gt[2] = t / c->G[1]; }
+            else if (a == 1) { gt[0] = t % c->G[0]; gt[1] = 0; gt[2] = t / c->G[0]; }
+            else { gt[0] = t % c->G[0]; gt[1] = t / c->G[0]; gt[2] = 0; }
+            double F[MAXV];
+            long cnt = 0;
+            if (c->m.bc[a] == OR_PERIODIC && f == c->G[a]) continue; /* copied from face 0 below */
+            face_flux(c, u, &W, a, f, gt, F, &cnt);
+            nfb += cnt;
+            for (int v = 0; v < c->nv; v++) W.flux[W.flux_off[a] + flux_index(c, a, f, t, v)] = F[v];
+        }
+        if (c->m.bc[a] == OR_PERIODIC)
+            for (long t = 0; t < trans; t++)
+                for (int v = 0; v < c->nv; v++)
+                    W.flux[W.flux_off[a] + flux_index(c, a, c->G[a], t, v)] = W.flux[W.flux_off[a] + flux_index(c, a, 0, t, v)];
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int e = 0; e < c->nel; e++) pass3_element(c, u, e, &W, dudt);
+    size_t na = sizeof(double) * (size_t)c->nel * c->A;
+    if (alpha_out) memcpy(alpha_out, W.alpha, na);
+    if (beta_out) memcpy(beta_out, W.beta, na);
+    if (xraw_out) memcpy(xraw_out, xraw, na);
+    if (araw_out) memcpy(araw_out, araw, na);
+    if (nfallback) *nfallback = nfb;
+    free(xraw);
+    free(araw);
+    free_work(&W);
+    return OR_OK;
+}
+
+int or_rhs(const or_mesh *m, const or_params *p, const double *u, double *dudt,
+           double *alpha, double *beta, const double *alpha_in,
+           double *xraw, double *araw, long *nfallback)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return OR_EINVAL;
+    int rc = make_ctx(m, p, c);
+    if (rc == OR_OK) rc = rhs_ctx(c, u, dudt, alpha, beta, alpha_in, xraw, araw, nfallback);
+    free(c);
+    return rc;
+}
+
+/* CFL step (eq. cfl-condition) with the maximum eigenvalue estimate of the
+   mean values (eq. euler-max-eigenvalue); dx = min over axes. */
+static double max_dt_ctx(const ctx_t *c, const double *u)
+{
+    double lam = 0.0;
+    int bad = 0;
+#pragma omp parallel for reduction(max : lam) reduction(| : bad)
+    for (long gi = 0; gi < c->dof; gi++) {
+        double pt[MAXV];
+        for (int v = 0; v < c->nv; v++) pt[v] = u[v * c->dof + gi];
+        if (!permissible(c->dim, c->m.gamma, pt)) { bad |= 1; continue; }
+        double cs = sqrt(c->m.gamma * pressure(c->dim, c->m.gamma, pt) / pt[0]);
+        for (int a = 0; a < c->dim; a++) {
+            double l = fabs(pt[1 + a] / pt[0]) + cs;
+            if (l > lam) lam = l;
+        }
+    }
+    if (bad || !(lam > 0.0)) return -1.0;
+    double dxm = c->dx[0];
+    for (int a = 1; a < c->dim; a++) dxm = fmin(dxm, c->dx[a]);
+    double denom = (double)(1 << (c->dim - 1)) * (2.0 * c->K - 1.0) * lam;
+    return c->p.cfl * dxm / denom;
+}
+
+double or_max_dt(const or_mesh *m, const or_params *p, const double *u)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return -1.0;
+    double dt = -1.0;
+    if (make_ctx(m, p, c) == OR_OK) dt = max_dt_ctx(c, u);
+    free(c);
+    return dt;
+}
+
+/* Three-stage SSP Runge-Kutta (Shu-Osher form):
+   u1 = u + dt L(u);  u2 = 3/4 u + 1/4 (u1 + dt L(u1));  u' = 1/3 u + 2/3 (u2 + dt L(u2)). */
+int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps, double dt_fixed, double *dt_log)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return OR_EINVAL;
+    int rc = make_ctx(m, p, c);
+    if (rc) { free(c); return rc; }
+    if (c->p.mode == OR_EXTERNAL) { free(c); return OR_EINVAL; }
+    size_t n = (size_t)c->nv * c->dof;
+    double *L = malloc(sizeof(double) * n), *u1 = malloc(sizeof(double) * n), *u2 = malloc(sizeof(double) * n);
+    for (int st = 0; st < nsteps && rc == OR_OK; st++) {
+        double dt = dt_fixed > 0.0 ? dt_fixed : max_dt_ctx(c, u);
+        if (!(dt > 0.0)) { rc = OR_ESTATE; break; }
+        if (dt_log) dt_log[st] = dt;
+        rc = rhs_ctx(c, u, L, NULL, NULL, NULL, NULL, NULL, NULL);
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u1[i] = u[i] + dt * L[i];
+        rc = rhs_ctx(c, u1, L, NULL, NULL, NULL, NULL, NULL, NULL);
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * L[i]);
+        rc = rhs_ctx(c, u2, L, NULL, NULL, NULL, NULL, NULL, NULL);
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u[i] = (1.0 / 3.0) * u[i] + (2.0 / 3.0) * (u2[i] + dt * L[i]);
+    }
+    free(L); free(u1); free(u2); free(c);
+    return rc;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
