@@ -1,0 +1,147 @@
+/*
+ * libsedg - sub-element adaptive blended DG/FV right-hand side on MI355X (gfx950).
+ *
+ * Method: Markert, Gassner & Walch, "A Sub-Element Adaptive Shock Capturing
+ * Approach for Discontinuous Galerkin Methods", arXiv:2011.03338.
+ *
+ * Each Cartesian element carries K^dim subcell mean values of the compressible
+ * Euler state (Sec. 2, eq. subcell-grid; App. 3D extension).  The library
+ * evaluates the semi-discrete right-hand side of the multi-level blending
+ * scheme (Sec. 2.6, eq. multilevel-blending-scheme and
+ * multilevel-blending-discretizations; App. eq. dgfv-scheme-3d): per element it
+ * reconstructs the hierarchy O(K) .. O(2) from the mean values (eq. reco-*),
+ * squeezes non-permissible reconstructions (eq. positivity-limiter), computes
+ * the sub-element blending factors (Sec. 2.7, eq. calc-blending-factor) with the
+ * level pruning of the multi-level algorithm (App. sketch of the algorithm),
+ * evaluates unique common interface fluxes (Sec. 2.6; App. eq.
+ * 3D-blend-interface-fluxes) and blends the level right-hand sides with the
+ * weights of eq. blending-weights.  Time stepping is the three-stage SSP
+ * Runge-Kutta scheme with the CFL step of eq. cfl-condition.
+ *
+ * Conventions
+ *   K      mean values per direction per element (the paper's N): 4 or 8.
+ *   dim    2 or 3; nvar = dim + 2, conserved (rho, rho*v, E).
+ *   State  device array of nvar * DOF doubles, structure of arrays on the
+ *          global subcell grid: u[var][gz][gy][gx], gx fastest, extents
+ *          G_a = nelem_a * K.  Elements are numbered ex fastest, then ey, ez.
+ *   Alpha  per element A = sum over DG levels n = top, top/2, ..., 2 of (K/n)^dim
+ *          values, level top first; inside a level the sub-element index is
+ *          sx + (K/n) * (sy + (K/n) * sz).  The same layout holds for beta.
+ *
+ * Ownership and errors
+ *   The caller owns every device pointer passed in (contiguous FP64 on the
+ *   current device); the library only borrows them for the call and enqueues
+ *   all work asynchronously on the given stream (a hipStream_t passed as
+ *   void*, NULL = default stream).  A context owns its operator tables,
+ *   interface buffers, blending-factor arrays and stage buffers.  Use one
+ *   context per stream; calls on one context are not thread-safe.
+ *   Functions return SEDG_OK (0) or a negative code; no exception or abort
+ *   crosses the interface.  Arguments are validated before anything is
+ *   enqueued (SEDG_EINVAL).  A mean value that is not permissible (rho <= 0,
+ *   p <= 0 or not finite) is detected on the device and reported by
+ *   sedg_check (SEDG_ESTATE); the kernels never index memory with data values,
+ *   so such a state yields garbage, never a fault.
+ */
+#ifndef SEDG_H
+#define SEDG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SEDG_OK = 0,
+    SEDG_EINVAL = -1,      /* bad argument */
+    SEDG_EHIP = -2,        /* HIP runtime error */
+    SEDG_ENOMEM = -3,      /* device allocation failed */
+    SEDG_ESTATE = -4,      /* non-permissible or non-finite mean value detected */
+    SEDG_EUNSUPPORTED = -5 /* configuration not compiled (dim, K) */
+};
+
+enum { SEDG_PERIODIC = 0, SEDG_OUTFLOW = 1 };
+enum { SEDG_GAUSS = 0, SEDG_LGL = 1 };
+enum { SEDG_ADAPTIVE = 0, SEDG_FORCE_DG = 1, SEDG_FORCE_FV = 2, SEDG_EXTERNAL = 3 };
+
+typedef struct sedg_mesh {
+    int dim;            /* 2 or 3 */
+    int K;              /* 4 or 8 */
+    int nelem[3];       /* elements per axis (1 on unused axes) */
+    double lo[3], hi[3];/* domain box */
+    int bc[3];          /* SEDG_PERIODIC or SEDG_OUTFLOW (zero-gradient) per axis */
+    double gamma;       /* ratio of specific heats (eq. equation-of-state) */
+    int family;         /* collocation nodes: SEDG_GAUSS (the paper's, Sec. 2.2) or SEDG_LGL */
+} sedg_mesh;
+
+typedef struct sedg_params {
+    double tau_A, tau_S;     /* indicator amplification / sensitivity (Sec. 2.7): 100, 0.05 */
+    double alpha_H, alpha_L; /* level snapping thresholds (Sec. 2.8): 0.99, 0.01 */
+    double beta_L;           /* squeeze rejection threshold (Sec. 2.8): 0.95 */
+    double cfl;              /* CFL number of eq. cfl-condition */
+    int top_level;           /* highest DG order used (DGFVn, Sec. 3.5); 0 = K */
+    unsigned level_mask;     /* bit log2(n) enables DG level n; 0 = all levels */
+    int mode;                /* SEDG_ADAPTIVE, SEDG_FORCE_DG (alpha_top = 1),
+                                SEDG_FORCE_FV (all alpha = 0), SEDG_EXTERNAL (alpha given) */
+} sedg_params;
+
+typedef struct sedg_ctx sedg_ctx;
+
+/* Create a context for one mesh and parameter set on the current HIP device.
+ * Builds the operator tables of Sec. 2.2-2.4 and 2.6 (nodes, weights, D, Dhat,
+ * Bhat, P, R, interface interpolation) and allocates the context's device
+ * buffers.  *out receives the context.  Returns SEDG_EINVAL for a bad mesh,
+ * SEDG_EUNSUPPORTED for (dim, K) not compiled, SEDG_ENOMEM, SEDG_EHIP. */
+int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out);
+
+/* Release a context (synchronises the device first).  NULL is allowed. */
+int sedg_destroy(sedg_ctx *ctx);
+
+/* Doubles in one state array (nvar * DOF) and in one blending-factor array
+ * (A * number of elements); negative on a NULL context. */
+long sedg_state_len(const sedg_ctx *ctx);
+long sedg_alpha_len(const sedg_ctx *ctx);
+
+/* Replace the parameters of an existing context (same mesh). */
+int sedg_set_params(sedg_ctx *ctx, const sedg_params *params);
+
+/* One evaluation of the blended right-hand side d(u)/dt (eq.
+ * multilevel-blending-scheme blended by eq. blending-weights).
+ *   u         device, state (read only)
+ *   dudt      device, output state-shaped array (must not alias u)
+ *   alpha_out device, optional (NULL): blending factors used, A per element
+ *   beta_out  device, optional (NULL): squeezing parameters, A per element
+ *   alpha_in  device, required in SEDG_EXTERNAL mode (ignored otherwise)
+ *   stream    hipStream_t or NULL
+ * Asynchronous; state errors are reported by sedg_check. */
+int sedg_rhs(sedg_ctx *ctx, const double *u, double *dudt, double *alpha_out, double *beta_out,
+             const double *alpha_in, void *stream);
+
+/* CFL step of the state u (eq. cfl-condition with eq. euler-max-eigenvalue),
+ * written to the device scalar *dt_dev. */
+int sedg_max_dt(sedg_ctx *ctx, const double *u, double *dt_dev, void *stream);
+
+/* Advance u in place by nsteps steps of three-stage SSP-RK (Shu-Osher form).
+ *   dt_fixed > 0: that step size; otherwise the CFL step of each step's
+ *   initial state, computed on the device.
+ *   dt_log_dev: device, optional, receives the nsteps step sizes.
+ * The step sequence is captured once into a HIP graph per (u, dt_log, mode)
+ * and replayed.  EXTERNAL mode is rejected (SEDG_EINVAL). */
+int sedg_rk_step(sedg_ctx *ctx, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream);
+
+/* Synchronise the context's last stream and report device-side state errors:
+ * SEDG_ESTATE with *bad_elem = index of an element holding a non-permissible
+ * or non-finite mean value, else SEDG_OK and *bad_elem = -1.  Clears the flag. */
+int sedg_check(sedg_ctx *ctx, long *bad_elem);
+
+/* Host-only: the library's own operator tables of level n (2, 4, 8) for node
+ * family fam, in the order xi[n], w[n], Dcal[n*n], D[n*n], bm[n], bp[n],
+ * P[n*n], R[n*n], Dhat[n*n], Bhat_left[n], Bhat_right[n], Iplus[n*n],
+ * Iminus[n*n] (row-major).  Returns the count written or SEDG_EINVAL. */
+int sedg_tables(int n, int family, double *out, int cap);
+
+/* Text of a return code. */
+const char *sedg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

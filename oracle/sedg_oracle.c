@@ -644,7 +644,12 @@ static void analyse_element(const ctx_t *c, const double *u, int e, double *alph
     }
     for (int q = 0; q < c->A; q++) alpha[q] = 0.0;
     if (c->p.mode == OR_FORCE_FV) return;
-    if (c->p.mode == OR_FORCE_DG) { alpha[0] = 1.0; return; }
+    if (c->p.mode == OR_FORCE_DG) {
+        /* pure DG of the top level: alpha = 1 on every top-level sub-element (Sec. 2.5 remark) */
+        int cnt = c->nlev > 1 ? c->lev_off[1] : c->A;
+        for (int q = 0; q < cnt; q++) alpha[q] = 1.0;
+        return;
+    }
     int broke = 0;
     for (int li = 0; li < c->nlev && !broke; li++) {
         if (!level_enabled(c, li)) continue;

@@ -1,0 +1,27 @@
+// Internal declarations shared by the host table builder and the HIP library.
+#ifndef SEDG_INTERNAL_H
+#define SEDG_INTERNAL_H
+
+#define MAXN 8
+
+// Operator tables of one DG level n; matrices are row-major with row stride n.
+struct sedg_level_tab {
+    int n;
+    int pad;
+    double xi[MAXN], w[MAXN];
+    double Dcal[MAXN * MAXN];   // l_j'(xi_i)
+    double D[MAXN * MAXN];      // M^-1 Dcal^T M
+    double bm[MAXN], bp[MAXN];  // l_j(-1/2), l_j(+1/2)
+    double P[MAXN * MAXN];      // projection nodal -> subcell means
+    double R[MAXN * MAXN];      // reconstruction subcell means -> nodal
+    double Dhat[MAXN * MAXN];   // P D
+    double Bhl[MAXN], Bhr[MAXN];// nonzero columns of P B^(0)
+    double Ip[MAXN * MAXN];     // l_j(mu_{i+1/2})
+    double Im[MAXN * MAXN];     // l_j(mu_{i-1/2})
+    double Ep[MAXN * MAXN];     // Ip R
+    double Em[MAXN * MAXN];     // Im R
+};
+
+int sedg_build_level(int n, int family, sedg_level_tab *T);
+
+#endif

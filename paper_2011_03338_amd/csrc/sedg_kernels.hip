@@ -1,0 +1,1327 @@
+// HIP kernels (gfx950) and C-ABI host code of libsedg: the sub-element adaptive
+// blended DG/FV right-hand side of arXiv:2011.03338 and its SSP-RK3 stages.
+//
+// Work decomposition (per RK stage, two launches plus a tiny reduction):
+//   analyse  : one thread per subcell, EPB elements per workgroup, all element
+//              data staged in LDS.  Reconstructs every level (eq. reco-*),
+//              computes the squeezing parameters (eq. calc-squeezing-parameter),
+//              the blending factors with level pruning (eq. calc-blending-factor,
+//              App. multi-level algorithm) and the blended interface states on
+//              the element's own faces (App. eq. 3D-prolongation, multi-level
+//              cascade of Sec. 2.6).  Writes alpha, beta and the face buffer
+//              (the only data another element reads), plus per-block maxima of
+//              the CFL eigenvalue estimate (eq. euler-max-eigenvalue).
+//   residual : same decomposition.  Per axis: blended interface states of every
+//              subcell, unique common fluxes at every subcell face (FV
+//              candidate plus per-level DG candidates projected along the face,
+//              App. eq. 3D-blend-interface-fluxes), then the FV and level DG
+//              right-hand sides (eq. multilevel-blending-scheme) blended with
+//              the weights of eq. blending-weights; the SSP-RK3 combination is
+//              fused into the store.
+// Element-face fluxes are computed by both adjacent elements from identical
+// inputs (the face buffer on both sides, the same code), so they agree bit for
+// bit and the scheme stays conservative without atomics.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "../../include/sedg.h"
+#include "sedg_internal.h"
+
+#define MAXLEV 3
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+
+struct KArgs {
+    const double *u;        // stage state (read)
+    const double *u0;       // u^n for RK stages 2, 3
+    double *out;            // dudt or the next stage state
+    double *alpha;          // nel * A
+    double *beta;           // nel * A
+    const double *alpha_in; // EXTERNAL mode
+    double *fbuf;           // face buffer
+    const sedg_level_tab *tabs;  // per level index
+    double *lam_part;       // per-block CFL eigenvalue maxima (nullable)
+    const double *dt;       // device scalar step (RK stages)
+    int *err;               // smallest bad element index (INT_MAX = none)
+    long long dof;
+    int nel;
+    int ne[3];
+    int G[3];
+    int bc[3];
+    double dx[3];
+    int nlev;
+    int lev_n[MAXLEV];
+    int lev_off[MAXLEV];
+    int A;
+    int mode;
+    unsigned level_mask;
+    int stage;              // 0: write dudt; 1, 2, 3: SSP-RK3 stage
+    double gamma, tau_A, tau_S, alpha_H, alpha_L, beta_L;
+};
+
+// ---------------------------------------------------------------------------
+// physics (Sec. 3.1) - same formulas as the HLL-Einfeldt flux of Sec. 3
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+__device__ __forceinline__ double pressure(const double *u, double g)
+{
+    if (!(u[0] > 0.0)) return -INFINITY;
+    double m2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) m2 += u[1 + a] * u[1 + a];
+    return (g - 1.0) * (u[DIM + 1] - 0.5 * m2 / u[0]);
+}
+
+template <int DIM>
+__device__ __forceinline__ bool permissible(const double *u, double g)
+{
+    if (!(u[0] > 0.0)) return false;
+    return pressure<DIM>(u, g) > 0.0;
+}
+
+template <int DIM>
+__device__ __forceinline__ void euler_flux(const double *u, int a, double g, double *f)
+{
+    double p = pressure<DIM>(u, g);
+    double va = u[1 + a] / u[0];
+    f[0] = u[1 + a];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) f[1 + b] = u[1 + b] * va + (a == b ? p : 0.0);
+    f[DIM + 1] = va * (u[DIM + 1] + p);
+}
+
+template <int DIM>
+__device__ void hlle(const double *uL, const double *uR, int a, double g, double *fs)
+{
+    constexpr int NV = DIM + 2;
+    double fL[NV], fR[NV];
+    euler_flux<DIM>(uL, a, g, fL);
+    euler_flux<DIM>(uR, a, g, fR);
+    double pL = pressure<DIM>(uL, g), pR = pressure<DIM>(uR, g);
+    double vL = uL[1 + a] / uL[0], vR = uR[1 + a] / uR[0];
+    double cL = sqrt(g * pL / uL[0]), cR = sqrt(g * pR / uR[0]);
+    double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
+    double HL = (uL[DIM + 1] + pL) / uL[0], HR = (uR[DIM + 1] + pR) / uR[0];
+    double vt2 = 0.0, vtn = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        double vb = (sqL * (uL[1 + b] / uL[0]) + sqR * (uR[1 + b] / uR[0])) / (sqL + sqR);
+        vt2 += vb * vb;
+        if (b == a) vtn = vb;
+    }
+    double Ht = (sqL * HL + sqR * HR) / (sqL + sqR);
+    double ct = sqrt((g - 1.0) * (Ht - 0.5 * vt2));
+    double SL = fmin(vL - cL, vtn - ct);
+    double SR = fmax(vR + cR, vtn + ct);
+    double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
+    double inv = 1.0 / (SRp - SLm);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fs[v] = (SRp * fL[v] - SLm * fR[v] + SLm * SRp * (uR[v] - uL[v])) * inv;
+}
+
+// ---------------------------------------------------------------------------
+// element geometry helpers
+// ---------------------------------------------------------------------------
+
+template <int DIM, int K>
+struct Geo {
+    static constexpr int NV = DIM + 2;
+    static constexpr int LOGK = (K == 2) ? 1 : (K == 4) ? 2 : 3;
+    static constexpr int KD = (DIM == 2) ? K * K : K * K * K;
+    static constexpr int KF = KD / K;
+    __device__ static int coord(int c, int a) { return (c >> (a * LOGK)) & (K - 1); }
+    __device__ static int stride(int a) { return 1 << (a * LOGK); }
+    // index of c inside the face plane orthogonal to a (remaining axes, increasing order)
+    __device__ static int trans(int c, int a)
+    {
+        if (DIM == 2) return coord(c, a == 0 ? 1 : 0);
+        if (a == 0) return coord(c, 1) + K * coord(c, 2);
+        if (a == 1) return coord(c, 0) + K * coord(c, 2);
+        return coord(c, 0) + K * coord(c, 1);
+    }
+    // cell of face plane index t for axis a at position pos along a
+    __device__ static int from_trans(int t, int a, int pos)
+    {
+        if (DIM == 2) return a == 0 ? (pos + K * t) : (t + K * pos);
+        int t0 = t & (K - 1), t1 = t >> LOGK;
+        if (a == 0) return pos + K * (t0 + K * t1);
+        if (a == 1) return t0 + K * (pos + K * t1);
+        return t0 + K * (t1 + K * pos);
+    }
+    __device__ static int subelem(int c, int n)
+    {
+        int ns = K / n;
+        int s = coord(c, 0) / n + ns * (coord(c, 1) / n);
+        if (DIM == 3) s += ns * ns * (coord(c, 2) / n);
+        return s;
+    }
+};
+
+__device__ __forceinline__ int ilog2i(int n) { return n == 8 ? 3 : n == 4 ? 2 : n == 2 ? 1 : 0; }
+
+// xor-butterfly reduction over the cells of one level-n sub-element (ln = log2 n;
+// ln = LOGK gives the whole element).  Bits inside a wavefront use cross-lane
+// shuffles, higher bits exchange through LDS; every lane ends with the same value.
+template <int DIM, int K, typename T, typename Op>
+__device__ T subreduce(T v, int ln, T *s_x, Op op)
+{
+    constexpr int LOGK = Geo<DIM, K>::LOGK;
+    const int tid = threadIdx.x;
+    for (int a = 0; a < DIM; ++a)
+        for (int b = 0; b < ln; ++b) {
+            int bit = a * LOGK + b;
+            int mask = 1 << bit;
+            if (bit < 6) {
+                T o = __shfl_xor(v, mask, 64);
+                v = op(v, o);
+            } else {
+                s_x[tid] = v;
+                __syncthreads();
+                T o = s_x[tid ^ mask];
+                __syncthreads();
+                v = op(v, o);
+            }
+        }
+    return v;
+}
+
+struct OpSum { __device__ double operator()(double a, double b) const { return a + b; } };
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpAnd { __device__ int operator()(int a, int b) const { return a & b; } };
+struct OpOr { __device__ int operator()(int a, int b) const { return a | b; } };
+
+// blocked n-mode product: out = sum_m M[lo][m] * src[base + m*stride] along axis a
+// for level n (lo = position of c inside its level-n sub-element along a)
+template <int DIM, int K>
+__device__ __forceinline__ double bapply(const double *src, int c, int a, int n, const double *M)
+{
+    typedef Geo<DIM, K> G;
+    int st = G::stride(a);
+    int lo = G::coord(c, a) & (n - 1);
+    int base = c - lo * st;
+    const double *row = M + lo * n;
+    double acc = 0.0;
+    for (int m = 0; m < n; ++m) acc += row[m] * src[base + m * st];
+    return acc;
+}
+
+// weights theta of one cell from an element's alpha vector (eq. blending-weights)
+__device__ __forceinline__ void theta_from_alpha(const double *al, const KArgs &P, const int *sidx, double *th)
+{
+    double prod = 1.0;
+    for (int li = 0; li < P.nlev; ++li) {
+        double a = al[P.lev_off[li] + sidx[li]];
+        th[1 + li] = a * prod;
+        prod *= (1.0 - a);
+    }
+    th[0] = prod;
+}
+
+template <int DIM, int K>
+__device__ __forceinline__ void subidx_all(int c, const KArgs &P, int *sidx)
+{
+    for (int li = 0; li < P.nlev; ++li) sidx[li] = Geo<DIM, K>::subelem(c, P.lev_n[li]);
+}
+
+template <int DIM, int K>
+__device__ __forceinline__ long long gindex(const KArgs &P, const int *e3, int c)
+{
+    typedef Geo<DIM, K> G;
+    long long gx = (long long)e3[0] * K + G::coord(c, 0);
+    long long gy = (long long)e3[1] * K + G::coord(c, 1);
+    long long gz = DIM == 3 ? (long long)e3[2] * K + G::coord(c, 2) : 0;
+    return gx + (long long)P.G[0] * (gy + (long long)P.G[1] * gz);
+}
+
+__device__ __forceinline__ void elem3(const KArgs &P, int e, int *e3)
+{
+    e3[0] = e % P.ne[0];
+    int r = e / P.ne[0];
+    e3[1] = r % P.ne[1];
+    e3[2] = r / P.ne[1];
+}
+
+// neighbour element across face (axis a, side 0 = low, 1 = high); -1 at an outflow boundary
+template <int DIM>
+__device__ __forceinline__ int neighbour(const KArgs &P, const int *e3, int a, int side)
+{
+    int f[3] = {e3[0], e3[1], e3[2]};
+    int d = side ? 1 : -1;
+    f[a] += d;
+    if (f[a] < 0 || f[a] >= P.ne[a]) {
+        if (P.bc[a] != SEDG_PERIODIC) return -1;
+        f[a] = (f[a] + P.ne[a]) % P.ne[a];
+    }
+    return f[0] + P.ne[0] * (f[1] + P.ne[1] * f[2]);
+}
+
+// face buffer slot: [elem][axis][side][var][face-plane index]
+template <int DIM, int K>
+__device__ __forceinline__ long long fb_index(int e, int a, int side, int v, int t)
+{
+    constexpr int NV = DIM + 2, KF = Geo<DIM, K>::KF;
+    return ((((long long)e * DIM + a) * 2 + side) * NV + v) * KF + t;
+}
+
+// ---------------------------------------------------------------------------
+// analyse kernel
+// ---------------------------------------------------------------------------
+
+template <int DIM, int K, int EPB>
+struct AnalyseSmem {
+    typedef Geo<DIM, K> G;
+    double u[EPB][G::NV][G::KD];
+    double r[EPB][G::LOGK][G::NV][G::KD];   // unlimited reconstruction per level index
+    double t[EPB][G::NV][G::KD];            // temporary
+    double w[EPB][G::NV][G::KD];            // primitive variables
+    double x[EPB * G::KD];                  // reduction exchange
+    int ix[EPB * G::KD];
+    double al[EPB][64 + 8 + 1];             // alpha of the element (A <= 73)
+    double be[EPB][64 + 8 + 1];
+    double lam[EPB * G::KD / 64 + 1];
+};
+
+template <int DIM, int K, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
+analyse_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    constexpr int NV = G::NV, KD = G::KD;
+    __shared__ AnalyseSmem<DIM, K, EPB> S;
+    const int tid = threadIdx.x;
+    const int le = tid / KD, c = tid % KD;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = e < P.nel;
+    const int ee = act ? e : P.nel - 1;
+    int e3[3];
+    elem3(P, ee, e3);
+    const long long g = gindex<DIM, K>(P, e3, c);
+    const double gam = P.gamma;
+
+    double ub[NV];
+    for (int v = 0; v < NV; ++v) {
+        ub[v] = P.u[v * P.dof + g];
+        S.u[le][v][c] = ub[v];
+    }
+    // state check and CFL eigenvalue estimate of the mean values
+    {
+        bool fin = true;
+        for (int v = 0; v < NV; ++v) fin = fin && isfinite(ub[v]);
+        bool ok = fin && permissible<DIM>(ub, gam);
+        if (act && !ok) atomicMin(P.err, e);
+        if (P.lam_part) {
+            double lam = 0.0;
+            if (act && ok) {
+                double cs = sqrt(gam * pressure<DIM>(ub, gam) / ub[0]);
+                for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
+            }
+            for (int off = 32; off >= 1; off >>= 1) lam = fmax(lam, __shfl_xor(lam, off, 64));
+            if ((tid & 63) == 0) S.lam[tid >> 6] = lam;
+            __syncthreads();
+            if (tid == 0) {
+                double m = 0.0;
+                for (int wv = 0; wv < (EPB * KD + 63) / 64; ++wv) m = fmax(m, S.lam[wv]);
+                P.lam_part[blockIdx.x] = m;
+            }
+        }
+    }
+    __syncthreads();
+
+    // unlimited reconstructions of every level: u x_1 R x_2 R (x_3 R)
+    for (int li = 0; li < P.nlev; ++li) {
+        const sedg_level_tab &T = P.tabs[li];
+        int n = P.lev_n[li];
+        if (DIM == 2) {
+            for (int v = 0; v < NV; ++v) S.t[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.r[le][li][v][c] = bapply<DIM, K>(S.t[le][v], c, 1, n, T.R);
+        } else {
+            for (int v = 0; v < NV; ++v) S.r[le][li][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.t[le][v][c] = bapply<DIM, K>(S.r[le][li][v], c, 1, n, T.R);
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.r[le][li][v][c] = bapply<DIM, K>(S.t[le][v], c, 2, n, T.R);
+        }
+        __syncthreads();
+    }
+
+    // squeezing parameter per level and sub-element; sub-element means
+    double mean[MAXLEV][NV];
+    double beta[MAXLEV];
+    for (int li = 0; li < P.nlev; ++li) {
+        const sedg_level_tab &T = P.tabs[li];
+        int n = P.lev_n[li], ln = ilog2i(n);
+        double nd = (DIM == 2) ? n * n : n * n * n;
+        for (int v = 0; v < NV; ++v) mean[li][v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+        double pt[NV];
+        for (int v = 0; v < NV; ++v) pt[v] = S.r[le][li][v][c];
+        double pp = pressure<DIM>(pt, gam);
+        int ok = (pt[0] > 0.0 && pp > 0.0) ? 1 : 0;
+        double rmin = pt[0], pmin = pp;
+        for (int a = 0; a < DIM; ++a) {
+            int lo = G::coord(c, a) & (n - 1);
+            for (int sd = 0; sd < 2; ++sd) {
+                if (lo != (sd ? n - 1 : 0)) continue;
+                const double *bv = sd ? T.bp : T.bm;
+                int st = G::stride(a), base = c - lo * st;
+                for (int v = 0; v < NV; ++v) {
+                    double s = 0.0;
+                    for (int m = 0; m < n; ++m) s += bv[m] * S.r[le][li][v][base + m * st];
+                    pt[v] = s;
+                }
+                double q = pressure<DIM>(pt, gam);
+                if (!(pt[0] > 0.0 && q > 0.0)) ok = 0;
+                rmin = fmin(rmin, pt[0]);
+                pmin = fmin(pmin, q);
+            }
+        }
+        ok = subreduce<DIM, K>(ok, ln, S.ix, OpAnd());
+        rmin = subreduce<DIM, K>(rmin, ln, S.x, OpMin());
+        pmin = subreduce<DIM, K>(pmin, ln, S.x, OpMin());
+        double b = 1.0;
+        if (!ok) {
+            double rmean = mean[li][0], pmean = pressure<DIM>(mean[li], gam);
+            double eps = fmin(1e-20, fmin(rmean, pmean));
+            double br = (rmean - rmin > 0.0) ? (rmean - eps) / (rmean - rmin) : 1.0;
+            double bq = (pmean - pmin > 0.0) ? (pmean - eps) / (pmean - pmin) : 1.0;
+            b = fmin(fmin(br, bq), 1.0);
+        }
+        beta[li] = b;
+        int s = G::subelem(c, n);
+        int nsub = 1;
+        for (int a = 0; a < DIM; ++a) nsub *= K / n;
+        bool leader = (c == 0) || (G::coord(c, 0) % n == 0 && G::coord(c, 1) % n == 0 &&
+                                   (DIM == 2 || G::coord(c, 2) % n == 0));
+        if (leader) S.be[le][P.lev_off[li] + s] = b;
+        (void)nsub;
+    }
+
+    // blending factors
+    double al[MAXLEV];
+    for (int li = 0; li < P.nlev; ++li) al[li] = 0.0;
+    if (P.mode == SEDG_EXTERNAL) {
+        for (int li = 0; li < P.nlev; ++li) al[li] = P.alpha_in[(long long)ee * P.A + P.lev_off[li] + G::subelem(c, P.lev_n[li])];
+    } else if (P.mode == SEDG_FORCE_DG) {
+        al[0] = 1.0;
+    } else if (P.mode == SEDG_ADAPTIVE) {
+        int broke = 0;
+        for (int li = 0; li < P.nlev; ++li) {
+            if (!__syncthreads_or(!broke)) break;
+            int n = P.lev_n[li], ln = ilog2i(n);
+            bool enabled = (P.level_mask == 0) || ((P.level_mask >> ln) & 1u);
+            if (!enabled) continue;   // uniform across the block
+            double a = 0.0;
+            if (n == 2) {
+                a = (beta[li] < P.beta_L) ? 0.0 : beta[li];
+            } else {
+                const sedg_level_tab &T = P.tabs[li];
+                const sedg_level_tab &H = P.tabs[li + 1];
+                int h = n / 2;
+                // primitive variables at the level-n nodes
+                double pt[NV], wv[NV];
+                for (int v = 0; v < NV; ++v) pt[v] = S.r[le][li][v][c];
+                int bad = (pt[0] > 0.0) ? 0 : 1;
+                wv[0] = pt[0];
+                for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
+                wv[DIM + 1] = pressure<DIM>(pt, gam);
+                for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
+                __syncthreads();
+                double sn[NV], sh[NV];
+                {
+                    double wq = 1.0;
+                    for (int d = 0; d < DIM; ++d) wq *= T.w[G::coord(c, d) & (n - 1)];
+                    for (int v = 0; v < NV; ++v) {
+                        double s = 0.0;
+                        for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, n, T.Dcal));
+                        sn[v] = wq * s;
+                    }
+                }
+                __syncthreads();
+                // primitive variables at the level-n/2 nodes (the 2^dim children)
+                for (int v = 0; v < NV; ++v) pt[v] = S.r[le][li + 1][v][c];
+                bad |= (pt[0] > 0.0) ? 0 : 1;
+                wv[0] = pt[0];
+                for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
+                wv[DIM + 1] = pressure<DIM>(pt, gam);
+                for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
+                __syncthreads();
+                {
+                    double wq = (DIM == 2) ? 0.5 : 0.25;   // child measure in parent coordinates
+                    for (int d = 0; d < DIM; ++d) wq *= H.w[G::coord(c, d) & (h - 1)];
+                    for (int v = 0; v < NV; ++v) {
+                        double s = 0.0;
+                        for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, h, H.Dcal));
+                        sh[v] = wq * s;
+                    }
+                }
+                __syncthreads();
+                for (int v = 0; v < NV; ++v) {
+                    sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
+                    sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
+                }
+                bad = subreduce<DIM, K>(bad, ln, S.ix, OpOr());
+                double amin = 1.0;
+                int nonfin = 0;
+                for (int v = 0; v < NV; ++v) {
+                    double den = fmax(fmax(sh[v], sn[v]), 1.0);
+                    double r = fabs(sn[v] - sh[v]) / den;
+                    double x = P.tau_A * (r - P.tau_S);
+                    if (!isfinite(x)) nonfin = 1;
+                    double cut = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+                    amin = fmin(amin, 1.0 - cut);
+                }
+                a = (bad || nonfin) ? 0.0 : amin;
+                if (beta[li] < P.beta_L) a = 0.0;
+            }
+            if (broke) a = 0.0;
+            // level decision over the whole element
+            int hi = subreduce<DIM, K>((a > P.alpha_H) ? 1 : 0, G::LOGK, S.ix, OpAnd());
+            int lo = subreduce<DIM, K>((a < P.alpha_L) ? 1 : 0, G::LOGK, S.ix, OpAnd());
+            if (!broke) {
+                if (hi) { a = 1.0; broke = 1; }
+                else if (lo) a = 0.0;
+                al[li] = a;
+            }
+        }
+    }
+    __syncthreads();
+    // publish alpha and beta; weights of this cell
+    {
+        bool leader0 = true;
+        for (int li = 0; li < P.nlev; ++li) {
+            int n = P.lev_n[li];
+            bool leader = (G::coord(c, 0) % n == 0) && (G::coord(c, 1) % n == 0) &&
+                          (DIM == 2 || G::coord(c, 2) % n == 0);
+            int s = G::subelem(c, n);
+            if (leader) {
+                S.al[le][P.lev_off[li] + s] = al[li];
+                if (act) {
+                    P.alpha[(long long)e * P.A + P.lev_off[li] + s] = al[li];
+                    P.beta[(long long)e * P.A + P.lev_off[li] + s] = beta[li];
+                }
+            }
+        }
+        (void)leader0;
+    }
+    double th[MAXLEV + 1];
+    {
+        int sidx[MAXLEV];
+        subidx_all<DIM, K>(c, P, sidx);
+        double prod = 1.0;
+        for (int li = 0; li < P.nlev; ++li) {
+            th[1 + li] = al[li] * prod;
+            prod *= (1.0 - al[li]);
+        }
+        th[0] = prod;
+        (void)sidx;
+    }
+    // blended interface states on the element faces: theta_FV * mean + sum_n theta_n *
+    // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation)
+    for (int a = 0; a < DIM; ++a) {
+        int pos = G::coord(c, a);
+        for (int sd = 0; sd < 2; ++sd) {
+            if (pos != (sd ? K - 1 : 0)) continue;
+            double st[NV];
+            for (int v = 0; v < NV; ++v) st[v] = th[0] * ub[v];
+            for (int li = 0; li < P.nlev; ++li) {
+                if (th[1 + li] == 0.0) continue;
+                const sedg_level_tab &T = P.tabs[li];
+                int n = P.lev_n[li];
+                const double *E = sd ? T.Ep : T.Em;
+                double b = beta[li];
+                for (int v = 0; v < NV; ++v) {
+                    double tr = bapply<DIM, K>(S.u[le][v], c, a, n, E);
+                    st[v] += th[1 + li] * ((1.0 - b) * mean[li][v] + b * tr);
+                }
+            }
+            if (act)
+                for (int v = 0; v < NV; ++v) P.fbuf[fb_index<DIM, K>(e, a, sd, v, G::trans(c, a))] = st[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// residual kernel
+// ---------------------------------------------------------------------------
+
+template <int DIM, int K, int EPB>
+struct ResidualSmem {
+    typedef Geo<DIM, K> G;
+    double u[EPB][G::NV][G::KD];
+    double F[EPB][G::NV][(K + 1) * G::KF];   // common fluxes along the current axis
+    double sp[EPB][G::NV][G::KD];            // side states (+) / recon ping
+    double sm[EPB][G::NV][G::KD];            // side states (-) / recon pong
+    double fn[EPB][G::NV][G::KD];            // nodal face fluxes / flux temp
+    double th[EPB][MAXLEV + 1][G::KD];       // weights of every cell
+    double x[EPB * G::KD];
+    int ix[EPB * G::KD];
+    double nal[EPB][2 * DIM][64 + 8 + 1];    // neighbour alpha
+};
+
+// theta of the cell across an element face, from the neighbour's alpha
+template <int DIM, int K>
+__device__ __forceinline__ void theta_cell_of(const double *al, const KArgs &P, int cell, double *th)
+{
+    int sidx[MAXLEV];
+    subidx_all<DIM, K>(cell, P, sidx);
+    theta_from_alpha(al, P, sidx, th);
+}
+
+template <int DIM, int K, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
+residual_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    constexpr int NV = G::NV, KD = G::KD, KF = G::KF;
+    __shared__ ResidualSmem<DIM, K, EPB> S;
+    const int tid = threadIdx.x;
+    const int le = tid / KD, c = tid % KD;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = e < P.nel;
+    const int ee = act ? e : P.nel - 1;
+    int e3[3];
+    elem3(P, ee, e3);
+    const long long g = gindex<DIM, K>(P, e3, c);
+    const double gam = P.gamma;
+
+    double ub[NV];
+    for (int v = 0; v < NV; ++v) {
+        ub[v] = P.u[v * P.dof + g];
+        S.u[le][v][c] = ub[v];
+    }
+    const double *al = P.alpha + (long long)ee * P.A;
+    const double *be = P.beta + (long long)ee * P.A;
+    int nb[3][2];
+    for (int a = 0; a < 3; ++a) nb[a][0] = nb[a][1] = -1;
+    for (int a = 0; a < DIM; ++a)
+        for (int sd = 0; sd < 2; ++sd) {
+            nb[a][sd] = neighbour<DIM>(P, e3, a, sd);
+            int src = nb[a][sd] >= 0 ? nb[a][sd] : ee;
+            for (int q = c; q < P.A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * P.A + q];
+        }
+    int sidx[MAXLEV];
+    subidx_all<DIM, K>(c, P, sidx);
+    double th[MAXLEV + 1];
+    theta_from_alpha(al, P, sidx, th);
+    for (int l = 0; l <= P.nlev; ++l) S.th[le][l][c] = th[l];
+    double beta[MAXLEV];
+    double mean[MAXLEV][NV];
+    for (int li = 0; li < P.nlev; ++li) {
+        beta[li] = be[P.lev_off[li] + sidx[li]];
+        int n = P.lev_n[li], ln = ilog2i(n);
+        double nd = (DIM == 2) ? n * n : n * n * n;
+        for (int v = 0; v < NV; ++v) mean[li][v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+    }
+    __syncthreads();
+
+    double rfv[NV];
+    double lr[MAXLEV][NV];
+    for (int v = 0; v < NV; ++v) rfv[v] = 0.0;
+    for (int li = 0; li < MAXLEV; ++li)
+        for (int v = 0; v < NV; ++v) lr[li][v] = 0.0;
+
+    for (int a = 0; a < DIM; ++a) {
+        const int st = G::stride(a);
+        const int pos = G::coord(c, a);
+        const int tr = G::trans(c, a);
+        // blended interface states of this cell on both sides along a
+        {
+            double sp[NV], sm[NV];
+            for (int v = 0; v < NV; ++v) { sp[v] = th[0] * ub[v]; sm[v] = th[0] * ub[v]; }
+            for (int li = 0; li < P.nlev; ++li) {
+                if (th[1 + li] == 0.0) continue;
+                const sedg_level_tab &T = P.tabs[li];
+                int n = P.lev_n[li];
+                double b = beta[li];
+                for (int v = 0; v < NV; ++v) {
+                    double tp = bapply<DIM, K>(S.u[le][v], c, a, n, T.Ep);
+                    double tm = bapply<DIM, K>(S.u[le][v], c, a, n, T.Em);
+                    sp[v] += th[1 + li] * ((1.0 - b) * mean[li][v] + b * tp);
+                    sm[v] += th[1 + li] * ((1.0 - b) * mean[li][v] + b * tm);
+                }
+            }
+            for (int v = 0; v < NV; ++v) { S.sp[le][v][c] = sp[v]; S.sm[le][v][c] = sm[v]; }
+        }
+        __syncthreads();
+
+        // common fluxes: round 0 = face at the low side of each cell, round 1 = high element face
+        for (int rnd = 0; rnd < 2; ++rnd) {
+            const int k = pos + rnd;
+            const bool has = (rnd == 0) || (pos == K - 1);
+            const bool lowface = (k == 0), highface = (k == K);
+            const int nbL = nb[a][0], nbR = nb[a][1];
+            // left / right states and weights at this face subcell
+            double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
+            // fallback means of the adjacent subcells
+            double mL[NV], mR[NV];
+            if (lowface) {
+                int cr = c;                                  // own cell (pos == 0)
+                int cl = G::from_trans(tr, a, K - 1);        // cell across in the low neighbour
+                for (int v = 0; v < NV; ++v) {
+                    uR[v] = P.fbuf[fb_index<DIM, K>(ee, a, 0, v, tr)];
+                    uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, a, 1, v, tr)] : uR[v];
+                    mR[v] = S.u[le][v][cr];
+                }
+                for (int l = 0; l <= P.nlev; ++l) thR[l] = S.th[le][l][cr];
+                if (nbL >= 0) {
+                    theta_cell_of<DIM, K>(S.nal[le][2 * a + 0], P, cl, thL);
+                    int n3[3];
+                    elem3(P, nbL, n3);
+                    long long gl = gindex<DIM, K>(P, n3, cl);
+                    for (int v = 0; v < NV; ++v) mL[v] = P.u[v * P.dof + gl];
+                } else {
+                    for (int l = 0; l <= P.nlev; ++l) thL[l] = thR[l];
+                    for (int v = 0; v < NV; ++v) mL[v] = mR[v];
+                }
+            } else if (highface) {
+                int cl = c;                                  // own cell (pos == K-1)
+                int cr = G::from_trans(tr, a, 0);
+                for (int v = 0; v < NV; ++v) {
+                    uL[v] = P.fbuf[fb_index<DIM, K>(ee, a, 1, v, tr)];
+                    uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, a, 0, v, tr)] : uL[v];
+                    mL[v] = S.u[le][v][cl];
+                }
+                for (int l = 0; l <= P.nlev; ++l) thL[l] = S.th[le][l][cl];
+                if (nbR >= 0) {
+                    theta_cell_of<DIM, K>(S.nal[le][2 * a + 1], P, cr, thR);
+                    int n3[3];
+                    elem3(P, nbR, n3);
+                    long long gr = gindex<DIM, K>(P, n3, cr);
+                    for (int v = 0; v < NV; ++v) mR[v] = P.u[v * P.dof + gr];
+                } else {
+                    for (int l = 0; l <= P.nlev; ++l) thR[l] = thL[l];
+                    for (int v = 0; v < NV; ++v) mR[v] = mL[v];
+                }
+            } else {
+                int cl = c - st, cr = c;
+                for (int v = 0; v < NV; ++v) {
+                    uL[v] = S.sp[le][v][cl];
+                    uR[v] = S.sm[le][v][cr];
+                    mL[v] = S.u[le][v][cl];
+                    mR[v] = S.u[le][v][cr];
+                }
+                for (int l = 0; l <= P.nlev; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
+            }
+            // DG candidates level by level (uniform loop: the segment exchange needs barriers)
+            double thFV = 1.0;
+            double cand[MAXLEV][NV];
+            double wdg[MAXLEV];
+            for (int li = 0; li < P.nlev; ++li) {
+                const sedg_level_tab &T = P.tabs[li];
+                int n = P.lev_n[li], ln = ilog2i(n);
+                double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
+                bool need = has && (k % n == 0) && (tb != 0.0);
+                wdg[li] = 0.0;
+                // face segment of this level: face-plane cells of the same sub-element face
+                // nodal face states at my position: R along every transverse axis
+                double nl[NV], nr[NV];
+                int okf = 1;
+                if (need) {
+                    for (int v = 0; v < NV; ++v) { nl[v] = 0.0; nr[v] = 0.0; }
+                    if (DIM == 2) {
+                        int b = 1 - a;
+                        int sb = G::stride(b);
+                        int lo = G::coord(c, b) & (n - 1);
+                        int base = c - lo * sb;
+                        for (int m = 0; m < n; ++m) {
+                            int cm = base + m * sb;
+                            int tm = G::trans(cm, a);
+                            double Rm = T.R[lo * n + m];
+                            for (int v = 0; v < NV; ++v) {
+                                double xl, xr;
+                                if (lowface) {
+                                    xr = P.fbuf[fb_index<DIM, K>(ee, a, 0, v, tm)];
+                                    xl = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, a, 1, v, tm)] : xr;
+                                } else if (highface) {
+                                    xl = P.fbuf[fb_index<DIM, K>(ee, a, 1, v, tm)];
+                                    xr = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, a, 0, v, tm)] : xl;
+                                } else {
+                                    xl = S.sp[le][v][cm - st];
+                                    xr = S.sm[le][v][cm];
+                                }
+                                nl[v] += Rm * xl;
+                                nr[v] += Rm * xr;
+                            }
+                        }
+                    } else {
+                        int b0 = (a == 0) ? 1 : 0, b1 = (a == 2) ? 1 : 2;
+                        int s0 = G::stride(b0), s1 = G::stride(b1);
+                        int lo0 = G::coord(c, b0) & (n - 1), lo1 = G::coord(c, b1) & (n - 1);
+                        int base = c - lo0 * s0 - lo1 * s1;
+                        // R along b0 first, then along b1 (same order as a mode product chain)
+                        double tl[MAXN][NV], trr[MAXN][NV];
+                        for (int m1 = 0; m1 < n; ++m1) {
+                            for (int v = 0; v < NV; ++v) { tl[m1][v] = 0.0; trr[m1][v] = 0.0; }
+                            for (int m0 = 0; m0 < n; ++m0) {
+                                int cm = base + m0 * s0 + m1 * s1;
+                                int tm = G::trans(cm, a);
+                                double Rm = T.R[lo0 * n + m0];
+                                for (int v = 0; v < NV; ++v) {
+                                    double xl, xr;
+                                    if (lowface) {
+                                        xr = P.fbuf[fb_index<DIM, K>(ee, a, 0, v, tm)];
+                                        xl = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, a, 1, v, tm)] : xr;
+                                    } else if (highface) {
+                                        xl = P.fbuf[fb_index<DIM, K>(ee, a, 1, v, tm)];
+                                        xr = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, a, 0, v, tm)] : xl;
+                                    } else {
+                                        xl = S.sp[le][v][cm - st];
+                                        xr = S.sm[le][v][cm];
+                                    }
+                                    tl[m1][v] += Rm * xl;
+                                    trr[m1][v] += Rm * xr;
+                                }
+                            }
+                        }
+                        for (int m1 = 0; m1 < n; ++m1) {
+                            double Rm = T.R[lo1 * n + m1];
+                            for (int v = 0; v < NV; ++v) { nl[v] += Rm * tl[m1][v]; nr[v] += Rm * trr[m1][v]; }
+                        }
+                    }
+                    okf = (permissible<DIM>(nl, gam) && permissible<DIM>(nr, gam)) ? 1 : 0;
+                }
+                // segment-wide permissibility (transverse bits of the level-n block)
+                {
+                    int flag = need ? okf : 1;
+                    for (int bax = 0; bax < DIM; ++bax) {
+                        if (bax == a) continue;
+                        for (int bb = 0; bb < ln; ++bb) {
+                            int bit = bax * G::LOGK + bb;
+                            int mask = 1 << bit;
+                            if (bit < 6) {
+                                flag &= __shfl_xor(flag, mask, 64);
+                            } else {
+                                S.ix[tid] = flag;
+                                __syncthreads();
+                                flag &= S.ix[tid ^ mask];
+                                __syncthreads();
+                            }
+                        }
+                    }
+                    okf = flag;
+                }
+                double fnod[NV];
+                if (need && okf) hlle<DIM>(nl, nr, a, gam, fnod);
+                else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
+                for (int v = 0; v < NV; ++v) S.fn[le][v][c] = fnod[v];
+                __syncthreads();
+                if (need) {
+                    if (okf) {
+                        // P along the transverse axes back to face means
+                        for (int v = 0; v < NV; ++v) cand[li][v] = 0.0;
+                        if (DIM == 2) {
+                            int b = 1 - a;
+                            int sb = G::stride(b);
+                            int lo = G::coord(c, b) & (n - 1);
+                            int base = c - lo * sb;
+                            for (int m = 0; m < n; ++m) {
+                                double Pm = T.P[lo * n + m];
+                                for (int v = 0; v < NV; ++v) cand[li][v] += Pm * S.fn[le][v][base + m * sb];
+                            }
+                        } else {
+                            int b0 = (a == 0) ? 1 : 0, b1 = (a == 2) ? 1 : 2;
+                            int s0 = G::stride(b0), s1 = G::stride(b1);
+                            int lo0 = G::coord(c, b0) & (n - 1), lo1 = G::coord(c, b1) & (n - 1);
+                            int base = c - lo0 * s0 - lo1 * s1;
+                            for (int m1 = 0; m1 < n; ++m1) {
+                                double tv[NV];
+                                for (int v = 0; v < NV; ++v) tv[v] = 0.0;
+                                for (int m0 = 0; m0 < n; ++m0) {
+                                    double Pm = T.P[lo0 * n + m0];
+                                    for (int v = 0; v < NV; ++v) tv[v] += Pm * S.fn[le][v][base + m0 * s0 + m1 * s1];
+                                }
+                                double Pm1 = T.P[lo1 * n + m1];
+                                for (int v = 0; v < NV; ++v) cand[li][v] += Pm1 * tv[v];
+                            }
+                        }
+                        wdg[li] = tb;
+                        thFV -= tb;
+                    }
+                }
+                __syncthreads();
+            }
+            double F[NV];
+            for (int v = 0; v < NV; ++v) F[v] = 0.0;
+            if (has) {
+                if (thFV != 0.0) {
+                    double aL[NV], aR[NV], fs[NV];
+                    for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
+                    if (!permissible<DIM>(aL, gam)) for (int v = 0; v < NV; ++v) aL[v] = mL[v];
+                    if (!permissible<DIM>(aR, gam)) for (int v = 0; v < NV; ++v) aR[v] = mR[v];
+                    hlle<DIM>(aL, aR, a, gam, fs);
+                    for (int v = 0; v < NV; ++v) F[v] = thFV * fs[v];
+                }
+                for (int li = 0; li < P.nlev; ++li)
+                    if (wdg[li] != 0.0)
+                        for (int v = 0; v < NV; ++v) F[v] += wdg[li] * cand[li][v];
+                for (int v = 0; v < NV; ++v) S.F[le][v][k * KF + tr] = F[v];
+            }
+        }
+        __syncthreads();
+
+        // FV part: -(K/dx_a) (F_{i+1/2} - F_{i-1/2})
+        {
+            double sc = K / P.dx[a];
+            for (int v = 0; v < NV; ++v)
+                rfv[v] -= sc * (S.F[le][v][(pos + 1) * KF + tr] - S.F[le][v][pos * KF + tr]);
+        }
+        // DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat)
+        for (int li = 0; li < P.nlev; ++li) {
+            const sedg_level_tab &T = P.tabs[li];
+            int n = P.lev_n[li];
+            bool on = th[1 + li] != 0.0;
+            // squeezed reconstruction at this cell's node (sp/sm reused as ping-pong)
+            double (*A0)[KD] = S.sp[le];
+            double (*A1)[KD] = S.sm[le];
+            double nodal[NV];
+            if (DIM == 2) {
+                if (on) for (int v = 0; v < NV; ++v) A0[v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+                __syncthreads();
+                if (on) for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(A0[v], c, 1, n, T.R);
+            } else {
+                if (on) for (int v = 0; v < NV; ++v) A0[v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+                __syncthreads();
+                if (on) for (int v = 0; v < NV; ++v) A1[v][c] = bapply<DIM, K>(A0[v], c, 1, n, T.R);
+                __syncthreads();
+                if (on) for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(A1[v], c, 2, n, T.R);
+            }
+            if (on) {
+                double b = beta[li];
+                for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * mean[li][v] + b * nodal[v];
+                double f[NV];
+                euler_flux<DIM>(nodal, a, gam, f);
+                for (int v = 0; v < NV; ++v) S.fn[le][v][c] = f[v];
+            }
+            __syncthreads();
+            double vol[NV];
+            if (on) for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(S.fn[le][v], c, a, n, T.Dhat);
+            // P along the other axes in increasing order
+            for (int bax = 0; bax < DIM; ++bax) {
+                if (bax == a) continue;
+                __syncthreads();
+                if (on) for (int v = 0; v < NV; ++v) A0[v][c] = vol[v];
+                __syncthreads();
+                if (on) for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(A0[v], c, bax, n, T.P);
+            }
+            if (on) {
+                int lo = pos & (n - 1);
+                int kl = pos - lo, kr = kl + n;
+                double sc = K / (n * P.dx[a]);
+                for (int v = 0; v < NV; ++v) {
+                    double surf = T.Bhl[lo] * S.F[le][v][kl * KF + tr] + T.Bhr[lo] * S.F[le][v][kr * KF + tr];
+                    lr[li][v] += sc * (vol[v] - surf);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // blend (eq. blending-weights) and store / RK stage
+    double out[NV];
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    if (th[0] != 0.0)
+        for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
+    for (int li = 0; li < P.nlev; ++li)
+        if (th[1 + li] != 0.0)
+            for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lr[li][v];
+    if (!act) return;
+    if (P.stage == 0) {
+        for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = out[v];
+    } else {
+        double dt = *P.dt;
+        for (int v = 0; v < NV; ++v) {
+            long long i = v * P.dof + g;
+            double r;
+            if (P.stage == 1) r = ub[v] + dt * out[v];
+            else if (P.stage == 2) r = 0.75 * P.u0[i] + 0.25 * (ub[v] + dt * out[v]);
+            else r = (1.0 / 3.0) * P.u0[i] + (2.0 / 3.0) * (ub[v] + dt * out[v]);
+            P.out[i] = r;
+        }
+    }
+}
+
+// CFL step from the per-block eigenvalue maxima (eq. cfl-condition); one block.
+__global__ void __launch_bounds__(256) finalize_dt_kernel(const double *lam_part, int nparts, double num, double *dt,
+                                                         double *dt_log, int *step_ctr)
+{
+    __shared__ double s[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) m = fmax(m, lam_part[i]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double d = num / s[0];
+        dt[0] = d;
+        if (dt_log) {
+            int k = step_ctr[0];
+            dt_log[k] = d;
+            step_ctr[0] = k + 1;
+        }
+    }
+}
+
+__global__ void set_scalars_kernel(double *dt, double val, int *step_ctr)
+{
+    if (threadIdx.x == 0) {
+        if (dt) dt[0] = val;
+        if (step_ctr) step_ctr[0] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct sedg_ctx {
+    sedg_mesh mesh;
+    sedg_params params;
+    int nv, nel, A, nlev;
+    int lev_n[MAXLEV], lev_off[MAXLEV];
+    long long dof;
+    int G[3];
+    double dx[3];
+    sedg_level_tab *d_tabs;
+    double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2;
+    int *d_err, *d_ctr;
+    int nblocks;
+    hipStream_t last;
+    std::map<std::tuple<double *, double *, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+int epb_for(int dim, int K)
+{
+    if (dim == 2) return K == 4 ? 16 : 4;
+    return K == 4 ? 4 : 1;
+}
+
+bool supported(int dim, int K) { return (dim == 2 || dim == 3) && (K == 4 || K == 8); }
+
+template <int DIM, int K>
+void launch_pair(const KArgs &P, int nblocks, hipStream_t s)
+{
+    constexpr int EPBv = (DIM == 2) ? (K == 4 ? 16 : 4) : (K == 4 ? 4 : 1);
+    constexpr int threads = EPBv * Geo<DIM, K>::KD;
+    hipLaunchKernelGGL((analyse_kernel<DIM, K, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+}
+
+template <int DIM, int K>
+void launch_residual(const KArgs &P, int nblocks, hipStream_t s)
+{
+    constexpr int EPBv = (DIM == 2) ? (K == 4 ? 16 : 4) : (K == 4 ? 4 : 1);
+    constexpr int threads = EPBv * Geo<DIM, K>::KD;
+    hipLaunchKernelGGL((residual_kernel<DIM, K, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+}
+
+void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s)
+{
+    int d = C->mesh.dim, K = C->mesh.K;
+    if (d == 2 && K == 4) launch_pair<2, 4>(P, C->nblocks, s);
+    else if (d == 2 && K == 8) launch_pair<2, 8>(P, C->nblocks, s);
+    else if (d == 3 && K == 4) launch_pair<3, 4>(P, C->nblocks, s);
+    else launch_pair<3, 8>(P, C->nblocks, s);
+}
+
+void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s)
+{
+    int d = C->mesh.dim, K = C->mesh.K;
+    if (d == 2 && K == 4) launch_residual<2, 4>(P, C->nblocks, s);
+    else if (d == 2 && K == 8) launch_residual<2, 8>(P, C->nblocks, s);
+    else if (d == 3 && K == 4) launch_residual<3, 4>(P, C->nblocks, s);
+    else launch_residual<3, 8>(P, C->nblocks, s);
+}
+
+KArgs base_args(const sedg_ctx *C)
+{
+    KArgs P;
+    std::memset(&P, 0, sizeof(P));
+    P.alpha = C->d_alpha;
+    P.beta = C->d_beta;
+    P.fbuf = C->d_fbuf;
+    P.tabs = C->d_tabs;
+    P.err = C->d_err;
+    P.dof = C->dof;
+    P.nel = C->nel;
+    for (int a = 0; a < 3; ++a) {
+        P.ne[a] = a < C->mesh.dim ? C->mesh.nelem[a] : 1;
+        P.G[a] = C->G[a];
+        P.bc[a] = C->mesh.bc[a];
+        P.dx[a] = C->dx[a];
+    }
+    P.nlev = C->nlev;
+    for (int li = 0; li < MAXLEV; ++li) { P.lev_n[li] = C->lev_n[li]; P.lev_off[li] = C->lev_off[li]; }
+    P.A = C->A;
+    P.mode = C->params.mode;
+    P.level_mask = C->params.level_mask;
+    P.gamma = C->mesh.gamma;
+    P.tau_A = C->params.tau_A;
+    P.tau_S = C->params.tau_S;
+    P.alpha_H = C->params.alpha_H;
+    P.alpha_L = C->params.alpha_L;
+    P.beta_L = C->params.beta_L;
+    return P;
+}
+
+double cfl_numerator(const sedg_ctx *C)
+{
+    double dxm = C->dx[0];
+    for (int a = 1; a < C->mesh.dim; ++a) dxm = dxm < C->dx[a] ? dxm : C->dx[a];
+    return C->params.cfl * dxm / ((double)(1 << (C->mesh.dim - 1)) * (2.0 * C->mesh.K - 1.0));
+}
+
+int set_levels(sedg_ctx *C, const sedg_params *p)
+{
+    int K = C->mesh.K;
+    int top = p->top_level > 0 ? p->top_level : K;
+    if (top < 2 || top > K || (top & (top - 1))) return SEDG_EINVAL;
+    if (p->mode < 0 || p->mode > 3) return SEDG_EINVAL;
+    C->params = *p;
+    C->nlev = 0;
+    int off = 0;
+    for (int n = top; n >= 2; n /= 2) {
+        int li = C->nlev++;
+        C->lev_n[li] = n;
+        C->lev_off[li] = off;
+        int per = 1;
+        for (int a = 0; a < C->mesh.dim; ++a) per *= K / n;
+        off += per;
+    }
+    for (int li = C->nlev; li < MAXLEV; ++li) { C->lev_n[li] = 2; C->lev_off[li] = 0; }
+    C->A = off;
+    sedg_level_tab h[MAXLEV];
+    std::memset(h, 0, sizeof(h));
+    for (int li = 0; li < C->nlev; ++li)
+        if (sedg_build_level(C->lev_n[li], C->mesh.family, &h[li])) return SEDG_EINVAL;
+    if (hipMemcpy(C->d_tabs, h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
+    C->graphs.clear();
+    return SEDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sedg_strerror(int code)
+{
+    switch (code) {
+    case SEDG_OK: return "ok";
+    case SEDG_EINVAL: return "invalid argument";
+    case SEDG_EHIP: return "HIP runtime error";
+    case SEDG_ENOMEM: return "device allocation failed";
+    case SEDG_ESTATE: return "non-permissible or non-finite mean value";
+    case SEDG_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+    }
+}
+
+int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out)
+{
+    if (!mesh || !params || !out) return SEDG_EINVAL;
+    *out = nullptr;
+    if (!supported(mesh->dim, mesh->K)) return SEDG_EUNSUPPORTED;
+    if (!(mesh->gamma > 1.0)) return SEDG_EINVAL;
+    if (mesh->family != SEDG_GAUSS && mesh->family != SEDG_LGL) return SEDG_EINVAL;
+    sedg_ctx *C = new sedg_ctx();
+    C->mesh = *mesh;
+    C->nv = mesh->dim + 2;
+    C->nel = 1;
+    C->dof = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < mesh->dim) {
+            if (mesh->nelem[a] < 1 || !(mesh->hi[a] > mesh->lo[a])) { delete C; return SEDG_EINVAL; }
+            if (mesh->bc[a] != SEDG_PERIODIC && mesh->bc[a] != SEDG_OUTFLOW) { delete C; return SEDG_EINVAL; }
+            C->G[a] = mesh->nelem[a] * mesh->K;
+            C->nel *= mesh->nelem[a];
+            C->dx[a] = (mesh->hi[a] - mesh->lo[a]) / mesh->nelem[a];
+        } else {
+            C->G[a] = 1;
+            C->dx[a] = 1.0;
+            C->mesh.nelem[a] = 1;
+        }
+        C->dof *= C->G[a];
+    }
+    int epb = epb_for(mesh->dim, mesh->K);
+    C->nblocks = (C->nel + epb - 1) / epb;
+    int maxA = 0;
+    for (int n = mesh->K; n >= 2; n /= 2) {
+        int per = 1;
+        for (int a = 0; a < mesh->dim; ++a) per *= mesh->K / n;
+        maxA += per;
+    }
+    size_t kf = 1;
+    for (int a = 1; a < mesh->dim; ++a) kf *= mesh->K;
+    size_t nst = (size_t)C->nv * C->dof;
+    bool ok = true;
+    ok = ok && hipMalloc(&C->d_tabs, sizeof(sedg_level_tab) * MAXLEV) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_alpha, sizeof(double) * (size_t)C->nel * maxA) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_beta, sizeof(double) * (size_t)C->nel * maxA) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_fbuf, sizeof(double) * (size_t)C->nel * mesh->dim * 2 * C->nv * kf) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_lam, sizeof(double) * (size_t)C->nblocks) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_dt, sizeof(double) * 2) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_u1, sizeof(double) * nst) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_u2, sizeof(double) * nst) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_err, sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_ctr, sizeof(int)) == hipSuccess;
+    if (!ok) { sedg_destroy(C); return SEDG_ENOMEM; }
+    int big = INT_MAX;
+    if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) { sedg_destroy(C); return SEDG_EHIP; }
+    int rc = set_levels(C, params);
+    if (rc) { sedg_destroy(C); return rc; }
+    C->last = nullptr;
+    *out = C;
+    return SEDG_OK;
+}
+
+int sedg_destroy(sedg_ctx *C)
+{
+    if (!C) return SEDG_OK;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
+    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete C;
+    return SEDG_OK;
+}
+
+long sedg_state_len(const sedg_ctx *C) { return C ? (long)(C->nv * C->dof) : SEDG_EINVAL; }
+long sedg_alpha_len(const sedg_ctx *C) { return C ? (long)C->A * C->nel : SEDG_EINVAL; }
+
+int sedg_set_params(sedg_ctx *C, const sedg_params *p)
+{
+    if (!C || !p) return SEDG_EINVAL;
+    (void)hipDeviceSynchronize();
+    return set_levels(C, p);
+}
+
+int sedg_rhs(sedg_ctx *C, const double *u, double *dudt, double *alpha_out, double *beta_out,
+             const double *alpha_in, void *stream)
+{
+    if (!C || !u || !dudt || u == dudt) return SEDG_EINVAL;
+    if (C->params.mode == SEDG_EXTERNAL && !alpha_in) return SEDG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    KArgs P = base_args(C);
+    P.u = u;
+    P.out = dudt;
+    P.alpha_in = alpha_in;
+    P.stage = 0;
+    launch_analyse_any(C, P, s);
+    launch_residual_any(C, P, s);
+    size_t na = sizeof(double) * (size_t)C->A * C->nel;
+    if (alpha_out && hipMemcpyAsync(alpha_out, C->d_alpha, na, hipMemcpyDeviceToDevice, s) != hipSuccess) return SEDG_EHIP;
+    if (beta_out && hipMemcpyAsync(beta_out, C->d_beta, na, hipMemcpyDeviceToDevice, s) != hipSuccess) return SEDG_EHIP;
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+int sedg_max_dt(sedg_ctx *C, const double *u, double *dt_dev, void *stream)
+{
+    if (!C || !u || !dt_dev) return SEDG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    KArgs P = base_args(C);
+    P.u = u;
+    P.lam_part = C->d_lam;
+    // the analyse pass also produces alpha/beta/face data (harmless side effect)
+    P.mode = SEDG_FORCE_FV;
+    launch_analyse_any(C, P, s);
+    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(256), 0, s, (const double *)C->d_lam, C->nblocks,
+                       cfl_numerator(C), dt_dev, (double *)nullptr, (int *)nullptr);
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log, hipStream_t s)
+{
+    KArgs P = base_args(C);
+    P.dt = C->d_dt;
+    // stage 1: u1 = u + dt L(u)
+    P.u = u;
+    P.out = C->d_u1;
+    P.stage = 1;
+    P.lam_part = dt_fixed > 0.0 ? nullptr : C->d_lam;
+    launch_analyse_any(C, P, s);
+    if (!(dt_fixed > 0.0))
+        hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(256), 0, s, (const double *)C->d_lam, C->nblocks,
+                           cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
+    launch_residual_any(C, P, s);
+    // stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1))
+    P.lam_part = nullptr;
+    P.u = C->d_u1;
+    P.u0 = u;
+    P.out = C->d_u2;
+    P.stage = 2;
+    launch_analyse_any(C, P, s);
+    launch_residual_any(C, P, s);
+    // stage 3: u = 1/3 u + 2/3 (u2 + dt L(u2))
+    P.u = C->d_u2;
+    P.u0 = u;
+    P.out = u;
+    P.stage = 3;
+    launch_analyse_any(C, P, s);
+    launch_residual_any(C, P, s);
+}
+
+int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream)
+{
+    if (!C || !u || nsteps < 0) return SEDG_EINVAL;
+    if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
+    if (nsteps == 0) return SEDG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // step counter / fixed step
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, C->d_dt, dt_fixed > 0.0 ? dt_fixed : 0.0, C->d_ctr);
+    auto key = std::make_tuple(u, dt_log_dev, dt_fixed > 0.0 ? 1 : 0);
+    hipGraphExec_t exec = nullptr;
+    auto it = C->graphs.find(key);
+    if (it != C->graphs.end()) {
+        exec = it->second;
+    } else {
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SEDG_EHIP;
+        hipGraph_t graph;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
+        enqueue_step(C, u, dt_fixed, dt_log_dev, cs);
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return SEDG_EHIP;
+        C->graphs[key] = exec;
+    }
+    for (int st = 0; st < nsteps; ++st)
+        if (hipGraphLaunch(exec, s) != hipSuccess) return SEDG_EHIP;
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+int sedg_check(sedg_ctx *C, long *bad_elem)
+{
+    if (!C || !bad_elem) return SEDG_EINVAL;
+    if (hipStreamSynchronize(C->last) != hipSuccess) return SEDG_EHIP;
+    int h = INT_MAX;
+    if (hipMemcpy(&h, C->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SEDG_EHIP;
+    if (h == INT_MAX) { *bad_elem = -1; return SEDG_OK; }
+    *bad_elem = h;
+    int big = INT_MAX;
+    if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    return SEDG_ESTATE;
+}
+
+}  // extern "C"

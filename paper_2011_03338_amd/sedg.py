@@ -1,0 +1,177 @@
+"""Python binding of libsedg (ctypes).  Argument marshalling only: every step of
+the right-hand side and the Runge-Kutta stages runs in the library's HIP kernels.
+Device memory comes from torch tensors (float64, contiguous, on the GPU) and
+the stream from torch's current stream.
+
+The functions mirror the C entry points declared in include/sedg.h:
+sedg_create / sedg_destroy / sedg_rhs / sedg_max_dt / sedg_rk_step / sedg_check
+/ sedg_tables.  A missing or unloadable library raises at first use; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsedg.so")
+
+SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "sedg_set_params",
+            "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror"]
+
+
+class SedgError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code) if _lib else "error", code))
+
+
+class Mesh_c(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("K", ctypes.c_int), ("nelem", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
+                ("gamma", ctypes.c_double), ("family", ctypes.c_int)]
+
+
+class Params_c(ctypes.Structure):
+    _fields_ = [("tau_A", ctypes.c_double), ("tau_S", ctypes.c_double), ("alpha_H", ctypes.c_double),
+                ("alpha_L", ctypes.c_double), ("beta_L", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load libsedg.so (raises OSError if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError("libsedg.so not built (run python -m paper_2011_03338_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    lib.sedg_create.argtypes = [ctypes.POINTER(Mesh_c), ctypes.POINTER(Params_c), ctypes.POINTER(vp)]
+    lib.sedg_destroy.argtypes = [vp]
+    lib.sedg_state_len.argtypes = [vp]
+    lib.sedg_state_len.restype = ctypes.c_long
+    lib.sedg_alpha_len.argtypes = [vp]
+    lib.sedg_alpha_len.restype = ctypes.c_long
+    lib.sedg_set_params.argtypes = [vp, ctypes.POINTER(Params_c)]
+    lib.sedg_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.sedg_max_dt.argtypes = [vp, vp, vp, vp]
+    lib.sedg_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
+    lib.sedg_check.argtypes = [vp, ctypes.POINTER(ctypes.c_long)]
+    lib.sedg_tables.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+    lib.sedg_strerror.argtypes = [ctypes.c_int]
+    lib.sedg_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().sedg_strerror(code).decode()
+
+
+def _check(rc, what):
+    if rc != SEDG_OK:
+        raise SedgError(rc, what)
+
+
+def mesh_c(m) -> Mesh_c:
+    ne, lo, hi, bc = m.full()
+    s = Mesh_c()
+    s.dim, s.K = m.dim, m.K
+    for a in range(3):
+        s.nelem[a], s.lo[a], s.hi[a], s.bc[a] = ne[a], lo[a], hi[a], bc[a]
+    s.gamma, s.family = m.gamma, m.family
+    return s
+
+
+def params_c(p) -> Params_c:
+    s = Params_c()
+    s.tau_A, s.tau_S, s.alpha_H, s.alpha_L, s.beta_L, s.cfl = p.tau_A, p.tau_S, p.alpha_H, p.alpha_L, p.beta_L, p.cfl
+    s.top_level, s.level_mask, s.mode = p.top_level, p.level_mask, p.mode
+    return s
+
+
+def tables(n: int, family: int = 0) -> dict:
+    """The library's own operator tables (host, no GPU needed)."""
+    buf = np.zeros(16 * 64)
+    cnt = load().sedg_tables(n, family, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), buf.size)
+    if cnt < 0:
+        raise SedgError(cnt, "sedg_tables")
+    out, o = {}, 0
+    for name, size, shp in [("xi", n, (n,)), ("w", n, (n,)), ("Dcal", n * n, (n, n)), ("D", n * n, (n, n)),
+                            ("bm", n, (n,)), ("bp", n, (n,)), ("P", n * n, (n, n)), ("R", n * n, (n, n)),
+                            ("Dhat", n * n, (n, n)), ("Bhl", n, (n,)), ("Bhr", n, (n,)),
+                            ("Ip", n * n, (n, n)), ("Im", n * n, (n, n))]:
+        out[name] = buf[o:o + size].reshape(shp).copy()
+        o += size
+    return out
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous(), "expected a contiguous float64 GPU tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One mesh/parameter context of the library on the current GPU."""
+
+    def __init__(self, mesh, params):
+        lib = load()
+        self.mesh, self.params = mesh, params
+        h = ctypes.c_void_p()
+        _check(lib.sedg_create(ctypes.byref(mesh_c(mesh)), ctypes.byref(params_c(params)), ctypes.byref(h)),
+               "sedg_create")
+        self._h = h
+        self.state_len = lib.sedg_state_len(h)
+        self.alpha_len = lib.sedg_alpha_len(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sedg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        self.params = params
+        _check(load().sedg_set_params(self._h, ctypes.byref(params_c(params))), "sedg_set_params")
+
+    def rhs(self, u, dudt, alpha_out=None, beta_out=None, alpha_in=None, stream=None):
+        _check(load().sedg_rhs(self._h, _ptr(u), _ptr(dudt), _ptr(alpha_out), _ptr(beta_out), _ptr(alpha_in),
+                               _stream(stream)), "sedg_rhs")
+
+    def max_dt(self, u, dt_out, stream=None):
+        _check(load().sedg_max_dt(self._h, _ptr(u), _ptr(dt_out), _stream(stream)), "sedg_max_dt")
+
+    def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, stream=None):
+        _check(load().sedg_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log), _stream(stream)),
+               "sedg_rk_step")
+
+    def check(self):
+        """Returns -1, or raises SedgError(SEDG_ESTATE) naming the bad element."""
+        bad = ctypes.c_long(0)
+        rc = load().sedg_check(self._h, ctypes.byref(bad))
+        if rc == SEDG_ESTATE:
+            raise SedgError(rc, "sedg_check: element %d" % bad.value)
+        _check(rc, "sedg_check")
+        return -1

@@ -1,0 +1,97 @@
+"""Helpers of the GPU parity tests: run the library through its C ABI and the
+oracle on the same seeded inputs and compare them.
+
+Tolerances (FP64 on both sides): one right-hand side within 1e-12 of the
+largest magnitude per conserved variable; states after 100 SSP-RK3 steps within
+1e-9.  Blending factors must agree exactly where they are clamped or snapped
+and within 1e-13 where they are continuous; a sub-element whose decision
+differs is accepted only if the oracle's pre-threshold quantity lies within
+1e-12 of that threshold, and the right-hand sides are then compared with the
+oracle's factors fed to both sides.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from paper_2011_03338_amd import sedg, workloads as W
+
+RHS_TOL = 1e-12
+STATE_TOL = 1e-9
+ALPHA_TOL = 1e-13
+THRESH_TOL = 1e-12
+
+DEV = torch.device("cuda:0")
+
+
+def say(*args):
+    print(*args, flush=True)
+
+
+def rel_err(g, o):
+    """max_v ||g_v - o_v||_inf / ||o_v||_inf (per conserved variable)."""
+    out = 0.0
+    for v in range(o.shape[0]):
+        den = np.abs(o[v]).max()
+        num = np.abs(g[v] - o[v]).max()
+        out = max(out, num / den if den > 0 else num)
+    return out
+
+
+def gpu_rhs(mesh, params, u, alpha_in=None):
+    s = sedg.Solver(mesh, params)
+    ug = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
+    dg = torch.zeros_like(ug)
+    A = W.alpha_len(mesh, params)
+    al = torch.zeros(mesh.nel * A, dtype=torch.float64, device=DEV)
+    be = torch.zeros_like(al)
+    ain = None if alpha_in is None else torch.from_numpy(np.ascontiguousarray(alpha_in).reshape(-1)).to(DEV)
+    s.rhs(ug, dg, al, be, ain)
+    s.check()
+    torch.cuda.synchronize()
+    out = dg.cpu().numpy(), al.cpu().numpy().reshape(mesh.nel, A), be.cpu().numpy().reshape(mesh.nel, A)
+    s.close()
+    return out
+
+
+def near_threshold(info, params, idx):
+    """Is the oracle's decision at (element, slot) idx within THRESH_TOL of a threshold?"""
+    e, q = idx
+    b = info["beta"][e, q]
+    x = info["xraw"][e, q]
+    ar = info["araw"][e, q]
+    close = abs(b - params.beta_L) <= THRESH_TOL
+    if np.isfinite(x):
+        close |= abs(x) <= THRESH_TOL or abs(x - 1.0) <= THRESH_TOL
+    if np.isfinite(ar):
+        close |= abs(ar - params.alpha_H) <= THRESH_TOL or abs(ar - params.alpha_L) <= THRESH_TOL
+    return close
+
+
+def compare_rhs(mesh, params, u, label=""):
+    """Full parity check of one right-hand side; returns (rel_err, n_exempt)."""
+    d_o, info = O.rhs(mesh, params, u, full=True)
+    d_g, a_g, b_g = gpu_rhs(mesh, params, u, info["alpha"] if params.mode == W.EXTERNAL else None)
+    a_o = info["alpha"]
+    # squeezing parameters are continuous
+    assert np.abs(b_g - info["beta"]).max() <= ALPHA_TOL, (label, "beta", np.abs(b_g - info["beta"]).max())
+    diff = np.abs(a_g - a_o)
+    clamped = (a_o == 0.0) | (a_o == 1.0) | (a_g == 0.0) | (a_g == 1.0)
+    bad = (clamped & (diff != 0.0)) | (~clamped & (diff > ALPHA_TOL))
+    n_exempt = 0
+    if np.any(bad):
+        for idx in zip(*np.nonzero(bad)):
+            # a snapped level flips whole elements: accept if any slot of the element is near a threshold
+            e = idx[0]
+            ok = any(near_threshold(info, params, (e, q)) for q in range(a_o.shape[1]))
+            assert ok, (label, "alpha mismatch not at a threshold", idx, a_g[idx], a_o[idx])
+            n_exempt += 1
+        # arithmetic parity with the oracle's decisions fed to both sides
+        pe = W.Params(**{**params.__dict__, "mode": W.EXTERNAL})
+        d_o = O.rhs(mesh, pe, u, alpha_in=a_o)
+        d_g, _, _ = gpu_rhs(mesh, pe, u, a_o)
+    err = rel_err(d_g, d_o)
+    say("  parity %-28s rel_err=%.3e exempt=%d" % (label, err, n_exempt))
+    assert err <= RHS_TOL, (label, err)
+    return err, n_exempt

@@ -1,0 +1,273 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the
+same seeded inputs.  Run on an MI355X with  pytest -m gpu."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_03338_amd import sedg, workloads as W
+from tests.parity import DEV, RHS_TOL, STATE_TOL, compare_rhs, gpu_rhs, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sedg.load()
+    yield
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rhs_config0(seed):
+    """2-D periodic 16x16 elements, K = 4, density wave with a seeded jump."""
+    mesh, u, _ = W.config0(seed, 16, 4)
+    compare_rhs(mesh, W.Params(), u, "config0 seed%d" % seed)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_rhs_config0_k8(seed):
+    mesh, u, _ = W.config0(seed, 8, 8)
+    compare_rhs(mesh, W.Params(), u, "config0 K8 seed%d" % seed)
+
+
+@pytest.mark.parametrize("K,ne", [(8, 8), (8, 13), (4, 16), (4, 7)])
+def test_rhs_sedov(K, ne):
+    """Sedov-type blast with outflow boundaries; odd element counts leave a ragged
+    last workgroup."""
+    mesh, u, _ = W.sedov(1, ne, K)
+    compare_rhs(mesh, W.Params(), u, "sedov K%d ne%d" % (K, ne))
+
+
+def test_rhs_sedov_resolved():
+    """The blast resolved over a few elements (mixed levels, squeezes, fallbacks)."""
+    mesh, u, _ = W.sedov(2, 12, 8, L=0.3, sigma=0.03)
+    compare_rhs(mesh, W.Params(), u, "sedov resolved")
+
+
+def test_rhs_nonsquare_ragged():
+    mesh, u0, _ = W.config0(4, 6, 8)
+    mesh = W.Mesh(2, 8, [5, 3], [0, 0], [1.0, 0.6], [0, 1])
+    rng = np.random.default_rng(9)
+    u = np.zeros(mesh.shape())
+    g = mesh.grid
+    u[0] = 1.0 + 0.5 * rng.uniform(size=(1, g[1], g[0]))
+    u[1] = 0.2 * u[0]
+    u[2] = -0.1 * u[0]
+    u[3] = (1.0 + 0.5 * rng.uniform(size=(1, g[1], g[0]))) / 0.4 + 0.5 * 0.05 * u[0]
+    compare_rhs(mesh, W.Params(), u, "5x3 random")
+
+
+@pytest.mark.parametrize("K", [4, 8])
+@pytest.mark.parametrize("mode", [W.FORCE_DG, W.FORCE_FV, W.EXTERNAL])
+def test_rhs_modes(K, mode):
+    mesh, u, _ = W.config0(5, 6 if K == 8 else 10, K)
+    p = W.Params(mode=mode)
+    if mode == W.EXTERNAL:
+        rng = np.random.default_rng(17)
+        A = W.alpha_len(mesh, p)
+        al = rng.uniform(0, 1, size=(mesh.nel, A))
+        d_o = O.rhs(mesh, p, u, alpha_in=al)
+        d_g, a_g, _ = gpu_rhs(mesh, p, u, al)
+        assert np.array_equal(a_g, al)
+        err = rel_err(d_g, d_o)
+        say("  parity external K%d rel_err=%.3e" % (K, err))
+        assert err <= RHS_TOL
+    else:
+        compare_rhs(mesh, p, u, "mode%d K%d" % (mode, K))
+
+
+def test_rhs_lgl_nodes():
+    mesh, u, _ = W.config0(6, 6, 8)
+    mesh.family = W.LGL
+    compare_rhs(mesh, W.Params(), u, "LGL K8")
+
+
+@pytest.mark.parametrize("top", [4, 2])
+def test_rhs_dgfv_top_level(top):
+    mesh, u, _ = W.sedov(3, 8, 8, L=0.5, sigma=0.05)
+    compare_rhs(mesh, W.Params(top_level=top), u, "DGFV%d" % top)
+
+
+def test_rhs_single_level_mask():
+    mesh, u, _ = W.sedov(3, 8, 8, L=0.5, sigma=0.05)
+    compare_rhs(mesh, W.Params(level_mask=1 << 3), u, "single level")
+
+
+@pytest.mark.parametrize("K,ne", [(4, 3), (8, 2)])
+def test_rhs_3d(K, ne):
+    mesh, u, _ = W.shear_layer_3d(0, ne, K)
+    u = u.numpy()
+    compare_rhs(mesh, W.Params(), u, "3d KH K%d" % K)
+    p = W.Params(mode=W.EXTERNAL)
+    rng = np.random.default_rng(23)
+    al = rng.uniform(0, 1, size=(mesh.nel, W.alpha_len(mesh, p)))
+    err = rel_err(gpu_rhs(mesh, p, u, al)[0], O.rhs(mesh, p, u, alpha_in=al))
+    say("  parity 3d external K%d rel_err=%.3e" % (K, err))
+    assert err <= RHS_TOL
+
+
+def test_rhs_3d_outflow_jump():
+    mesh = W.Mesh(3, 4, [3, 2, 2], [0, 0, 0], [1, 1, 1], [1, 0, 1])
+    g = mesh.grid
+    x = (np.arange(g[0]) + 0.5) / g[0]
+    u = np.zeros(mesh.shape())
+    u[0] = np.where(x < 0.45, 1.0, 0.2)[None, None, :]
+    u[1] = 0.3 * u[0]
+    u[4] = np.where(x < 0.45, 2.0, 0.3)[None, None, :] / 0.4 + 0.5 * 0.09 * u[0]
+    compare_rhs(mesh, W.Params(), u, "3d outflow jump")
+
+
+def test_rk3_100_steps_config0():
+    """100 SSP-RK3 steps at CFL 0.5 on the 16x16, K = 4 case: state within 1e-9,
+    step sizes within 1e-14."""
+    mesh, u, _ = W.config0(0, 16, 4)
+    p = W.Params(cfl=0.5)
+    u_o, dts_o = O.rk3(mesh, p, u, 100)
+    s = sedg.Solver(mesh, p)
+    ug = torch.from_numpy(u).to(DEV)
+    dts = torch.zeros(100, dtype=torch.float64, device=DEV)
+    s.rk_step(ug, 100, 0.0, dts)
+    s.check()
+    err = rel_err(ug.cpu().numpy(), u_o)
+    dterr = np.abs(dts.cpu().numpy() - dts_o).max() / dts_o.max()
+    say("  rk3 100 steps rel_err=%.3e dt_err=%.3e" % (err, dterr))
+    assert err <= STATE_TOL and dterr <= 1e-14
+    s.close()
+
+
+def test_rk3_sedov_k8_steps():
+    mesh, u, _ = W.sedov(4, 10, 8, L=0.4, sigma=0.04)
+    p = W.Params(cfl=0.5)
+    u_o, dts_o = O.rk3(mesh, p, u, 20)
+    s = sedg.Solver(mesh, p)
+    ug = torch.from_numpy(u).to(DEV)
+    dts = torch.zeros(20, dtype=torch.float64, device=DEV)
+    s.rk_step(ug, 20, 0.0, dts)
+    s.check()
+    err = rel_err(ug.cpu().numpy(), u_o)
+    say("  rk3 sedov K8 20 steps rel_err=%.3e" % err)
+    assert err <= STATE_TOL
+    s.close()
+
+
+def test_rk3_fixed_dt_and_repeat_bitwise():
+    mesh, u, _ = W.config0(1, 8, 8)
+    p = W.Params()
+    outs = []
+    for _ in range(2):
+        s = sedg.Solver(mesh, p)
+        ug = torch.from_numpy(u).to(DEV)
+        s.rk_step(ug, 5, 1e-4)
+        s.check()
+        outs.append(ug.cpu().numpy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    u_o, _ = O.rk3(mesh, p, u, 5, 1e-4)
+    assert rel_err(outs[0], u_o) <= STATE_TOL
+
+
+def test_max_dt():
+    mesh, u, _ = W.sedov(0, 16, 8)
+    p = W.Params(cfl=0.5)
+    s = sedg.Solver(mesh, p)
+    ug = torch.from_numpy(u).to(DEV)
+    d = torch.zeros(1, dtype=torch.float64, device=DEV)
+    s.max_dt(ug, d)
+    s.check()
+    assert abs(d.item() - O.max_dt(mesh, p, u)) <= 1e-15 * d.item()
+    s.close()
+
+
+def test_full_size_sedov_windows():
+    """256x256 elements, K = 8 (the benchmark's launch configuration): the right-hand
+    side of sampled element windows equals the oracle's on the window cut out with
+    one ring of neighbours (blending factors and face states are element-local)."""
+    mesh, u, _ = W.sedov(0, 256, 8)
+    p = W.Params()
+    s = sedg.Solver(mesh, p)
+    ug = torch.from_numpy(u).to(DEV)
+    dg = torch.zeros_like(ug)
+    s.rhs(ug, dg)
+    s.check()
+    d = dg.cpu().numpy()
+    s.close()
+    K = 8
+    rng = np.random.default_rng(0)
+    centres = [(128, 128), (126, 131), (0, 0), (255, 100)] + [tuple(rng.integers(1, 255, 2)) for _ in range(3)]
+    for (ex, ey) in centres:
+        x0, x1 = max(ex - 2, 0), min(ex + 3, 256)
+        y0, y1 = max(ey - 2, 0), min(ey + 3, 256)
+        sub = u[:, :, y0 * K:y1 * K, x0 * K:x1 * K]
+        h = 3.0 / 256
+        bc = [1, 1]
+        wm = W.Mesh(2, K, [x1 - x0, y1 - y0], [-1.5 + x0 * h, -1.5 + y0 * h], [-1.5 + x1 * h, -1.5 + y1 * h], bc)
+        do = O.rhs(wm, p, np.ascontiguousarray(sub))
+        # compare the interior of the window (elements not on a cut edge)
+        ix0 = 1 if x0 > 0 else 0
+        ix1 = (x1 - x0) - (1 if x1 < 256 else 0)
+        iy0 = 1 if y0 > 0 else 0
+        iy1 = (y1 - y0) - (1 if y1 < 256 else 0)
+        go = d[:, :, (y0 + iy0) * K:(y0 + iy1) * K, (x0 + ix0) * K:(x0 + ix1) * K]
+        oo = do[:, :, iy0 * K:iy1 * K, ix0 * K:ix1 * K]
+        err = rel_err(go, oo)
+        say("  window (%d,%d) rel_err=%.3e" % (ex, ey, err))
+        assert err <= RHS_TOL
+
+
+def test_full_size_conservation_periodic():
+    """128x128 elements, K = 8, periodic: the domain sum of the right-hand side
+    vanishes to round-off for adaptive and random blending factors."""
+    mesh, u, _ = W.pressure_pulse(0, 128, 8)
+    for mode in (W.ADAPTIVE, W.EXTERNAL):
+        p = W.Params(mode=mode)
+        al = None
+        if mode == W.EXTERNAL:
+            al = np.random.default_rng(1).uniform(0, 1, size=(mesh.nel, W.alpha_len(mesh, p)))
+        d, _, _ = gpu_rhs(mesh, p, u, al)
+        tot = d.reshape(4, -1).sum(1)
+        scale = np.abs(d).reshape(4, -1).sum(1)
+        say("  conservation mode%d rel=%s" % (mode, (np.abs(tot) / scale)))
+        assert np.all(np.abs(tot) <= 1e-13 * scale)
+
+
+def test_free_stream_gpu():
+    mesh = W.Mesh(2, 8, [9, 7], [0, 0], [1, 1], [0, 0])
+    u = np.zeros(mesh.shape())
+    u[0], u[1], u[2], u[3] = 1.3, 0.4, -0.25, 3.0
+    p = W.Params(mode=W.EXTERNAL)
+    al = np.random.default_rng(2).uniform(0, 1, size=(mesh.nel, W.alpha_len(mesh, p)))
+    d, _, _ = gpu_rhs(mesh, p, u, al)
+    assert np.abs(d).max() <= 1e-13 * 10 * 8 * 9
+
+
+def test_bad_state_reported():
+    """A negative density is reported by sedg_check with its element; the kernels
+    finish normally."""
+    mesh, u, _ = W.config0(0, 8, 4)
+    u = u.copy()
+    u[0, 0, 13, 9] = -1.0     # subcell (9, 13) lies in element (2, 3) = 2 + 8 * 3
+    s = sedg.Solver(mesh, W.Params())
+    ug = torch.from_numpy(u).to(DEV)
+    dg = torch.zeros_like(ug)
+    s.rhs(ug, dg)
+    with pytest.raises(sedg.SedgError) as ei:
+        s.check()
+    assert ei.value.code == sedg.SEDG_ESTATE and "element 26" in str(ei.value)
+    assert s.check() == -1     # flag cleared
+    s.close()
+
+
+def test_invalid_arguments():
+    mesh, u, _ = W.config0(0, 4, 4)
+    with pytest.raises(sedg.SedgError):
+        sedg.Solver(W.Mesh(2, 6, [2, 2], [0, 0], [1, 1], [0, 0]), W.Params())
+    with pytest.raises(sedg.SedgError):
+        sedg.Solver(mesh, W.Params(top_level=3))
+    s = sedg.Solver(mesh, W.Params(mode=W.EXTERNAL))
+    ug = torch.from_numpy(u).to(DEV)
+    with pytest.raises(sedg.SedgError):
+        s.rhs(ug, torch.zeros_like(ug))        # EXTERNAL without alpha_in
+    with pytest.raises(sedg.SedgError):
+        s.rk_step(ug, 1)                        # EXTERNAL cannot step
+    s.close()
