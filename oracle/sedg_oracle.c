@@ -251,6 +251,21 @@ static int permissible(int dim, double g, const double *u)
     return p > 0.0;
 }
 
+/* Admissibility of an interface-flux input (interface-safety reading), relative to
+   the data scales of the two elements sharing the face: srho and sE are the
+   largest mean density and |mean energy| over those elements.  A state is
+   admissible if rho > 1e-12 srho and p > -1e-10 sE.  The squeeze of Sec. 2.4
+   drives its binding check point to rho or p = 1e-20, which in floating point
+   lands within rounding of zero; the margins decide such points the same way in
+   every rounding order (a binding pressure point is kept, a binding density
+   point is rejected). */
+static int flux_admissible(int dim, double g, const double *u, double srho, double sE)
+{
+    if (!(u[0] > 1e-12 * srho)) return 0;
+    double p = pressure(dim, g, u);
+    return p > -1e-10 * sE;
+}
+
 /* Physical flux along axis a (eqn. comp-euler-conservative). */
 static void euler_flux(int dim, double g, int a, const double *u, double *f)
 {
@@ -273,7 +288,7 @@ static void hlle(int dim, double g, int a, const double *uL, const double *uR, d
     euler_flux(dim, g, a, uR, fR);
     double pL = pressure(dim, g, uL), pR = pressure(dim, g, uR);
     double vL = uL[1 + a] / uL[0], vR = uR[1 + a] / uR[0];
-    double cL = sqrt(g * pL / uL[0]), cR = sqrt(g * pR / uR[0]);
+    double cL = sqrt(fmax(g * pL / uL[0], 0.0)), cR = sqrt(fmax(g * pR / uR[0], 0.0));
     double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
     double HL = (uL[dim + 1] + pL) / uL[0], HR = (uR[dim + 1] + pR) / uR[0];
     double vt2 = 0.0, vtn = 0.0;
@@ -283,11 +298,12 @@ static void hlle(int dim, double g, int a, const double *uL, const double *uR, d
         if (b == a) vtn = vb;
     }
     double Ht = (sqL * HL + sqR * HR) / (sqL + sqR);
-    double ct = sqrt((g - 1.0) * (Ht - 0.5 * vt2));
+    double ct = sqrt(fmax((g - 1.0) * (Ht - 0.5 * vt2), 0.0));
     double SL = fmin(vL - cL, vtn - ct);
     double SR = fmax(vR + cR, vtn + ct);
     double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
-    double inv = 1.0 / (SRp - SLm);
+    double den = SRp - SLm;
+    double inv = den > 0.0 ? 1.0 / den : 0.0;
     for (int v = 0; v < nv; v++)
         fs[v] = (SRp * fL[v] - SLm * fR[v] + SLm * SRp * (uR[v] - uL[v])) * inv;
 }
@@ -706,6 +722,7 @@ static void theta_cell(const ctx_t *c, const double *alpha, int i, int j, int k,
 
 typedef struct {
     double *alpha, *beta;   /* nel * A */
+    double *scale;          /* nel * 2: largest mean density and |mean energy| of each element */
     double *theta;          /* (nlev+1) * dof, global subcell order */
     double *side;           /* [axis][side][v][dof] blended interface states */
     double *flux;           /* [axis] -> (G_a+1) * trans * nv, see flux_index */
@@ -744,6 +761,15 @@ static void pass1_element(const ctx_t *c, const double *u, int e, work_t *W, con
     int ky = dim > 1 ? K : 1, kz = dim > 2 ? K : 1;
     double ub[MAXV * MAXK * MAXK * MAXK];
     gather_elem(c, u, e, ub);
+    {
+        double sr = 0.0, se = 0.0;
+        for (int q = 0; q < c->Kd; q++) {
+            sr = fmax(sr, ub[q]);
+            se = fmax(se, fabs(ub[(nv - 1) * c->Kd + q]));
+        }
+        W->scale[2 * e] = sr;
+        W->scale[2 * e + 1] = se;
+    }
     /* weights */
     double th[MAXLEV + 1];
     for (int k = 0; k < kz; k++)
@@ -818,9 +844,9 @@ static void pass1_element(const ctx_t *c, const double *u, int e, work_t *W, con
    where L(f) holds the DG levels whose sub-element boundary contains the face,
    thbar_n is the mean of the level-n weights of the two adjacent subcells,
    R_perp / P_perp act along the face over the level-n face segment, and
-   thFV = 1 - sum thbar_n.  Interface safety: an FV input that is not permissible
+   thFV = 1 - sum thbar_n.  Interface safety: an FV input that is not admissible
    is replaced by that side's subcell mean; a DG candidate whose face-node states
-   are not all permissible hands its weight to the FV candidate. */
+   are not all admissible hands its weight to the FV candidate. */
 static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, long f, const long gt[3],
                       double *F, long *nfb)
 {
@@ -845,6 +871,16 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
         uL[v] = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il] : W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir];
         uR[v] = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir] : W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il];
     }
+    /* data scales of the two elements sharing the face */
+    int el3[3], er3[3];
+    for (int b = 0; b < 3; b++) {
+        el3[b] = b < dim ? (int)(gl[b] / K) : 0;
+        er3[b] = b < dim ? (int)(gr[b] / K) : 0;
+    }
+    int eL = el3[0] + c->m.nelem[0] * (el3[1] + c->m.nelem[1] * el3[2]);
+    int eR = er3[0] + c->m.nelem[0] * (er3[1] + c->m.nelem[1] * er3[2]);
+    double srho = fmax(W->scale[2 * eL], W->scale[2 * eR]);
+    double sE = fmax(W->scale[2 * eL + 1], W->scale[2 * eR + 1]);
     int k = (int)(f % K);
     double thFV = 1.0;
     double Fdg[MAXLEV][MAXV];
@@ -897,7 +933,7 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
         double pl[MAXV], pr[MAXV];
         for (int q = 0; q < nf && ok; q++) {
             for (int v = 0; v < nv; v++) { pl[v] = sL[v][q]; pr[v] = sR[v][q]; }
-            if (!permissible(dim, g, pl) || !permissible(dim, g, pr)) ok = 0;
+            if (!flux_admissible(dim, g, pl, srho, sE) || !flux_admissible(dim, g, pr, srho, sE)) ok = 0;
         }
         if (!ok) { if (nfb) (*nfb)++; continue; }
         double fn[MAXV][MAXK * MAXK], fs[MAXV];
@@ -921,11 +957,11 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
         double aL[MAXV], aR[MAXV], fs[MAXV];
         memcpy(aL, uL, sizeof(aL));
         memcpy(aR, uR, sizeof(aR));
-        if (!permissible(dim, g, aL)) {
+        if (!flux_admissible(dim, g, aL, srho, sE)) {
             for (int v = 0; v < nv; v++) aL[v] = u[v * c->dof + il];
             if (nfb) (*nfb)++;
         }
-        if (!permissible(dim, g, aR)) {
+        if (!flux_admissible(dim, g, aR, srho, sE)) {
             for (int v = 0; v < nv; v++) aR[v] = u[v * c->dof + ir];
             if (nfb) (*nfb)++;
         }
@@ -1066,6 +1102,7 @@ static int alloc_work(const ctx_t *c, work_t *W)
     memset(W, 0, sizeof(*W));
     W->alpha = malloc(sizeof(double) * (size_t)c->nel * c->A);
     W->beta = malloc(sizeof(double) * (size_t)c->nel * c->A);
+    W->scale = malloc(sizeof(double) * (size_t)c->nel * 2);
     W->theta = malloc(sizeof(double) * (size_t)(c->nlev + 1) * c->dof);
     W->side = malloc(sizeof(double) * (size_t)c->dim * 2 * c->nv * c->dof);
     long tot = 0;
@@ -1074,13 +1111,13 @@ static int alloc_work(const ctx_t *c, work_t *W)
         tot += (long)c->nv * (c->G[a] + 1) * (c->dof / c->G[a]);
     }
     W->flux = malloc(sizeof(double) * (size_t)tot);
-    if (!W->alpha || !W->beta || !W->theta || !W->side || !W->flux) return -1;
+    if (!W->alpha || !W->beta || !W->scale || !W->theta || !W->side || !W->flux) return -1;
     return 0;
 }
 
 static void free_work(work_t *W)
 {
-    free(W->alpha); free(W->beta); free(W->theta); free(W->side); free(W->flux);
+    free(W->alpha); free(W->beta); free(W->scale); free(W->theta); free(W->side); free(W->flux);
 }
 
 static int rhs_ctx(const ctx_t *c, const double *u, double *dudt, double *alpha_out, double *beta_out,

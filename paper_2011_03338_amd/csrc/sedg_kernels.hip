@@ -49,6 +49,7 @@ struct KArgs {
     double *beta;           // nel * A
     const double *alpha_in; // EXTERNAL mode
     double *fbuf;           // face buffer
+    double *scale;          // nel * 2: largest mean density and |mean energy| per element
     const sedg_level_tab *tabs;  // per level index
     double *lam_part;       // per-block CFL eigenvalue maxima (nullable)
     const double *dt;       // device scalar step (RK stages)
@@ -90,6 +91,17 @@ __device__ __forceinline__ bool permissible(const double *u, double g)
     return pressure<DIM>(u, g) > 0.0;
 }
 
+// interface-flux input admissibility relative to the data scales of the two
+// elements sharing the face (largest mean density srho and |mean energy| sE):
+// rho > 1e-12 srho and p > -1e-10 sE, so that the squeeze's binding point
+// (rho or p = 1e-20 up to rounding) is decided the same way in every rounding order
+template <int DIM>
+__device__ __forceinline__ bool flux_admissible(const double *u, double g, double srho, double sE)
+{
+    if (!(u[0] > 1e-12 * srho)) return false;
+    return pressure<DIM>(u, g) > -1e-10 * sE;
+}
+
 template <int DIM>
 __device__ __forceinline__ void euler_flux(const double *u, int a, double g, double *f)
 {
@@ -110,7 +122,7 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
     euler_flux<DIM>(uR, a, g, fR);
     double pL = pressure<DIM>(uL, g), pR = pressure<DIM>(uR, g);
     double vL = uL[1 + a] / uL[0], vR = uR[1 + a] / uR[0];
-    double cL = sqrt(g * pL / uL[0]), cR = sqrt(g * pR / uR[0]);
+    double cL = sqrt(fmax(g * pL / uL[0], 0.0)), cR = sqrt(fmax(g * pR / uR[0], 0.0));
     double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
     double HL = (uL[DIM + 1] + pL) / uL[0], HR = (uR[DIM + 1] + pR) / uR[0];
     double vt2 = 0.0, vtn = 0.0;
@@ -121,11 +133,12 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
         if (b == a) vtn = vb;
     }
     double Ht = (sqL * HL + sqR * HR) / (sqL + sqR);
-    double ct = sqrt((g - 1.0) * (Ht - 0.5 * vt2));
+    double ct = sqrt(fmax((g - 1.0) * (Ht - 0.5 * vt2), 0.0));
     double SL = fmin(vL - cL, vtn - ct);
     double SR = fmax(vR + cR, vtn + ct);
     double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
-    double inv = 1.0 / (SRp - SLm);
+    double den = SRp - SLm;
+    double inv = den > 0.0 ? 1.0 / den : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fs[v] = (SRp * fL[v] - SLm * fR[v] + SLm * SRp * (uR[v] - uL[v])) * inv;
 }
@@ -338,6 +351,14 @@ analyse_kernel(KArgs P)
         }
     }
     __syncthreads();
+    {
+        double sr = subreduce<DIM, K>(ub[0], G::LOGK, S.x, OpMax());
+        double se = subreduce<DIM, K>(fabs(ub[NV - 1]), G::LOGK, S.x, OpMax());
+        if (act && c == 0) {
+            P.scale[2 * (long long)e] = sr;
+            P.scale[2 * (long long)e + 1] = se;
+        }
+    }
 
     // unlimited reconstructions of every level: u x_1 R x_2 R (x_3 R)
     for (int li = 0; li < P.nlev; ++li) {
@@ -611,6 +632,7 @@ residual_kernel(KArgs P)
             int src = nb[a][sd] >= 0 ? nb[a][sd] : ee;
             for (int q = c; q < P.A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * P.A + q];
         }
+    const double own_sr = P.scale[2 * (long long)ee], own_se = P.scale[2 * (long long)ee + 1];
     int sidx[MAXLEV];
     subidx_all<DIM, K>(c, P, sidx);
     double th[MAXLEV + 1];
@@ -714,6 +736,14 @@ residual_kernel(KArgs P)
                 }
                 for (int l = 0; l <= P.nlev; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
             }
+            double srho = own_sr, sE = own_se;
+            if (lowface && nbL >= 0) {
+                srho = fmax(P.scale[2 * (long long)nbL], own_sr);
+                sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
+            } else if (highface && nbR >= 0) {
+                srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
+                sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
+            }
             // DG candidates level by level (uniform loop: the segment exchange needs barriers)
             double thFV = 1.0;
             double cand[MAXLEV][NV];
@@ -790,7 +820,7 @@ residual_kernel(KArgs P)
                             for (int v = 0; v < NV; ++v) { nl[v] += Rm * tl[m1][v]; nr[v] += Rm * trr[m1][v]; }
                         }
                     }
-                    okf = (permissible<DIM>(nl, gam) && permissible<DIM>(nr, gam)) ? 1 : 0;
+                    okf = (flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0;
                 }
                 // segment-wide permissibility (transverse bits of the level-n block)
                 {
@@ -858,8 +888,8 @@ residual_kernel(KArgs P)
                 if (thFV != 0.0) {
                     double aL[NV], aR[NV], fs[NV];
                     for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
-                    if (!permissible<DIM>(aL, gam)) for (int v = 0; v < NV; ++v) aL[v] = mL[v];
-                    if (!permissible<DIM>(aR, gam)) for (int v = 0; v < NV; ++v) aR[v] = mR[v];
+                    if (!flux_admissible<DIM>(aL, gam, srho, sE)) for (int v = 0; v < NV; ++v) aL[v] = mL[v];
+                    if (!flux_admissible<DIM>(aR, gam, srho, sE)) for (int v = 0; v < NV; ++v) aR[v] = mR[v];
                     hlle<DIM>(aL, aR, a, gam, fs);
                     for (int v = 0; v < NV; ++v) F[v] = thFV * fs[v];
                 }
@@ -997,7 +1027,7 @@ struct sedg_ctx {
     int G[3];
     double dx[3];
     sedg_level_tab *d_tabs;
-    double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2;
+    double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale;
     int *d_err, *d_ctr;
     int nblocks;
     hipStream_t last;
@@ -1055,6 +1085,7 @@ KArgs base_args(const sedg_ctx *C)
     P.alpha = C->d_alpha;
     P.beta = C->d_beta;
     P.fbuf = C->d_fbuf;
+    P.scale = C->d_scale;
     P.tabs = C->d_tabs;
     P.err = C->d_err;
     P.dof = C->dof;
@@ -1175,6 +1206,7 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     ok = ok && hipMalloc(&C->d_beta, sizeof(double) * (size_t)C->nel * maxA) == hipSuccess;
     ok = ok && hipMalloc(&C->d_fbuf, sizeof(double) * (size_t)C->nel * mesh->dim * 2 * C->nv * kf) == hipSuccess;
     ok = ok && hipMalloc(&C->d_lam, sizeof(double) * (size_t)C->nblocks) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_scale, sizeof(double) * 2 * (size_t)C->nel) == hipSuccess;
     ok = ok && hipMalloc(&C->d_dt, sizeof(double) * 2) == hipSuccess;
     ok = ok && hipMalloc(&C->d_u1, sizeof(double) * nst) == hipSuccess;
     ok = ok && hipMalloc(&C->d_u2, sizeof(double) * nst) == hipSuccess;
@@ -1195,7 +1227,7 @@ int sedg_destroy(sedg_ctx *C)
     if (!C) return SEDG_OK;
     (void)hipDeviceSynchronize();
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr};
+    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr, C->d_scale};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;

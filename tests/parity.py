@@ -2,7 +2,7 @@
 oracle on the same seeded inputs and compare them.
 
 Tolerances (FP64 on both sides): one right-hand side within 1e-12 of the
-largest magnitude per conserved variable; states after 100 SSP-RK3 steps within
+largest right-hand-side magnitude over the conserved variables; states after 100 SSP-RK3 steps within
 1e-9.  Blending factors must agree exactly where they are clamped or snapped
 and within 1e-13 where they are continuous; a sub-element whose decision
 differs is accepted only if the oracle's pre-threshold quantity lies within
@@ -30,13 +30,23 @@ def say(*args):
 
 
 def rel_err(g, o):
-    """max_v ||g_v - o_v||_inf / ||o_v||_inf (per conserved variable)."""
-    out = 0.0
+    """||g - o||_inf / ||o||_inf with both norms taken over all conserved variables.
+
+    One scale for the whole state: several benchmark states have a conserved
+    variable whose right-hand side vanishes identically (the density of a blast at
+    rest, the spanwise momentum of the shear layer), and a per-variable ratio would
+    then divide rounding by rounding.  Variables whose right-hand side is at least
+    1e-3 of the largest are additionally held to 1e-10 of their own magnitude."""
+    o = np.asarray(o)
+    g = np.asarray(g)
+    smax = np.abs(o).max()
+    if smax == 0.0:
+        return np.abs(g).max()
     for v in range(o.shape[0]):
-        den = np.abs(o[v]).max()
-        num = np.abs(g[v] - o[v]).max()
-        out = max(out, num / den if den > 0 else num)
-    return out
+        sv = np.abs(o[v]).max()
+        if sv >= 1e-3 * smax:
+            assert np.abs(g[v] - o[v]).max() <= 1e-10 * sv, ("variable", v)
+    return np.abs(g - o).max() / smax
 
 
 def gpu_rhs(mesh, params, u, alpha_in=None):
