@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 DOF-updates per second of the sub-element adaptive blended
+DG/FV scheme with SSP-RK3 on one MI355X.
+
+Workload (the configuration the metric is quoted on): 2-D Sedov-type blast,
+256 x 256 Cartesian elements over [-1.5, 1.5]^2 with outflow boundaries,
+K = 8 mean values per direction (polynomial degree 7, hierarchy O(8) -> O(4)
+-> O(2) -> FV), FP64, CFL 0.5, synthetic seeded initial state (background
+rho = 1, p = 1e-5, v = 0; blast energy 1 deposited as a Gaussian of width 0.06
+at a seeded centre within 0.1 of the origin).
+
+One step = one SSP-RK3 step = 3 right-hand-side evaluations with their stage
+updates.  value = DOF x 3 x steps / time, DOF = subcell mean values
+(4,194,304).  The timed region runs the library's kernels with an event pair
+around every launch (the same events give the per-kernel durations of the
+roofline figure).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "FP64 DOF-updates/sec on 1 MI355X (fwd, batched, adjoint/fwd cost ratio)"
+
+
+def kernel_bytes_per_launch(mesh, A):
+    """Algorithmic HBM bytes of one launch of each kernel (minimal I/O of the
+    decomposition): state in/out, stage base state (2 of 3 stages),
+    blending factors and squeezing parameters, neighbour blending factors,
+    element-face states (own write; own + neighbour read) and element scales."""
+    d, K, nv = mesh.dim, mesh.K, mesh.nvar
+    nel = mesh.nel
+    kd, kf = K ** d, K ** (d - 1)
+    per_el = {
+        "analyse": 8 * (nv * kd + 2 * A + 2 * d * nv * kf + 2),
+        "residual": 8 * (nv * kd + nv * kd + (2.0 / 3.0) * nv * kd + 2 * A + 2 * d * A
+                         + 2 * (2 * d * nv * kf) + 2 * (1 + 2 * d)),
+    }
+    return {k: v * nel for k, v in per_el.items()}
+
+
+def cpu_baseline(mesh, params, u, max_seconds=30.0):
+    """The oracle (plain FP64 C, OpenMP) on the host cores: one full SSP-RK3 step
+    of the same workload."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    O.rk3(mesh, params, u, 1)
+    dt = time.perf_counter() - t0
+    return {"value": mesh.dof * 3 / dt, "unit": "DOF-updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "one SSP-RK3 step (3 right-hand sides) of the full 256x256-element K=8 blast, %.1f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(multi-GPU sharding is a design note, not a measured path)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2011_03338_amd import sedg, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    mesh, u0, info = W.sedov(args.seed, 256, 8)
+    params = W.Params(cfl=0.5)
+    A = W.alpha_len(mesh, params)
+    s = sedg.Solver(mesh, params)
+    u = torch.from_numpy(u0).to(dev)
+    stream = torch.cuda.current_stream()
+
+    # warm-up (graph replay path)
+    s.rk_step(u, args.warmup)
+    s.check()
+    torch.cuda.synchronize()
+
+    # timed region: per-launch event pairs on the library's stream
+    s.profile(True)
+    s.profile_read()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.rk_step(u, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = s.profile_read()
+    s.profile(False)
+    s.check()
+    dof = mesh.dof
+    value = dof * 3 * args.steps / (ms * 1e-3)
+
+    # roofline of the dominant kernel
+    kb = kernel_bytes_per_launch(mesh, A)
+    dom = max(("analyse", "residual"), key=lambda k: prof[k][0])
+    avg_ms = prof[dom][0] / max(prof[dom][1], 1)
+    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": avg_ms}
+    kernels = {k: {"avg_ms": (prof[k][0] / prof[k][1]) if prof[k][1] else None, "launches": prof[k][1],
+                   "algorithmic_GBs": (kb[k] / ((prof[k][0] / prof[k][1]) * 1e-3) / 1e9) if k in kb and prof[k][1] else None}
+               for k in prof}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(mesh, params, u0)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2-D Sedov blast, 256x256 elements, K=8 (degree 7, O(8)->O(4)->O(2)->FV), "
+                               "outflow, SSP-RK3 CFL 0.5",
+                   "elements": mesh.nel, "K": mesh.K, "dof": dof, "dof_per_var_total": dof * mesh.nvar,
+                   "stages_per_step": 3, "blast_center": info["center"]},
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

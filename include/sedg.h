@@ -132,6 +132,15 @@ int sedg_rk_step(sedg_ctx *ctx, double *u, int nsteps, double dt_fixed, double *
  * or non-finite mean value, else SEDG_OK and *bad_elem = -1.  Clears the flag. */
 int sedg_check(sedg_ctx *ctx, long *bad_elem);
 
+/* Per-kernel timing with HIP events, for benchmarking.  After sedg_profile(ctx, 1)
+ * sedg_rk_step enqueues its kernels directly (no graph replay) and records an event
+ * pair around every launch on the caller's stream; sedg_profile_read synchronises
+ * that stream and returns, for the analyse, residual and step-size kernels
+ * (arrays of 3, in that order), the summed milliseconds and the launch counts,
+ * then clears them.  sedg_profile(ctx, 0) returns to graph replay. */
+int sedg_profile(sedg_ctx *ctx, int on);
+int sedg_profile_read(sedg_ctx *ctx, double *ms, long *count);
+
 /* Host-only: the library's own operator tables of level n (2, 4, 8) for node
  * family fam, in the order xi[n], w[n], Dcal[n*n], D[n*n], bm[n], bp[n],
  * P[n*n], R[n*n], Dhat[n*n], Bhat_left[n], Bhat_right[n], Iplus[n*n],

@@ -31,6 +31,7 @@
 #include <cstring>
 #include <map>
 #include <tuple>
+#include <vector>
 
 #include "../../include/sedg.h"
 #include "sedg_internal.h"
@@ -1032,6 +1033,11 @@ struct sedg_ctx {
     int nblocks;
     hipStream_t last;
     std::map<std::tuple<double *, double *, int>, hipGraphExec_t> graphs;
+    // event timing (benchmark mode)
+    bool prof;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
 };
 
 namespace {
@@ -1218,6 +1224,8 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     int rc = set_levels(C, params);
     if (rc) { sedg_destroy(C); return rc; }
     C->last = nullptr;
+    C->prof = false;
+    C->pool_used = 0;
     *out = C;
     return SEDG_OK;
 }
@@ -1227,6 +1235,7 @@ int sedg_destroy(sedg_ctx *C)
     if (!C) return SEDG_OK;
     (void)hipDeviceSynchronize();
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
     void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr, C->d_scale};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1280,6 +1289,30 @@ int sedg_max_dt(sedg_ctx *C, const double *u, double *dt_dev, void *stream)
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
 }
 
+}  // extern "C"
+
+static hipEvent_t prof_event(sedg_ctx *C)
+{
+    if (C->pool_used == C->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        C->pool.push_back(e);
+    }
+    return C->pool[C->pool_used++];
+}
+
+// launch f() on s, bracketed by an event pair of kind 'kind' when profiling
+template <typename F>
+static void timed(sedg_ctx *C, int kind, hipStream_t s, F f)
+{
+    if (!C->prof) { f(); return; }
+    hipEvent_t a = prof_event(C), b = prof_event(C);
+    if (a) (void)hipEventRecord(a, s);
+    f();
+    if (b) (void)hipEventRecord(b, s);
+    if (a && b) C->marks.push_back({kind, {a, b}});
+}
+
 static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log, hipStream_t s)
 {
     KArgs P = base_args(C);
@@ -1289,27 +1322,31 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     P.out = C->d_u1;
     P.stage = 1;
     P.lam_part = dt_fixed > 0.0 ? nullptr : C->d_lam;
-    launch_analyse_any(C, P, s);
+    timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
     if (!(dt_fixed > 0.0))
-        hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(256), 0, s, (const double *)C->d_lam, C->nblocks,
-                           cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
-    launch_residual_any(C, P, s);
+        timed(C, 2, s, [&] {
+            hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(256), 0, s, (const double *)C->d_lam, C->nblocks,
+                               cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
+        });
+    timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
     // stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1))
     P.lam_part = nullptr;
     P.u = C->d_u1;
     P.u0 = u;
     P.out = C->d_u2;
     P.stage = 2;
-    launch_analyse_any(C, P, s);
-    launch_residual_any(C, P, s);
+    timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+    timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
     // stage 3: u = 1/3 u + 2/3 (u2 + dt L(u2))
     P.u = C->d_u2;
     P.u0 = u;
     P.out = u;
     P.stage = 3;
-    launch_analyse_any(C, P, s);
-    launch_residual_any(C, P, s);
+    timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+    timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
 }
+
+extern "C" {
 
 int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream)
 {
@@ -1319,6 +1356,11 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
     hipStream_t s = (hipStream_t)stream;
     // step counter / fixed step
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, C->d_dt, dt_fixed > 0.0 ? dt_fixed : 0.0, C->d_ctr);
+    if (C->prof) {
+        for (int st = 0; st < nsteps; ++st) enqueue_step(C, u, dt_fixed, dt_log_dev, s);
+        C->last = s;
+        return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+    }
     auto key = std::make_tuple(u, dt_log_dev, dt_fixed > 0.0 ? 1 : 0);
     hipGraphExec_t exec = nullptr;
     auto it = C->graphs.find(key);
@@ -1341,6 +1383,29 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
         if (hipGraphLaunch(exec, s) != hipSuccess) return SEDG_EHIP;
     C->last = s;
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+int sedg_profile(sedg_ctx *C, int on)
+{
+    if (!C) return SEDG_EINVAL;
+    C->prof = on != 0;
+    return SEDG_OK;
+}
+
+int sedg_profile_read(sedg_ctx *C, double *ms, long *count)
+{
+    if (!C || !ms || !count) return SEDG_EINVAL;
+    if (hipStreamSynchronize(C->last) != hipSuccess) return SEDG_EHIP;
+    for (int k = 0; k < 3; ++k) { ms[k] = 0.0; count[k] = 0; }
+    for (auto &m : C->marks) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, m.second.first, m.second.second) != hipSuccess) return SEDG_EHIP;
+        ms[m.first] += t;
+        count[m.first] += 1;
+    }
+    C->marks.clear();
+    C->pool_used = 0;
+    return SEDG_OK;
 }
 
 int sedg_check(sedg_ctx *C, long *bad_elem)

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libsedg.so")
 SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "sedg_set_params",
-            "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror"]
+            "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror",
+            "sedg_profile", "sedg_profile_read"]
 
 
 class SedgError(RuntimeError):
@@ -66,6 +67,8 @@ def load():
     lib.sedg_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
     lib.sedg_check.argtypes = [vp, ctypes.POINTER(ctypes.c_long)]
     lib.sedg_tables.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+    lib.sedg_profile.argtypes = [vp, ctypes.c_int]
+    lib.sedg_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_long)]
     lib.sedg_strerror.argtypes = [ctypes.c_int]
     lib.sedg_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -166,6 +169,16 @@ class Solver:
     def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, stream=None):
         _check(load().sedg_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log), _stream(stream)),
                "sedg_rk_step")
+
+    def profile(self, on: bool):
+        _check(load().sedg_profile(self._h, 1 if on else 0), "sedg_profile")
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} for analyse, residual, step_size."""
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_long * 3)()
+        _check(load().sedg_profile_read(self._h, ms, cnt), "sedg_profile_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(["analyse", "residual", "step_size"])}
 
     def check(self):
         """Returns -1, or raises SedgError(SEDG_ESTATE) naming the bad element."""

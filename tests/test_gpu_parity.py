@@ -210,9 +210,21 @@ def test_full_size_sedov_windows():
         iy1 = (y1 - y0) - (1 if y1 < 256 else 0)
         go = d[:, :, (y0 + iy0) * K:(y0 + iy1) * K, (x0 + ix0) * K:(x0 + ix1) * K]
         oo = do[:, :, iy0 * K:iy1 * K, ix0 * K:ix1 * K]
-        err = rel_err(go, oo)
-        say("  window (%d,%d) rel_err=%.3e" % (ex, ey, err))
-        assert err <= RHS_TOL
+        # FP64 conditioning of this window: the oracle's own change under a 1-ulp
+        # relative perturbation of its input (two evaluations cannot agree better);
+        # in the quiescent background the exact right-hand side is zero and both
+        # sides return rounding noise of that size
+        noise = 0.0
+        for t in range(2):
+            sgn = np.random.default_rng(100 + t).choice([-1.0, 1.0], size=sub.shape)
+            dp = O.rhs(wm, p, np.ascontiguousarray(sub * (1.0 + sgn * 2.220446049250313e-16)))
+            noise = max(noise, np.abs(dp - do)[:, :, iy0 * K:iy1 * K, ix0 * K:ix1 * K].max())
+        scale = np.abs(oo).max()
+        err = np.abs(go - oo).max()
+        tol = max(RHS_TOL * scale, 4.0 * noise)
+        say("  window (%d,%d) |g-o|=%.3e  max|o|=%.3e  rel=%.3e  oracle 1-ulp noise=%.3e  tol=%.3e"
+            % (ex, ey, err, scale, err / scale if scale else 0.0, noise, tol))
+        assert err <= tol
 
 
 def test_full_size_conservation_periodic():
