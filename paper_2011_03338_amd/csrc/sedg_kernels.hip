@@ -51,6 +51,7 @@ struct KArgs {
     const double *alpha_in; // EXTERNAL mode
     double *fbuf;           // face buffer
     double *scale;          // nel * 2: largest mean density and |mean energy| per element
+    double *mean;           // nel * NV * A: sub-element means per level
     const sedg_level_tab *tabs;  // per level index
     double *lam_part;       // per-block CFL eigenvalue maxima (nullable)
     const double *dt;       // device scalar step (RK stages)
@@ -532,6 +533,7 @@ analyse_kernel(KArgs P)
                 if (act) {
                     P.alpha[(long long)e * P.A + P.lev_off[li] + s] = al[li];
                     P.beta[(long long)e * P.A + P.lev_off[li] + s] = beta[li];
+                    for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * P.A + P.lev_off[li] + s] = mean[li][v];
                 }
             }
         }
@@ -577,19 +579,32 @@ analyse_kernel(KArgs P)
 // ---------------------------------------------------------------------------
 // residual kernel
 // ---------------------------------------------------------------------------
+//
+// Per element: (1) weights of every cell from the element's alpha; (2) unique
+// common fluxes on the faces some level uses - the element faces always, an
+// interior subcell face only when the FV level or a DG level whose sub-element
+// boundary contains it is active - processed K faces per round, one lane per
+// face subcell; (3) the FV part, then for each active DG level the squeezed
+// reconstruction, nodal fluxes, Dhat along the flux axis, P along the others
+// and the Bhat surface term; (4) blend and store (SSP-RK3 stage fused).
+// In 3-D the flux buffer holds one axis at a time (LDS budget), so the
+// reconstruction is repeated per axis; in 2-D all axes are held.
 
 template <int DIM, int K, int EPB>
 struct ResidualSmem {
     typedef Geo<DIM, K> G;
+    static constexpr bool AXO = (DIM == 3);
+    static constexpr int NAX = AXO ? 1 : DIM;
     double u[EPB][G::NV][G::KD];
-    double F[EPB][G::NV][(K + 1) * G::KF];   // common fluxes along the current axis
-    double sp[EPB][G::NV][G::KD];            // side states (+) / recon ping
-    double sm[EPB][G::NV][G::KD];            // side states (-) / recon pong
-    double fn[EPB][G::NV][G::KD];            // nodal face fluxes / flux temp
-    double th[EPB][MAXLEV + 1][G::KD];       // weights of every cell
-    double x[EPB * G::KD];
-    int ix[EPB * G::KD];
-    double nal[EPB][2 * DIM][64 + 8 + 1];    // neighbour alpha
+    double F[EPB][NAX][G::NV][(K + 1) * G::KF];
+    double nod[EPB][G::NV][G::KD];
+    double tmp[EPB][G::NV][G::KD];
+    double th[EPB][MAXLEV + 1][G::KD];
+    double mean[EPB][G::NV][73];
+    double be[EPB][73];
+    double nal[EPB][2 * DIM][73];
+    double wsL[EPB * G::KD], wsR[EPB * G::KD];
+    int act[EPB][MAXLEV + 1];
 };
 
 // theta of the cell across an element face, from the neighbour's alpha
@@ -601,13 +616,42 @@ __device__ __forceinline__ void theta_cell_of(const double *al, const KArgs &P, 
     theta_from_alpha(al, P, sidx, th);
 }
 
+// is interior face k (1..K-1) used by some active level of the element?
+__device__ __forceinline__ bool face_needed(const KArgs &P, const int *act, int k)
+{
+    if (act[0]) return true;
+    for (int li = 0; li < P.nlev; ++li)
+        if (act[1 + li] && (k % P.lev_n[li]) == 0) return true;
+    return false;
+}
+
+// the fidx-th needed face of axes [a0, a1): element faces first, then interior ones
+template <int K>
+__device__ __forceinline__ int face_at(const KArgs &P, const int *act, int a0, int a1, int fidx, int *fa, int *fk)
+{
+    int cnt = 0;
+    for (int a = a0; a < a1; ++a)
+        for (int s = 0; s < 2; ++s) {
+            if (cnt == fidx) { *fa = a; *fk = s ? K : 0; }
+            ++cnt;
+        }
+    for (int a = a0; a < a1; ++a)
+        for (int k = 1; k < K; ++k)
+            if (face_needed(P, act, k)) {
+                if (cnt == fidx) { *fa = a; *fk = k; }
+                ++cnt;
+            }
+    return cnt;
+}
+
 template <int DIM, int K, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
 residual_kernel(KArgs P)
 {
     typedef Geo<DIM, K> G;
+    typedef ResidualSmem<DIM, K, EPB> SM;
     constexpr int NV = G::NV, KD = G::KD, KF = G::KF;
-    __shared__ ResidualSmem<DIM, K, EPB> S;
+    __shared__ SM S;
     const int tid = threadIdx.x;
     const int le = tid / KD, c = tid % KD;
     const int e = blockIdx.x * EPB + le;
@@ -624,7 +668,10 @@ residual_kernel(KArgs P)
         S.u[le][v][c] = ub[v];
     }
     const double *al = P.alpha + (long long)ee * P.A;
-    const double *be = P.beta + (long long)ee * P.A;
+    for (int q = c; q < P.A; q += KD) {
+        S.be[le][q] = P.beta[(long long)ee * P.A + q];
+        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * P.A + q];
+    }
     int nb[3][2];
     for (int a = 0; a < 3; ++a) nb[a][0] = nb[a][1] = -1;
     for (int a = 0; a < DIM; ++a)
@@ -633,257 +680,222 @@ residual_kernel(KArgs P)
             int src = nb[a][sd] >= 0 ? nb[a][sd] : ee;
             for (int q = c; q < P.A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * P.A + q];
         }
-    const double own_sr = P.scale[2 * (long long)ee], own_se = P.scale[2 * (long long)ee + 1];
     int sidx[MAXLEV];
     subidx_all<DIM, K>(c, P, sidx);
     double th[MAXLEV + 1];
     theta_from_alpha(al, P, sidx, th);
     for (int l = 0; l <= P.nlev; ++l) S.th[le][l][c] = th[l];
-    double beta[MAXLEV];
-    double mean[MAXLEV][NV];
-    for (int li = 0; li < P.nlev; ++li) {
-        beta[li] = be[P.lev_off[li] + sidx[li]];
-        int n = P.lev_n[li], ln = ilog2i(n);
-        double nd = (DIM == 2) ? n * n : n * n * n;
-        for (int v = 0; v < NV; ++v) mean[li][v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+    // active levels of the element (any cell with a nonzero weight)
+    {
+        int flags = 0;
+        for (int l = 0; l <= P.nlev; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
+        flags = subreduce<DIM, K>(flags, G::LOGK, (int *)S.wsL, OpOr());
+        if (c == 0)
+            for (int l = 0; l <= MAXLEV; ++l) S.act[le][l] = (flags >> l) & 1;
     }
+    const double own_sr = P.scale[2 * (long long)ee], own_se = P.scale[2 * (long long)ee + 1];
     __syncthreads();
+    int actv[MAXLEV + 1];
+    for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
 
+    double out[NV];
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
     double rfv[NV];
-    double lr[MAXLEV][NV];
     for (int v = 0; v < NV; ++v) rfv[v] = 0.0;
+    double lr[MAXLEV][NV];
     for (int li = 0; li < MAXLEV; ++li)
         for (int v = 0; v < NV; ++v) lr[li][v] = 0.0;
 
-    for (int a = 0; a < DIM; ++a) {
-        const int st = G::stride(a);
-        const int pos = G::coord(c, a);
-        const int tr = G::trans(c, a);
-        // blended interface states of this cell on both sides along a
-        {
-            double sp[NV], sm[NV];
-            for (int v = 0; v < NV; ++v) { sp[v] = th[0] * ub[v]; sm[v] = th[0] * ub[v]; }
-            for (int li = 0; li < P.nlev; ++li) {
-                if (th[1 + li] == 0.0) continue;
-                const sedg_level_tab &T = P.tabs[li];
-                int n = P.lev_n[li];
-                double b = beta[li];
-                for (int v = 0; v < NV; ++v) {
-                    double tp = bapply<DIM, K>(S.u[le][v], c, a, n, T.Ep);
-                    double tm = bapply<DIM, K>(S.u[le][v], c, a, n, T.Em);
-                    sp[v] += th[1 + li] * ((1.0 - b) * mean[li][v] + b * tp);
-                    sm[v] += th[1 + li] * ((1.0 - b) * mean[li][v] + b * tm);
-                }
-            }
-            for (int v = 0; v < NV; ++v) { S.sp[le][v][c] = sp[v]; S.sm[le][v][c] = sm[v]; }
+    constexpr int NPASS = SM::AXO ? DIM : 1;
+    for (int pass = 0; pass < NPASS; ++pass) {
+        const int a0 = SM::AXO ? pass : 0, a1 = SM::AXO ? pass + 1 : DIM;
+        // ---------------- common fluxes on the needed faces of axes [a0, a1) ----------------
+        int dummy_a = 0, dummy_k = 0;
+        int nfaces = face_at<K>(P, actv, a0, a1, 1 << 30, &dummy_a, &dummy_k);
+        int nfmax = nfaces;
+        if (EPB > 1) {
+            S.wsL[tid] = (double)nfaces;
+            __syncthreads();
+            for (int q = 0; q < EPB; ++q) nfmax = max(nfmax, (int)S.wsL[q * KD]);
+            __syncthreads();
         }
-        __syncthreads();
-
-        // common fluxes: round 0 = face at the low side of each cell, round 1 = high element face
-        for (int rnd = 0; rnd < 2; ++rnd) {
-            const int k = pos + rnd;
-            const bool has = (rnd == 0) || (pos == K - 1);
+        const int slot = c / KF, t = c % KF;
+        for (int r0 = 0; r0 < nfmax; r0 += K) {
+            const int fidx = r0 + slot;
+            int fa = 0, k = 0;
+            const bool has = fidx < nfaces;
+            if (has) face_at<K>(P, actv, a0, a1, fidx, &fa, &k);
+            const int st = G::stride(fa);
             const bool lowface = (k == 0), highface = (k == K);
-            const int nbL = nb[a][0], nbR = nb[a][1];
-            // left / right states and weights at this face subcell
-            double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
-            // fallback means of the adjacent subcells
-            double mL[NV], mR[NV];
+            const int nbL = nb[fa][0], nbR = nb[fa][1];
+            double uL[NV], uR[NV], mL[NV], mR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
+            double srho = own_sr, sE = own_se;
             if (lowface) {
-                int cr = c;                                  // own cell (pos == 0)
-                int cl = G::from_trans(tr, a, K - 1);        // cell across in the low neighbour
+                int cr = G::from_trans(t, fa, 0), cl = G::from_trans(t, fa, K - 1);
                 for (int v = 0; v < NV; ++v) {
-                    uR[v] = P.fbuf[fb_index<DIM, K>(ee, a, 0, v, tr)];
-                    uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, a, 1, v, tr)] : uR[v];
+                    uR[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 0, v, t)];
+                    uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, fa, 1, v, t)] : uR[v];
                     mR[v] = S.u[le][v][cr];
                 }
                 for (int l = 0; l <= P.nlev; ++l) thR[l] = S.th[le][l][cr];
                 if (nbL >= 0) {
-                    theta_cell_of<DIM, K>(S.nal[le][2 * a + 0], P, cl, thL);
+                    theta_cell_of<DIM, K>(S.nal[le][2 * fa + 0], P, cl, thL);
                     int n3[3];
                     elem3(P, nbL, n3);
                     long long gl = gindex<DIM, K>(P, n3, cl);
                     for (int v = 0; v < NV; ++v) mL[v] = P.u[v * P.dof + gl];
+                    srho = fmax(P.scale[2 * (long long)nbL], own_sr);
+                    sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
                 } else {
                     for (int l = 0; l <= P.nlev; ++l) thL[l] = thR[l];
                     for (int v = 0; v < NV; ++v) mL[v] = mR[v];
                 }
             } else if (highface) {
-                int cl = c;                                  // own cell (pos == K-1)
-                int cr = G::from_trans(tr, a, 0);
+                int cl = G::from_trans(t, fa, K - 1), cr = G::from_trans(t, fa, 0);
                 for (int v = 0; v < NV; ++v) {
-                    uL[v] = P.fbuf[fb_index<DIM, K>(ee, a, 1, v, tr)];
-                    uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, a, 0, v, tr)] : uL[v];
+                    uL[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 1, v, t)];
+                    uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, fa, 0, v, t)] : uL[v];
                     mL[v] = S.u[le][v][cl];
                 }
                 for (int l = 0; l <= P.nlev; ++l) thL[l] = S.th[le][l][cl];
                 if (nbR >= 0) {
-                    theta_cell_of<DIM, K>(S.nal[le][2 * a + 1], P, cr, thR);
+                    theta_cell_of<DIM, K>(S.nal[le][2 * fa + 1], P, cr, thR);
                     int n3[3];
                     elem3(P, nbR, n3);
                     long long gr = gindex<DIM, K>(P, n3, cr);
                     for (int v = 0; v < NV; ++v) mR[v] = P.u[v * P.dof + gr];
+                    srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
+                    sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
                 } else {
                     for (int l = 0; l <= P.nlev; ++l) thR[l] = thL[l];
                     for (int v = 0; v < NV; ++v) mR[v] = mL[v];
                 }
             } else {
-                int cl = c - st, cr = c;
+                // interior face: blended interface states of the two adjacent cells
+                int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
+                for (int l = 0; l <= P.nlev; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
                 for (int v = 0; v < NV; ++v) {
-                    uL[v] = S.sp[le][v][cl];
-                    uR[v] = S.sm[le][v][cr];
                     mL[v] = S.u[le][v][cl];
                     mR[v] = S.u[le][v][cr];
+                    uL[v] = thL[0] * mL[v];
+                    uR[v] = thR[0] * mR[v];
                 }
-                for (int l = 0; l <= P.nlev; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
+                for (int li = 0; li < P.nlev; ++li) {
+                    const sedg_level_tab &T = P.tabs[li];
+                    int n = P.lev_n[li];
+                    if (thL[1 + li] != 0.0) {
+                        int s = G::subelem(cl, n);
+                        double b = S.be[le][P.lev_off[li] + s];
+                        for (int v = 0; v < NV; ++v) {
+                            double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
+                            uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * tr);
+                        }
+                    }
+                    if (thR[1 + li] != 0.0) {
+                        int s = G::subelem(cr, n);
+                        double b = S.be[le][P.lev_off[li] + s];
+                        for (int v = 0; v < NV; ++v) {
+                            double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
+                            uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * tr);
+                        }
+                    }
+                }
             }
-            double srho = own_sr, sE = own_se;
-            if (lowface && nbL >= 0) {
-                srho = fmax(P.scale[2 * (long long)nbL], own_sr);
-                sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
-            } else if (highface && nbR >= 0) {
-                srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
-                sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
-            }
-            // DG candidates level by level (uniform loop: the segment exchange needs barriers)
+            // DG candidates level by level: R along the face, HLLE at the face nodes, P back
             double thFV = 1.0;
+            double F[NV];
             double cand[MAXLEV][NV];
             double wdg[MAXLEV];
             for (int li = 0; li < P.nlev; ++li) {
-                const sedg_level_tab &T = P.tabs[li];
-                int n = P.lev_n[li], ln = ilog2i(n);
-                double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
-                bool need = has && (k % n == 0) && (tb != 0.0);
                 wdg[li] = 0.0;
-                // face segment of this level: face-plane cells of the same sub-element face
-                // nodal face states at my position: R along every transverse axis
+                // uniform skip: no element of the block has this level active on a needed face
+                if (!__syncthreads_or(has && (k % P.lev_n[li] == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+                    continue;
+                const sedg_level_tab &T = P.tabs[li];
+                const int n = P.lev_n[li], ln = ilog2i(n);
+                const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
+                const bool need = has && (k % n == 0) && (tb != 0.0);
                 double nl[NV], nr[NV];
-                int okf = 1;
-                if (need) {
-                    for (int v = 0; v < NV; ++v) { nl[v] = 0.0; nr[v] = 0.0; }
-                    if (DIM == 2) {
-                        int b = 1 - a;
-                        int sb = G::stride(b);
-                        int lo = G::coord(c, b) & (n - 1);
-                        int base = c - lo * sb;
-                        for (int m = 0; m < n; ++m) {
-                            int cm = base + m * sb;
-                            int tm = G::trans(cm, a);
-                            double Rm = T.R[lo * n + m];
-                            for (int v = 0; v < NV; ++v) {
-                                double xl, xr;
-                                if (lowface) {
-                                    xr = P.fbuf[fb_index<DIM, K>(ee, a, 0, v, tm)];
-                                    xl = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, a, 1, v, tm)] : xr;
-                                } else if (highface) {
-                                    xl = P.fbuf[fb_index<DIM, K>(ee, a, 1, v, tm)];
-                                    xr = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, a, 0, v, tm)] : xl;
-                                } else {
-                                    xl = S.sp[le][v][cm - st];
-                                    xr = S.sm[le][v][cm];
-                                }
-                                nl[v] += Rm * xl;
-                                nr[v] += Rm * xr;
-                            }
-                        }
-                    } else {
-                        int b0 = (a == 0) ? 1 : 0, b1 = (a == 2) ? 1 : 2;
-                        int s0 = G::stride(b0), s1 = G::stride(b1);
-                        int lo0 = G::coord(c, b0) & (n - 1), lo1 = G::coord(c, b1) & (n - 1);
-                        int base = c - lo0 * s0 - lo1 * s1;
-                        // R along b0 first, then along b1 (same order as a mode product chain)
-                        double tl[MAXN][NV], trr[MAXN][NV];
-                        for (int m1 = 0; m1 < n; ++m1) {
-                            for (int v = 0; v < NV; ++v) { tl[m1][v] = 0.0; trr[m1][v] = 0.0; }
-                            for (int m0 = 0; m0 < n; ++m0) {
-                                int cm = base + m0 * s0 + m1 * s1;
-                                int tm = G::trans(cm, a);
-                                double Rm = T.R[lo0 * n + m0];
-                                for (int v = 0; v < NV; ++v) {
-                                    double xl, xr;
-                                    if (lowface) {
-                                        xr = P.fbuf[fb_index<DIM, K>(ee, a, 0, v, tm)];
-                                        xl = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, a, 1, v, tm)] : xr;
-                                    } else if (highface) {
-                                        xl = P.fbuf[fb_index<DIM, K>(ee, a, 1, v, tm)];
-                                        xr = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, a, 0, v, tm)] : xl;
-                                    } else {
-                                        xl = S.sp[le][v][cm - st];
-                                        xr = S.sm[le][v][cm];
-                                    }
-                                    tl[m1][v] += Rm * xl;
-                                    trr[m1][v] += Rm * xr;
-                                }
-                            }
-                        }
-                        for (int m1 = 0; m1 < n; ++m1) {
-                            double Rm = T.R[lo1 * n + m1];
-                            for (int v = 0; v < NV; ++v) { nl[v] += Rm * tl[m1][v]; nr[v] += Rm * trr[m1][v]; }
-                        }
-                    }
-                    okf = (flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0;
+                const int sbase = slot * KF;
+                int lo0, lo1 = 0, tb0, tb1 = 0;
+                if (DIM == 2) { lo0 = t & (n - 1); tb0 = t - lo0; }
+                else {
+                    int t0 = t & (K - 1), t1 = t >> G::LOGK;
+                    lo0 = t0 & (n - 1); tb0 = t0 - lo0;
+                    lo1 = t1 & (n - 1); tb1 = t1 - lo1;
                 }
-                // segment-wide permissibility (transverse bits of the level-n block)
-                {
-                    int flag = need ? okf : 1;
-                    for (int bax = 0; bax < DIM; ++bax) {
-                        if (bax == a) continue;
-                        for (int bb = 0; bb < ln; ++bb) {
-                            int bit = bax * G::LOGK + bb;
-                            int mask = 1 << bit;
-                            if (bit < 6) {
-                                flag &= __shfl_xor(flag, mask, 64);
-                            } else {
-                                S.ix[tid] = flag;
-                                __syncthreads();
-                                flag &= S.ix[tid ^ mask];
-                                __syncthreads();
-                            }
-                        }
-                    }
-                    okf = flag;
-                }
-                double fnod[NV];
-                if (need && okf) hlle<DIM>(nl, nr, a, gam, fnod);
-                else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
-                for (int v = 0; v < NV; ++v) S.fn[le][v][c] = fnod[v];
-                __syncthreads();
-                if (need) {
-                    if (okf) {
-                        // P along the transverse axes back to face means
-                        for (int v = 0; v < NV; ++v) cand[li][v] = 0.0;
+                for (int v = 0; v < NV; ++v) {
+                    S.wsL[le * KD + c] = uL[v];
+                    S.wsR[le * KD + c] = uR[v];
+                    __syncthreads();
+                    double sl = 0.0, sr = 0.0;
+                    if (need) {
                         if (DIM == 2) {
-                            int b = 1 - a;
-                            int sb = G::stride(b);
-                            int lo = G::coord(c, b) & (n - 1);
-                            int base = c - lo * sb;
                             for (int m = 0; m < n; ++m) {
-                                double Pm = T.P[lo * n + m];
-                                for (int v = 0; v < NV; ++v) cand[li][v] += Pm * S.fn[le][v][base + m * sb];
+                                double Rm = T.R[lo0 * n + m];
+                                sl += Rm * S.wsL[le * KD + sbase + tb0 + m];
+                                sr += Rm * S.wsR[le * KD + sbase + tb0 + m];
                             }
                         } else {
-                            int b0 = (a == 0) ? 1 : 0, b1 = (a == 2) ? 1 : 2;
-                            int s0 = G::stride(b0), s1 = G::stride(b1);
-                            int lo0 = G::coord(c, b0) & (n - 1), lo1 = G::coord(c, b1) & (n - 1);
-                            int base = c - lo0 * s0 - lo1 * s1;
                             for (int m1 = 0; m1 < n; ++m1) {
-                                double tv[NV];
-                                for (int v = 0; v < NV; ++v) tv[v] = 0.0;
+                                double al0 = 0.0, ar0 = 0.0;
                                 for (int m0 = 0; m0 < n; ++m0) {
-                                    double Pm = T.P[lo0 * n + m0];
-                                    for (int v = 0; v < NV; ++v) tv[v] += Pm * S.fn[le][v][base + m0 * s0 + m1 * s1];
+                                    double Rm = T.R[lo0 * n + m0];
+                                    int q = sbase + (tb0 + m0) + K * (tb1 + m1);
+                                    al0 += Rm * S.wsL[le * KD + q];
+                                    ar0 += Rm * S.wsR[le * KD + q];
                                 }
-                                double Pm1 = T.P[lo1 * n + m1];
-                                for (int v = 0; v < NV; ++v) cand[li][v] += Pm1 * tv[v];
+                                double Rm1 = T.R[lo1 * n + m1];
+                                sl += Rm1 * al0;
+                                sr += Rm1 * ar0;
                             }
                         }
-                        wdg[li] = tb;
-                        thFV -= tb;
                     }
+                    nl[v] = sl;
+                    nr[v] = sr;
+                    __syncthreads();
                 }
-                __syncthreads();
+                int okf = need ? ((flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0) : 1;
+                // segment-wide admissibility (transverse bits of the level-n block of this face)
+                for (int q = 0; q < DIM - 1; ++q)
+                    for (int bb = 0; bb < ln; ++bb) {
+                        int bit = q * G::LOGK + bb;
+                        int mask = 1 << bit;
+                        if (bit < 6) okf &= __shfl_xor(okf, mask, 64);
+                        else {
+                            ((int *)S.wsL)[tid] = okf;
+                            __syncthreads();
+                            okf &= ((int *)S.wsL)[tid ^ mask];
+                            __syncthreads();
+                        }
+                    }
+                double fnod[NV];
+                if (need && okf) hlle<DIM>(nl, nr, fa, gam, fnod);
+                else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
+                for (int v = 0; v < NV; ++v) {
+                    S.wsL[le * KD + c] = fnod[v];
+                    __syncthreads();
+                    double sacc = 0.0;
+                    if (need && okf) {
+                        if (DIM == 2) {
+                            for (int m = 0; m < n; ++m) sacc += T.P[lo0 * n + m] * S.wsL[le * KD + sbase + tb0 + m];
+                        } else {
+                            for (int m1 = 0; m1 < n; ++m1) {
+                                double a0s = 0.0;
+                                for (int m0 = 0; m0 < n; ++m0)
+                                    a0s += T.P[lo0 * n + m0] * S.wsL[le * KD + sbase + (tb0 + m0) + K * (tb1 + m1)];
+                                sacc += T.P[lo1 * n + m1] * a0s;
+                            }
+                        }
+                    }
+                    cand[li][v] = sacc;
+                    __syncthreads();
+                }
+                if (need && okf) {
+                    wdg[li] = tb;
+                    thFV -= tb;
+                }
             }
-            double F[NV];
             for (int v = 0; v < NV; ++v) F[v] = 0.0;
             if (has) {
                 if (thFV != 0.0) {
@@ -891,68 +903,77 @@ residual_kernel(KArgs P)
                     for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
                     if (!flux_admissible<DIM>(aL, gam, srho, sE)) for (int v = 0; v < NV; ++v) aL[v] = mL[v];
                     if (!flux_admissible<DIM>(aR, gam, srho, sE)) for (int v = 0; v < NV; ++v) aR[v] = mR[v];
-                    hlle<DIM>(aL, aR, a, gam, fs);
+                    hlle<DIM>(aL, aR, fa, gam, fs);
                     for (int v = 0; v < NV; ++v) F[v] = thFV * fs[v];
                 }
                 for (int li = 0; li < P.nlev; ++li)
                     if (wdg[li] != 0.0)
                         for (int v = 0; v < NV; ++v) F[v] += wdg[li] * cand[li][v];
-                for (int v = 0; v < NV; ++v) S.F[le][v][k * KF + tr] = F[v];
+                const int axs = SM::AXO ? 0 : fa;
+                for (int v = 0; v < NV; ++v) S.F[le][axs][v][k * KF + t] = F[v];
             }
         }
         __syncthreads();
 
-        // FV part: -(K/dx_a) (F_{i+1/2} - F_{i-1/2})
-        {
-            double sc = K / P.dx[a];
-            for (int v = 0; v < NV; ++v)
-                rfv[v] -= sc * (S.F[le][v][(pos + 1) * KF + tr] - S.F[le][v][pos * KF + tr]);
-        }
-        // DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat)
+        // ---------------- FV part: -(K/dx_a) (F_{i+1/2} - F_{i-1/2}) ----------------
+        if (th[0] != 0.0)
+            for (int a = a0; a < a1; ++a) {
+                const int axs = SM::AXO ? 0 : a;
+                const int pos = G::coord(c, a), tr = G::trans(c, a);
+                double sc = K / P.dx[a];
+                for (int v = 0; v < NV; ++v)
+                    rfv[v] -= sc * (S.F[le][axs][v][(pos + 1) * KF + tr] - S.F[le][axs][v][pos * KF + tr]);
+            }
+
+        // ---------------- DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat) ----------------
         for (int li = 0; li < P.nlev; ++li) {
+            if (!__syncthreads_or(actv[1 + li])) continue;
             const sedg_level_tab &T = P.tabs[li];
-            int n = P.lev_n[li];
-            bool on = th[1 + li] != 0.0;
-            // squeezed reconstruction at this cell's node (sp/sm reused as ping-pong)
-            double (*A0)[KD] = S.sp[le];
-            double (*A1)[KD] = S.sm[le];
+            const int n = P.lev_n[li];
+            const bool on = th[1 + li] != 0.0;
+            // squeezed reconstruction at this cell's node
             double nodal[NV];
             if (DIM == 2) {
-                if (on) for (int v = 0; v < NV; ++v) A0[v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
                 __syncthreads();
-                if (on) for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(A0[v], c, 1, n, T.R);
+                for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(S.tmp[le][v], c, 1, n, T.R);
             } else {
-                if (on) for (int v = 0; v < NV; ++v) A0[v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+                for (int v = 0; v < NV; ++v) S.nod[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
                 __syncthreads();
-                if (on) for (int v = 0; v < NV; ++v) A1[v][c] = bapply<DIM, K>(A0[v], c, 1, n, T.R);
+                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.nod[le][v], c, 1, n, T.R);
                 __syncthreads();
-                if (on) for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(A1[v], c, 2, n, T.R);
+                for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(S.tmp[le][v], c, 2, n, T.R);
             }
-            if (on) {
-                double b = beta[li];
-                for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * mean[li][v] + b * nodal[v];
+            {
+                int s = sidx[li];
+                double b = S.be[le][P.lev_off[li] + s];
+                for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * nodal[v];
+            }
+            for (int a = a0; a < a1; ++a) {
+                const int axs = SM::AXO ? 0 : a;
                 double f[NV];
                 euler_flux<DIM>(nodal, a, gam, f);
-                for (int v = 0; v < NV; ++v) S.fn[le][v][c] = f[v];
-            }
-            __syncthreads();
-            double vol[NV];
-            if (on) for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(S.fn[le][v], c, a, n, T.Dhat);
-            // P along the other axes in increasing order
-            for (int bax = 0; bax < DIM; ++bax) {
-                if (bax == a) continue;
                 __syncthreads();
-                if (on) for (int v = 0; v < NV; ++v) A0[v][c] = vol[v];
+                for (int v = 0; v < NV; ++v) S.nod[le][v][c] = f[v];
                 __syncthreads();
-                if (on) for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(A0[v], c, bax, n, T.P);
-            }
-            if (on) {
-                int lo = pos & (n - 1);
-                int kl = pos - lo, kr = kl + n;
-                double sc = K / (n * P.dx[a]);
-                for (int v = 0; v < NV; ++v) {
-                    double surf = T.Bhl[lo] * S.F[le][v][kl * KF + tr] + T.Bhr[lo] * S.F[le][v][kr * KF + tr];
-                    lr[li][v] += sc * (vol[v] - surf);
+                double vol[NV];
+                for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(S.nod[le][v], c, a, n, T.Dhat);
+                for (int bax = 0; bax < DIM; ++bax) {
+                    if (bax == a) continue;
+                    __syncthreads();
+                    for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = vol[v];
+                    __syncthreads();
+                    for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(S.tmp[le][v], c, bax, n, T.P);
+                }
+                if (on) {
+                    const int pos = G::coord(c, a), tr = G::trans(c, a);
+                    const int lo = pos & (n - 1);
+                    const int kl = pos - lo, kr = kl + n;
+                    const double sc = K / (n * P.dx[a]);
+                    for (int v = 0; v < NV; ++v) {
+                        double surf = T.Bhl[lo] * S.F[le][axs][v][kl * KF + tr] + T.Bhr[lo] * S.F[le][axs][v][kr * KF + tr];
+                        lr[li][v] += sc * (vol[v] - surf);
+                    }
                 }
             }
             __syncthreads();
@@ -960,8 +981,6 @@ residual_kernel(KArgs P)
     }
 
     // blend (eq. blending-weights) and store / RK stage
-    double out[NV];
-    for (int v = 0; v < NV; ++v) out[v] = 0.0;
     if (th[0] != 0.0)
         for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
     for (int li = 0; li < P.nlev; ++li)
@@ -1028,7 +1047,7 @@ struct sedg_ctx {
     int G[3];
     double dx[3];
     sedg_level_tab *d_tabs;
-    double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale;
+    double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale, *d_mean;
     int *d_err, *d_ctr;
     int nblocks;
     hipStream_t last;
@@ -1044,8 +1063,8 @@ namespace {
 
 int epb_for(int dim, int K)
 {
-    if (dim == 2) return K == 4 ? 16 : 4;
-    return K == 4 ? 4 : 1;
+    if (dim == 2) return K == 4 ? 4 : 1;
+    return 1;
 }
 
 bool supported(int dim, int K) { return (dim == 2 || dim == 3) && (K == 4 || K == 8); }
@@ -1053,7 +1072,7 @@ bool supported(int dim, int K) { return (dim == 2 || dim == 3) && (K == 4 || K =
 template <int DIM, int K>
 void launch_pair(const KArgs &P, int nblocks, hipStream_t s)
 {
-    constexpr int EPBv = (DIM == 2) ? (K == 4 ? 16 : 4) : (K == 4 ? 4 : 1);
+    constexpr int EPBv = (DIM == 2 && K == 4) ? 4 : 1;
     constexpr int threads = EPBv * Geo<DIM, K>::KD;
     hipLaunchKernelGGL((analyse_kernel<DIM, K, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
 }
@@ -1061,7 +1080,7 @@ void launch_pair(const KArgs &P, int nblocks, hipStream_t s)
 template <int DIM, int K>
 void launch_residual(const KArgs &P, int nblocks, hipStream_t s)
 {
-    constexpr int EPBv = (DIM == 2) ? (K == 4 ? 16 : 4) : (K == 4 ? 4 : 1);
+    constexpr int EPBv = (DIM == 2 && K == 4) ? 4 : 1;
     constexpr int threads = EPBv * Geo<DIM, K>::KD;
     hipLaunchKernelGGL((residual_kernel<DIM, K, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
 }
@@ -1092,6 +1111,7 @@ KArgs base_args(const sedg_ctx *C)
     P.beta = C->d_beta;
     P.fbuf = C->d_fbuf;
     P.scale = C->d_scale;
+    P.mean = C->d_mean;
     P.tabs = C->d_tabs;
     P.err = C->d_err;
     P.dof = C->dof;
@@ -1213,6 +1233,7 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     ok = ok && hipMalloc(&C->d_fbuf, sizeof(double) * (size_t)C->nel * mesh->dim * 2 * C->nv * kf) == hipSuccess;
     ok = ok && hipMalloc(&C->d_lam, sizeof(double) * (size_t)C->nblocks) == hipSuccess;
     ok = ok && hipMalloc(&C->d_scale, sizeof(double) * 2 * (size_t)C->nel) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_mean, sizeof(double) * (size_t)C->nel * C->nv * maxA) == hipSuccess;
     ok = ok && hipMalloc(&C->d_dt, sizeof(double) * 2) == hipSuccess;
     ok = ok && hipMalloc(&C->d_u1, sizeof(double) * nst) == hipSuccess;
     ok = ok && hipMalloc(&C->d_u2, sizeof(double) * nst) == hipSuccess;
@@ -1236,7 +1257,7 @@ int sedg_destroy(sedg_ctx *C)
     (void)hipDeviceSynchronize();
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
-    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr, C->d_scale};
+    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr, C->d_scale, C->d_mean};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
