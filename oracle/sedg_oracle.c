@@ -627,41 +627,48 @@ static double indicator(const ctx_t *c, int li, const double *us, const double *
     return alpha;
 }
 
-/* Per element: squeeze parameters of every level, blending factors by the
-   multi-level algorithm (App. sketch of the algorithm, multi-level):
-   levels from the top down; beta < beta_L gives alpha = 0, level 2 takes
-   alpha = beta, higher levels use the indicator on the unlimited data; if every
-   factor of a level exceeds alpha_H they are set to 1 and lower levels are not
-   visited; if every factor is below alpha_L they are set to 0. */
+/* Squeezing parameters of every sub-element of level index li. */
+static void squeeze_level(const ctx_t *c, const double *ub, int li, double *beta)
+{
+    int dim = c->dim, K = c->K;
+    double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK], mean[MAXV];
+    int n = c->lev_n[li], ns = K / n;
+    int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+    for (int s3 = 0; s3 < sz; s3++)
+        for (int s2 = 0; s2 < sy; s2++)
+            for (int s1 = 0; s1 < ns; s1++) {
+                int s = s1 + ns * (s2 + ns * s3);
+                gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                reconstruct(c, &c->L[li], us, ut);
+                beta[c->lev_off[li] + s] = squeeze_beta(c, &c->L[li], us, ut, mean);
+            }
+}
+
+/* Per element: blending factors by the multi-level algorithm (App. sketch of
+   the algorithm, multi-level): levels from the top down; beta < beta_L gives
+   alpha = 0, level 2 takes alpha = beta, higher levels use the indicator on the
+   unlimited data; if every factor of a level exceeds alpha_H they are set to 1
+   and lower levels are not visited; if every factor is below alpha_L they are
+   set to 0.  Squeezing parameters are evaluated on the levels the algorithm
+   visits (every level in EXTERNAL mode, the top level in FORCE_DG, none in
+   FORCE_FV) and reported as 1 on the others, whose weights are zero. */
 static void analyse_element(const ctx_t *c, const double *u, int e, double *alpha, double *beta,
                             const double *alpha_in, double *xraw, double *araw)
 {
-    int dim = c->dim, K = c->K, nv = c->nv;
+    int dim = c->dim, K = c->K;
     double ub[MAXV * MAXK * MAXK * MAXK];
     double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK];
-    double mean[MAXV];
     gather_elem(c, u, e, ub);
-    for (int q = 0; q < c->A; q++) { xraw[q] = NAN; araw[q] = NAN; }
-    for (int li = 0; li < c->nlev; li++) {
-        int n = c->lev_n[li], ns = K / n;
-        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
-        for (int s3 = 0; s3 < sz; s3++)
-            for (int s2 = 0; s2 < sy; s2++)
-                for (int s1 = 0; s1 < ns; s1++) {
-                    int s = s1 + ns * (s2 + ns * s3);
-                    gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
-                    reconstruct(c, &c->L[li], us, ut);
-                    beta[c->lev_off[li] + s] = squeeze_beta(c, &c->L[li], us, ut, mean);
-                }
-    }
+    for (int q = 0; q < c->A; q++) { xraw[q] = NAN; araw[q] = NAN; beta[q] = 1.0; alpha[q] = 0.0; }
     if (c->p.mode == OR_EXTERNAL) {
+        for (int li = 0; li < c->nlev; li++) squeeze_level(c, ub, li, beta);
         for (int q = 0; q < c->A; q++) alpha[q] = alpha_in[q];
         return;
     }
-    for (int q = 0; q < c->A; q++) alpha[q] = 0.0;
     if (c->p.mode == OR_FORCE_FV) return;
     if (c->p.mode == OR_FORCE_DG) {
         /* pure DG of the top level: alpha = 1 on every top-level sub-element (Sec. 2.5 remark) */
+        squeeze_level(c, ub, 0, beta);
         int cnt = c->nlev > 1 ? c->lev_off[1] : c->A;
         for (int q = 0; q < cnt; q++) alpha[q] = 1.0;
         return;
@@ -669,6 +676,7 @@ static void analyse_element(const ctx_t *c, const double *u, int e, double *alph
     int broke = 0;
     for (int li = 0; li < c->nlev && !broke; li++) {
         if (!level_enabled(c, li)) continue;
+        squeeze_level(c, ub, li, beta);
         int n = c->lev_n[li], ns = K / n;
         int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
         int cnt = ns * sy * sz, nhi = 0, nlo = 0;
@@ -698,7 +706,6 @@ static void analyse_element(const ctx_t *c, const double *u, int e, double *alph
             for (int s = 0; s < cnt; s++) al[s] = 0.0;
         }
     }
-    (void)nv;
 }
 
 /* Blending weights of local subcell (i,j,k) (eq. blending-weights):
@@ -952,7 +959,11 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
         wdg[li] = tb;
         thFV -= tb;
     }
+    /* accumulation order: DG candidates level by level from the top, then the FV candidate */
     for (int v = 0; v < nv; v++) F[v] = 0.0;
+    for (int li = 0; li < c->nlev; li++)
+        if (wdg[li] != 0.0)
+            for (int v = 0; v < nv; v++) F[v] += wdg[li] * Fdg[li][v];
     if (thFV != 0.0) {
         double aL[MAXV], aR[MAXV], fs[MAXV];
         memcpy(aL, uL, sizeof(aL));
@@ -966,11 +977,8 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
             if (nfb) (*nfb)++;
         }
         hlle(dim, g, a, aL, aR, fs);
-        for (int v = 0; v < nv; v++) F[v] = thFV * fs[v];
+        for (int v = 0; v < nv; v++) F[v] += thFV * fs[v];
     }
-    for (int li = 0; li < c->nlev; li++)
-        if (wdg[li] != 0.0)
-            for (int v = 0; v < nv; v++) F[v] += wdg[li] * Fdg[li][v];
 }
 
 /* Pass 3, per element: level right-hand sides and their blend

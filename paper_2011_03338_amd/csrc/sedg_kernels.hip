@@ -293,20 +293,48 @@ __device__ __forceinline__ long long fb_index(int e, int a, int side, int v, int
 // ---------------------------------------------------------------------------
 // analyse kernel
 // ---------------------------------------------------------------------------
+//
+// Levels are visited as the multi-level algorithm descends (all levels in
+// EXTERNAL mode, the top level in FORCE_DG, none in FORCE_FV); the children's
+// reconstruction needed by the indicator of level n is the reconstruction of
+// level n/2, so every reconstruction is computed once.  Sub-element means and
+// the minima of the check set are reduced only on levels where some
+// sub-element fails the permissibility check (beta = 1 needs neither).
 
 template <int DIM, int K, int EPB>
 struct AnalyseSmem {
     typedef Geo<DIM, K> G;
     double u[EPB][G::NV][G::KD];
-    double r[EPB][G::LOGK][G::NV][G::KD];   // unlimited reconstruction per level index
+    double r[EPB][2][G::NV][G::KD];         // reconstructions of the current level and of its children
     double t[EPB][G::NV][G::KD];            // temporary
     double w[EPB][G::NV][G::KD];            // primitive variables
     double x[EPB * G::KD];                  // reduction exchange
     int ix[EPB * G::KD];
-    double al[EPB][64 + 8 + 1];             // alpha of the element (A <= 73)
-    double be[EPB][64 + 8 + 1];
     double lam[EPB * G::KD / 64 + 1];
+    double al[EPB][73];                     // per sub-element: blending factor,
+    double be[EPB][73];                     //   squeezing parameter,
+    double mean[EPB][G::NV][73];            //   mean value
 };
+
+// unlimited reconstruction of level li of every variable into dst: u x_1 R x_2 R (x_3 R)
+template <int DIM, int K, int EPB>
+__device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, EPB> &S, int le, int c, const sedg_level_tab &T, int n,
+                                            double (*dst)[Geo<DIM, K>::KD])
+{
+    constexpr int NV = Geo<DIM, K>::NV;
+    if (DIM == 2) {
+        for (int v = 0; v < NV; ++v) S.t[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+        __syncthreads();
+        for (int v = 0; v < NV; ++v) dst[v][c] = bapply<DIM, K>(S.t[le][v], c, 1, n, T.R);
+    } else {
+        for (int v = 0; v < NV; ++v) dst[v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+        __syncthreads();
+        for (int v = 0; v < NV; ++v) S.t[le][v][c] = bapply<DIM, K>(dst[v], c, 1, n, T.R);
+        __syncthreads();
+        for (int v = 0; v < NV; ++v) dst[v][c] = bapply<DIM, K>(S.t[le][v], c, 2, n, T.R);
+    }
+    __syncthreads();
+}
 
 template <int DIM, int K, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
@@ -352,7 +380,6 @@ analyse_kernel(KArgs P)
             }
         }
     }
-    __syncthreads();
     {
         double sr = subreduce<DIM, K>(ub[0], G::LOGK, S.x, OpMax());
         double se = subreduce<DIM, K>(fabs(ub[NV - 1]), G::LOGK, S.x, OpMax());
@@ -361,35 +388,38 @@ analyse_kernel(KArgs P)
             P.scale[2 * (long long)e + 1] = se;
         }
     }
+    __syncthreads();
 
-    // unlimited reconstructions of every level: u x_1 R x_2 R (x_3 R)
-    for (int li = 0; li < P.nlev; ++li) {
-        const sedg_level_tab &T = P.tabs[li];
-        int n = P.lev_n[li];
-        if (DIM == 2) {
-            for (int v = 0; v < NV; ++v) S.t[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
-            __syncthreads();
-            for (int v = 0; v < NV; ++v) S.r[le][li][v][c] = bapply<DIM, K>(S.t[le][v], c, 1, n, T.R);
-        } else {
-            for (int v = 0; v < NV; ++v) S.r[le][li][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
-            __syncthreads();
-            for (int v = 0; v < NV; ++v) S.t[le][v][c] = bapply<DIM, K>(S.r[le][li][v], c, 1, n, T.R);
-            __syncthreads();
-            for (int v = 0; v < NV; ++v) S.r[le][li][v][c] = bapply<DIM, K>(S.t[le][v], c, 2, n, T.R);
-        }
-        __syncthreads();
+    for (int q = c; q < P.A; q += KD) {
+        S.al[le][q] = (P.mode == SEDG_EXTERNAL) ? P.alpha_in[(long long)ee * P.A + q] : 0.0;
+        S.be[le][q] = 1.0;
+        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = 0.0;
     }
+    __syncthreads();
 
-    // squeezing parameter per level and sub-element; sub-element means
-    double mean[MAXLEV][NV];
-    double beta[MAXLEV];
+    int broke = 0;
+    int have_rec = -1;      // level index whose reconstruction sits in S.r[li & 1]
     for (int li = 0; li < P.nlev; ++li) {
+        const int n = P.lev_n[li], ln = ilog2i(n);
+        const bool enabled = (P.level_mask == 0) || ((P.level_mask >> ln) & 1u);
+        bool visit;
+        if (P.mode == SEDG_EXTERNAL) visit = true;
+        else if (P.mode == SEDG_FORCE_DG) visit = (li == 0);
+        else if (P.mode == SEDG_FORCE_FV) visit = false;
+        else visit = enabled && !broke;
+        if (!__syncthreads_or(visit)) {
+            if (P.mode != SEDG_ADAPTIVE || !__syncthreads_or(!broke)) break;
+            continue;
+        }
         const sedg_level_tab &T = P.tabs[li];
-        int n = P.lev_n[li], ln = ilog2i(n);
-        double nd = (DIM == 2) ? n * n : n * n * n;
-        for (int v = 0; v < NV; ++v) mean[li][v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+        if (have_rec != li) {
+            recon_level<DIM, K, EPB>(S, le, c, T, n, S.r[le][li & 1]);
+            have_rec = li;
+        }
+        double (*R0)[KD] = S.r[le][li & 1];
+        // ---- squeezing parameter (eq. calc-squeezing-parameter) ----
         double pt[NV];
-        for (int v = 0; v < NV; ++v) pt[v] = S.r[le][li][v][c];
+        for (int v = 0; v < NV; ++v) pt[v] = R0[v][c];
         double pp = pressure<DIM>(pt, gam);
         int ok = (pt[0] > 0.0 && pp > 0.0) ? 1 : 0;
         double rmin = pt[0], pmin = pp;
@@ -401,7 +431,7 @@ analyse_kernel(KArgs P)
                 int st = G::stride(a), base = c - lo * st;
                 for (int v = 0; v < NV; ++v) {
                     double s = 0.0;
-                    for (int m = 0; m < n; ++m) s += bv[m] * S.r[le][li][v][base + m * st];
+                    for (int m = 0; m < n; ++m) s += bv[m] * R0[v][base + m * st];
                     pt[v] = s;
                 }
                 double q = pressure<DIM>(pt, gam);
@@ -411,146 +441,121 @@ analyse_kernel(KArgs P)
             }
         }
         ok = subreduce<DIM, K>(ok, ln, S.ix, OpAnd());
-        rmin = subreduce<DIM, K>(rmin, ln, S.x, OpMin());
-        pmin = subreduce<DIM, K>(pmin, ln, S.x, OpMin());
         double b = 1.0;
-        if (!ok) {
-            double rmean = mean[li][0], pmean = pressure<DIM>(mean[li], gam);
-            double eps = fmin(1e-20, fmin(rmean, pmean));
-            double br = (rmean - rmin > 0.0) ? (rmean - eps) / (rmean - rmin) : 1.0;
-            double bq = (pmean - pmin > 0.0) ? (pmean - eps) / (pmean - pmin) : 1.0;
-            b = fmin(fmin(br, bq), 1.0);
+        const int sub = G::subelem(c, n);
+        const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
+        if (__syncthreads_or(visit && !ok)) {
+            double nd = (DIM == 2) ? n * n : n * n * n;
+            double mn[NV];
+            for (int v = 0; v < NV; ++v) mn[v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+            rmin = subreduce<DIM, K>(rmin, ln, S.x, OpMin());
+            pmin = subreduce<DIM, K>(pmin, ln, S.x, OpMin());
+            if (!ok) {
+                double rmean = mn[0], pmean = pressure<DIM>(mn, gam);
+                double eps = fmin(1e-20, fmin(rmean, pmean));
+                double br = (rmean - rmin > 0.0) ? (rmean - eps) / (rmean - rmin) : 1.0;
+                double bq = (pmean - pmin > 0.0) ? (pmean - eps) / (pmean - pmin) : 1.0;
+                b = fmin(fmin(br, bq), 1.0);
+            }
+            if (visit && leader)
+                for (int v = 0; v < NV; ++v) S.mean[le][v][P.lev_off[li] + sub] = mn[v];
         }
-        beta[li] = b;
-        int s = G::subelem(c, n);
-        int nsub = 1;
-        for (int a = 0; a < DIM; ++a) nsub *= K / n;
-        bool leader = (c == 0) || (G::coord(c, 0) % n == 0 && G::coord(c, 1) % n == 0 &&
-                                   (DIM == 2 || G::coord(c, 2) % n == 0));
-        if (leader) S.be[le][P.lev_off[li] + s] = b;
-        (void)nsub;
-    }
-
-    // blending factors
-    double al[MAXLEV];
-    for (int li = 0; li < P.nlev; ++li) al[li] = 0.0;
-    if (P.mode == SEDG_EXTERNAL) {
-        for (int li = 0; li < P.nlev; ++li) al[li] = P.alpha_in[(long long)ee * P.A + P.lev_off[li] + G::subelem(c, P.lev_n[li])];
-    } else if (P.mode == SEDG_FORCE_DG) {
-        al[0] = 1.0;
-    } else if (P.mode == SEDG_ADAPTIVE) {
-        int broke = 0;
-        for (int li = 0; li < P.nlev; ++li) {
-            if (!__syncthreads_or(!broke)) break;
-            int n = P.lev_n[li], ln = ilog2i(n);
-            bool enabled = (P.level_mask == 0) || ((P.level_mask >> ln) & 1u);
-            if (!enabled) continue;   // uniform across the block
-            double a = 0.0;
-            if (n == 2) {
-                a = (beta[li] < P.beta_L) ? 0.0 : beta[li];
-            } else {
-                const sedg_level_tab &T = P.tabs[li];
-                const sedg_level_tab &H = P.tabs[li + 1];
-                int h = n / 2;
-                // primitive variables at the level-n nodes
-                double pt[NV], wv[NV];
-                for (int v = 0; v < NV; ++v) pt[v] = S.r[le][li][v][c];
-                int bad = (pt[0] > 0.0) ? 0 : 1;
-                wv[0] = pt[0];
-                for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
-                wv[DIM + 1] = pressure<DIM>(pt, gam);
-                for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
-                __syncthreads();
-                double sn[NV], sh[NV];
-                {
-                    double wq = 1.0;
-                    for (int d = 0; d < DIM; ++d) wq *= T.w[G::coord(c, d) & (n - 1)];
-                    for (int v = 0; v < NV; ++v) {
-                        double s = 0.0;
-                        for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, n, T.Dcal));
-                        sn[v] = wq * s;
-                    }
-                }
-                __syncthreads();
-                // primitive variables at the level-n/2 nodes (the 2^dim children)
-                for (int v = 0; v < NV; ++v) pt[v] = S.r[le][li + 1][v][c];
-                bad |= (pt[0] > 0.0) ? 0 : 1;
-                wv[0] = pt[0];
-                for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
-                wv[DIM + 1] = pressure<DIM>(pt, gam);
-                for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
-                __syncthreads();
-                {
-                    double wq = (DIM == 2) ? 0.5 : 0.25;   // child measure in parent coordinates
-                    for (int d = 0; d < DIM; ++d) wq *= H.w[G::coord(c, d) & (h - 1)];
-                    for (int v = 0; v < NV; ++v) {
-                        double s = 0.0;
-                        for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, h, H.Dcal));
-                        sh[v] = wq * s;
-                    }
-                }
-                __syncthreads();
+        if (!visit) b = 1.0;
+        if (leader) S.be[le][P.lev_off[li] + sub] = b;
+        // children reconstruction = next level's reconstruction
+        const bool need_next = (li + 1 < P.nlev) &&
+                               (P.mode == SEDG_EXTERNAL || (P.mode == SEDG_ADAPTIVE && n >= 4));
+        if (__syncthreads_or(visit && need_next)) {
+            recon_level<DIM, K, EPB>(S, le, c, P.tabs[li + 1], n / 2, S.r[le][(li + 1) & 1]);
+            have_rec = li + 1;
+        }
+        if (P.mode != SEDG_ADAPTIVE) continue;
+        // ---- blending factor (eq. calc-blending-factor) ----
+        double a = 0.0;
+        if (n == 2) {
+            a = (b < P.beta_L) ? 0.0 : b;
+        } else {
+            const sedg_level_tab &H = P.tabs[li + 1];
+            double (*R1)[KD] = S.r[le][(li + 1) & 1];
+            const int h = n / 2;
+            double wv[NV];
+            for (int v = 0; v < NV; ++v) pt[v] = R0[v][c];
+            int bad = (pt[0] > 0.0) ? 0 : 1;
+            wv[0] = pt[0];
+            for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
+            wv[DIM + 1] = pressure<DIM>(pt, gam);
+            for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
+            __syncthreads();
+            double sn[NV], sh[NV];
+            {
+                double wq = 1.0;
+                for (int d = 0; d < DIM; ++d) wq *= T.w[G::coord(c, d) & (n - 1)];
                 for (int v = 0; v < NV; ++v) {
-                    sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
-                    sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
+                    double s = 0.0;
+                    for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, n, T.Dcal));
+                    sn[v] = wq * s;
                 }
-                bad = subreduce<DIM, K>(bad, ln, S.ix, OpOr());
-                double amin = 1.0;
-                int nonfin = 0;
+            }
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) pt[v] = R1[v][c];
+            bad |= (pt[0] > 0.0) ? 0 : 1;
+            wv[0] = pt[0];
+            for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
+            wv[DIM + 1] = pressure<DIM>(pt, gam);
+            for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
+            __syncthreads();
+            {
+                double wq = (DIM == 2) ? 0.5 : 0.25;   // child measure in parent coordinates
+                for (int d = 0; d < DIM; ++d) wq *= H.w[G::coord(c, d) & (h - 1)];
                 for (int v = 0; v < NV; ++v) {
-                    double den = fmax(fmax(sh[v], sn[v]), 1.0);
-                    double r = fabs(sn[v] - sh[v]) / den;
-                    double x = P.tau_A * (r - P.tau_S);
-                    if (!isfinite(x)) nonfin = 1;
-                    double cut = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
-                    amin = fmin(amin, 1.0 - cut);
+                    double s = 0.0;
+                    for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, h, H.Dcal));
+                    sh[v] = wq * s;
                 }
-                a = (bad || nonfin) ? 0.0 : amin;
-                if (beta[li] < P.beta_L) a = 0.0;
             }
-            if (broke) a = 0.0;
-            // level decision over the whole element
-            int hi = subreduce<DIM, K>((a > P.alpha_H) ? 1 : 0, G::LOGK, S.ix, OpAnd());
-            int lo = subreduce<DIM, K>((a < P.alpha_L) ? 1 : 0, G::LOGK, S.ix, OpAnd());
-            if (!broke) {
-                if (hi) { a = 1.0; broke = 1; }
-                else if (lo) a = 0.0;
-                al[li] = a;
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) {
+                sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
+                sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
             }
+            bad = subreduce<DIM, K>(bad, ln, S.ix, OpOr());
+            double amin = 1.0;
+            int nonfin = 0;
+            for (int v = 0; v < NV; ++v) {
+                double den = fmax(fmax(sh[v], sn[v]), 1.0);
+                double r = fabs(sn[v] - sh[v]) / den;
+                double x = P.tau_A * (r - P.tau_S);
+                if (!isfinite(x)) nonfin = 1;
+                double cut = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+                amin = fmin(amin, 1.0 - cut);
+            }
+            a = (bad || nonfin) ? 0.0 : amin;
+            if (b < P.beta_L) a = 0.0;
+        }
+        if (!visit) a = 0.0;
+        // level decision over the whole element (strict comparisons)
+        int hi = subreduce<DIM, K>((a > P.alpha_H) ? 1 : 0, G::LOGK, S.ix, OpAnd());
+        int lo = subreduce<DIM, K>((a < P.alpha_L) ? 1 : 0, G::LOGK, S.ix, OpAnd());
+        if (visit) {
+            if (hi) { a = 1.0; broke = 1; }
+            else if (lo) a = 0.0;
+            if (leader) S.al[le][P.lev_off[li] + sub] = a;
         }
     }
+    if (P.mode == SEDG_FORCE_DG)
+        for (int q = c; q < P.lev_off[1 < P.nlev ? 1 : 0] + (P.nlev > 1 ? 0 : P.A); q += KD) S.al[le][q] = 1.0;
     __syncthreads();
-    // publish alpha and beta; weights of this cell
-    {
-        bool leader0 = true;
-        for (int li = 0; li < P.nlev; ++li) {
-            int n = P.lev_n[li];
-            bool leader = (G::coord(c, 0) % n == 0) && (G::coord(c, 1) % n == 0) &&
-                          (DIM == 2 || G::coord(c, 2) % n == 0);
-            int s = G::subelem(c, n);
-            if (leader) {
-                S.al[le][P.lev_off[li] + s] = al[li];
-                if (act) {
-                    P.alpha[(long long)e * P.A + P.lev_off[li] + s] = al[li];
-                    P.beta[(long long)e * P.A + P.lev_off[li] + s] = beta[li];
-                    for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * P.A + P.lev_off[li] + s] = mean[li][v];
-                }
-            }
+    // publish alpha, beta and the sub-element means (coalesced)
+    if (act)
+        for (int q = c; q < P.A; q += KD) {
+            P.alpha[(long long)e * P.A + q] = S.al[le][q];
+            P.beta[(long long)e * P.A + q] = S.be[le][q];
+            for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * P.A + q] = S.mean[le][v][q];
         }
-        (void)leader0;
-    }
+    int sidx[MAXLEV];
+    subidx_all<DIM, K>(c, P, sidx);
     double th[MAXLEV + 1];
-    {
-        int sidx[MAXLEV];
-        subidx_all<DIM, K>(c, P, sidx);
-        double prod = 1.0;
-        for (int li = 0; li < P.nlev; ++li) {
-            th[1 + li] = al[li] * prod;
-            prod *= (1.0 - al[li]);
-        }
-        th[0] = prod;
-        (void)sidx;
-    }
+    theta_from_alpha(S.al[le], P, sidx, th);
     // blended interface states on the element faces: theta_FV * mean + sum_n theta_n *
     // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation)
     for (int a = 0; a < DIM; ++a) {
@@ -564,10 +569,11 @@ analyse_kernel(KArgs P)
                 const sedg_level_tab &T = P.tabs[li];
                 int n = P.lev_n[li];
                 const double *E = sd ? T.Ep : T.Em;
-                double b = beta[li];
+                const int q = P.lev_off[li] + sidx[li];
+                double b = S.be[le][q];
                 for (int v = 0; v < NV; ++v) {
                     double tr = bapply<DIM, K>(S.u[le][v], c, a, n, E);
-                    st[v] += th[1 + li] * ((1.0 - b) * mean[li][v] + b * tr);
+                    st[v] += th[1 + li] * ((1.0 - b) * S.mean[le][v][q] + b * tr);
                 }
             }
             if (act)
@@ -702,8 +708,8 @@ residual_kernel(KArgs P)
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
     double rfv[NV];
     for (int v = 0; v < NV; ++v) rfv[v] = 0.0;
-    double lr[MAXLEV][NV];
-    for (int li = 0; li < MAXLEV; ++li)
+    double lr[SM::AXO ? MAXLEV : 1][NV];
+    for (int li = 0; li < (SM::AXO ? MAXLEV : 1); ++li)
         for (int v = 0; v < NV; ++v) lr[li][v] = 0.0;
 
     constexpr int NPASS = SM::AXO ? DIM : 1;
@@ -804,10 +810,8 @@ residual_kernel(KArgs P)
             // DG candidates level by level: R along the face, HLLE at the face nodes, P back
             double thFV = 1.0;
             double F[NV];
-            double cand[MAXLEV][NV];
-            double wdg[MAXLEV];
+            for (int v = 0; v < NV; ++v) F[v] = 0.0;
             for (int li = 0; li < P.nlev; ++li) {
-                wdg[li] = 0.0;
                 // uniform skip: no element of the block has this level active on a needed face
                 if (!__syncthreads_or(has && (k % P.lev_n[li] == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
                     continue;
@@ -888,15 +892,11 @@ residual_kernel(KArgs P)
                             }
                         }
                     }
-                    cand[li][v] = sacc;
+                    if (need && okf) F[v] += tb * sacc;
                     __syncthreads();
                 }
-                if (need && okf) {
-                    wdg[li] = tb;
-                    thFV -= tb;
-                }
+                if (need && okf) thFV -= tb;
             }
-            for (int v = 0; v < NV; ++v) F[v] = 0.0;
             if (has) {
                 if (thFV != 0.0) {
                     double aL[NV], aR[NV], fs[NV];
@@ -904,11 +904,8 @@ residual_kernel(KArgs P)
                     if (!flux_admissible<DIM>(aL, gam, srho, sE)) for (int v = 0; v < NV; ++v) aL[v] = mL[v];
                     if (!flux_admissible<DIM>(aR, gam, srho, sE)) for (int v = 0; v < NV; ++v) aR[v] = mR[v];
                     hlle<DIM>(aL, aR, fa, gam, fs);
-                    for (int v = 0; v < NV; ++v) F[v] = thFV * fs[v];
+                    for (int v = 0; v < NV; ++v) F[v] += thFV * fs[v];
                 }
-                for (int li = 0; li < P.nlev; ++li)
-                    if (wdg[li] != 0.0)
-                        for (int v = 0; v < NV; ++v) F[v] += wdg[li] * cand[li][v];
                 const int axs = SM::AXO ? 0 : fa;
                 for (int v = 0; v < NV; ++v) S.F[le][axs][v][k * KF + t] = F[v];
             }
@@ -916,7 +913,7 @@ residual_kernel(KArgs P)
         __syncthreads();
 
         // ---------------- FV part: -(K/dx_a) (F_{i+1/2} - F_{i-1/2}) ----------------
-        if (th[0] != 0.0)
+        if (th[0] != 0.0) {
             for (int a = a0; a < a1; ++a) {
                 const int axs = SM::AXO ? 0 : a;
                 const int pos = G::coord(c, a), tr = G::trans(c, a);
@@ -924,6 +921,9 @@ residual_kernel(KArgs P)
                 for (int v = 0; v < NV; ++v)
                     rfv[v] -= sc * (S.F[le][axs][v][(pos + 1) * KF + tr] - S.F[le][axs][v][pos * KF + tr]);
             }
+            if (!SM::AXO)
+                for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
+        }
 
         // ---------------- DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat) ----------------
         for (int li = 0; li < P.nlev; ++li) {
@@ -949,6 +949,8 @@ residual_kernel(KArgs P)
                 double b = S.be[le][P.lev_off[li] + s];
                 for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * nodal[v];
             }
+            double lrl[NV];
+            for (int v = 0; v < NV; ++v) lrl[v] = SM::AXO ? lr[li][v] : 0.0;
             for (int a = a0; a < a1; ++a) {
                 const int axs = SM::AXO ? 0 : a;
                 double f[NV];
@@ -972,20 +974,27 @@ residual_kernel(KArgs P)
                     const double sc = K / (n * P.dx[a]);
                     for (int v = 0; v < NV; ++v) {
                         double surf = T.Bhl[lo] * S.F[le][axs][v][kl * KF + tr] + T.Bhr[lo] * S.F[le][axs][v][kr * KF + tr];
-                        lr[li][v] += sc * (vol[v] - surf);
+                        lrl[v] += sc * (vol[v] - surf);
                     }
                 }
+            }
+            if (SM::AXO) {
+                for (int v = 0; v < NV; ++v) lr[li][v] = lrl[v];
+            } else if (on) {
+                for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lrl[v];
             }
             __syncthreads();
         }
     }
 
-    // blend (eq. blending-weights) and store / RK stage
-    if (th[0] != 0.0)
-        for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
-    for (int li = 0; li < P.nlev; ++li)
-        if (th[1 + li] != 0.0)
-            for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lr[li][v];
+    // blend (eq. blending-weights): FV first, then the levels from the top
+    if (SM::AXO) {
+        if (th[0] != 0.0)
+            for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
+        for (int li = 0; li < P.nlev; ++li)
+            if (th[1 + li] != 0.0)
+                for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lr[li][v];
+    }
     if (!act) return;
     if (P.stage == 0) {
         for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = out[v];
