@@ -185,6 +185,28 @@ struct Geo {
 
 __device__ __forceinline__ int ilog2i(int n) { return n == 8 ? 3 : n == 4 ? 2 : n == 2 ? 1 : 0; }
 
+// Compile-time level hierarchy of a DGFV-TOP scheme on K^DIM subcells: DG levels
+// n = TOP, TOP/2, ..., 2 (level index li = 0, 1, ...), their sub-element counts
+// and offsets in the per-element blending-factor vector.
+template <int DIM, int K, int TOP>
+struct Lv {
+    static constexpr int NLEV = (TOP == 8) ? 3 : (TOP == 4) ? 2 : 1;
+    static constexpr int n(int li) { return TOP >> li; }
+    static constexpr int per(int li)
+    {
+        int r = 1;
+        for (int a = 0; a < DIM; ++a) r *= K / n(li);
+        return r;
+    }
+    static constexpr int off(int li)
+    {
+        int o = 0;
+        for (int j = 0; j < li; ++j) o += per(j);
+        return o;
+    }
+    static constexpr int A = off(NLEV);
+};
+
 // xor-butterfly reduction over the cells of one level-n sub-element (ln = log2 n;
 // ln = LOGK gives the whole element).  Bits inside a wavefront use cross-lane
 // shuffles, higher bits exchange through LDS; every lane ends with the same value.
@@ -233,21 +255,24 @@ __device__ __forceinline__ double bapply(const double *src, int c, int a, int n,
 }
 
 // weights theta of one cell from an element's alpha vector (eq. blending-weights)
-__device__ __forceinline__ void theta_from_alpha(const double *al, const KArgs &P, const int *sidx, double *th)
+template <class LV>
+__device__ __forceinline__ void theta_from_alpha(const double *al, const int *sidx, double *th)
 {
     double prod = 1.0;
-    for (int li = 0; li < P.nlev; ++li) {
-        double a = al[P.lev_off[li] + sidx[li]];
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        double a = al[LV::off(li) + sidx[li]];
         th[1 + li] = a * prod;
         prod *= (1.0 - a);
     }
     th[0] = prod;
 }
 
-template <int DIM, int K>
-__device__ __forceinline__ void subidx_all(int c, const KArgs &P, int *sidx)
+template <int DIM, int K, class LV>
+__device__ __forceinline__ void subidx_all(int c, int *sidx)
 {
-    for (int li = 0; li < P.nlev; ++li) sidx[li] = Geo<DIM, K>::subelem(c, P.lev_n[li]);
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) sidx[li] = Geo<DIM, K>::subelem(c, LV::n(li));
 }
 
 template <int DIM, int K>
@@ -336,11 +361,12 @@ __device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, EPB> &S, int le,
     __syncthreads();
 }
 
-template <int DIM, int K, int EPB>
+template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
 analyse_kernel(KArgs P)
 {
     typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
     constexpr int NV = G::NV, KD = G::KD;
     __shared__ AnalyseSmem<DIM, K, EPB> S;
     const int tid = threadIdx.x;
@@ -390,8 +416,8 @@ analyse_kernel(KArgs P)
     }
     __syncthreads();
 
-    for (int q = c; q < P.A; q += KD) {
-        S.al[le][q] = (P.mode == SEDG_EXTERNAL) ? P.alpha_in[(long long)ee * P.A + q] : 0.0;
+    for (int q = c; q < LV::A; q += KD) {
+        S.al[le][q] = (P.mode == SEDG_EXTERNAL) ? P.alpha_in[(long long)ee * LV::A + q] : 0.0;
         S.be[le][q] = 1.0;
         for (int v = 0; v < NV; ++v) S.mean[le][v][q] = 0.0;
     }
@@ -399,8 +425,9 @@ analyse_kernel(KArgs P)
 
     int broke = 0;
     int have_rec = -1;      // level index whose reconstruction sits in S.r[li & 1]
-    for (int li = 0; li < P.nlev; ++li) {
-        const int n = P.lev_n[li], ln = ilog2i(n);
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        const int n = LV::n(li), ln = ilog2i(n);
         const bool enabled = (P.level_mask == 0) || ((P.level_mask >> ln) & 1u);
         bool visit;
         if (P.mode == SEDG_EXTERNAL) visit = true;
@@ -458,12 +485,12 @@ analyse_kernel(KArgs P)
                 b = fmin(fmin(br, bq), 1.0);
             }
             if (visit && leader)
-                for (int v = 0; v < NV; ++v) S.mean[le][v][P.lev_off[li] + sub] = mn[v];
+                for (int v = 0; v < NV; ++v) S.mean[le][v][LV::off(li) + sub] = mn[v];
         }
         if (!visit) b = 1.0;
-        if (leader) S.be[le][P.lev_off[li] + sub] = b;
+        if (leader) S.be[le][LV::off(li) + sub] = b;
         // children reconstruction = next level's reconstruction
-        const bool need_next = (li + 1 < P.nlev) &&
+        const bool need_next = (li + 1 < LV::NLEV) &&
                                (P.mode == SEDG_EXTERNAL || (P.mode == SEDG_ADAPTIVE && n >= 4));
         if (__syncthreads_or(visit && need_next)) {
             recon_level<DIM, K, EPB>(S, le, c, P.tabs[li + 1], n / 2, S.r[le][(li + 1) & 1]);
@@ -539,23 +566,23 @@ analyse_kernel(KArgs P)
         if (visit) {
             if (hi) { a = 1.0; broke = 1; }
             else if (lo) a = 0.0;
-            if (leader) S.al[le][P.lev_off[li] + sub] = a;
+            if (leader) S.al[le][LV::off(li) + sub] = a;
         }
     }
     if (P.mode == SEDG_FORCE_DG)
-        for (int q = c; q < P.lev_off[1 < P.nlev ? 1 : 0] + (P.nlev > 1 ? 0 : P.A); q += KD) S.al[le][q] = 1.0;
+        for (int q = c; q < LV::off(1 < LV::NLEV ? 1 : 0) + (LV::NLEV > 1 ? 0 : LV::A); q += KD) S.al[le][q] = 1.0;
     __syncthreads();
     // publish alpha, beta and the sub-element means (coalesced)
     if (act)
-        for (int q = c; q < P.A; q += KD) {
-            P.alpha[(long long)e * P.A + q] = S.al[le][q];
-            P.beta[(long long)e * P.A + q] = S.be[le][q];
-            for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * P.A + q] = S.mean[le][v][q];
+        for (int q = c; q < LV::A; q += KD) {
+            P.alpha[(long long)e * LV::A + q] = S.al[le][q];
+            P.beta[(long long)e * LV::A + q] = S.be[le][q];
+            for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * LV::A + q] = S.mean[le][v][q];
         }
     int sidx[MAXLEV];
-    subidx_all<DIM, K>(c, P, sidx);
+    subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
-    theta_from_alpha(S.al[le], P, sidx, th);
+    theta_from_alpha<LV>(S.al[le], sidx, th);
     // blended interface states on the element faces: theta_FV * mean + sum_n theta_n *
     // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation)
     for (int a = 0; a < DIM; ++a) {
@@ -564,12 +591,13 @@ analyse_kernel(KArgs P)
             if (pos != (sd ? K - 1 : 0)) continue;
             double st[NV];
             for (int v = 0; v < NV; ++v) st[v] = th[0] * ub[v];
-            for (int li = 0; li < P.nlev; ++li) {
+#pragma unroll
+            for (int li = 0; li < LV::NLEV; ++li) {
                 if (th[1 + li] == 0.0) continue;
                 const sedg_level_tab &T = P.tabs[li];
-                int n = P.lev_n[li];
+                int n = LV::n(li);
                 const double *E = sd ? T.Ep : T.Em;
-                const int q = P.lev_off[li] + sidx[li];
+                const int q = LV::off(li) + sidx[li];
                 double b = S.be[le][q];
                 for (int v = 0; v < NV; ++v) {
                     double tr = bapply<DIM, K>(S.u[le][v], c, a, n, E);
@@ -614,47 +642,39 @@ struct ResidualSmem {
 };
 
 // theta of the cell across an element face, from the neighbour's alpha
-template <int DIM, int K>
-__device__ __forceinline__ void theta_cell_of(const double *al, const KArgs &P, int cell, double *th)
+template <int DIM, int K, class LV>
+__device__ __forceinline__ void theta_cell_of(const double *al, int cell, double *th)
 {
     int sidx[MAXLEV];
-    subidx_all<DIM, K>(cell, P, sidx);
-    theta_from_alpha(al, P, sidx, th);
+    subidx_all<DIM, K, LV>(cell, sidx);
+    theta_from_alpha<LV>(al, sidx, th);
 }
 
-// is interior face k (1..K-1) used by some active level of the element?
-__device__ __forceinline__ bool face_needed(const KArgs &P, const int *act, int k)
-{
-    if (act[0]) return true;
-    for (int li = 0; li < P.nlev; ++li)
-        if (act[1 + li] && (k % P.lev_n[li]) == 0) return true;
-    return false;
-}
-
-// the fidx-th needed face of axes [a0, a1): element faces first, then interior ones
+// The needed faces of na axes starting at a0: first the two element faces of each
+// axis, then the interior faces at multiples of 'step' (1 when the FV level is
+// active, else the smallest active DG level; K leaves none).
 template <int K>
-__device__ __forceinline__ int face_at(const KArgs &P, const int *act, int a0, int a1, int fidx, int *fa, int *fk)
+__device__ __forceinline__ int face_count(int na, int step) { return na * (2 + K / step - 1); }
+
+template <int K>
+__device__ __forceinline__ void face_at(int a0, int na, int step, int fidx, int *fa, int *fk)
 {
-    int cnt = 0;
-    for (int a = a0; a < a1; ++a)
-        for (int s = 0; s < 2; ++s) {
-            if (cnt == fidx) { *fa = a; *fk = s ? K : 0; }
-            ++cnt;
-        }
-    for (int a = a0; a < a1; ++a)
-        for (int k = 1; k < K; ++k)
-            if (face_needed(P, act, k)) {
-                if (cnt == fidx) { *fa = a; *fk = k; }
-                ++cnt;
-            }
-    return cnt;
+    if (fidx < 2 * na) {
+        *fa = a0 + (fidx >> 1);
+        *fk = (fidx & 1) * K;
+    } else {
+        int j = fidx - 2 * na, cnt = K / step - 1;
+        *fa = a0 + j / cnt;
+        *fk = step * (1 + j % cnt);
+    }
 }
 
-template <int DIM, int K, int EPB>
+template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
 residual_kernel(KArgs P)
 {
     typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
     typedef ResidualSmem<DIM, K, EPB> SM;
     constexpr int NV = G::NV, KD = G::KD, KF = G::KF;
     __shared__ SM S;
@@ -673,10 +693,10 @@ residual_kernel(KArgs P)
         ub[v] = P.u[v * P.dof + g];
         S.u[le][v][c] = ub[v];
     }
-    const double *al = P.alpha + (long long)ee * P.A;
-    for (int q = c; q < P.A; q += KD) {
-        S.be[le][q] = P.beta[(long long)ee * P.A + q];
-        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * P.A + q];
+    const double *al = P.alpha + (long long)ee * LV::A;
+    for (int q = c; q < LV::A; q += KD) {
+        S.be[le][q] = P.beta[(long long)ee * LV::A + q];
+        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * LV::A + q];
     }
     int nb[3][2];
     for (int a = 0; a < 3; ++a) nb[a][0] = nb[a][1] = -1;
@@ -684,17 +704,17 @@ residual_kernel(KArgs P)
         for (int sd = 0; sd < 2; ++sd) {
             nb[a][sd] = neighbour<DIM>(P, e3, a, sd);
             int src = nb[a][sd] >= 0 ? nb[a][sd] : ee;
-            for (int q = c; q < P.A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * P.A + q];
+            for (int q = c; q < LV::A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * LV::A + q];
         }
     int sidx[MAXLEV];
-    subidx_all<DIM, K>(c, P, sidx);
+    subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
-    theta_from_alpha(al, P, sidx, th);
-    for (int l = 0; l <= P.nlev; ++l) S.th[le][l][c] = th[l];
+    theta_from_alpha<LV>(al, sidx, th);
+    for (int l = 0; l <= LV::NLEV; ++l) S.th[le][l][c] = th[l];
     // active levels of the element (any cell with a nonzero weight)
     {
         int flags = 0;
-        for (int l = 0; l <= P.nlev; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
+        for (int l = 0; l <= LV::NLEV; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
         flags = subreduce<DIM, K>(flags, G::LOGK, (int *)S.wsL, OpOr());
         if (c == 0)
             for (int l = 0; l <= MAXLEV; ++l) S.act[le][l] = (flags >> l) & 1;
@@ -716,8 +736,12 @@ residual_kernel(KArgs P)
     for (int pass = 0; pass < NPASS; ++pass) {
         const int a0 = SM::AXO ? pass : 0, a1 = SM::AXO ? pass + 1 : DIM;
         // ---------------- common fluxes on the needed faces of axes [a0, a1) ----------------
-        int dummy_a = 0, dummy_k = 0;
-        int nfaces = face_at<K>(P, actv, a0, a1, 1 << 30, &dummy_a, &dummy_k);
+        int step = K;
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li)
+            if (actv[1 + li]) step = min(step, LV::n(li));
+        if (actv[0]) step = 1;
+        const int nfaces = face_count<K>(a1 - a0, step);
         int nfmax = nfaces;
         if (EPB > 1) {
             S.wsL[tid] = (double)nfaces;
@@ -730,7 +754,7 @@ residual_kernel(KArgs P)
             const int fidx = r0 + slot;
             int fa = 0, k = 0;
             const bool has = fidx < nfaces;
-            if (has) face_at<K>(P, actv, a0, a1, fidx, &fa, &k);
+            if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k);
             const int st = G::stride(fa);
             const bool lowface = (k == 0), highface = (k == K);
             const int nbL = nb[fa][0], nbR = nb[fa][1];
@@ -743,9 +767,9 @@ residual_kernel(KArgs P)
                     uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, fa, 1, v, t)] : uR[v];
                     mR[v] = S.u[le][v][cr];
                 }
-                for (int l = 0; l <= P.nlev; ++l) thR[l] = S.th[le][l][cr];
+                for (int l = 0; l <= LV::NLEV; ++l) thR[l] = S.th[le][l][cr];
                 if (nbL >= 0) {
-                    theta_cell_of<DIM, K>(S.nal[le][2 * fa + 0], P, cl, thL);
+                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 0], cl, thL);
                     int n3[3];
                     elem3(P, nbL, n3);
                     long long gl = gindex<DIM, K>(P, n3, cl);
@@ -753,7 +777,7 @@ residual_kernel(KArgs P)
                     srho = fmax(P.scale[2 * (long long)nbL], own_sr);
                     sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
                 } else {
-                    for (int l = 0; l <= P.nlev; ++l) thL[l] = thR[l];
+                    for (int l = 0; l <= LV::NLEV; ++l) thL[l] = thR[l];
                     for (int v = 0; v < NV; ++v) mL[v] = mR[v];
                 }
             } else if (highface) {
@@ -763,9 +787,9 @@ residual_kernel(KArgs P)
                     uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, fa, 0, v, t)] : uL[v];
                     mL[v] = S.u[le][v][cl];
                 }
-                for (int l = 0; l <= P.nlev; ++l) thL[l] = S.th[le][l][cl];
+                for (int l = 0; l <= LV::NLEV; ++l) thL[l] = S.th[le][l][cl];
                 if (nbR >= 0) {
-                    theta_cell_of<DIM, K>(S.nal[le][2 * fa + 1], P, cr, thR);
+                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 1], cr, thR);
                     int n3[3];
                     elem3(P, nbR, n3);
                     long long gr = gindex<DIM, K>(P, n3, cr);
@@ -773,36 +797,37 @@ residual_kernel(KArgs P)
                     srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
                     sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
                 } else {
-                    for (int l = 0; l <= P.nlev; ++l) thR[l] = thL[l];
+                    for (int l = 0; l <= LV::NLEV; ++l) thR[l] = thL[l];
                     for (int v = 0; v < NV; ++v) mR[v] = mL[v];
                 }
             } else {
                 // interior face: blended interface states of the two adjacent cells
                 int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
-                for (int l = 0; l <= P.nlev; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
+                for (int l = 0; l <= LV::NLEV; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
                 for (int v = 0; v < NV; ++v) {
                     mL[v] = S.u[le][v][cl];
                     mR[v] = S.u[le][v][cr];
                     uL[v] = thL[0] * mL[v];
                     uR[v] = thR[0] * mR[v];
                 }
-                for (int li = 0; li < P.nlev; ++li) {
+#pragma unroll
+                for (int li = 0; li < LV::NLEV; ++li) {
                     const sedg_level_tab &T = P.tabs[li];
-                    int n = P.lev_n[li];
+                    int n = LV::n(li);
                     if (thL[1 + li] != 0.0) {
                         int s = G::subelem(cl, n);
-                        double b = S.be[le][P.lev_off[li] + s];
+                        double b = S.be[le][LV::off(li) + s];
                         for (int v = 0; v < NV; ++v) {
                             double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
-                            uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * tr);
+                            uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
                         }
                     }
                     if (thR[1 + li] != 0.0) {
                         int s = G::subelem(cr, n);
-                        double b = S.be[le][P.lev_off[li] + s];
+                        double b = S.be[le][LV::off(li) + s];
                         for (int v = 0; v < NV; ++v) {
                             double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
-                            uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * tr);
+                            uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
                         }
                     }
                 }
@@ -811,12 +836,13 @@ residual_kernel(KArgs P)
             double thFV = 1.0;
             double F[NV];
             for (int v = 0; v < NV; ++v) F[v] = 0.0;
-            for (int li = 0; li < P.nlev; ++li) {
+#pragma unroll
+            for (int li = 0; li < LV::NLEV; ++li) {
                 // uniform skip: no element of the block has this level active on a needed face
-                if (!__syncthreads_or(has && (k % P.lev_n[li] == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+                if (!__syncthreads_or(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
                     continue;
                 const sedg_level_tab &T = P.tabs[li];
-                const int n = P.lev_n[li], ln = ilog2i(n);
+                const int n = LV::n(li), ln = ilog2i(n);
                 const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
                 const bool need = has && (k % n == 0) && (tb != 0.0);
                 double nl[NV], nr[NV];
@@ -926,10 +952,11 @@ residual_kernel(KArgs P)
         }
 
         // ---------------- DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat) ----------------
-        for (int li = 0; li < P.nlev; ++li) {
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li) {
             if (!__syncthreads_or(actv[1 + li])) continue;
             const sedg_level_tab &T = P.tabs[li];
-            const int n = P.lev_n[li];
+            const int n = LV::n(li);
             const bool on = th[1 + li] != 0.0;
             // squeezed reconstruction at this cell's node
             double nodal[NV];
@@ -946,8 +973,8 @@ residual_kernel(KArgs P)
             }
             {
                 int s = sidx[li];
-                double b = S.be[le][P.lev_off[li] + s];
-                for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * S.mean[le][v][P.lev_off[li] + s] + b * nodal[v];
+                double b = S.be[le][LV::off(li) + s];
+                for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * nodal[v];
             }
             double lrl[NV];
             for (int v = 0; v < NV; ++v) lrl[v] = SM::AXO ? lr[li][v] : 0.0;
@@ -991,7 +1018,8 @@ residual_kernel(KArgs P)
     if (SM::AXO) {
         if (th[0] != 0.0)
             for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
-        for (int li = 0; li < P.nlev; ++li)
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li)
             if (th[1 + li] != 0.0)
                 for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lr[li][v];
     }
@@ -1078,39 +1106,34 @@ int epb_for(int dim, int K)
 
 bool supported(int dim, int K) { return (dim == 2 || dim == 3) && (K == 4 || K == 8); }
 
-template <int DIM, int K>
-void launch_pair(const KArgs &P, int nblocks, hipStream_t s)
+template <int DIM, int K, int TOP>
+void launch_kernel(int which, const KArgs &P, int nblocks, hipStream_t s)
 {
     constexpr int EPBv = (DIM == 2 && K == 4) ? 4 : 1;
     constexpr int threads = EPBv * Geo<DIM, K>::KD;
-    hipLaunchKernelGGL((analyse_kernel<DIM, K, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    if (which == 0) hipLaunchKernelGGL((analyse_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else hipLaunchKernelGGL((residual_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
 }
 
 template <int DIM, int K>
-void launch_residual(const KArgs &P, int nblocks, hipStream_t s)
+void launch_top(int which, int top, const KArgs &P, int nblocks, hipStream_t s)
 {
-    constexpr int EPBv = (DIM == 2 && K == 4) ? 4 : 1;
-    constexpr int threads = EPBv * Geo<DIM, K>::KD;
-    hipLaunchKernelGGL((residual_kernel<DIM, K, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    if (top == 2) launch_kernel<DIM, K, 2>(which, P, nblocks, s);
+    else if (top == 4) launch_kernel<DIM, K, 4>(which, P, nblocks, s);
+    else launch_kernel<DIM, K, (K >= 8 ? 8 : 4)>(which, P, nblocks, s);
 }
 
-void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s)
+void launch_any(int which, const sedg_ctx *C, const KArgs &P, hipStream_t s)
 {
-    int d = C->mesh.dim, K = C->mesh.K;
-    if (d == 2 && K == 4) launch_pair<2, 4>(P, C->nblocks, s);
-    else if (d == 2 && K == 8) launch_pair<2, 8>(P, C->nblocks, s);
-    else if (d == 3 && K == 4) launch_pair<3, 4>(P, C->nblocks, s);
-    else launch_pair<3, 8>(P, C->nblocks, s);
+    int d = C->mesh.dim, K = C->mesh.K, top = C->lev_n[0];
+    if (d == 2 && K == 4) launch_top<2, 4>(which, top, P, C->nblocks, s);
+    else if (d == 2 && K == 8) launch_top<2, 8>(which, top, P, C->nblocks, s);
+    else if (d == 3 && K == 4) launch_top<3, 4>(which, top, P, C->nblocks, s);
+    else launch_top<3, 8>(which, top, P, C->nblocks, s);
 }
 
-void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s)
-{
-    int d = C->mesh.dim, K = C->mesh.K;
-    if (d == 2 && K == 4) launch_residual<2, 4>(P, C->nblocks, s);
-    else if (d == 2 && K == 8) launch_residual<2, 8>(P, C->nblocks, s);
-    else if (d == 3 && K == 4) launch_residual<3, 4>(P, C->nblocks, s);
-    else launch_residual<3, 8>(P, C->nblocks, s);
-}
+void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(0, C, P, s); }
+void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(1, C, P, s); }
 
 KArgs base_args(const sedg_ctx *C)
 {
