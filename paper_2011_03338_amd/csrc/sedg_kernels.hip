@@ -37,6 +37,7 @@
 #include "sedg_internal.h"
 
 #define MAXLEV 3
+#define LAM_SLOTS 256   // slots of the per-step CFL eigenvalue maximum
 
 // ---------------------------------------------------------------------------
 // kernel arguments
@@ -402,7 +403,9 @@ analyse_kernel(KArgs P)
             if (tid == 0) {
                 double m = 0.0;
                 for (int wv = 0; wv < (EPB * KD + 63) / 64; ++wv) m = fmax(m, S.lam[wv]);
-                P.lam_part[blockIdx.x] = m;
+                // non-negative doubles order like their bit patterns: an integer max is exact
+                atomicMax((unsigned long long *)&P.lam_part[blockIdx.x & (LAM_SLOTS - 1)],
+                          (unsigned long long)__double_as_longlong(m));
             }
         }
     }
@@ -624,19 +627,20 @@ analyse_kernel(KArgs P)
 // In 3-D the flux buffer holds one axis at a time (LDS budget), so the
 // reconstruction is repeated per axis; in 2-D all axes are held.
 
-template <int DIM, int K, int EPB>
+template <int DIM, int K, int TOP, int EPB>
 struct ResidualSmem {
     typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
     static constexpr bool AXO = (DIM == 3);
     static constexpr int NAX = AXO ? 1 : DIM;
     double u[EPB][G::NV][G::KD];
     double F[EPB][NAX][G::NV][(K + 1) * G::KF];
     double nod[EPB][G::NV][G::KD];
     double tmp[EPB][G::NV][G::KD];
-    double th[EPB][MAXLEV + 1][G::KD];
-    double mean[EPB][G::NV][73];
-    double be[EPB][73];
-    double nal[EPB][2 * DIM][73];
+    double al[EPB][LV::A];
+    double mean[EPB][G::NV][LV::A];
+    double be[EPB][LV::A];
+    double nal[EPB][2 * DIM][LV::A];
     double wsL[EPB * G::KD], wsR[EPB * G::KD];
     int act[EPB][MAXLEV + 1];
 };
@@ -671,11 +675,11 @@ __device__ __forceinline__ void face_at(int a0, int na, int step, int fidx, int 
 
 template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
-residual_kernel(KArgs P)
+__attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
 {
     typedef Geo<DIM, K> G;
     typedef Lv<DIM, K, TOP> LV;
-    typedef ResidualSmem<DIM, K, EPB> SM;
+    typedef ResidualSmem<DIM, K, TOP, EPB> SM;
     constexpr int NV = G::NV, KD = G::KD, KF = G::KF;
     __shared__ SM S;
     const int tid = threadIdx.x;
@@ -688,29 +692,22 @@ residual_kernel(KArgs P)
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    double ub[NV];
-    for (int v = 0; v < NV; ++v) {
-        ub[v] = P.u[v * P.dof + g];
-        S.u[le][v][c] = ub[v];
-    }
-    const double *al = P.alpha + (long long)ee * LV::A;
+    for (int v = 0; v < NV; ++v) S.u[le][v][c] = P.u[v * P.dof + g];
     for (int q = c; q < LV::A; q += KD) {
+        S.al[le][q] = P.alpha[(long long)ee * LV::A + q];
         S.be[le][q] = P.beta[(long long)ee * LV::A + q];
         for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * LV::A + q];
     }
-    int nb[3][2];
-    for (int a = 0; a < 3; ++a) nb[a][0] = nb[a][1] = -1;
     for (int a = 0; a < DIM; ++a)
         for (int sd = 0; sd < 2; ++sd) {
-            nb[a][sd] = neighbour<DIM>(P, e3, a, sd);
-            int src = nb[a][sd] >= 0 ? nb[a][sd] : ee;
+            const int nbs = neighbour<DIM>(P, e3, a, sd);
+            const int src = nbs >= 0 ? nbs : ee;
             for (int q = c; q < LV::A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * LV::A + q];
         }
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
-    theta_from_alpha<LV>(al, sidx, th);
-    for (int l = 0; l <= LV::NLEV; ++l) S.th[le][l][c] = th[l];
+    theta_from_alpha<LV>(P.alpha + (long long)ee * LV::A, sidx, th);
     // active levels of the element (any cell with a nonzero weight)
     {
         int flags = 0;
@@ -757,58 +754,57 @@ residual_kernel(KArgs P)
             if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k);
             const int st = G::stride(fa);
             const bool lowface = (k == 0), highface = (k == K);
-            const int nbL = nb[fa][0], nbR = nb[fa][1];
-            double uL[NV], uR[NV], mL[NV], mR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
+            const int nbL = neighbour<DIM>(P, e3, fa, 0), nbR = neighbour<DIM>(P, e3, fa, 1);
+            double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
+            // cells whose means replace a non-admissible FV input (element -1: own element)
+            int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
             double srho = own_sr, sE = own_se;
             if (lowface) {
                 int cr = G::from_trans(t, fa, 0), cl = G::from_trans(t, fa, K - 1);
                 for (int v = 0; v < NV; ++v) {
                     uR[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 0, v, t)];
                     uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, fa, 1, v, t)] : uR[v];
-                    mR[v] = S.u[le][v][cr];
                 }
-                for (int l = 0; l <= LV::NLEV; ++l) thR[l] = S.th[le][l][cr];
+                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
+                mRc = cr;
                 if (nbL >= 0) {
                     theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 0], cl, thL);
-                    int n3[3];
-                    elem3(P, nbL, n3);
-                    long long gl = gindex<DIM, K>(P, n3, cl);
-                    for (int v = 0; v < NV; ++v) mL[v] = P.u[v * P.dof + gl];
+                    mLe = nbL;
+                    mLc = cl;
                     srho = fmax(P.scale[2 * (long long)nbL], own_sr);
                     sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
                 } else {
                     for (int l = 0; l <= LV::NLEV; ++l) thL[l] = thR[l];
-                    for (int v = 0; v < NV; ++v) mL[v] = mR[v];
+                    mLc = cr;
                 }
             } else if (highface) {
                 int cl = G::from_trans(t, fa, K - 1), cr = G::from_trans(t, fa, 0);
                 for (int v = 0; v < NV; ++v) {
                     uL[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 1, v, t)];
                     uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, fa, 0, v, t)] : uL[v];
-                    mL[v] = S.u[le][v][cl];
                 }
-                for (int l = 0; l <= LV::NLEV; ++l) thL[l] = S.th[le][l][cl];
+                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
+                mLc = cl;
                 if (nbR >= 0) {
                     theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 1], cr, thR);
-                    int n3[3];
-                    elem3(P, nbR, n3);
-                    long long gr = gindex<DIM, K>(P, n3, cr);
-                    for (int v = 0; v < NV; ++v) mR[v] = P.u[v * P.dof + gr];
+                    mRe = nbR;
+                    mRc = cr;
                     srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
                     sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
                 } else {
                     for (int l = 0; l <= LV::NLEV; ++l) thR[l] = thL[l];
-                    for (int v = 0; v < NV; ++v) mR[v] = mL[v];
+                    mRc = cl;
                 }
             } else {
                 // interior face: blended interface states of the two adjacent cells
                 int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
-                for (int l = 0; l <= LV::NLEV; ++l) { thL[l] = S.th[le][l][cl]; thR[l] = S.th[le][l][cr]; }
+                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
+                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
+                mLc = cl;
+                mRc = cr;
                 for (int v = 0; v < NV; ++v) {
-                    mL[v] = S.u[le][v][cl];
-                    mR[v] = S.u[le][v][cr];
-                    uL[v] = thL[0] * mL[v];
-                    uR[v] = thR[0] * mR[v];
+                    uL[v] = thL[0] * S.u[le][v][cl];
+                    uR[v] = thR[0] * S.u[le][v][cr];
                 }
 #pragma unroll
                 for (int li = 0; li < LV::NLEV; ++li) {
@@ -927,8 +923,24 @@ residual_kernel(KArgs P)
                 if (thFV != 0.0) {
                     double aL[NV], aR[NV], fs[NV];
                     for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
-                    if (!flux_admissible<DIM>(aL, gam, srho, sE)) for (int v = 0; v < NV; ++v) aL[v] = mL[v];
-                    if (!flux_admissible<DIM>(aR, gam, srho, sE)) for (int v = 0; v < NV; ++v) aR[v] = mR[v];
+                    if (!flux_admissible<DIM>(aL, gam, srho, sE)) {
+                        if (mLe < 0) for (int v = 0; v < NV; ++v) aL[v] = S.u[le][v][mLc];
+                        else {
+                            int n3[3];
+                            elem3(P, mLe, n3);
+                            long long gn = gindex<DIM, K>(P, n3, mLc);
+                            for (int v = 0; v < NV; ++v) aL[v] = P.u[v * P.dof + gn];
+                        }
+                    }
+                    if (!flux_admissible<DIM>(aR, gam, srho, sE)) {
+                        if (mRe < 0) for (int v = 0; v < NV; ++v) aR[v] = S.u[le][v][mRc];
+                        else {
+                            int n3[3];
+                            elem3(P, mRe, n3);
+                            long long gn = gindex<DIM, K>(P, n3, mRc);
+                            for (int v = 0; v < NV; ++v) aR[v] = P.u[v * P.dof + gn];
+                        }
+                    }
                     hlle<DIM>(aL, aR, fa, gam, fs);
                     for (int v = 0; v < NV; ++v) F[v] += thFV * fs[v];
                 }
@@ -1028,6 +1040,8 @@ residual_kernel(KArgs P)
         for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = out[v];
     } else {
         double dt = *P.dt;
+        double ub[NV];
+        for (int v = 0; v < NV; ++v) ub[v] = S.u[le][v][c];
         for (int v = 0; v < NV; ++v) {
             long long i = v * P.dof + g;
             double r;
@@ -1039,16 +1053,17 @@ residual_kernel(KArgs P)
     }
 }
 
-// CFL step from the per-block eigenvalue maxima (eq. cfl-condition); one block.
-__global__ void __launch_bounds__(256) finalize_dt_kernel(const double *lam_part, int nparts, double num, double *dt,
-                                                         double *dt_log, int *step_ctr)
+// CFL step from the eigenvalue maxima folded into LAM_SLOTS slots (eq. cfl-condition);
+// one block of LAM_SLOTS threads, which also clears the slots for the next step.
+__global__ void __launch_bounds__(LAM_SLOTS) finalize_dt_kernel(double *lam_part, int nparts, double num, double *dt,
+                                                               double *dt_log, int *step_ctr)
 {
-    __shared__ double s[256];
-    double m = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) m = fmax(m, lam_part[i]);
-    s[threadIdx.x] = m;
+    __shared__ double s[LAM_SLOTS];
+    (void)nparts;
+    s[threadIdx.x] = lam_part[threadIdx.x];
+    lam_part[threadIdx.x] = 0.0;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = LAM_SLOTS / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
@@ -1263,7 +1278,7 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     ok = ok && hipMalloc(&C->d_alpha, sizeof(double) * (size_t)C->nel * maxA) == hipSuccess;
     ok = ok && hipMalloc(&C->d_beta, sizeof(double) * (size_t)C->nel * maxA) == hipSuccess;
     ok = ok && hipMalloc(&C->d_fbuf, sizeof(double) * (size_t)C->nel * mesh->dim * 2 * C->nv * kf) == hipSuccess;
-    ok = ok && hipMalloc(&C->d_lam, sizeof(double) * (size_t)C->nblocks) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_lam, sizeof(double) * LAM_SLOTS) == hipSuccess;
     ok = ok && hipMalloc(&C->d_scale, sizeof(double) * 2 * (size_t)C->nel) == hipSuccess;
     ok = ok && hipMalloc(&C->d_mean, sizeof(double) * (size_t)C->nel * C->nv * maxA) == hipSuccess;
     ok = ok && hipMalloc(&C->d_dt, sizeof(double) * 2) == hipSuccess;
@@ -1274,6 +1289,7 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     if (!ok) { sedg_destroy(C); return SEDG_ENOMEM; }
     int big = INT_MAX;
     if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) { sedg_destroy(C); return SEDG_EHIP; }
+    if (hipMemset(C->d_lam, 0, sizeof(double) * LAM_SLOTS) != hipSuccess) { sedg_destroy(C); return SEDG_EHIP; }
     int rc = set_levels(C, params);
     if (rc) { sedg_destroy(C); return rc; }
     C->last = nullptr;
@@ -1336,7 +1352,7 @@ int sedg_max_dt(sedg_ctx *C, const double *u, double *dt_dev, void *stream)
     // the analyse pass also produces alpha/beta/face data (harmless side effect)
     P.mode = SEDG_FORCE_FV;
     launch_analyse_any(C, P, s);
-    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(256), 0, s, (const double *)C->d_lam, C->nblocks,
+    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
                        cfl_numerator(C), dt_dev, (double *)nullptr, (int *)nullptr);
     C->last = s;
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
@@ -1378,7 +1394,7 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
     if (!(dt_fixed > 0.0))
         timed(C, 2, s, [&] {
-            hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(256), 0, s, (const double *)C->d_lam, C->nblocks,
+            hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
                                cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
         });
     timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
