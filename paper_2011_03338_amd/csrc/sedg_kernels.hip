@@ -208,20 +208,50 @@ struct Lv {
     static constexpr int A = off(NLEV);
 };
 
+// Exact lane exchange v <- v[lane ^ mask] inside a wavefront.  Masks below 16 use
+// DPP lane permutations (xor 1 / xor 2: quad permutes; xor 4: half-row mirror then
+// quad reverse; xor 8: rotation by 8 inside a 16-lane row); 16 and 32 cross rows
+// through ds_bpermute.
+__device__ __forceinline__ int lane_xor_i(int v, int mask)
+{
+    switch (mask) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    case 4: {
+        int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+        return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);
+    }
+    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    default: return __shfl_xor(v, mask, 64);
+    }
+}
+
+__device__ __forceinline__ int lane_xor(int v, int mask) { return lane_xor_i(v, mask); }
+
+__device__ __forceinline__ double lane_xor(double v, int mask)
+{
+    int lo = lane_xor_i(__double2loint(v), mask);
+    int hi = lane_xor_i(__double2hiint(v), mask);
+    return __hiloint2double(hi, lo);
+}
+
 // xor-butterfly reduction over the cells of one level-n sub-element (ln = log2 n;
-// ln = LOGK gives the whole element).  Bits inside a wavefront use cross-lane
-// shuffles, higher bits exchange through LDS; every lane ends with the same value.
+// ln = LOGK gives the whole element).  Bits inside a wavefront use lane exchanges,
+// higher bits exchange through LDS; every lane ends with the same value.
 template <int DIM, int K, typename T, typename Op>
 __device__ T subreduce(T v, int ln, T *s_x, Op op)
 {
     constexpr int LOGK = Geo<DIM, K>::LOGK;
     const int tid = threadIdx.x;
+#pragma unroll
     for (int a = 0; a < DIM; ++a)
-        for (int b = 0; b < ln; ++b) {
+#pragma unroll
+        for (int b = 0; b < LOGK; ++b) {
+            if (b >= ln) continue;
             int bit = a * LOGK + b;
             int mask = 1 << bit;
             if (bit < 6) {
-                T o = __shfl_xor(v, mask, 64);
+                T o = lane_xor(v, mask);
                 v = op(v, o);
             } else {
                 s_x[tid] = v;
@@ -397,7 +427,8 @@ analyse_kernel(KArgs P)
                 double cs = sqrt(gam * pressure<DIM>(ub, gam) / ub[0]);
                 for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
             }
-            for (int off = 32; off >= 1; off >>= 1) lam = fmax(lam, __shfl_xor(lam, off, 64));
+            #pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) lam = fmax(lam, lane_xor(lam, off));
             if ((tid & 63) == 0) S.lam[tid >> 6] = lam;
             __syncthreads();
             if (tid == 0) {
@@ -887,7 +918,7 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
                     for (int bb = 0; bb < ln; ++bb) {
                         int bit = q * G::LOGK + bb;
                         int mask = 1 << bit;
-                        if (bit < 6) okf &= __shfl_xor(okf, mask, 64);
+                        if (bit < 6) okf &= lane_xor(okf, mask);
                         else {
                             ((int *)S.wsL)[tid] = okf;
                             __syncthreads();
