@@ -149,3 +149,41 @@ def rk3(mesh, params, u, nsteps: int, dt_fixed: float = 0.0):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def _setup_frozen():
+    L = lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.or_rhs_frozen.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), dp, dp, dp, dp]
+    L.or_rhs_frozen.restype = ctypes.c_int
+    L.or_adjoint_rhs.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), dp, dp, dp, dp, dp]
+    L.or_adjoint_rhs.restype = ctypes.c_int
+    return L
+
+
+def rhs_frozen(mesh, params, u, alpha, beta):
+    """Right-hand side with the blending factors and squeezing parameters held fixed."""
+    L = _setup_frozen()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    out = np.zeros_like(u)
+    rc = L.or_rhs_frozen(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(u), _ptr(al), _ptr(be), _ptr(out))
+    if rc != 0:
+        raise OracleError("or_rhs_frozen failed: %d" % rc)
+    return out
+
+
+def adjoint_rhs(mesh, params, u, alpha, beta, lam):
+    """(dL/du)^T lam of the frozen right-hand side at u."""
+    L = _setup_frozen()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.zeros_like(u)
+    rc = L.or_adjoint_rhs(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(u), _ptr(al), _ptr(be),
+                          _ptr(lam), _ptr(out))
+    if rc != 0:
+        raise OracleError("or_adjoint_rhs failed: %d" % rc)
+    return out

@@ -41,6 +41,8 @@ typedef struct {
     double Bhl[MAXK], Bhr[MAXK];    /* nonzero first / last columns of P B^(0) */
     double Ip[MAXK * MAXK];         /* Ip[i][j] = l_j(mu_{i+1/2}) */
     double Im[MAXK * MAXK];         /* Im[i][j] = l_j(mu_{i-1/2}) */
+    /* transposes, for the adjoint */
+    double Rt[MAXK * MAXK], Pt[MAXK * MAXK], Dhatt[MAXK * MAXK], Ipt[MAXK * MAXK], Imt[MAXK * MAXK];
 } lvl_t;
 
 typedef long double ld;
@@ -200,6 +202,14 @@ static int build_level(int n, int fam, lvl_t *L)
             /* subcell interfaces mu_{i+1/2} = -1/2 + (i+1)/n, mu_{i-1/2} = -1/2 + i/n (eq. subcell-grid) */
             L->Ip[i * n + j] = (double)lagr(n, x, j, -0.5L + (ld)(i + 1) / n);
             L->Im[i * n + j] = (double)lagr(n, x, j, -0.5L + (ld)i / n);
+        }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            L->Rt[i * n + j] = L->R[j * n + i];
+            L->Pt[i * n + j] = L->P[j * n + i];
+            L->Dhatt[i * n + j] = L->Dhat[j * n + i];
+            L->Ipt[i * n + j] = L->Ip[j * n + i];
+            L->Imt[i * n + j] = L->Im[j * n + i];
         }
     /* B^(0) has nonzero columns -l_i(-1/2)/w_i (first) and l_i(1/2)/w_i (last)
        (eq. boundary-evalution-matrix, tweak-boundary-evaluation-matrix); Bhat = P B^(0). */
@@ -362,6 +372,7 @@ typedef struct {
     lvl_t L[MAXLEV];   /* tables per DG level index */
     lvl_t Lhalf[MAXLEV];   /* tables of level n/2 (for the indicator), n >= 4 */
     double dx[3];
+    const double *beta_in; /* squeezing parameters of OR_FROZEN mode (nel * A) */
 } ctx_t;
 
 static int ilog2(int n) { int r = 0; while ((1 << r) < n) r++; return r; }
@@ -660,6 +671,10 @@ static void analyse_element(const ctx_t *c, const double *u, int e, double *alph
     double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK];
     gather_elem(c, u, e, ub);
     for (int q = 0; q < c->A; q++) { xraw[q] = NAN; araw[q] = NAN; beta[q] = 1.0; alpha[q] = 0.0; }
+    if (c->p.mode == OR_FROZEN) {
+        for (int q = 0; q < c->A; q++) { alpha[q] = alpha_in[q]; beta[q] = c->beta_in[(long)e * c->A + q]; }
+        return;
+    }
     if (c->p.mode == OR_EXTERNAL) {
         for (int li = 0; li < c->nlev; li++) squeeze_level(c, ub, li, beta);
         for (int q = 0; q < c->A; q++) alpha[q] = alpha_in[q];
@@ -1133,7 +1148,8 @@ static int rhs_ctx(const ctx_t *c, const double *u, double *dudt, double *alpha_
 {
     int rc = check_state(c, u);
     if (rc) return rc;
-    if (c->p.mode == OR_EXTERNAL && !alpha_in) return OR_EINVAL;
+    if ((c->p.mode == OR_EXTERNAL || c->p.mode == OR_FROZEN) && !alpha_in) return OR_EINVAL;
+    if (c->p.mode == OR_FROZEN && !c->beta_in) return OR_EINVAL;
     work_t W;
     if (alloc_work(c, &W)) { free_work(&W); return OR_EINVAL; }
     double *xraw = malloc(sizeof(double) * (size_t)c->nel * c->A);
@@ -1232,7 +1248,7 @@ int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps, double d
     if (!c) return OR_EINVAL;
     int rc = make_ctx(m, p, c);
     if (rc) { free(c); return rc; }
-    if (c->p.mode == OR_EXTERNAL) { free(c); return OR_EINVAL; }
+    if (c->p.mode == OR_EXTERNAL || c->p.mode == OR_FROZEN) { free(c); return OR_EINVAL; }
     size_t n = (size_t)c->nv * c->dof;
     double *L = malloc(sizeof(double) * n), *u1 = malloc(sizeof(double) * n), *u2 = malloc(sizeof(double) * n);
     for (int st = 0; st < nsteps && rc == OR_OK; st++) {
@@ -1260,4 +1276,542 @@ int or_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Frozen linearisation and its adjoint                                       */
+/* ------------------------------------------------------------------------- */
+/* With the blending factors alpha and the squeezing parameters beta held
+   fixed, the right-hand side is a composition of linear maps (reconstruction,
+   squeeze with fixed beta, traces, face means, projections, D-hat, B-hat, the
+   blend) and pointwise nonlinear maps (Euler flux, HLLE).  The adjoint runs the
+   three passes backwards: pass 3 (level right-hand sides) -> face-flux and
+   state adjoints, pass 2 (common fluxes) -> interface-state adjoints, pass 1
+   (interface states) -> state adjoints.  Linear maps are applied transposed;
+   the Jacobians of the pointwise maps come from forward-mode dual numbers
+   evaluated at u (taking the branch of every min/max that is active there). */
+
+#define ND (2 * MAXV)
+typedef struct { double v; double d[ND]; } dual;
+
+static dual dconst(double x) { dual r; r.v = x; memset(r.d, 0, sizeof(r.d)); return r; }
+static dual dadd(dual a, dual b) { dual r; r.v = a.v + b.v; for (int k = 0; k < ND; k++) r.d[k] = a.d[k] + b.d[k]; return r; }
+static dual dsub(dual a, dual b) { dual r; r.v = a.v - b.v; for (int k = 0; k < ND; k++) r.d[k] = a.d[k] - b.d[k]; return r; }
+static dual dmul(dual a, dual b) { dual r; r.v = a.v * b.v; for (int k = 0; k < ND; k++) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+static dual ddiv(dual a, dual b)
+{
+    dual r;
+    r.v = a.v / b.v;
+    for (int k = 0; k < ND; k++) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+}
+static dual dscal(dual a, double s) { dual r; r.v = a.v * s; for (int k = 0; k < ND; k++) r.d[k] = a.d[k] * s; return r; }
+static dual dsqrt(dual a)
+{
+    dual r;
+    r.v = sqrt(a.v);
+    for (int k = 0; k < ND; k++) r.d[k] = r.v > 0.0 ? a.d[k] / (2.0 * r.v) : 0.0;
+    return r;
+}
+static dual dmin(dual a, dual b) { return (b.v < a.v) ? b : a; }
+static dual dmax(dual a, dual b) { return (b.v > a.v) ? b : a; }
+
+static dual pressure_d(int dim, double g, const dual *u)
+{
+    dual m2 = dconst(0.0);
+    for (int a = 0; a < dim; a++) m2 = dadd(m2, dmul(u[1 + a], u[1 + a]));
+    return dscal(dsub(u[dim + 1], dscal(ddiv(m2, u[0]), 0.5)), g - 1.0);
+}
+
+static void euler_flux_d(int dim, double g, int a, const dual *u, dual *f)
+{
+    dual p = pressure_d(dim, g, u);
+    dual va = ddiv(u[1 + a], u[0]);
+    f[0] = u[1 + a];
+    for (int b = 0; b < dim; b++) f[1 + b] = (a == b) ? dadd(dmul(u[1 + b], va), p) : dmul(u[1 + b], va);
+    f[dim + 1] = dmul(va, dadd(u[dim + 1], p));
+}
+
+/* the HLLE formula of hlle(), in dual numbers */
+static void hlle_d(int dim, double g, int a, const dual *uL, const dual *uR, dual *fs)
+{
+    int nv = dim + 2;
+    dual fL[MAXV], fR[MAXV];
+    euler_flux_d(dim, g, a, uL, fL);
+    euler_flux_d(dim, g, a, uR, fR);
+    dual pL = pressure_d(dim, g, uL), pR = pressure_d(dim, g, uR);
+    dual vL = ddiv(uL[1 + a], uL[0]), vR = ddiv(uR[1 + a], uR[0]);
+    dual zero = dconst(0.0);
+    dual cL = dsqrt(dmax(ddiv(dscal(pL, g), uL[0]), zero)), cR = dsqrt(dmax(ddiv(dscal(pR, g), uR[0]), zero));
+    dual sqL = dsqrt(uL[0]), sqR = dsqrt(uR[0]);
+    dual HL = ddiv(dadd(uL[dim + 1], pL), uL[0]), HR = ddiv(dadd(uR[dim + 1], pR), uR[0]);
+    dual vt2 = dconst(0.0), vtn = dconst(0.0);
+    for (int b = 0; b < dim; b++) {
+        dual vb = ddiv(dadd(dmul(sqL, ddiv(uL[1 + b], uL[0])), dmul(sqR, ddiv(uR[1 + b], uR[0]))), dadd(sqL, sqR));
+        vt2 = dadd(vt2, dmul(vb, vb));
+        if (b == a) vtn = vb;
+    }
+    dual Ht = ddiv(dadd(dmul(sqL, HL), dmul(sqR, HR)), dadd(sqL, sqR));
+    dual ct = dsqrt(dmax(dscal(dsub(Ht, dscal(vt2, 0.5)), g - 1.0), zero));
+    dual SL = dmin(dsub(vL, cL), dsub(vtn, ct));
+    dual SR = dmax(dadd(vR, cR), dadd(vtn, ct));
+    dual SLm = dmin(SL, zero), SRp = dmax(SR, zero);
+    dual den = dsub(SRp, SLm);
+    dual inv = den.v > 0.0 ? ddiv(dconst(1.0), den) : dconst(0.0);
+    for (int v = 0; v < nv; v++)
+        fs[v] = dmul(dadd(dsub(dmul(SRp, fL[v]), dmul(SLm, fR[v])), dmul(dmul(SLm, SRp), dsub(uR[v], uL[v]))), inv);
+}
+
+/* J[v][k] = d HLLE_v / d (uL, uR)_k, k < nv: left inputs, k >= nv: right inputs */
+static void hlle_jac(int dim, double g, int a, const double *uL, const double *uR, double J[MAXV][ND])
+{
+    int nv = dim + 2;
+    dual dl[MAXV], dr[MAXV], fs[MAXV];
+    for (int v = 0; v < nv; v++) {
+        dl[v] = dconst(uL[v]);
+        dr[v] = dconst(uR[v]);
+        dl[v].d[v] = 1.0;
+        dr[v].d[nv + v] = 1.0;
+    }
+    hlle_d(dim, g, a, dl, dr, fs);
+    for (int v = 0; v < nv; v++)
+        for (int k = 0; k < 2 * nv; k++) J[v][k] = fs[v].d[k];
+}
+
+/* J[v][k] = d f_a,v / d u_k */
+static void flux_jac(int dim, double g, int a, const double *u, double J[MAXV][ND])
+{
+    int nv = dim + 2;
+    dual du[MAXV], f[MAXV];
+    for (int v = 0; v < nv; v++) {
+        du[v] = dconst(u[v]);
+        du[v].d[v] = 1.0;
+    }
+    euler_flux_d(dim, g, a, du, f);
+    for (int v = 0; v < nv; v++)
+        for (int k = 0; k < nv; k++) J[v][k] = f[v].d[k];
+}
+
+/* Adjoint of the squeezed reconstruction ut = (1-b) mean(us) + b (us x_all R):
+   gus += b (gut x_all R^T) + (1-b)/nd sum(gut). */
+static void squeeze_recon_adjoint(const ctx_t *c, const lvl_t *L, double b, const double *gut, double *gus)
+{
+    int n = L->n, nd = 1;
+    for (int a = 0; a < c->dim; a++) nd *= n;
+    double t[MAXK * MAXK * MAXK], tmp[MAXK * MAXK * MAXK];
+    for (int v = 0; v < c->nv; v++) {
+        memcpy(t, gut + v * nd, sizeof(double) * nd);
+        apply_all(t, tmp, c->dim, n, L->Rt, -1);
+        double s = 0.0;
+        for (int q = 0; q < nd; q++) s += gut[v * nd + q];
+        for (int q = 0; q < nd; q++) gus[v * nd + q] += b * t[q] + (1.0 - b) * s / nd;
+    }
+}
+
+/* squeezed nodal values of one sub-element */
+static void squeezed(const ctx_t *c, const lvl_t *L, double b, const double *us, double *ut)
+{
+    int n = L->n, nd = 1;
+    for (int a = 0; a < c->dim; a++) nd *= n;
+    reconstruct(c, L, us, ut);
+    for (int v = 0; v < c->nv; v++) {
+        double sum = 0.0;
+        for (int q = 0; q < nd; q++) sum += us[v * nd + q];
+        double mean = sum / nd;
+        for (int q = 0; q < nd; q++) ut[v * nd + q] = (1.0 - b) * mean + b * ut[v * nd + q];
+    }
+}
+
+/* scatter a sub-element array (extent n^dim per variable) added into the global state-shaped g */
+static void scatter_sub_add(const ctx_t *c, const int e3[3], int n, int i0, int j0, int k0, const double *gs, double *g)
+{
+    int ny = c->dim > 1 ? n : 1, nz = c->dim > 2 ? n : 1, nd = n * ny * nz;
+    for (int v = 0; v < c->nv; v++)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < n; i++)
+                    g[v * c->dof + gidx(c, e3, i0 + i, j0 + j, k0 + k)] += gs[v * nd + i + n * (j + n * k)];
+}
+
+/* reverse of pass 3 for one element: lam -> face-flux adjoints gF and state adjoints gu */
+static void adj_pass3_element(const ctx_t *c, const double *u, int e, const work_t *W, const double *lam,
+                              double *gF, double *gu)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    double g = c->m.gamma;
+    int e3[3];
+    elem_coords(c, e, e3);
+    int ky = dim > 1 ? K : 1, kz = dim > 2 ? K : 1;
+    const double *beta = W->beta + (long)e * c->A;
+    /* FV part: out += th1 * sum_a -(K/dx_a)(F[right] - F[left]) */
+    for (int k = 0; k < kz; k++)
+        for (int j = 0; j < ky; j++)
+            for (int i = 0; i < K; i++) {
+                long gi = gidx(c, e3, i, j, k);
+                double t1 = W->theta[gi];
+                if (t1 == 0.0) continue;
+                long gg[3] = {(long)e3[0] * K + i, dim > 1 ? (long)e3[1] * K + j : 0, dim > 2 ? (long)e3[2] * K + k : 0};
+                for (int a = 0; a < dim; a++) {
+                    long t = trans_index(c, a, gg);
+                    double sc = K / c->dx[a];
+                    for (int v = 0; v < nv; v++) {
+                        double lv = t1 * lam[v * c->dof + gi];
+                        gF[W->flux_off[a] + flux_index(c, a, gg[a] + 1, t, v)] -= sc * lv;
+                        gF[W->flux_off[a] + flux_index(c, a, gg[a], t, v)] += sc * lv;
+                    }
+                }
+            }
+    /* DG levels */
+    double ub[MAXV * MAXK * MAXK * MAXK];
+    gather_elem(c, u, e, ub);
+    double us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK];
+    double glr[MAXV * MAXK * MAXK * MAXK], gut[MAXV * MAXK * MAXK * MAXK], gus[MAXV * MAXK * MAXK * MAXK];
+    double gv[MAXK * MAXK * MAXK], gfl[MAXV][MAXK * MAXK * MAXK], tmp[MAXK * MAXK * MAXK];
+    for (int li = 0; li < c->nlev; li++) {
+        const lvl_t *L = &c->L[li];
+        int n = L->n, ns = K / n;
+        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+        int ny = dim > 1 ? n : 1, nz = dim > 2 ? n : 1, nd = n * ny * nz;
+        int ext[3] = {n, ny, nz};
+        for (int s3 = 0; s3 < sz; s3++)
+            for (int s2 = 0; s2 < sy; s2++)
+                for (int s1 = 0; s1 < ns; s1++) {
+                    long g0 = gidx(c, e3, s1 * n, s2 * n, s3 * n);
+                    double thn = W->theta[(1 + li) * c->dof + g0];
+                    if (thn == 0.0) continue;
+                    int s = s1 + ns * (s2 + ns * s3);
+                    double b = beta[c->lev_off[li] + s];
+                    gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                    squeezed(c, L, b, us, ut);
+                    for (int v = 0; v < nv; v++)
+                        for (int kk = 0; kk < nz; kk++)
+                            for (int jj = 0; jj < ny; jj++)
+                                for (int ii = 0; ii < n; ii++)
+                                    glr[v * nd + ii + n * (jj + n * kk)] =
+                                        thn * lam[v * c->dof + gidx(c, e3, s1 * n + ii, s2 * n + jj, s3 * n + kk)];
+                    memset(gut, 0, sizeof(double) * nv * nd);
+                    for (int a = 0; a < dim; a++) {
+                        double sc = K / (n * c->dx[a]);
+                        /* surface: lr -= sc (Bhl[lo] F[left] + Bhr[lo] F[right]) */
+                        for (int kk = 0; kk < nz; kk++)
+                            for (int jj = 0; jj < ny; jj++)
+                                for (int ii = 0; ii < n; ii++) {
+                                    int loc[3] = {ii, jj, kk};
+                                    long gg[3] = {(long)e3[0] * K + s1 * n + ii, dim > 1 ? (long)e3[1] * K + s2 * n + jj : 0,
+                                                  dim > 2 ? (long)e3[2] * K + s3 * n + kk : 0};
+                                    long t = trans_index(c, a, gg);
+                                    long fL = gg[a] - loc[a], fR = fL + n;
+                                    int q = ii + n * (jj + n * kk);
+                                    for (int v = 0; v < nv; v++) {
+                                        gF[W->flux_off[a] + flux_index(c, a, fL, t, v)] -= sc * L->Bhl[loc[a]] * glr[v * nd + q];
+                                        gF[W->flux_off[a] + flux_index(c, a, fR, t, v)] -= sc * L->Bhr[loc[a]] * glr[v * nd + q];
+                                    }
+                                }
+                        /* volume: lr += sc (f_a x_a Dhat x_perp P) */
+                        for (int v = 0; v < nv; v++) {
+                            for (int q = 0; q < nd; q++) gv[q] = sc * glr[v * nd + q];
+                            apply_all(gv, tmp, dim, n, L->Pt, a);
+                            mode_product(gv, ext, a, L->Dhatt, n, gfl[v]);
+                        }
+                        for (int q = 0; q < nd; q++) {
+                            double pt[MAXV], J[MAXV][ND];
+                            for (int v = 0; v < nv; v++) pt[v] = ut[v * nd + q];
+                            flux_jac(dim, g, a, pt, J);
+                            for (int w = 0; w < nv; w++) {
+                                double acc = 0.0;
+                                for (int v = 0; v < nv; v++) acc += J[v][w] * gfl[v][q];
+                                gut[w * nd + q] += acc;
+                            }
+                        }
+                    }
+                    memset(gus, 0, sizeof(double) * nv * nd);
+                    squeeze_recon_adjoint(c, L, b, gut, gus);
+                    scatter_sub_add(c, e3, n, s1 * n, s2 * n, s3 * n, gus, gu);
+                }
+    }
+}
+
+/* side-state slot: axis a, side sd (1 = the cell's high face, 0 = low face), cell gi */
+static long side_index(const ctx_t *c, int a, int sd, int v, long gi)
+{
+    return (((long)a * 2 + sd) * c->nv + v) * c->dof + gi;
+}
+
+/* reverse of pass 2 for one face subcell: gF -> interface-state adjoints gside (and gu for
+   FV inputs replaced by subcell means); the forward quantities are recomputed at u */
+static void adj_face(const ctx_t *c, const double *u, const work_t *W, int a, long f, const long gt[3],
+                     const double *gF, double *gside, double *gu)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    double g = c->m.gamma;
+    int Ga = c->G[a];
+    int periodic = c->m.bc[a] == OR_PERIODIC;
+    long gl[3] = {gt[0], gt[1], gt[2]}, gr[3] = {gt[0], gt[1], gt[2]};
+    int haveL = 1, haveR = 1;
+    if (f == 0) { if (periodic) gl[a] = Ga - 1; else haveL = 0; }
+    else gl[a] = f - 1;
+    if (f == Ga) { if (periodic) gr[a] = 0; else haveR = 0; }
+    else gr[a] = f;
+    if (!haveL) gl[a] = gr[a];
+    if (!haveR) gr[a] = gl[a];
+    long il = gl[0] + c->G[0] * (gl[1] + (long)c->G[1] * gl[2]);
+    long ir = gr[0] + c->G[0] * (gr[1] + (long)c->G[1] * gr[2]);
+    /* where the left / right interface states come from (outflow mirrors) */
+    long srcL = haveL ? side_index(c, a, 1, 0, il) : side_index(c, a, 0, 0, ir);
+    long srcR = haveR ? side_index(c, a, 0, 0, ir) : side_index(c, a, 1, 0, il);
+    double uL[MAXV], uR[MAXV];
+    for (int v = 0; v < nv; v++) {
+        uL[v] = W->side[srcL + (long)v * c->dof];
+        uR[v] = W->side[srcR + (long)v * c->dof];
+    }
+    int el3[3], er3[3];
+    for (int b = 0; b < 3; b++) {
+        el3[b] = b < dim ? (int)(gl[b] / K) : 0;
+        er3[b] = b < dim ? (int)(gr[b] / K) : 0;
+    }
+    int eL = el3[0] + c->m.nelem[0] * (el3[1] + c->m.nelem[1] * el3[2]);
+    int eR = er3[0] + c->m.nelem[0] * (er3[1] + c->m.nelem[1] * er3[2]);
+    double srho = fmax(W->scale[2 * eL], W->scale[2 * eR]);
+    double sE = fmax(W->scale[2 * eL + 1], W->scale[2 * eR + 1]);
+    long t = trans_index(c, a, gt);
+    double gFv[MAXV];
+    for (int v = 0; v < nv; v++) gFv[v] = gF[W->flux_off[a] + flux_index(c, a, f, t, v)];
+    int k = (int)(f % K);
+    double thFV = 1.0;
+    for (int li = 0; li < c->nlev; li++) {
+        int n = c->lev_n[li];
+        if (k % n != 0) continue;
+        double tb = 0.5 * (W->theta[(1 + li) * c->dof + il] + W->theta[(1 + li) * c->dof + ir]);
+        if (tb == 0.0) continue;
+        int tax[2], nt = 0;
+        for (int b = 0; b < dim; b++) if (b != a) tax[nt++] = b;
+        long base[3] = {gt[0], gt[1], gt[2]};
+        int pos[2] = {0, 0};
+        for (int q = 0; q < nt; q++) {
+            long gb = gt[tax[q]];
+            long loc = gb % K;
+            base[tax[q]] = gb - loc + (loc / n) * n;
+            pos[q] = (int)(loc % n);
+        }
+        int ext[3] = {n, nt > 1 ? n : 1, 1};
+        if (nt == 0) ext[0] = 1;
+        int nf = ext[0] * ext[1];
+        double sL[MAXV][MAXK * MAXK], sR[MAXV][MAXK * MAXK];
+        long slotL[MAXK * MAXK], slotR[MAXK * MAXK];
+        for (int q1 = 0; q1 < ext[1]; q1++)
+            for (int q0 = 0; q0 < ext[0]; q0++) {
+                long cl[3] = {gl[0], gl[1], gl[2]}, cr[3] = {gr[0], gr[1], gr[2]};
+                if (nt > 0) { cl[tax[0]] = base[tax[0]] + q0; cr[tax[0]] = base[tax[0]] + q0; }
+                if (nt > 1) { cl[tax[1]] = base[tax[1]] + q1; cr[tax[1]] = base[tax[1]] + q1; }
+                long jl = cl[0] + c->G[0] * (cl[1] + (long)c->G[1] * cl[2]);
+                long jr = cr[0] + c->G[0] * (cr[1] + (long)c->G[1] * cr[2]);
+                int q = q0 + ext[0] * q1;
+                slotL[q] = haveL ? side_index(c, a, 1, 0, jl) : side_index(c, a, 0, 0, jr);
+                slotR[q] = haveR ? side_index(c, a, 0, 0, jr) : side_index(c, a, 1, 0, jl);
+                for (int v = 0; v < nv; v++) {
+                    sL[v][q] = W->side[slotL[q] + (long)v * c->dof];
+                    sR[v][q] = W->side[slotR[q] + (long)v * c->dof];
+                }
+            }
+        double nL[MAXV][MAXK * MAXK], nR[MAXV][MAXK * MAXK], tmp[MAXK * MAXK];
+        for (int v = 0; v < nv; v++) {
+            memcpy(nL[v], sL[v], sizeof(double) * nf);
+            memcpy(nR[v], sR[v], sizeof(double) * nf);
+            for (int q = 0; q < nt; q++) {
+                mode_product(nL[v], ext, q, c->L[li].R, n, tmp);
+                memcpy(nL[v], tmp, sizeof(double) * nf);
+                mode_product(nR[v], ext, q, c->L[li].R, n, tmp);
+                memcpy(nR[v], tmp, sizeof(double) * nf);
+            }
+        }
+        int ok = 1;
+        for (int q = 0; q < nf && ok; q++) {
+            double pl[MAXV], pr[MAXV];
+            for (int v = 0; v < nv; v++) { pl[v] = nL[v][q]; pr[v] = nR[v][q]; }
+            if (!flux_admissible(dim, g, pl, srho, sE) || !flux_admissible(dim, g, pr, srho, sE)) ok = 0;
+        }
+        if (!ok) continue;
+        thFV -= tb;
+        /* F += tb * (fn x_perp P)[pos]: weights of the face nodes j are prod_q P[pos_q][j_q] */
+        double gnL[MAXV][MAXK * MAXK], gnR[MAXV][MAXK * MAXK];
+        for (int q1 = 0; q1 < ext[1]; q1++)
+            for (int q0 = 0; q0 < ext[0]; q0++) {
+                int q = q0 + ext[0] * q1;
+                double w = tb;
+                if (nt > 0) w *= c->L[li].P[pos[0] * n + q0];
+                if (nt > 1) w *= c->L[li].P[pos[1] * n + q1];
+                double pl[MAXV], pr[MAXV], J[MAXV][ND];
+                for (int v = 0; v < nv; v++) { pl[v] = nL[v][q]; pr[v] = nR[v][q]; }
+                hlle_jac(dim, g, a, pl, pr, J);
+                for (int x = 0; x < nv; x++) {
+                    double al = 0.0, ar = 0.0;
+                    for (int v = 0; v < nv; v++) {
+                        al += J[v][x] * w * gFv[v];
+                        ar += J[v][nv + x] * w * gFv[v];
+                    }
+                    gnL[x][q] = al;
+                    gnR[x][q] = ar;
+                }
+            }
+        /* nodal states = face means x_perp R  ->  face-mean adjoints = x_perp R^T */
+        for (int v = 0; v < nv; v++) {
+            for (int q = nt - 1; q >= 0; q--) {
+                mode_product(gnL[v], ext, q, c->L[li].Rt, n, tmp);
+                memcpy(gnL[v], tmp, sizeof(double) * nf);
+                mode_product(gnR[v], ext, q, c->L[li].Rt, n, tmp);
+                memcpy(gnR[v], tmp, sizeof(double) * nf);
+            }
+            for (int q = 0; q < nf; q++) {
+                gside[slotL[q] + (long)v * c->dof] += gnL[v][q];
+                gside[slotR[q] + (long)v * c->dof] += gnR[v][q];
+            }
+        }
+    }
+    if (thFV != 0.0) {
+        double aL[MAXV], aR[MAXV], J[MAXV][ND];
+        memcpy(aL, uL, sizeof(aL));
+        memcpy(aR, uR, sizeof(aR));
+        int fbL = 0, fbR = 0;
+        if (!flux_admissible(dim, g, aL, srho, sE)) { for (int v = 0; v < nv; v++) aL[v] = u[v * c->dof + il]; fbL = 1; }
+        if (!flux_admissible(dim, g, aR, srho, sE)) { for (int v = 0; v < nv; v++) aR[v] = u[v * c->dof + ir]; fbR = 1; }
+        hlle_jac(dim, g, a, aL, aR, J);
+        for (int x = 0; x < nv; x++) {
+            double al = 0.0, ar = 0.0;
+            for (int v = 0; v < nv; v++) {
+                al += J[v][x] * thFV * gFv[v];
+                ar += J[v][nv + x] * thFV * gFv[v];
+            }
+            if (fbL) gu[x * c->dof + il] += al;
+            else gside[srcL + (long)x * c->dof] += al;
+            if (fbR) gu[x * c->dof + ir] += ar;
+            else gside[srcR + (long)x * c->dof] += ar;
+        }
+    }
+}
+
+/* reverse of pass 1 for one element: interface-state adjoints -> state adjoints */
+static void adj_pass1_element(const ctx_t *c, const double *u, int e, const work_t *W, const double *gside, double *gu)
+{
+    int dim = c->dim, K = c->K, nv = c->nv;
+    int e3[3];
+    elem_coords(c, e, e3);
+    int ky = dim > 1 ? K : 1, kz = dim > 2 ? K : 1;
+    const double *beta = W->beta + (long)e * c->A;
+    /* FV part of the interface states: theta1 * mean */
+    for (int k = 0; k < kz; k++)
+        for (int j = 0; j < ky; j++)
+            for (int i = 0; i < K; i++) {
+                long gi = gidx(c, e3, i, j, k);
+                double t1 = W->theta[gi];
+                for (int a = 0; a < dim; a++)
+                    for (int sd = 0; sd < 2; sd++)
+                        for (int v = 0; v < nv; v++) gu[v * c->dof + gi] += t1 * gside[side_index(c, a, sd, v, gi)];
+            }
+    double ub[MAXV * MAXK * MAXK * MAXK];
+    gather_elem(c, u, e, ub);
+    double gT[MAXK * MAXK * MAXK], gtr[MAXK * MAXK * MAXK], tmp[MAXK * MAXK * MAXK];
+    double gut[MAXV * MAXK * MAXK * MAXK], gus[MAXV * MAXK * MAXK * MAXK];
+    for (int li = 0; li < c->nlev; li++) {
+        const lvl_t *L = &c->L[li];
+        int n = L->n, ns = K / n;
+        int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+        int ny = dim > 1 ? n : 1, nz = dim > 2 ? n : 1, nd = n * ny * nz;
+        int ext[3] = {n, ny, nz};
+        for (int s3 = 0; s3 < sz; s3++)
+            for (int s2 = 0; s2 < sy; s2++)
+                for (int s1 = 0; s1 < ns; s1++) {
+                    long g0 = gidx(c, e3, s1 * n, s2 * n, s3 * n);
+                    double thn = W->theta[(1 + li) * c->dof + g0];
+                    if (thn == 0.0) continue;
+                    int s = s1 + ns * (s2 + ns * s3);
+                    double b = beta[c->lev_off[li] + s];
+                    memset(gut, 0, sizeof(double) * nv * nd);
+                    for (int a = 0; a < dim; a++)
+                        for (int sd = 0; sd < 2; sd++) {
+                            const double *It = sd ? L->Ipt : L->Imt;
+                            for (int v = 0; v < nv; v++) {
+                                for (int kk = 0; kk < nz; kk++)
+                                    for (int jj = 0; jj < ny; jj++)
+                                        for (int ii = 0; ii < n; ii++) {
+                                            long gi = gidx(c, e3, s1 * n + ii, s2 * n + jj, s3 * n + kk);
+                                            gT[ii + n * (jj + n * kk)] = thn * gside[side_index(c, a, sd, v, gi)];
+                                        }
+                                /* T = ut x_a I x_perp P  ->  gut += gT x_perp P^T x_a I^T */
+                                apply_all(gT, tmp, dim, n, L->Pt, a);
+                                mode_product(gT, ext, a, It, n, gtr);
+                                for (int q = 0; q < nd; q++) gut[v * nd + q] += gtr[q];
+                            }
+                        }
+                    memset(gus, 0, sizeof(double) * nv * nd);
+                    squeeze_recon_adjoint(c, L, b, gut, gus);
+                    scatter_sub_add(c, e3, n, s1 * n, s2 * n, s3 * n, gus, gu);
+                }
+    }
+}
+
+int or_rhs_frozen(const or_mesh *m, const or_params *p, const double *u, const double *alpha,
+                  const double *beta, double *dudt)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return OR_EINVAL;
+    or_params q = *p;
+    q.mode = OR_FROZEN;
+    int rc = make_ctx(m, &q, c);
+    if (rc == OR_OK) {
+        c->beta_in = beta;
+        rc = rhs_ctx(c, u, dudt, NULL, NULL, alpha, NULL, NULL, NULL);
+    }
+    free(c);
+    return rc;
+}
+
+int or_adjoint_rhs(const or_mesh *m, const or_params *p, const double *u, const double *alpha,
+                   const double *beta, const double *lam, double *lam_out)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return OR_EINVAL;
+    or_params q = *p;
+    q.mode = OR_FROZEN;
+    int rc = make_ctx(m, &q, c);
+    if (rc) { free(c); return rc; }
+    c->beta_in = beta;
+    rc = check_state(c, u);
+    if (rc) { free(c); return rc; }
+    work_t W;
+    if (alloc_work(c, &W)) { free_work(&W); free(c); return OR_EINVAL; }
+    double *xraw = malloc(sizeof(double) * (size_t)c->nel * c->A);
+    double *araw = malloc(sizeof(double) * (size_t)c->nel * c->A);
+    for (int e = 0; e < c->nel; e++) pass1_element(c, u, e, &W, alpha, xraw, araw);
+    long ftot = 0;
+    for (int a = 0; a < c->dim; a++) ftot += (long)c->nv * (c->G[a] + 1) * (c->dof / c->G[a]);
+    size_t n = (size_t)c->nv * c->dof;
+    double *gF = calloc((size_t)ftot, sizeof(double));
+    double *gside = calloc((size_t)c->dim * 2 * n, sizeof(double));
+    double *gu = calloc(n, sizeof(double));
+    for (int e = 0; e < c->nel; e++) adj_pass3_element(c, u, e, &W, lam, gF, gu);
+    for (int a = 0; a < c->dim; a++) {
+        long trans = c->dof / c->G[a];
+        /* a periodic axis stores its seam flux twice (faces 0 and G_a): fold the adjoints */
+        if (c->m.bc[a] == OR_PERIODIC)
+            for (long tt = 0; tt < trans; tt++)
+                for (int v = 0; v < c->nv; v++) {
+                    gF[W.flux_off[a] + flux_index(c, a, 0, tt, v)] += gF[W.flux_off[a] + flux_index(c, a, c->G[a], tt, v)];
+                    gF[W.flux_off[a] + flux_index(c, a, c->G[a], tt, v)] = 0.0;
+                }
+        long nfaces = (long)c->G[a] + (c->m.bc[a] == OR_PERIODIC ? 0 : 1);
+        for (long idx = 0; idx < nfaces * trans; idx++) {
+            long f = idx / trans, tt = idx % trans;
+            long gt[3];
+            if (a == 0) { gt[0] = 0; gt[1] = tt % c->G[1]; gt[2] = tt / c->G[1]; }
+            else if (a == 1) { gt[0] = tt % c->G[0]; gt[1] = 0; gt[2] = tt / c->G[0]; }
+            else { gt[0] = tt % c->G[0]; gt[1] = tt / c->G[0]; gt[2] = 0; }
+            adj_face(c, u, &W, a, f, gt, gF, gside, gu);
+        }
+    }
+    for (int e = 0; e < c->nel; e++) adj_pass1_element(c, u, e, &W, gside, gu);
+    memcpy(lam_out, gu, sizeof(double) * n);
+    free(gF); free(gside); free(gu); free(xraw); free(araw);
+    free_work(&W);
+    free(c);
+    return OR_OK;
 }

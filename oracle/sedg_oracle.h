@@ -30,7 +30,7 @@ extern "C" {
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ESTATE = -4 };
 enum { OR_PERIODIC = 0, OR_OUTFLOW = 1 };
 enum { OR_GAUSS = 0, OR_LGL = 1 };
-enum { OR_ADAPTIVE = 0, OR_FORCE_DG = 1, OR_FORCE_FV = 2, OR_EXTERNAL = 3 };
+enum { OR_ADAPTIVE = 0, OR_FORCE_DG = 1, OR_FORCE_FV = 2, OR_EXTERNAL = 3, OR_FROZEN = 4 };
 
 typedef struct or_mesh {
     int dim;            /* 1, 2 or 3 */
@@ -83,6 +83,17 @@ double or_max_dt(const or_mesh *m, const or_params *p, const double *u);
  * step of each step's initial state.  dt_log (nsteps) may be NULL. */
 int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps,
            double dt_fixed, double *dt_log);
+
+/* Right-hand side with frozen blending factors and squeezing parameters
+ * (alpha, beta: nel * A each): the map whose derivative the adjoint transposes. */
+int or_rhs_frozen(const or_mesh *m, const or_params *p, const double *u, const double *alpha,
+                  const double *beta, double *dudt);
+
+/* Adjoint of the frozen right-hand side at u: lam_out = (dL/du)^T lam, with alpha
+ * and beta held fixed, the interface-safety decisions and the HLLE wave-speed
+ * branches taken at u. */
+int or_adjoint_rhs(const or_mesh *m, const or_params *p, const double *u, const double *alpha,
+                   const double *beta, const double *lam, double *lam_out);
 
 /* Number of OpenMP threads the oracle runs with. */
 int or_num_threads(void);

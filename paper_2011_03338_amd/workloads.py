@@ -20,7 +20,7 @@ import numpy as np
 
 PERIODIC, OUTFLOW = 0, 1
 GAUSS, LGL = 0, 1
-ADAPTIVE, FORCE_DG, FORCE_FV, EXTERNAL = 0, 1, 2, 3
+ADAPTIVE, FORCE_DG, FORCE_FV, EXTERNAL, FROZEN = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass
