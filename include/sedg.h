@@ -141,6 +141,46 @@ int sedg_check(sedg_ctx *ctx, long *bad_elem);
 int sedg_profile(sedg_ctx *ctx, int on);
 int sedg_profile_read(sedg_ctx *ctx, double *ms, long *count);
 
+/* ---- frozen map and its adjoint --------------------------------------------
+ * The paper defines the forward scheme only; differentiation is an extension.
+ * The frozen map is the right-hand side with the blending factors alpha and the
+ * squeezing parameters beta of eq. calc-squeezing-parameter held fixed (weights
+ * of eq. blending-weights from alpha), every other step as in sedg_rhs.  Its
+ * adjoint is the exact transposed Jacobian of that map at u: the interface-safety
+ * decisions (non-admissible flux inputs) are taken at u and held, and the
+ * min/max of the HLL-Einfeldt wave speeds are differentiated on the branch the
+ * evaluation at u takes.  alpha and beta are device arrays of sedg_alpha_len
+ * doubles in the layout above (e.g. sedg_rhs's alpha_out / beta_out). */
+
+/* dudt = frozen right-hand side at u.  Any dim and K the context supports. */
+int sedg_rhs_frozen(sedg_ctx *ctx, const double *u, const double *alpha, const double *beta, double *dudt,
+                    void *stream);
+
+/* lam_out = (dL/du)^T lam for the frozen map L at u (vector-Jacobian product).
+ *   u, lam    device, state-shaped (read only)
+ *   lam_out   device, state-shaped output; must alias neither u nor lam
+ * SEDG_EUNSUPPORTED at dim 3 with K = 8 (one element's adjoint data exceed the
+ * on-chip memory of a workgroup).  Allocates the context's adjoint buffers on
+ * first use (SEDG_ENOMEM).  State errors are reported by sedg_check. */
+int sedg_adjoint_rhs(sedg_ctx *ctx, const double *u, const double *alpha, const double *beta, const double *lam,
+                     double *lam_out, void *stream);
+
+/* Doubles in one step tape: the three stage states of one SSP-RK3 step and the
+ * blending factors and squeezing parameters of each stage,
+ * [u^n | u^(1) | u^(2) | alpha x 3 | beta x 3]. */
+long sedg_tape_len(const sedg_ctx *ctx);
+
+/* One SSP-RK3 step of u in place with the step size *dt_dev (device scalar),
+ * recording the step's tape (device, sedg_tape_len doubles, caller-owned).  The
+ * arithmetic is that of sedg_rk_step, so a step replayed from a checkpoint with
+ * the logged step size reproduces the original step bit for bit. */
+int sedg_rk_step_tape(sedg_ctx *ctx, double *u, const double *dt_dev, double *tape, void *stream);
+
+/* Transposed SSP-RK3 step: on entry lam holds dJ/du^(n+1); on return dJ/du^n for
+ * the step recorded in tape, with alpha, beta and the step size frozen.
+ * Same support and allocation rules as sedg_adjoint_rhs. */
+int sedg_adjoint_rk_step(sedg_ctx *ctx, const double *tape, const double *dt_dev, double *lam, void *stream);
+
 /* Host-only: the library's own operator tables of level n (2, 4, 8) for node
  * family fam, in the order xi[n], w[n], Dcal[n*n], D[n*n], bm[n], bp[n],
  * P[n*n], R[n*n], Dhat[n*n], Bhat_left[n], Bhat_right[n], Iplus[n*n],

@@ -20,6 +20,8 @@ struct sedg_level_tab {
     double Im[MAXN * MAXN];     // l_j(mu_{i-1/2})
     double Ep[MAXN * MAXN];     // Ip R
     double Em[MAXN * MAXN];     // Im R
+    // transposes, for the adjoint
+    double RT[MAXN * MAXN], PT[MAXN * MAXN], DhatT[MAXN * MAXN], EpT[MAXN * MAXN], EmT[MAXN * MAXN];
 };
 
 int sedg_build_level(int n, int family, sedg_level_tab *T);

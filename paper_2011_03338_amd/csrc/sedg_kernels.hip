@@ -57,6 +57,9 @@ struct KArgs {
     double *lam_part;       // per-block CFL eigenvalue maxima (nullable)
     const double *dt;       // device scalar step (RK stages)
     int *err;               // smallest bad element index (INT_MAX = none)
+    const double *lam;      // adjoint: input adjoint state
+    double *gfb;            // adjoint: per element, its own share of the flux adjoints on its faces
+    double *acc;            // adjoint RK: running adjoint of the step's initial state
     long long dof;
     int nel;
     int ne[3];
@@ -144,6 +147,194 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
     double inv = den > 0.0 ? 1.0 / den : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fs[v] = (SRp * fL[v] - SLm * fR[v] + SLm * SRp * (uR[v] - uL[v])) * inv;
+}
+
+// ---------------------------------------------------------------------------
+// reverse-mode building blocks of the adjoint (vector-Jacobian products)
+// ---------------------------------------------------------------------------
+
+// gu = (d f_a / d u)^T gf for the Euler flux of eqn. comp-euler-conservative
+template <int DIM>
+__device__ __forceinline__ void euler_flux_adj(const double *u, int a, double g, const double *gf, double *gu)
+{
+    constexpr int NV = DIM + 2;
+    const double ir = 1.0 / u[0];
+    double m2 = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) m2 += u[1 + b] * u[1 + b];
+    const double p = (g - 1.0) * (u[DIM + 1] - 0.5 * m2 * ir);
+    const double va = u[1 + a] * ir;
+    double gp = gf[1 + a] + gf[NV - 1] * va;
+    double gva = gf[NV - 1] * (u[DIM + 1] + p);
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) gva += gf[1 + b] * u[1 + b];
+    double gm[DIM];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) gm[b] = gf[1 + b] * va;
+    gm[a] += gf[0];
+    double gE = gf[NV - 1] * va;
+    double gir = 0.0;
+    // va = m_a ir
+    gm[a] += gva * ir;
+    gir += gva * u[1 + a];
+    // p = (g-1)(E - 0.5 m2 ir)
+    gE += (g - 1.0) * gp;
+    const double gm2 = -0.5 * (g - 1.0) * ir * gp;
+    gir += -0.5 * (g - 1.0) * m2 * gp;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) gm[b] += 2.0 * u[1 + b] * gm2;
+    gu[0] = -gir * ir * ir;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) gu[1 + b] = gm[b];
+    gu[NV - 1] = gE;
+}
+
+// (guL, guR) = (d HLLE / d(uL, uR))^T gfs at (uL, uR), branches of every min/max
+// taken as the forward evaluation takes them
+template <int DIM>
+__device__ void hlle_adj(const double *uL, const double *uR, int a, double g, const double *gfs, double *guL, double *guR)
+{
+    constexpr int NV = DIM + 2;
+    const double *U[2] = {uL, uR};
+    double ir[2], m2[2], p[2], vel[2][DIM], f[2][NV], c[2], sq[2], H[2], q[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const double *w = U[s];
+        ir[s] = 1.0 / w[0];
+        m2[s] = 0.0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) m2[s] += w[1 + b] * w[1 + b];
+        p[s] = (g - 1.0) * (w[DIM + 1] - 0.5 * m2[s] * ir[s]);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) vel[s][b] = w[1 + b] * ir[s];
+        f[s][0] = w[1 + a];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) f[s][1 + b] = w[1 + b] * vel[s][a] + (a == b ? p[s] : 0.0);
+        f[s][NV - 1] = vel[s][a] * (w[DIM + 1] + p[s]);
+        q[s] = g * p[s] * ir[s];
+        c[s] = sqrt(fmax(q[s], 0.0));
+        sq[s] = sqrt(w[0]);
+        H[s] = (w[DIM + 1] + p[s]) * ir[s];
+    }
+    const double S = sq[0] + sq[1];
+    double vt[DIM], vt2 = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        vt[b] = (sq[0] * vel[0][b] + sq[1] * vel[1][b]) / S;
+        vt2 += vt[b] * vt[b];
+    }
+    const double Ht = (sq[0] * H[0] + sq[1] * H[1]) / S;
+    const double ct2 = (g - 1.0) * (Ht - 0.5 * vt2);
+    const double ct = sqrt(fmax(ct2, 0.0));
+    const double aL1 = vel[0][a] - c[0], aL2 = vt[a] - ct;
+    const double aR1 = vel[1][a] + c[1], aR2 = vt[a] + ct;
+    const bool selL2 = aL2 < aL1, selR2 = aR2 > aR1;
+    const double SL = selL2 ? aL2 : aL1, SR = selR2 ? aR2 : aR1;
+    const bool SLpos = 0.0 < SL, SRneg = 0.0 > SR;
+    const double SLm = SLpos ? 0.0 : SL, SRp = SRneg ? 0.0 : SR;
+    const double den = SRp - SLm;
+    const double inv = den > 0.0 ? 1.0 / den : 0.0;
+    // fs = num * inv
+    double gnum[NV], ginv = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double num = SRp * f[0][v] - SLm * f[1][v] + SLm * SRp * (uR[v] - uL[v]);
+        gnum[v] = gfs[v] * inv;
+        ginv += gfs[v] * num;
+    }
+    const double gden = den > 0.0 ? -ginv * inv * inv : 0.0;
+    double gSRp = gden, gSLm = -gden;
+    double gf[2][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double du = uR[v] - uL[v];
+        gSRp += gnum[v] * (f[0][v] + SLm * du);
+        gSLm += gnum[v] * (-f[1][v] + SRp * du);
+        gf[0][v] = gnum[v] * SRp;
+        gf[1][v] = -gnum[v] * SLm;
+        guR[v] = gnum[v] * SLm * SRp;
+        guL[v] = -gnum[v] * SLm * SRp;
+    }
+    const double gSL = SLpos ? 0.0 : gSLm;
+    const double gSR = SRneg ? 0.0 : gSRp;
+    double gvel[2][DIM], gc[2] = {0.0, 0.0}, gvt[DIM], gct = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) { gvel[0][b] = 0.0; gvel[1][b] = 0.0; gvt[b] = 0.0; }
+    if (selL2) { gvt[a] += gSL; gct -= gSL; } else { gvel[0][a] += gSL; gc[0] -= gSL; }
+    if (selR2) { gvt[a] += gSR; gct += gSR; } else { gvel[1][a] += gSR; gc[1] += gSR; }
+    const double gct2 = (ct > 0.0) ? gct / (2.0 * ct) : 0.0;
+    const double gHt = (g - 1.0) * gct2;
+    const double gvt2 = -0.5 * (g - 1.0) * gct2;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) gvt[b] += 2.0 * vt[b] * gvt2;
+    double gsq[2] = {0.0, 0.0}, gS = 0.0, gH[2];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const double gN = gvt[b] / S;
+        gS -= gvt[b] * vt[b] / S;
+        gsq[0] += gN * vel[0][b];
+        gsq[1] += gN * vel[1][b];
+        gvel[0][b] += gN * sq[0];
+        gvel[1][b] += gN * sq[1];
+    }
+    {
+        const double gNH = gHt / S;
+        gS -= gHt * Ht / S;
+        gsq[0] += gNH * H[0];
+        gsq[1] += gNH * H[1];
+        gH[0] = gNH * sq[0];
+        gH[1] = gNH * sq[1];
+    }
+    gsq[0] += gS;
+    gsq[1] += gS;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const double *w = U[s];
+        double *gw = s ? guR : guL;
+        double gp = 0.0, gir = 0.0, gE = 0.0;
+        // H = (E + p) ir
+        gE += gH[s] * ir[s];
+        gp += gH[s] * ir[s];
+        gir += gH[s] * (w[DIM + 1] + p[s]);
+        // sq = sqrt(rho)
+        double grho = sq[s] > 0.0 ? gsq[s] / (2.0 * sq[s]) : 0.0;
+        // c = sqrt(max(q, 0)), q = g p ir
+        if (q[s] > 0.0 && c[s] > 0.0) {
+            const double gq = gc[s] / (2.0 * c[s]);
+            gp += gq * g * ir[s];
+            gir += gq * g * p[s];
+        }
+        // flux
+        const double va = vel[s][a];
+        double gva = gf[s][NV - 1] * (w[DIM + 1] + p[s]);
+        gE += gf[s][NV - 1] * va;
+        gp += gf[s][NV - 1] * va + gf[s][1 + a];
+        double gm[DIM];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            gm[b] = gf[s][1 + b] * va;
+            gva += gf[s][1 + b] * w[1 + b];
+        }
+        gm[a] += gf[s][0];
+        gvel[s][a] += gva;
+        // vel_b = m_b ir
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            gm[b] += gvel[s][b] * ir[s];
+            gir += gvel[s][b] * w[1 + b];
+        }
+        // p = (g-1)(E - 0.5 m2 ir)
+        gE += (g - 1.0) * gp;
+        const double gm2 = -0.5 * (g - 1.0) * ir[s] * gp;
+        gir += -0.5 * (g - 1.0) * m2[s] * gp;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) gm[b] += 2.0 * w[1 + b] * gm2;
+        grho += -gir * ir[s] * ir[s];
+        gw[0] += grho;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) gw[1 + b] += gm[b];
+        gw[NV - 1] += gE;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,6 +1275,642 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
     }
 }
 
+// ---------------------------------------------------------------------------
+// frozen blending factors: preparation kernel
+// ---------------------------------------------------------------------------
+//
+// With alpha and beta given (the frozen map of the adjoint), the residual needs
+// the sub-element means of every level, the element data scales and the face
+// buffer.  For the adjoint the same launch also publishes each element's own
+// share of the flux adjoints on its element faces (the part its neighbour cannot
+// form from its own data).
+
+// Flux-adjoint contributions of one element's subcells to face k (0..K) along axis a
+// at face-plane index t, for the adjoint state lam: the FV part gives
+// -(K/dx_a) theta_FV lam on the cell left of the face and +(K/dx_a) theta_FV lam on
+// the cell right of it; the level-n surface term gives -(K/(n dx_a)) theta_n Bhat lam
+// over the sub-element rows ending (Bhr) or starting (Bhl) at the face.  Cells left
+// (right) of the face exist for k > 0 (k < K).
+template <int DIM, int K, class LV>
+__device__ void own_face_adjoint(const KArgs &P, const double *al, const double (*lam)[Geo<DIM, K>::KD], int a, int k,
+                                 int t, double *gf)
+{
+    typedef Geo<DIM, K> G;
+    constexpr int NV = G::NV;
+    for (int v = 0; v < NV; ++v) gf[v] = 0.0;
+    const double sc = K / P.dx[a];
+    const int st = G::stride(a);
+    double th[MAXLEV + 1];
+    if (k > 0) {
+        const int cl = G::from_trans(t, a, k - 1);
+        theta_cell_of<DIM, K, LV>(al, cl, th);
+        if (th[0] != 0.0)
+            for (int v = 0; v < NV; ++v) gf[v] -= sc * th[0] * lam[v][cl];
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li) {
+            const int n = LV::n(li);
+            if (k % n != 0 || th[1 + li] == 0.0) continue;
+            const sedg_level_tab &T = P.tabs[li];
+            const double w = (K / (n * P.dx[a])) * th[1 + li];
+            for (int lo = 0; lo < n; ++lo) {
+                const int cell = cl - (n - 1 - lo) * st;
+                for (int v = 0; v < NV; ++v) gf[v] -= w * T.Bhr[lo] * lam[v][cell];
+            }
+        }
+    }
+    if (k < K) {
+        const int cr = G::from_trans(t, a, k);
+        theta_cell_of<DIM, K, LV>(al, cr, th);
+        if (th[0] != 0.0)
+            for (int v = 0; v < NV; ++v) gf[v] += sc * th[0] * lam[v][cr];
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li) {
+            const int n = LV::n(li);
+            if (k % n != 0 || th[1 + li] == 0.0) continue;
+            const sedg_level_tab &T = P.tabs[li];
+            const double w = (K / (n * P.dx[a])) * th[1 + li];
+            for (int lo = 0; lo < n; ++lo) {
+                const int cell = cr + lo * st;
+                for (int v = 0; v < NV; ++v) gf[v] -= w * T.Bhl[lo] * lam[v][cell];
+            }
+        }
+    }
+}
+
+// out(t) = sum over the level-n face segment holding face-plane index t of
+// M[lo][m] src(m) (2-D), or M[lo0][m0] M[lo1][m1] src(m0, m1) (3-D); src is a
+// face-plane array of K^(DIM-1) values
+template <int DIM, int K>
+__device__ __forceinline__ double seg_apply(const double *src, int t, int n, const double *M)
+{
+    if (DIM == 2) {
+        const int lo0 = t & (n - 1), tb0 = t - lo0;
+        double s = 0.0;
+        for (int m = 0; m < n; ++m) s += M[lo0 * n + m] * src[tb0 + m];
+        return s;
+    }
+    const int t0 = t & (K - 1), t1 = t >> Geo<DIM, K>::LOGK;
+    const int lo0 = t0 & (n - 1), tb0 = t0 - lo0, lo1 = t1 & (n - 1), tb1 = t1 - lo1;
+    double s = 0.0;
+    for (int m1 = 0; m1 < n; ++m1) {
+        double a0 = 0.0;
+        for (int m0 = 0; m0 < n; ++m0) a0 += M[lo0 * n + m0] * src[(tb0 + m0) + K * (tb1 + m1)];
+        s += M[lo1 * n + m1] * a0;
+    }
+    return s;
+}
+
+template <int DIM, int K, int TOP, int EPB>
+struct PrepSmem {
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    double u[EPB][G::NV][G::KD];
+    double lam[EPB][G::NV][G::KD];
+    double x[EPB * G::KD];
+    double al[EPB][LV::A];
+    double be[EPB][LV::A];
+    double mean[EPB][G::NV][LV::A];
+};
+
+template <int DIM, int K, int TOP, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int NV = G::NV, KD = G::KD;
+    __shared__ PrepSmem<DIM, K, TOP, EPB> S;
+    const int tid = threadIdx.x;
+    const int le = tid / KD, c = tid % KD;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = e < P.nel;
+    const int ee = act ? e : P.nel - 1;
+    int e3[3];
+    elem3(P, ee, e3);
+    const long long g = gindex<DIM, K>(P, e3, c);
+    const double gam = P.gamma;
+    const bool adj = P.lam != nullptr;
+
+    double ub[NV];
+    bool fin = true;
+    for (int v = 0; v < NV; ++v) {
+        ub[v] = P.u[v * P.dof + g];
+        S.u[le][v][c] = ub[v];
+        fin = fin && isfinite(ub[v]);
+        if (adj) S.lam[le][v][c] = P.lam[v * P.dof + g];
+    }
+    if (act && !(fin && permissible<DIM>(ub, gam))) atomicMin(P.err, e);
+    {
+        double sr = subreduce<DIM, K>(ub[0], G::LOGK, S.x, OpMax());
+        double se = subreduce<DIM, K>(fabs(ub[NV - 1]), G::LOGK, S.x, OpMax());
+        if (act && c == 0) {
+            P.scale[2 * (long long)e] = sr;
+            P.scale[2 * (long long)e + 1] = se;
+        }
+    }
+    for (int q = c; q < LV::A; q += KD) {
+        S.al[le][q] = P.alpha[(long long)ee * LV::A + q];
+        S.be[le][q] = P.beta[(long long)ee * LV::A + q];
+    }
+    // sub-element means of every level (the same reduction as the analyse kernel)
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        const int n = LV::n(li), ln = ilog2i(n);
+        double nd = (DIM == 2) ? n * n : n * n * n;
+        double mn[NV];
+        for (int v = 0; v < NV; ++v) mn[v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+        const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
+        if (leader)
+            for (int v = 0; v < NV; ++v) S.mean[le][v][LV::off(li) + G::subelem(c, n)] = mn[v];
+    }
+    __syncthreads();
+    if (act)
+        for (int q = c; q < LV::A; q += KD)
+            for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * LV::A + q] = S.mean[le][v][q];
+    int sidx[MAXLEV];
+    subidx_all<DIM, K, LV>(c, sidx);
+    double th[MAXLEV + 1];
+    theta_from_alpha<LV>(S.al[le], sidx, th);
+    // blended interface states on the element faces (as in the analyse kernel)
+    for (int a = 0; a < DIM; ++a) {
+        int pos = G::coord(c, a);
+        for (int sd = 0; sd < 2; ++sd) {
+            if (pos != (sd ? K - 1 : 0)) continue;
+            double st[NV];
+            for (int v = 0; v < NV; ++v) st[v] = th[0] * ub[v];
+#pragma unroll
+            for (int li = 0; li < LV::NLEV; ++li) {
+                if (th[1 + li] == 0.0) continue;
+                const sedg_level_tab &T = P.tabs[li];
+                int n = LV::n(li);
+                const double *E = sd ? T.Ep : T.Em;
+                const int q = LV::off(li) + sidx[li];
+                double b = S.be[le][q];
+                for (int v = 0; v < NV; ++v) {
+                    double tr = bapply<DIM, K>(S.u[le][v], c, a, n, E);
+                    st[v] += th[1 + li] * ((1.0 - b) * S.mean[le][v][q] + b * tr);
+                }
+            }
+            if (act)
+                for (int v = 0; v < NV; ++v) P.fbuf[fb_index<DIM, K>(e, a, sd, v, G::trans(c, a))] = st[v];
+            if (adj) {
+                double gf[NV];
+                own_face_adjoint<DIM, K, LV>(P, S.al[le], S.lam[le], a, sd ? K : 0, G::trans(c, a), gf);
+                if (act)
+                    for (int v = 0; v < NV; ++v) P.gfb[fb_index<DIM, K>(e, a, sd, v, G::trans(c, a))] = gf[v];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint kernel: lam_out = (dL/du)^T lam of the frozen right-hand side
+// ---------------------------------------------------------------------------
+//
+// Reverse of the residual kernel, axis by axis, one element per EPB slot, every
+// element writing only its own cells:
+//   (1) flux adjoints gF at every face of the axis: interior faces from the
+//       element's own adjoint state; element faces from the two elements' shares
+//       published by the preparation kernel (so both sides see the same sum);
+//   (2) reverse of the common fluxes on the faces the forward evaluated: the FV
+//       candidate and the level DG candidates (P_perp^T, HLLE Jacobian^T,
+//       R_perp^T), giving adjoints of the blended interface states (GS) and of
+//       subcell means that replaced a flux input (GD); at an element face only the
+//       element's own side is kept, the neighbour does the other;
+//   (3) interface-state adjoints -> state adjoints: theta_FV directly, the level-n
+//       traces through E^T along the axis and the squeeze mean;
+//   (4) DG volume terms: P^T across, Dhat^T along the axis, Euler-flux Jacobian^T
+//       at the squeezed nodal values;
+// and finally the squeezed reconstruction's reverse (R^T on every axis plus the
+// sub-element mean).  The RK variants fuse the transposed SSP-RK3 combinations
+// into the store.
+
+template <int DIM, int K, int TOP, int EPB>
+struct AdjointSmem {
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    double u[EPB][G::NV][G::KD];
+    double lam[EPB][G::NV][G::KD];
+    double gF[EPB][G::NV][(K + 1) * G::KF];
+    double GS[EPB][2][G::NV][G::KD];
+    double GD[EPB][2][G::NV][G::KD];
+    double tmp[EPB][G::NV][G::KD];
+    double al[EPB][LV::A];
+    double be[EPB][LV::A];
+    double mean[EPB][G::NV][LV::A];
+    double nal[EPB][2 * DIM][LV::A];
+    double wsL[EPB * G::KD], wsR[EPB * G::KD];
+    int act[EPB][MAXLEV + 1];
+};
+
+template <int DIM, int K, int TOP, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) adjoint_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int NV = G::NV, KD = G::KD, KF = G::KF;
+    __shared__ AdjointSmem<DIM, K, TOP, EPB> S;
+    const int tid = threadIdx.x;
+    const int le = tid / KD, c = tid % KD;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = e < P.nel;
+    const int ee = act ? e : P.nel - 1;
+    int e3[3];
+    elem3(P, ee, e3);
+    const long long g = gindex<DIM, K>(P, e3, c);
+    const double gam = P.gamma;
+
+    for (int v = 0; v < NV; ++v) {
+        S.u[le][v][c] = P.u[v * P.dof + g];
+        S.lam[le][v][c] = P.lam[v * P.dof + g];
+    }
+    for (int q = c; q < LV::A; q += KD) {
+        S.al[le][q] = P.alpha[(long long)ee * LV::A + q];
+        S.be[le][q] = P.beta[(long long)ee * LV::A + q];
+        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * LV::A + q];
+    }
+    for (int a = 0; a < DIM; ++a)
+        for (int sd = 0; sd < 2; ++sd) {
+            const int nbs = neighbour<DIM>(P, e3, a, sd);
+            const int src = nbs >= 0 ? nbs : ee;
+            for (int q = c; q < LV::A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * LV::A + q];
+        }
+    int sidx[MAXLEV];
+    subidx_all<DIM, K, LV>(c, sidx);
+    double th[MAXLEV + 1];
+    theta_from_alpha<LV>(P.alpha + (long long)ee * LV::A, sidx, th);
+    {
+        int flags = 0;
+        for (int l = 0; l <= LV::NLEV; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
+        flags = subreduce<DIM, K>(flags, G::LOGK, (int *)S.wsL, OpOr());
+        if (c == 0)
+            for (int l = 0; l <= MAXLEV; ++l) S.act[le][l] = (flags >> l) & 1;
+    }
+    const double own_sr = P.scale[2 * (long long)ee], own_se = P.scale[2 * (long long)ee + 1];
+    __syncthreads();
+    int actv[MAXLEV + 1];
+    for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
+
+    // squeezed nodal values of every active level at this cell
+    double ut[LV::NLEV][NV];
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        for (int v = 0; v < NV; ++v) ut[li][v] = 0.0;
+        if (!__syncthreads_or(actv[1 + li])) continue;
+        const sedg_level_tab &T = P.tabs[li];
+        const int n = LV::n(li);
+        if (DIM == 2) {
+            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) ut[li][v] = bapply<DIM, K>(S.tmp[le][v], c, 1, n, T.R);
+        } else {
+            for (int v = 0; v < NV; ++v) S.GS[le][0][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.GS[le][0][v], c, 1, n, T.R);
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) ut[li][v] = bapply<DIM, K>(S.tmp[le][v], c, 2, n, T.R);
+        }
+        const int s = sidx[li];
+        const double b = S.be[le][LV::off(li) + s];
+        for (int v = 0; v < NV; ++v) ut[li][v] = (1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * ut[li][v];
+        __syncthreads();
+    }
+
+    double gu[NV], gut[LV::NLEV][NV], gm[LV::NLEV][NV];
+    for (int v = 0; v < NV; ++v) {
+        gu[v] = 0.0;
+        for (int li = 0; li < LV::NLEV; ++li) { gut[li][v] = 0.0; gm[li][v] = 0.0; }
+    }
+
+    for (int a = 0; a < DIM; ++a) {
+        const int nbL = neighbour<DIM>(P, e3, a, 0), nbR = neighbour<DIM>(P, e3, a, 1);
+        // ---------------- (1) flux adjoints on every face of axis a ----------------
+        for (int q = c; q < (K + 1) * KF; q += KD) {
+            const int k = q / KF, t = q % KF;
+            double gf[NV];
+            if (k == 0 || k == K) {
+                const int sd = (k == K) ? 1 : 0;
+                const int nb = sd ? nbR : nbL;
+                for (int v = 0; v < NV; ++v) {
+                    double o = nb >= 0 ? P.gfb[fb_index<DIM, K>(nb, a, 1 - sd, v, t)] : 0.0;
+                    gf[v] = P.gfb[fb_index<DIM, K>(ee, a, sd, v, t)] + o;
+                }
+            } else {
+                own_face_adjoint<DIM, K, LV>(P, S.al[le], S.lam[le], a, k, t, gf);
+            }
+            for (int v = 0; v < NV; ++v) S.gF[le][v][q] = gf[v];
+        }
+        for (int sd = 0; sd < 2; ++sd)
+            for (int v = 0; v < NV; ++v) {
+                S.GS[le][sd][v][c] = 0.0;
+                S.GD[le][sd][v][c] = 0.0;
+            }
+        __syncthreads();
+
+        // ---------------- (2) reverse of the common fluxes ----------------
+        int step = K;
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li)
+            if (actv[1 + li]) step = min(step, LV::n(li));
+        if (actv[0]) step = 1;
+        const int nfaces = face_count<K>(1, step);
+        int nfmax = nfaces;
+        if (EPB > 1) {
+            S.wsL[tid] = (double)nfaces;
+            __syncthreads();
+            for (int q = 0; q < EPB; ++q) nfmax = max(nfmax, (int)S.wsL[q * KD]);
+            __syncthreads();
+        }
+        const int slot = c / KF, t = c % KF;
+        for (int r0 = 0; r0 < nfmax; r0 += K) {
+            const int fidx = r0 + slot;
+            int fa = a, k = 0;
+            const bool has = fidx < nfaces;
+            if (has) face_at<K>(a, 1, step, fidx, &fa, &k);
+            const bool lowface = (k == 0), highface = (k == K);
+            double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
+            int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
+            double srho = own_sr, sE = own_se;
+            if (lowface) {
+                int cr = G::from_trans(t, fa, 0), cl = G::from_trans(t, fa, K - 1);
+                for (int v = 0; v < NV; ++v) {
+                    uR[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 0, v, t)];
+                    uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, fa, 1, v, t)] : uR[v];
+                }
+                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
+                mRc = cr;
+                if (nbL >= 0) {
+                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 0], cl, thL);
+                    mLe = nbL;
+                    mLc = cl;
+                    srho = fmax(P.scale[2 * (long long)nbL], own_sr);
+                    sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
+                } else {
+                    for (int l = 0; l <= LV::NLEV; ++l) thL[l] = thR[l];
+                    mLc = cr;
+                }
+            } else if (highface) {
+                int cl = G::from_trans(t, fa, K - 1), cr = G::from_trans(t, fa, 0);
+                for (int v = 0; v < NV; ++v) {
+                    uL[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 1, v, t)];
+                    uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, fa, 0, v, t)] : uL[v];
+                }
+                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
+                mLc = cl;
+                if (nbR >= 0) {
+                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 1], cr, thR);
+                    mRe = nbR;
+                    mRc = cr;
+                    srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
+                    sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
+                } else {
+                    for (int l = 0; l <= LV::NLEV; ++l) thR[l] = thL[l];
+                    mRc = cl;
+                }
+            } else {
+                int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
+                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
+                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
+                mLc = cl;
+                mRc = cr;
+                for (int v = 0; v < NV; ++v) {
+                    uL[v] = thL[0] * S.u[le][v][cl];
+                    uR[v] = thR[0] * S.u[le][v][cr];
+                }
+#pragma unroll
+                for (int li = 0; li < LV::NLEV; ++li) {
+                    const sedg_level_tab &T = P.tabs[li];
+                    int n = LV::n(li);
+                    if (thL[1 + li] != 0.0) {
+                        int s = G::subelem(cl, n);
+                        double b = S.be[le][LV::off(li) + s];
+                        for (int v = 0; v < NV; ++v) {
+                            double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
+                            uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
+                        }
+                    }
+                    if (thR[1 + li] != 0.0) {
+                        int s = G::subelem(cr, n);
+                        double b = S.be[le][LV::off(li) + s];
+                        for (int v = 0; v < NV; ++v) {
+                            double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
+                            uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
+                        }
+                    }
+                }
+            }
+            double gFv[NV];
+            for (int v = 0; v < NV; ++v) gFv[v] = S.gF[le][v][k * KF + t];
+            double guL[NV], guR[NV], gdL[NV], gdR[NV];
+            for (int v = 0; v < NV; ++v) { guL[v] = 0.0; guR[v] = 0.0; gdL[v] = 0.0; gdR[v] = 0.0; }
+            double thFV = 1.0;
+            const int sbase = slot * KF;
+#pragma unroll
+            for (int li = 0; li < LV::NLEV; ++li) {
+                if (!__syncthreads_or(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+                    continue;
+                const sedg_level_tab &T = P.tabs[li];
+                const int n = LV::n(li), ln = ilog2i(n);
+                const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
+                const bool need = has && (k % n == 0) && (tb != 0.0);
+                // nodal face states R_perp uL, R_perp uR
+                double nl[NV], nr[NV];
+                for (int v = 0; v < NV; ++v) {
+                    S.wsL[le * KD + c] = uL[v];
+                    S.wsR[le * KD + c] = uR[v];
+                    __syncthreads();
+                    nl[v] = need ? seg_apply<DIM, K>(&S.wsL[le * KD + sbase], t, n, T.R) : 0.0;
+                    nr[v] = need ? seg_apply<DIM, K>(&S.wsR[le * KD + sbase], t, n, T.R) : 0.0;
+                    __syncthreads();
+                }
+                int okf = need ? ((flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0) : 1;
+                for (int q = 0; q < DIM - 1; ++q)
+                    for (int bb = 0; bb < ln; ++bb) {
+                        int bit = q * G::LOGK + bb;
+                        int mask = 1 << bit;
+                        if (bit < 6) okf &= lane_xor(okf, mask);
+                        else {
+                            ((int *)S.wsL)[tid] = okf;
+                            __syncthreads();
+                            okf &= ((int *)S.wsL)[tid ^ mask];
+                            __syncthreads();
+                        }
+                    }
+                const bool use = need && okf;
+                // face-node flux adjoints tb * P_perp^T gF, then the HLLE Jacobian^T
+                double gnl[NV], gnr[NV];
+                for (int v = 0; v < NV; ++v) { gnl[v] = 0.0; gnr[v] = 0.0; }
+                if (use) {
+                    double gh[NV];
+                    for (int v = 0; v < NV; ++v) gh[v] = tb * seg_apply<DIM, K>(&S.gF[le][v][k * KF], t, n, T.PT);
+                    hlle_adj<DIM>(nl, nr, fa, gam, gh, gnl, gnr);
+                }
+                // back to face means: R_perp^T
+                for (int v = 0; v < NV; ++v) {
+                    S.wsL[le * KD + c] = gnl[v];
+                    S.wsR[le * KD + c] = gnr[v];
+                    __syncthreads();
+                    if (use) {
+                        guL[v] += seg_apply<DIM, K>(&S.wsL[le * KD + sbase], t, n, T.RT);
+                        guR[v] += seg_apply<DIM, K>(&S.wsR[le * KD + sbase], t, n, T.RT);
+                    }
+                    __syncthreads();
+                }
+                if (use) thFV -= tb;
+            }
+            if (has && thFV != 0.0) {
+                double aL[NV], aR[NV];
+                for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
+                const bool fbL = !flux_admissible<DIM>(aL, gam, srho, sE);
+                const bool fbR = !flux_admissible<DIM>(aR, gam, srho, sE);
+                if (fbL) {
+                    if (mLe < 0) for (int v = 0; v < NV; ++v) aL[v] = S.u[le][v][mLc];
+                    else {
+                        int n3[3];
+                        elem3(P, mLe, n3);
+                        long long gn = gindex<DIM, K>(P, n3, mLc);
+                        for (int v = 0; v < NV; ++v) aL[v] = P.u[v * P.dof + gn];
+                    }
+                }
+                if (fbR) {
+                    if (mRe < 0) for (int v = 0; v < NV; ++v) aR[v] = S.u[le][v][mRc];
+                    else {
+                        int n3[3];
+                        elem3(P, mRe, n3);
+                        long long gn = gindex<DIM, K>(P, n3, mRc);
+                        for (int v = 0; v < NV; ++v) aR[v] = P.u[v * P.dof + gn];
+                    }
+                }
+                double gfs[NV], gaL[NV], gaR[NV];
+                for (int v = 0; v < NV; ++v) { gfs[v] = thFV * gFv[v]; gaL[v] = 0.0; gaR[v] = 0.0; }
+                hlle_adj<DIM>(aL, aR, fa, gam, gfs, gaL, gaR);
+                for (int v = 0; v < NV; ++v) {
+                    if (fbL) gdL[v] += gaL[v]; else guL[v] += gaL[v];
+                    if (fbR) gdR[v] += gaR[v]; else guR[v] += gaR[v];
+                }
+            }
+            if (has) {
+                if (lowface) {
+                    // own side = right; an outflow mirror feeds both sides from it
+                    const int cr = G::from_trans(t, fa, 0);
+                    for (int v = 0; v < NV; ++v) {
+                        S.GS[le][0][v][cr] = guR[v] + (nbL < 0 ? guL[v] : 0.0);
+                        S.GD[le][0][v][cr] = gdR[v] + (nbL < 0 ? gdL[v] : 0.0);
+                    }
+                } else if (highface) {
+                    const int cl = G::from_trans(t, fa, K - 1);
+                    for (int v = 0; v < NV; ++v) {
+                        S.GS[le][1][v][cl] = guL[v] + (nbR < 0 ? guR[v] : 0.0);
+                        S.GD[le][1][v][cl] = gdL[v] + (nbR < 0 ? gdR[v] : 0.0);
+                    }
+                } else {
+                    const int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
+                    for (int v = 0; v < NV; ++v) {
+                        S.GS[le][1][v][cl] = guL[v];
+                        S.GS[le][0][v][cr] = guR[v];
+                        S.GD[le][1][v][cl] = gdL[v];
+                        S.GD[le][0][v][cr] = gdR[v];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---------------- (3) interface-state adjoints -> state adjoints ----------------
+        {
+            double gs[NV];
+            for (int v = 0; v < NV; ++v) {
+                gs[v] = S.GS[le][0][v][c] + S.GS[le][1][v][c];
+                gu[v] += th[0] * gs[v] + S.GD[le][0][v][c] + S.GD[le][1][v][c];
+            }
+#pragma unroll
+            for (int li = 0; li < LV::NLEV; ++li) {
+                const double thn = th[1 + li];
+                if (thn == 0.0) continue;
+                const sedg_level_tab &T = P.tabs[li];
+                const int n = LV::n(li);
+                const double b = S.be[le][LV::off(li) + sidx[li]];
+                for (int v = 0; v < NV; ++v) {
+                    double tr = bapply<DIM, K>(S.GS[le][0][v], c, a, n, T.EmT) + bapply<DIM, K>(S.GS[le][1][v], c, a, n, T.EpT);
+                    gu[v] += thn * b * tr;
+                    gm[li][v] += thn * gs[v];
+                }
+            }
+        }
+
+        // ---------------- (4) DG volume terms along a ----------------
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li) {
+            if (!__syncthreads_or(actv[1 + li])) continue;
+            const sedg_level_tab &T = P.tabs[li];
+            const int n = LV::n(li);
+            const double thn = th[1 + li];
+            const double sc = K / (n * P.dx[a]);
+            double gv[NV];
+            for (int v = 0; v < NV; ++v) gv[v] = sc * thn * S.lam[le][v][c];
+            for (int bax = 0; bax < DIM; ++bax) {
+                if (bax == a) continue;
+                __syncthreads();
+                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = gv[v];
+                __syncthreads();
+                for (int v = 0; v < NV; ++v) gv[v] = bapply<DIM, K>(S.tmp[le][v], c, bax, n, T.PT);
+            }
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = gv[v];
+            __syncthreads();
+            double gfl[NV], gj[NV];
+            for (int v = 0; v < NV; ++v) gfl[v] = bapply<DIM, K>(S.tmp[le][v], c, a, n, T.DhatT);
+            if (thn != 0.0) {
+                euler_flux_adj<DIM>(ut[li], a, gam, gfl, gj);
+                for (int v = 0; v < NV; ++v) gut[li][v] += gj[v];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---------------- reverse of the squeezed reconstructions ----------------
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        if (!__syncthreads_or(actv[1 + li])) continue;
+        const sedg_level_tab &T = P.tabs[li];
+        const int n = LV::n(li), ln = ilog2i(n);
+        double y[NV];
+        for (int v = 0; v < NV; ++v) y[v] = gut[li][v];
+        for (int ax = DIM - 1; ax >= 0; --ax) {
+            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = y[v];
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) y[v] = bapply<DIM, K>(S.tmp[le][v], c, ax, n, T.RT);
+            __syncthreads();
+        }
+        double nd = (DIM == 2) ? n * n : n * n * n;
+        double ms[NV];
+        for (int v = 0; v < NV; ++v) ms[v] = subreduce<DIM, K>(gut[li][v] + gm[li][v], ln, S.wsL, OpSum());
+        if (th[1 + li] != 0.0) {
+            const double b = S.be[le][LV::off(li) + sidx[li]];
+            for (int v = 0; v < NV; ++v) gu[v] += b * y[v] + (1.0 - b) * ms[v] / nd;
+        }
+    }
+    if (!act) return;
+    if (P.stage == 0) {
+        for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = gu[v];
+        return;
+    }
+    // transposed SSP-RK3 stages (stage codes 13, 12, 11 reverse stages 3, 2, 1)
+    const double dt = *P.dt;
+    for (int v = 0; v < NV; ++v) {
+        const long long i = v * P.dof + g;
+        const double l = S.lam[le][v][c];
+        if (P.stage == 13) {
+            P.out[i] = (2.0 / 3.0) * (l + dt * gu[v]);
+            P.acc[i] = (1.0 / 3.0) * l;
+        } else if (P.stage == 12) {
+            P.out[i] = 0.25 * (l + dt * gu[v]);
+            P.acc[i] += 0.75 * l;
+        } else {
+            P.out[i] = P.acc[i] + l + dt * gu[v];
+        }
+    }
+}
+
 // CFL step from the eigenvalue maxima folded into LAM_SLOTS slots (eq. cfl-condition);
 // one block of LAM_SLOTS threads, which also clears the slots for the next step.
 __global__ void __launch_bounds__(LAM_SLOTS) finalize_dt_kernel(double *lam_part, int nparts, double num, double *dt,
@@ -1131,6 +1958,7 @@ struct sedg_ctx {
     double dx[3];
     sedg_level_tab *d_tabs;
     double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale, *d_mean;
+    double *d_gfb, *d_l1, *d_l2, *d_acc;   // adjoint (allocated on first use)
     int *d_err, *d_ctr;
     int nblocks;
     hipStream_t last;
@@ -1158,7 +1986,10 @@ void launch_kernel(int which, const KArgs &P, int nblocks, hipStream_t s)
     constexpr int EPBv = (DIM == 2 && K == 4) ? 4 : 1;
     constexpr int threads = EPBv * Geo<DIM, K>::KD;
     if (which == 0) hipLaunchKernelGGL((analyse_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
-    else hipLaunchKernelGGL((residual_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else if (which == 1) hipLaunchKernelGGL((residual_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else if (which == 2) hipLaunchKernelGGL((frozen_prep_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else if constexpr (!(DIM == 3 && K == 8))  // one element's adjoint data exceed the LDS at 3-D K = 8
+        hipLaunchKernelGGL((adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
 }
 
 template <int DIM, int K>
@@ -1180,6 +2011,31 @@ void launch_any(int which, const sedg_ctx *C, const KArgs &P, hipStream_t s)
 
 void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(0, C, P, s); }
 void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(1, C, P, s); }
+void launch_prep_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(2, C, P, s); }
+void launch_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(3, C, P, s); }
+
+bool adjoint_supported(const sedg_ctx *C) { return !(C->mesh.dim == 3 && C->mesh.K == 8); }
+
+// adjoint work buffers, allocated on first use
+int ensure_adjoint_buffers(sedg_ctx *C)
+{
+    if (C->d_gfb) return SEDG_OK;
+    size_t kf = 1;
+    for (int a = 1; a < C->mesh.dim; ++a) kf *= C->mesh.K;
+    size_t nst = (size_t)C->nv * C->dof;
+    bool ok = hipMalloc(&C->d_gfb, sizeof(double) * (size_t)C->nel * C->mesh.dim * 2 * C->nv * kf) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_l1, sizeof(double) * nst) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_l2, sizeof(double) * nst) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_acc, sizeof(double) * nst) == hipSuccess;
+    if (!ok) {
+        void *ptrs[] = {C->d_gfb, C->d_l1, C->d_l2, C->d_acc};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        C->d_gfb = C->d_l1 = C->d_l2 = C->d_acc = nullptr;
+        return SEDG_ENOMEM;
+    }
+    return SEDG_OK;
+}
 
 KArgs base_args(const sedg_ctx *C)
 {
@@ -1336,7 +2192,8 @@ int sedg_destroy(sedg_ctx *C)
     (void)hipDeviceSynchronize();
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
-    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr, C->d_scale, C->d_mean};
+    void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr,
+                    C->d_scale, C->d_mean, C->d_gfb, C->d_l1, C->d_l2, C->d_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
@@ -1519,6 +2376,149 @@ int sedg_check(sedg_ctx *C, long *bad_elem)
     int big = INT_MAX;
     if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
     return SEDG_ESTATE;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// frozen map and adjoint
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int sedg_rhs_frozen(sedg_ctx *C, const double *u, const double *alpha, const double *beta, double *dudt, void *stream)
+{
+    if (!C || !u || !alpha || !beta || !dudt || u == dudt) return SEDG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    KArgs P = base_args(C);
+    P.u = u;
+    P.out = dudt;
+    P.alpha = const_cast<double *>(alpha);
+    P.beta = const_cast<double *>(beta);
+    P.stage = 0;
+    launch_prep_any(C, P, s);
+    launch_residual_any(C, P, s);
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+int sedg_adjoint_rhs(sedg_ctx *C, const double *u, const double *alpha, const double *beta, const double *lam,
+                     double *lam_out, void *stream)
+{
+    if (!C || !u || !alpha || !beta || !lam || !lam_out || lam == lam_out || u == lam_out) return SEDG_EINVAL;
+    if (!adjoint_supported(C)) return SEDG_EUNSUPPORTED;
+    int rc = ensure_adjoint_buffers(C);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    KArgs P = base_args(C);
+    P.u = u;
+    P.lam = lam;
+    P.out = lam_out;
+    P.alpha = const_cast<double *>(alpha);
+    P.beta = const_cast<double *>(beta);
+    P.gfb = C->d_gfb;
+    P.stage = 0;
+    launch_prep_any(C, P, s);
+    launch_adjoint_any(C, P, s);
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+long sedg_tape_len(const sedg_ctx *C)
+{
+    if (!C) return SEDG_EINVAL;
+    return 3L * C->nv * C->dof + 6L * C->A * C->nel;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Tape {
+    double *u[3], *alpha[3], *beta[3];
+};
+
+Tape tape_view(const sedg_ctx *C, double *tape)
+{
+    Tape T;
+    const long ns = (long)C->nv * C->dof, na = (long)C->A * C->nel;
+    for (int k = 0; k < 3; ++k) {
+        T.u[k] = tape + k * ns;
+        T.alpha[k] = tape + 3 * ns + k * na;
+        T.beta[k] = tape + 3 * ns + (3 + k) * na;
+    }
+    return T;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedg_rk_step_tape(sedg_ctx *C, double *u, const double *dt_dev, double *tape, void *stream)
+{
+    if (!C || !u || !dt_dev || !tape) return SEDG_EINVAL;
+    if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Tape T = tape_view(C, tape);
+    if (hipMemcpyAsync(T.u[0], u, sizeof(double) * (size_t)C->nv * C->dof, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return SEDG_EHIP;
+    KArgs P = base_args(C);
+    P.dt = dt_dev;
+    // the three stages of one step, as in sedg_rk_step, with the stage states and the
+    // blending factors and squeezing parameters of every stage kept on the tape
+    P.u = u;
+    P.out = T.u[1];
+    P.alpha = T.alpha[0];
+    P.beta = T.beta[0];
+    P.stage = 1;
+    launch_analyse_any(C, P, s);
+    launch_residual_any(C, P, s);
+    P.u = T.u[1];
+    P.u0 = u;
+    P.out = T.u[2];
+    P.alpha = T.alpha[1];
+    P.beta = T.beta[1];
+    P.stage = 2;
+    launch_analyse_any(C, P, s);
+    launch_residual_any(C, P, s);
+    P.u = T.u[2];
+    P.u0 = u;
+    P.out = u;
+    P.alpha = T.alpha[2];
+    P.beta = T.beta[2];
+    P.stage = 3;
+    launch_analyse_any(C, P, s);
+    launch_residual_any(C, P, s);
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+int sedg_adjoint_rk_step(sedg_ctx *C, const double *tape, const double *dt_dev, double *lam, void *stream)
+{
+    if (!C || !tape || !dt_dev || !lam) return SEDG_EINVAL;
+    if (!adjoint_supported(C)) return SEDG_EUNSUPPORTED;
+    int rc = ensure_adjoint_buffers(C);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Tape T = tape_view(C, const_cast<double *>(tape));
+    KArgs P = base_args(C);
+    P.dt = dt_dev;
+    P.gfb = C->d_gfb;
+    P.acc = C->d_acc;
+    const double *lin[3] = {C->d_l1, C->d_l2, lam};   // adjoint entering reverse stage 1, 2, 3
+    double *lout[3] = {lam, C->d_l1, C->d_l2};
+    for (int st = 2; st >= 0; --st) {
+        P.u = T.u[st];
+        P.alpha = T.alpha[st];
+        P.beta = T.beta[st];
+        P.lam = lin[st];
+        P.out = lout[st];
+        P.stage = 11 + st;
+        launch_prep_any(C, P, s);
+        launch_adjoint_any(C, P, s);
+    }
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
 }
 
 }  // extern "C"

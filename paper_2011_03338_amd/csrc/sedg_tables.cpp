@@ -233,6 +233,14 @@ int sedg_build_level(int n, int family, sedg_level_tab *T)
             T->Em[i * n + j] = (double)em;
         }
     }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            T->RT[i * n + j] = T->R[j * n + i];
+            T->PT[i * n + j] = T->P[j * n + i];
+            T->DhatT[i * n + j] = T->Dhat[j * n + i];
+            T->EpT[i * n + j] = T->Ep[j * n + i];
+            T->EmT[i * n + j] = T->Em[j * n + i];
+        }
     return 0;
 }
 

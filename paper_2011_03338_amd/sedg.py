@@ -5,7 +5,8 @@ the stream from torch's current stream.
 
 The functions mirror the C entry points declared in include/sedg.h:
 sedg_create / sedg_destroy / sedg_rhs / sedg_max_dt / sedg_rk_step / sedg_check
-/ sedg_tables.  A missing or unloadable library raises at first use; there is
+/ sedg_tables, and the frozen map with its adjoint: sedg_rhs_frozen /
+sedg_adjoint_rhs / sedg_tape_len / sedg_rk_step_tape / sedg_adjoint_rk_step.  A missing or unloadable library raises at first use; there is
 no fallback path.
 """
 from __future__ import annotations
@@ -22,7 +23,8 @@ SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED = 0
 
 EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "sedg_set_params",
             "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror",
-            "sedg_profile", "sedg_profile_read"]
+            "sedg_profile", "sedg_profile_read", "sedg_rhs_frozen", "sedg_adjoint_rhs", "sedg_tape_len",
+            "sedg_rk_step_tape", "sedg_adjoint_rk_step"]
 
 
 class SedgError(RuntimeError):
@@ -69,6 +71,12 @@ def load():
     lib.sedg_tables.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
     lib.sedg_profile.argtypes = [vp, ctypes.c_int]
     lib.sedg_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_long)]
+    lib.sedg_rhs_frozen.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sedg_adjoint_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.sedg_tape_len.argtypes = [vp]
+    lib.sedg_tape_len.restype = ctypes.c_long
+    lib.sedg_rk_step_tape.argtypes = [vp, vp, vp, vp, vp]
+    lib.sedg_adjoint_rk_step.argtypes = [vp, vp, vp, vp, vp]
     lib.sedg_strerror.argtypes = [ctypes.c_int]
     lib.sedg_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -169,6 +177,31 @@ class Solver:
     def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, stream=None):
         _check(load().sedg_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log), _stream(stream)),
                "sedg_rk_step")
+
+    def rhs_frozen(self, u, alpha, beta, dudt, stream=None):
+        """Right-hand side with alpha and beta held fixed."""
+        _check(load().sedg_rhs_frozen(self._h, _ptr(u), _ptr(alpha), _ptr(beta), _ptr(dudt), _stream(stream)),
+               "sedg_rhs_frozen")
+
+    def adjoint_rhs(self, u, alpha, beta, lam, lam_out, stream=None):
+        """lam_out = (dL/du)^T lam of the frozen right-hand side at u."""
+        _check(load().sedg_adjoint_rhs(self._h, _ptr(u), _ptr(alpha), _ptr(beta), _ptr(lam), _ptr(lam_out),
+                                       _stream(stream)), "sedg_adjoint_rhs")
+
+    @property
+    def tape_len(self) -> int:
+        return load().sedg_tape_len(self._h)
+
+    def rk_step_tape(self, u, dt_dev, tape, stream=None):
+        """One SSP-RK3 step of u in place with step size dt_dev (a one-element GPU tensor
+        or a view into a step-size log), recording the step's tape."""
+        _check(load().sedg_rk_step_tape(self._h, _ptr(u), _ptr(dt_dev), _ptr(tape), _stream(stream)),
+               "sedg_rk_step_tape")
+
+    def adjoint_rk_step(self, tape, dt_dev, lam, stream=None):
+        """lam <- (du^(n+1)/du^n)^T lam for the step recorded in tape."""
+        _check(load().sedg_adjoint_rk_step(self._h, _ptr(tape), _ptr(dt_dev), _ptr(lam), _stream(stream)),
+               "sedg_adjoint_rk_step")
 
     def profile(self, on: bool):
         _check(load().sedg_profile(self._h, 1 if on else 0), "sedg_profile")

@@ -1,0 +1,308 @@
+"""GPU parity of the frozen right-hand side and its adjoint (vector-Jacobian
+product) against the oracle, of the transposed SSP-RK3 step against the oracle's
+adjoint composed over the three stages, and of the checkpointed
+torch.autograd evolution against central differences of the frozen forward map.
+
+The blending factors and squeezing parameters fed to both sides come from the
+oracle (or from a seeded generator); the adjoint states are seeded normals."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_03338_amd import sedg, workloads as W
+from tests.parity import DEV, say
+
+pytestmark = pytest.mark.gpu
+
+# one frozen right-hand side / one adjoint: the joint relative norm of tests/parity.py
+FROZEN_TOL = 1e-12
+ADJ_TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sedg.load()
+    yield
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _rel(g, o):
+    return np.abs(np.asarray(g) - np.asarray(o)).max() / np.abs(np.asarray(o)).max()
+
+
+def _oracle_frozen_inputs(mesh, u, kind, seed=0):
+    """(alpha, beta): the oracle's own at u, or seeded factors with the oracle's beta."""
+    _, info = O.rhs(mesh, W.Params(), u, full=True)
+    al, be = info["alpha"], info["beta"]
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        al = rng.uniform(0.0, 1.0, al.shape)
+    elif kind == "mid":
+        al = rng.uniform(0.2, 0.8, al.shape)
+    elif kind == "fv":
+        al = np.zeros_like(al)
+    return al, be
+
+
+def _cases():
+    out = []
+    m, u, _ = W.config0(0, 16, 4)
+    out.append(("config0 K4 adaptive", m, u, "adaptive"))
+    m, u, _ = W.config0(1, 6, 8)
+    out.append(("config0 K8 random", m, u, "random"))
+    out.append(("config0 K8 adaptive", m, u, "adaptive"))
+    m, u, _ = W.sedov(2, 6, 8, L=0.3, sigma=0.03)
+    out.append(("sedov resolved adaptive", m, u, "adaptive"))
+    out.append(("sedov resolved mid", m, u, "mid"))
+    out.append(("sedov resolved fv", m, u, "fv"))
+    m, u, _ = W.sedov(1, 7, 4, L=0.3, sigma=0.03)
+    out.append(("sedov K4 7x7 mid", m, u, "mid"))
+    m, u, _ = W.pressure_pulse(0, 6, 8)
+    out.append(("pulse K8 adaptive", m, u, "adaptive"))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_frozen_rhs_matches_oracle(case):
+    label, mesh, u, kind = CASES[case]
+    al, be = _oracle_frozen_inputs(mesh, u, kind)
+    d_o = O.rhs_frozen(mesh, W.Params(), u, al, be)
+    s = sedg.Solver(mesh, W.Params())
+    dg = torch.zeros_like(_t(u))
+    s.rhs_frozen(_t(u), _t(al), _t(be), dg)
+    s.check()
+    err = _rel(dg.cpu().numpy(), d_o)
+    say("  frozen %-26s rel_err=%.3e" % (label, err))
+    assert err <= FROZEN_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("K,ne", [(4, 16), (8, 8)])
+def test_frozen_rhs_equals_adaptive_bitwise(K, ne):
+    """With the factors the adaptive evaluation chose, the frozen map reproduces it
+    bit for bit (same means, same face data, same residual kernel)."""
+    mesh, u, _ = W.sedov(0, ne, K, L=0.3, sigma=0.03)
+    s = sedg.Solver(mesh, W.Params())
+    ug = _t(u)
+    d1 = torch.zeros_like(ug)
+    al = torch.zeros(s.alpha_len, dtype=torch.float64, device=DEV)
+    be = torch.zeros_like(al)
+    s.rhs(ug, d1, al, be)
+    d2 = torch.zeros_like(ug)
+    s.rhs_frozen(ug, al, be, d2)
+    s.check()
+    assert torch.equal(d1, d2)
+    s.close()
+
+
+def _gpu_adjoint(mesh, u, al, be, lam):
+    s = sedg.Solver(mesh, W.Params())
+    out = torch.zeros_like(_t(u))
+    s.adjoint_rhs(_t(u), _t(al), _t(be), _t(lam), out)
+    s.check()
+    r = out.cpu().numpy()
+    s.close()
+    return r
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_adjoint_rhs_matches_oracle(case):
+    label, mesh, u, kind = CASES[case]
+    al, be = _oracle_frozen_inputs(mesh, u, kind)
+    lam = np.random.default_rng(11).standard_normal(u.shape)
+    a_o = O.adjoint_rhs(mesh, W.Params(), u, al, be, lam)
+    a_g = _gpu_adjoint(mesh, u, al, be, lam)
+    err = _rel(a_g, a_o)
+    say("  adjoint %-25s rel_err=%.3e" % (label, err))
+    assert err <= ADJ_TOL
+
+
+def test_adjoint_single_periodic_element():
+    """One periodic element: both element faces are the element's own seam."""
+    K = 8
+    mesh = W.Mesh(2, K, [1, 1], [0, 0], [1, 1], [0, 0])
+    u = W.density_wave(mesh, vel=(0.3, -0.2, 0), amp=0.2)
+    al, be = _oracle_frozen_inputs(mesh, u, "random", seed=4)
+    lam = np.random.default_rng(12).standard_normal(u.shape)
+    err = _rel(_gpu_adjoint(mesh, u, al, be, lam), O.adjoint_rhs(mesh, W.Params(), u, al, be, lam))
+    say("  adjoint single element rel_err=%.3e" % err)
+    assert err <= ADJ_TOL
+
+
+def test_adjoint_3d_k4():
+    mesh = W.Mesh(3, 4, [3, 2, 2], [0.0] * 3, [1.0] * 3, [0, 1, 0])
+    rng = np.random.default_rng(3)
+    u = np.zeros(mesh.shape())
+    u[0] = 1.0 + 0.5 * rng.uniform(size=u[0].shape)
+    u[1] = 0.3 * u[0]
+    u[2] = -0.2 * u[0]
+    u[4] = (1.0 + 0.5 * rng.uniform(size=u[0].shape)) / 0.4 + 0.5 * 0.13 * u[0]
+    al, be = _oracle_frozen_inputs(mesh, u, "random", seed=5)
+    lam = rng.standard_normal(u.shape)
+    err = _rel(_gpu_adjoint(mesh, u, al, be, lam), O.adjoint_rhs(mesh, W.Params(), u, al, be, lam))
+    say("  adjoint 3-D K4 rel_err=%.3e" % err)
+    assert err <= ADJ_TOL
+
+
+def test_adjoint_unsupported_and_invalid():
+    mesh = W.Mesh(3, 8, [1, 1, 1], [0.0] * 3, [1.0] * 3, [0, 0, 0])
+    s = sedg.Solver(mesh, W.Params())
+    x = torch.ones(s.state_len, dtype=torch.float64, device=DEV)
+    a = torch.ones(s.alpha_len, dtype=torch.float64, device=DEV)
+    with pytest.raises(sedg.SedgError) as ei:
+        s.adjoint_rhs(x, a, a, x.clone(), torch.zeros_like(x))
+    assert ei.value.code == sedg.SEDG_EUNSUPPORTED
+    s.close()
+    mesh, u, _ = W.config0(0, 4, 4)
+    s = sedg.Solver(mesh, W.Params())
+    x = _t(u).reshape(-1)
+    a = torch.ones(s.alpha_len, dtype=torch.float64, device=DEV)
+    with pytest.raises(sedg.SedgError) as ei:
+        s.adjoint_rhs(x, a, a, x, x)          # output aliases the input
+    assert ei.value.code == sedg.SEDG_EINVAL
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# transposed RK3 step
+# ---------------------------------------------------------------------------
+
+def _oracle_step_adjoint(mesh, u0, dt, lam3):
+    """The oracle's stage states (adaptive factors at each stage) and the transposed
+    step composed from the oracle's adjoint right-hand side."""
+    p = W.Params()
+    L0, i0 = O.rhs(mesh, p, u0, full=True)
+    u1 = u0 + dt * L0
+    L1, i1 = O.rhs(mesh, p, u1, full=True)
+    u2 = 0.75 * u0 + 0.25 * (u1 + dt * L1)
+    _, i2 = O.rhs(mesh, p, u2, full=True)
+    A = lambda u, info, lam: O.adjoint_rhs(mesh, p, u, info["alpha"], info["beta"], lam)
+    l2 = (2.0 / 3.0) * (lam3 + dt * A(u2, i2, lam3))
+    l1 = 0.25 * (l2 + dt * A(u1, i1, l2))
+    return (1.0 / 3.0) * lam3 + 0.75 * l2 + l1 + dt * A(u0, i0, l1)
+
+
+@pytest.mark.parametrize("name", ["config0", "sedov", "sedov K4", "pulse"])
+def test_adjoint_rk_step_matches_oracle(name):
+    """The blasts here keep every stage state permissible at the CFL step (squeezed
+    sub-elements in both)."""
+    if name == "config0":
+        mesh, u0, _ = W.config0(2, 8, 4)
+    elif name == "sedov":
+        mesh, u0, _ = W.sedov(1, 8, 8)
+    elif name == "sedov K4":
+        mesh, u0, _ = W.sedov(2, 8, 4, L=0.5, sigma=0.05)
+    else:
+        mesh, u0, _ = W.pressure_pulse(1, 6, 8)
+    dt = O.max_dt(mesh, W.Params(), u0)
+    lam3 = np.random.default_rng(21).standard_normal(u0.shape)
+    ref = _oracle_step_adjoint(mesh, u0, dt, lam3)
+    s = sedg.Solver(mesh, W.Params())
+    ug = _t(u0).reshape(-1)
+    tape = torch.zeros(s.tape_len, dtype=torch.float64, device=DEV)
+    dtd = torch.tensor([dt], dtype=torch.float64, device=DEV)
+    s.rk_step_tape(ug, dtd, tape)
+    lam = _t(lam3).reshape(-1)
+    s.adjoint_rk_step(tape, dtd, lam)
+    s.check()
+    err = _rel(lam.cpu().numpy().reshape(u0.shape), ref)
+    say("  adjoint RK step %-10s rel_err=%.3e" % (name, err))
+    assert err <= ADJ_TOL
+    s.close()
+
+
+def test_tape_step_reproduces_rk_step():
+    """A taped step with the logged step size reproduces sedg_rk_step bit for bit."""
+    mesh, u0, _ = W.sedov(0, 8, 8, L=0.3, sigma=0.03)
+    s = sedg.Solver(mesh, W.Params())
+    ua = _t(u0).reshape(-1)
+    ub = ua.clone()
+    log = torch.zeros(3, dtype=torch.float64, device=DEV)
+    s.rk_step(ua, 3, 0.0, log)
+    tape = torch.zeros(s.tape_len, dtype=torch.float64, device=DEV)
+    for j in range(3):
+        s.rk_step_tape(ub, log[j:j + 1], tape)
+    s.check()
+    assert torch.equal(ua, ub)
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# checkpointed autograd evolution vs central differences of the frozen map
+# ---------------------------------------------------------------------------
+
+def _frozen_evolve(s, u0, tapes, dts):
+    """The frozen forward map: every stage with the recorded factors and step sizes."""
+    ns, na = s.state_len, s.alpha_len
+    u = u0.clone()
+    d = torch.zeros_like(u)
+    for tape, dt in zip(tapes, dts):
+        al = [tape[3 * ns + k * na:3 * ns + (k + 1) * na] for k in range(3)]
+        be = [tape[3 * ns + (3 + k) * na:3 * ns + (4 + k) * na] for k in range(3)]
+        s.rhs_frozen(u, al[0], be[0], d)
+        u1 = u + dt * d
+        s.rhs_frozen(u1, al[1], be[1], d)
+        u2 = 0.75 * u + 0.25 * (u1 + dt * d)
+        s.rhs_frozen(u2, al[2], be[2], d)
+        u = (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + dt * d)
+    return u
+
+
+def test_autograd_evolution_finite_differences():
+    """Pulse workload (periodic, K = 8) on 8x8 elements, 25 steps with a checkpoint
+    every 7 steps (ragged last segment).  J = sum of rho^2 |cell| over the centre
+    window [0.4, 0.6]^2; directional derivatives along 8 seeded unit directions
+    against central differences of the frozen map at eps = 1e-6 (relative to the
+    state's magnitude)."""
+    from paper_2011_03338_amd import adjoint as ADJ
+    mesh, u0n, _ = W.pressure_pulse(0, 8, 8)
+    s = sedg.Solver(mesh, W.Params())
+    u0 = _t(u0n).reshape(-1)
+    G = mesh.grid
+    xc = (np.arange(G[0]) + 0.5) / G[0]
+    yc = (np.arange(G[1]) + 0.5) / G[1]
+    win = _t(((yc[:, None] >= 0.4) & (yc[:, None] <= 0.6) & (xc[None, :] >= 0.4) & (xc[None, :] <= 0.6)).astype(float))
+    cell = 1.0 / (G[0] * G[1])
+
+    def J(u):
+        return (u[:G[0] * G[1]].reshape(G[1], G[0]) ** 2 * win).sum() * cell
+
+    nsteps, every = 25, 7
+    x = u0.clone().requires_grad_(True)
+    uT = ADJ.evolve(x, s, nsteps, every)
+    J(uT).backward()
+    grad = x.grad.detach()
+    dts = ADJ.dt_log_of(uT)[:nsteps].clone()
+    # the frozen factors: replay with tapes from the initial state
+    tapes = []
+    u = u0.clone()
+    for j in range(nsteps):
+        t = torch.zeros(s.tape_len, dtype=torch.float64, device=DEV)
+        s.rk_step_tape(u, dts[j:j + 1], t)
+        tapes.append(t)
+    assert torch.equal(u, uT.detach())
+    dtl = [float(v) for v in dts.cpu()]
+    assert torch.allclose(_frozen_evolve(s, u0, tapes, dtl), uT.detach(), rtol=0, atol=1e-12)
+    rng = np.random.default_rng(17)
+    scale = u0.abs()
+    errs = []
+    for k in range(8):
+        v = _t(rng.standard_normal(u0.shape[0])) * scale
+        v = v / v.norm()
+        eps = 1e-6 * u0.norm()
+        jp = J(_frozen_evolve(s, u0 + eps * v, tapes, dtl))
+        jm = J(_frozen_evolve(s, u0 - eps * v, tapes, dtl))
+        fd = float((jp - jm) / (2 * eps))
+        ad = float((grad * v).sum())
+        errs.append(abs(fd - ad) / abs(ad))
+    say("  autograd FD rel errors: " + " ".join("%.1e" % e for e in errs))
+    assert max(errs) <= 1e-5
+    s.close()
