@@ -57,6 +57,71 @@ def cpu_baseline(mesh, params, u, max_seconds=30.0):
             "sample": "one SSP-RK3 step (3 right-hand sides) of the full 256x256-element K=8 blast, %.1f s" % dt}
 
 
+def adjoint_bench(args, dev):
+    """Adjoint workload: 2-D Euler, 128x128 periodic elements over [0,1]^2, K = 8;
+    config-0 state plus a Gaussian pressure pulse (amplitude 5, width 0.05).
+    J = sum of rho^2 |cell| over the cells centred in [0.4, 0.6]^2 after `adj_steps`
+    SSP-RK3 steps (CFL 0.5); gradient with respect to the initial state through the
+    checkpointed autograd evolution (checkpoint every 20 steps, frozen factors and
+    step sizes).  Reports the forward time, the backward time (replay of every
+    segment from its checkpoint plus the transposed steps) and their ratio, and
+    central differences of the frozen map along seeded unit directions."""
+    import numpy as np
+    import torch
+    from paper_2011_03338_amd import adjoint as ADJ, sedg, workloads as W
+    mesh, u0n, info = W.pressure_pulse(args.seed, 128, 8)
+    s = sedg.Solver(mesh, W.Params(cfl=0.5))
+    u0 = torch.from_numpy(u0n).to(dev).reshape(-1)
+    G = mesh.grid
+    xc = (np.arange(G[0]) + 0.5) / G[0]
+    yc = (np.arange(G[1]) + 0.5) / G[1]
+    win = torch.from_numpy(((yc[:, None] >= 0.4) & (yc[:, None] <= 0.6) &
+                            (xc[None, :] >= 0.4) & (xc[None, :] <= 0.6)).astype(np.float64)).to(dev)
+    cell = 1.0 / (G[0] * G[1])
+
+    def J(u):
+        return (u[:G[0] * G[1]].reshape(G[1], G[0]) ** 2 * win).sum() * cell
+
+    x = u0.clone().requires_grad_(True)
+    J(ADJ.evolve(x, s, 3, 20)).backward()           # warm-up: graph capture, buffers
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    x = u0.clone().requires_grad_(True)
+    ev[0].record()
+    uT = ADJ.evolve(x, s, args.adj_steps, 20)
+    jv = J(uT)
+    ev[1].record()
+    jv.backward()
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    grad = x.grad.detach()
+    fd = None
+    if args.adj_fd > 0:
+        dts = ADJ.dt_log_of(uT)[:args.adj_steps].clone()
+        frozen = ADJ.record_frozen(s, u0, dts)
+        rng = np.random.default_rng(args.seed + 1000)
+        eps = 1e-6 * float(u0.norm())
+        errs = []
+        for _ in range(args.adj_fd):
+            v = torch.from_numpy(rng.standard_normal(u0.numel())).to(dev)
+            v = v / v.norm()
+            jp = J(ADJ.frozen_evolve(s, u0 + eps * v, frozen, dts))
+            jm = J(ADJ.frozen_evolve(s, u0 - eps * v, frozen, dts))
+            fdv = float((jp - jm) / (2 * eps))
+            ad = float((grad * v).sum())
+            errs.append(abs(fdv - ad) / max(abs(ad), 1e-300))
+        fd = {"directions": args.adj_fd, "eps_relative_to_norm": 1e-6, "max_rel_err": max(errs),
+              "rel_errs": errs}
+    s.check()
+    dof = mesh.dof
+    return {"workload": "2-D Euler pressure pulse, 128x128 periodic elements, K=8, %d SSP-RK3 steps, "
+                        "checkpoint every 20" % args.adj_steps,
+            "J": float(jv), "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "adjoint_fwd_cost_ratio": bwd_ms / fwd_ms,
+            "fwd_dof_updates_per_s": dof * 3 * args.adj_steps / (fwd_ms * 1e-3),
+            "finite_differences": fd, "pulse_center": info["pulse_center"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +129,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--adj-fd", type=int, default=2, help="finite-difference directions of the adjoint check")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -117,6 +185,8 @@ def main():
                    "algorithmic_GBs": (kb[k] / ((prof[k][0] / prof[k][1]) * 1e-3) / 1e9) if k in kb and prof[k][1] else None}
                for k in prof}
 
+    adj = None if args.no_adjoint else adjoint_bench(args, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(mesh, params, u0)
@@ -141,6 +211,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 

@@ -22,6 +22,12 @@ import torch
 from . import sedg
 
 
+def _segment_dt(solver, every, device):
+    # one step-size buffer per forward call keeps the library's captured step graph
+    # (keyed by the state and log buffers) the same for every segment
+    return torch.zeros(every, dtype=torch.float64, device=device)
+
+
 class RK3Evolve(torch.autograd.Function):
     """u_T = `nsteps` SSP-RK3 steps of u0 with CFL step sizes (state layout of
     sedg_state_len, float64 on the GPU)."""
@@ -32,12 +38,14 @@ class RK3Evolve(torch.autograd.Function):
             raise ValueError("nsteps >= 0 and every >= 1 required")
         u = u0.detach().contiguous().clone()
         dt_log = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=u.device)
+        seg_dt = _segment_dt(solver, every, u.device)
         checkpoints = []
         s = 0
         while s < nsteps:
             checkpoints.append(u.clone())
             m = min(every, nsteps - s)
-            solver.rk_step(u, m, 0.0, dt_log[s:s + m])
+            solver.rk_step(u, m, 0.0, seg_dt)
+            dt_log[s:s + m].copy_(seg_dt[:m])
             s += m
         solver.check()
         ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
@@ -71,3 +79,33 @@ def evolve(u0: torch.Tensor, solver: sedg.Solver, nsteps: int, every: int = 20) 
 def dt_log_of(u_out: torch.Tensor) -> torch.Tensor:
     """The step sizes used by the evolution that produced u_out."""
     return u_out.grad_fn.dt_log
+
+
+def record_frozen(solver: sedg.Solver, u0: torch.Tensor, dt_log: torch.Tensor):
+    """Replay the evolution from u0 with the logged step sizes and return, per step,
+    the (3, 2, alpha_len) blending factors and squeezing parameters of its stages."""
+    ns, na = solver.state_len, solver.alpha_len
+    u = u0.detach().contiguous().clone()
+    tape = torch.empty(solver.tape_len, dtype=torch.float64, device=u.device)
+    out = []
+    for j in range(dt_log.numel()):
+        solver.rk_step_tape(u, dt_log[j:j + 1], tape)
+        out.append(tape[3 * ns:].view(2, 3, na).transpose(0, 1).clone(memory_format=torch.contiguous_format))
+    solver.check()
+    return out
+
+
+def frozen_evolve(solver: sedg.Solver, u0: torch.Tensor, frozen, dt_log: torch.Tensor) -> torch.Tensor:
+    """The frozen forward map: SSP-RK3 with every stage's factors held at `frozen`
+    (from record_frozen) and the logged step sizes; no autograd."""
+    u = u0.detach().contiguous().clone()
+    d = torch.empty_like(u)
+    dts = [float(v) for v in dt_log.cpu()]
+    for fz, dt in zip(frozen, dts):
+        solver.rhs_frozen(u, fz[0, 0], fz[0, 1], d)
+        u1 = u + dt * d
+        solver.rhs_frozen(u1, fz[1, 0], fz[1, 1], d)
+        u2 = 0.75 * u + 0.25 * (u1 + dt * d)
+        solver.rhs_frozen(u2, fz[2, 0], fz[2, 1], d)
+        u = (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + dt * d)
+    return u

@@ -153,6 +153,18 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
 // reverse-mode building blocks of the adjoint (vector-Jacobian products)
 // ---------------------------------------------------------------------------
 
+// The axis a is a run-time value in the kernels: components along a are picked and
+// scattered with selects over the unrolled component loop, never by indexing a
+// register array with a.
+template <int DIM>
+__device__ __forceinline__ double pick(const double *x, int a)
+{
+    double r = x[0];
+#pragma unroll
+    for (int b = 1; b < DIM; ++b) r = (b == a) ? x[b] : r;
+    return r;
+}
+
 // gu = (d f_a / d u)^T gf for the Euler flux of eqn. comp-euler-conservative
 template <int DIM>
 __device__ __forceinline__ void euler_flux_adj(const double *u, int a, double g, const double *gf, double *gu)
@@ -163,29 +175,21 @@ __device__ __forceinline__ void euler_flux_adj(const double *u, int a, double g,
 #pragma unroll
     for (int b = 0; b < DIM; ++b) m2 += u[1 + b] * u[1 + b];
     const double p = (g - 1.0) * (u[DIM + 1] - 0.5 * m2 * ir);
-    const double va = u[1 + a] * ir;
-    double gp = gf[1 + a] + gf[NV - 1] * va;
+    const double ma = pick<DIM>(u + 1, a);
+    const double va = ma * ir;
+    const double gp = pick<DIM>(gf + 1, a) + gf[NV - 1] * va;
     double gva = gf[NV - 1] * (u[DIM + 1] + p);
 #pragma unroll
     for (int b = 0; b < DIM; ++b) gva += gf[1 + b] * u[1 + b];
-    double gm[DIM];
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) gm[b] = gf[1 + b] * va;
-    gm[a] += gf[0];
-    double gE = gf[NV - 1] * va;
-    double gir = 0.0;
-    // va = m_a ir
-    gm[a] += gva * ir;
-    gir += gva * u[1 + a];
-    // p = (g-1)(E - 0.5 m2 ir)
-    gE += (g - 1.0) * gp;
+    const double gE = gf[NV - 1] * va + (g - 1.0) * gp;
     const double gm2 = -0.5 * (g - 1.0) * ir * gp;
-    gir += -0.5 * (g - 1.0) * m2 * gp;
+    const double gir = gva * ma - 0.5 * (g - 1.0) * m2 * gp;
+    // f_0 = m_a, f_(1+b) = m_b va + delta_ab p, f_E = va (E + p); va = m_a / rho;
+    // p = (g - 1)(E - m.m / (2 rho))
 #pragma unroll
-    for (int b = 0; b < DIM; ++b) gm[b] += 2.0 * u[1 + b] * gm2;
+    for (int b = 0; b < DIM; ++b)
+        gu[1 + b] = gf[1 + b] * va + 2.0 * u[1 + b] * gm2 + ((b == a) ? (gf[0] + gva * ir) : 0.0);
     gu[0] = -gir * ir * ir;
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) gu[1 + b] = gm[b];
     gu[NV - 1] = gE;
 }
 
@@ -195,22 +199,16 @@ template <int DIM>
 __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, const double *gfs, double *guL, double *guR)
 {
     constexpr int NV = DIM + 2;
-    const double *U[2] = {uL, uR};
-    double ir[2], m2[2], p[2], vel[2][DIM], f[2][NV], c[2], sq[2], H[2], q[2];
+    double ir[2], m2[2], p[2], va[2], c[2], sq[2], H[2], q[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const double *w = U[s];
+        const double *w = s ? uR : uL;
         ir[s] = 1.0 / w[0];
         m2[s] = 0.0;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) m2[s] += w[1 + b] * w[1 + b];
         p[s] = (g - 1.0) * (w[DIM + 1] - 0.5 * m2[s] * ir[s]);
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) vel[s][b] = w[1 + b] * ir[s];
-        f[s][0] = w[1 + a];
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) f[s][1 + b] = w[1 + b] * vel[s][a] + (a == b ? p[s] : 0.0);
-        f[s][NV - 1] = vel[s][a] * (w[DIM + 1] + p[s]);
+        va[s] = pick<DIM>(w + 1, a) * ir[s];
         q[s] = g * p[s] * ir[s];
         c[s] = sqrt(fmax(q[s], 0.0));
         sq[s] = sqrt(w[0]);
@@ -220,77 +218,83 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
     double vt[DIM], vt2 = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        vt[b] = (sq[0] * vel[0][b] + sq[1] * vel[1][b]) / S;
+        vt[b] = (sq[0] * (uL[1 + b] * ir[0]) + sq[1] * (uR[1 + b] * ir[1])) / S;
         vt2 += vt[b] * vt[b];
     }
+    const double vta = pick<DIM>(vt, a);
     const double Ht = (sq[0] * H[0] + sq[1] * H[1]) / S;
     const double ct2 = (g - 1.0) * (Ht - 0.5 * vt2);
     const double ct = sqrt(fmax(ct2, 0.0));
-    const double aL1 = vel[0][a] - c[0], aL2 = vt[a] - ct;
-    const double aR1 = vel[1][a] + c[1], aR2 = vt[a] + ct;
+    const double aL1 = va[0] - c[0], aL2 = vta - ct;
+    const double aR1 = va[1] + c[1], aR2 = vta + ct;
     const bool selL2 = aL2 < aL1, selR2 = aR2 > aR1;
     const double SL = selL2 ? aL2 : aL1, SR = selR2 ? aR2 : aR1;
     const bool SLpos = 0.0 < SL, SRneg = 0.0 > SR;
     const double SLm = SLpos ? 0.0 : SL, SRp = SRneg ? 0.0 : SR;
     const double den = SRp - SLm;
     const double inv = den > 0.0 ? 1.0 / den : 0.0;
-    // fs = num * inv
-    double gnum[NV], ginv = 0.0;
+    // fs = (SRp fL - SLm fR + SLm SRp (uR - uL)) inv
+    double gnum[NV], ginv = 0.0, gSRp = 0.0, gSLm = 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const double num = SRp * f[0][v] - SLm * f[1][v] + SLm * SRp * (uR[v] - uL[v]);
+        double fl, fr;
+        if (v == 0) { fl = pick<DIM>(uL + 1, a); fr = pick<DIM>(uR + 1, a); }
+        else if (v == NV - 1) { fl = va[0] * (uL[DIM + 1] + p[0]); fr = va[1] * (uR[DIM + 1] + p[1]); }
+        else {
+            fl = uL[v] * va[0] + ((v - 1 == a) ? p[0] : 0.0);
+            fr = uR[v] * va[1] + ((v - 1 == a) ? p[1] : 0.0);
+        }
+        const double du = uR[v] - uL[v];
+        const double num = SRp * fl - SLm * fr + SLm * SRp * du;
         gnum[v] = gfs[v] * inv;
         ginv += gfs[v] * num;
-    }
-    const double gden = den > 0.0 ? -ginv * inv * inv : 0.0;
-    double gSRp = gden, gSLm = -gden;
-    double gf[2][NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double du = uR[v] - uL[v];
-        gSRp += gnum[v] * (f[0][v] + SLm * du);
-        gSLm += gnum[v] * (-f[1][v] + SRp * du);
-        gf[0][v] = gnum[v] * SRp;
-        gf[1][v] = -gnum[v] * SLm;
+        gSRp += gnum[v] * (fl + SLm * du);
+        gSLm += gnum[v] * (-fr + SRp * du);
         guR[v] = gnum[v] * SLm * SRp;
         guL[v] = -gnum[v] * SLm * SRp;
     }
+    const double gden = den > 0.0 ? -ginv * inv * inv : 0.0;
+    gSRp += gden;
+    gSLm -= gden;
     const double gSL = SLpos ? 0.0 : gSLm;
     const double gSR = SRneg ? 0.0 : gSRp;
-    double gvel[2][DIM], gc[2] = {0.0, 0.0}, gvt[DIM], gct = 0.0;
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) { gvel[0][b] = 0.0; gvel[1][b] = 0.0; gvt[b] = 0.0; }
-    if (selL2) { gvt[a] += gSL; gct -= gSL; } else { gvel[0][a] += gSL; gc[0] -= gSL; }
-    if (selR2) { gvt[a] += gSR; gct += gSR; } else { gvel[1][a] += gSR; gc[1] += gSR; }
+    // wave-speed estimates: SL = min(vL - cL, vt_a - ct), SR = max(vR + cR, vt_a + ct)
+    double gva[2], gc[2];
+    gva[0] = selL2 ? 0.0 : gSL;
+    gc[0] = selL2 ? 0.0 : -gSL;
+    gva[1] = selR2 ? 0.0 : gSR;
+    gc[1] = selR2 ? 0.0 : gSR;
+    const double gvta = (selL2 ? gSL : 0.0) + (selR2 ? gSR : 0.0);
+    const double gct = (selR2 ? gSR : 0.0) - (selL2 ? gSL : 0.0);
+    // Roe averages
     const double gct2 = (ct > 0.0) ? gct / (2.0 * ct) : 0.0;
     const double gHt = (g - 1.0) * gct2;
     const double gvt2 = -0.5 * (g - 1.0) * gct2;
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) gvt[b] += 2.0 * vt[b] * gvt2;
-    double gsq[2] = {0.0, 0.0}, gS = 0.0, gH[2];
+    double gsq[2], gS = -gHt * Ht / S, gH[2];
+    gsq[0] = gHt / S * H[0];
+    gsq[1] = gHt / S * H[1];
+    gH[0] = gHt / S * sq[0];
+    gH[1] = gHt / S * sq[1];
+    double gvel[2][DIM];
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        const double gN = gvt[b] / S;
-        gS -= gvt[b] * vt[b] / S;
-        gsq[0] += gN * vel[0][b];
-        gsq[1] += gN * vel[1][b];
-        gvel[0][b] += gN * sq[0];
-        gvel[1][b] += gN * sq[1];
-    }
-    {
-        const double gNH = gHt / S;
-        gS -= gHt * Ht / S;
-        gsq[0] += gNH * H[0];
-        gsq[1] += gNH * H[1];
-        gH[0] = gNH * sq[0];
-        gH[1] = gNH * sq[1];
+        const double gvtb = 2.0 * vt[b] * gvt2 + ((b == a) ? gvta : 0.0);
+        const double gN = gvtb / S;
+        const double v0 = uL[1 + b] * ir[0], v1 = uR[1 + b] * ir[1];
+        gS -= gvtb * vt[b] / S;
+        gsq[0] += gN * v0;
+        gsq[1] += gN * v1;
+        gvel[0][b] = gN * sq[0];
+        gvel[1][b] = gN * sq[1];
     }
     gsq[0] += gS;
     gsq[1] += gS;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const double *w = U[s];
+        const double *w = s ? uR : uL;
         double *gw = s ? guR : guL;
+        const double *gfs_ = gnum;   // flux adjoint of side s: SRp gnum (left), -SLm gnum (right)
+        const double fsc = s ? -SLm : SRp;
         double gp = 0.0, gir = 0.0, gE = 0.0;
         // H = (E + p) ir
         gE += gH[s] * ir[s];
@@ -304,35 +308,33 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
             gp += gq * g * ir[s];
             gir += gq * g * p[s];
         }
-        // flux
-        const double va = vel[s][a];
-        double gva = gf[s][NV - 1] * (w[DIM + 1] + p[s]);
-        gE += gf[s][NV - 1] * va;
-        gp += gf[s][NV - 1] * va + gf[s][1 + a];
+        // flux f_a(w) with adjoint fsc * gnum
+        const double gfE = fsc * gfs_[NV - 1];
+        double gvas = gva[s] + gfE * (w[DIM + 1] + p[s]);
+        gE += gfE * va[s];
+        gp += gfE * va[s] + fsc * pick<DIM>(gfs_ + 1, a);
         double gm[DIM];
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            gm[b] = gf[s][1 + b] * va;
-            gva += gf[s][1 + b] * w[1 + b];
+            const double gfb = fsc * gfs_[1 + b];
+            gm[b] = gfb * va[s];
+            gvas += gfb * w[1 + b];
         }
-        gm[a] += gf[s][0];
-        gvel[s][a] += gva;
-        // vel_b = m_b ir
+        // velocities vel_b = m_b ir (the normal one carries gvas, all carry the Roe parts)
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            gm[b] += gvel[s][b] * ir[s];
-            gir += gvel[s][b] * w[1 + b];
+            const double gvb = gvel[s][b] + ((b == a) ? gvas : 0.0);
+            gm[b] += gvb * ir[s] + ((b == a) ? fsc * gfs_[0] : 0.0);
+            gir += gvb * w[1 + b];
         }
         // p = (g-1)(E - 0.5 m2 ir)
         gE += (g - 1.0) * gp;
         const double gm2 = -0.5 * (g - 1.0) * ir[s] * gp;
         gir += -0.5 * (g - 1.0) * m2[s] * gp;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) gm[b] += 2.0 * w[1 + b] * gm2;
         grho += -gir * ir[s] * ir[s];
         gw[0] += grho;
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) gw[1 + b] += gm[b];
+        for (int b = 0; b < DIM; ++b) gw[1 + b] += gm[b] + 2.0 * w[1 + b] * gm2;
         gw[NV - 1] += gE;
     }
 }
@@ -1466,8 +1468,11 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
 // adjoint kernel: lam_out = (dL/du)^T lam of the frozen right-hand side
 // ---------------------------------------------------------------------------
 //
-// Reverse of the residual kernel, axis by axis, one element per EPB slot, every
-// element writing only its own cells:
+// Reverse of the residual kernel, one element per EPB slot, every element writing
+// only its own cells.  First the DG volume terms of every level (P^T across,
+// Dhat^T along each axis, Euler-flux Jacobian^T at the squeezed nodal values),
+// taken back through the squeezed reconstruction (R^T on every axis plus the
+// sub-element mean).  Then, axis by axis:
 //   (1) flux adjoints gF at every face of the axis: interior faces from the
 //       element's own adjoint state; element faces from the two elements' shares
 //       published by the preparation kernel (so both sides see the same sum);
@@ -1477,12 +1482,9 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
 //       subcell means that replaced a flux input (GD); at an element face only the
 //       element's own side is kept, the neighbour does the other;
 //   (3) interface-state adjoints -> state adjoints: theta_FV directly, the level-n
-//       traces through E^T along the axis and the squeeze mean;
-//   (4) DG volume terms: P^T across, Dhat^T along the axis, Euler-flux Jacobian^T
-//       at the squeezed nodal values;
-// and finally the squeezed reconstruction's reverse (R^T on every axis plus the
-// sub-element mean).  The RK variants fuse the transposed SSP-RK3 combinations
-// into the store.
+//       traces through E^T along the axis and the squeeze mean.
+// Only the state adjoint stays live across the face loop.  The RK variants fuse
+// the transposed SSP-RK3 combinations into the store.
 
 template <int DIM, int K, int TOP, int EPB>
 struct AdjointSmem {
@@ -1503,7 +1505,8 @@ struct AdjointSmem {
 };
 
 template <int DIM, int K, int TOP, int EPB>
-__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) adjoint_kernel(KArgs P)
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
+__attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
 {
     typedef Geo<DIM, K> G;
     typedef Lv<DIM, K, TOP> LV;
@@ -1550,35 +1553,69 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) adjoint_kernel(KArgs 
     int actv[MAXLEV + 1];
     for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
 
-    // squeezed nodal values of every active level at this cell
-    double ut[LV::NLEV][NV];
+    double gu[NV];
+    for (int v = 0; v < NV; ++v) gu[v] = 0.0;
+
+    // ---------------- DG volume terms of every level, reversed through the squeeze ----------------
+    // per level: squeezed nodal values ut; over the axes gut += J_a(ut)^T (sc theta_n lam x_perp P^T
+    // x_a Dhat^T); then gu += b (gut x_all R^T) + (1 - b) / n^DIM * (sum of gut over the sub-element)
 #pragma unroll
     for (int li = 0; li < LV::NLEV; ++li) {
-        for (int v = 0; v < NV; ++v) ut[li][v] = 0.0;
         if (!__syncthreads_or(actv[1 + li])) continue;
         const sedg_level_tab &T = P.tabs[li];
-        const int n = LV::n(li);
+        const int n = LV::n(li), ln = ilog2i(n);
+        const double thn = th[1 + li];
+        const double b = S.be[le][LV::off(li) + sidx[li]];
+        double ut[NV];
         if (DIM == 2) {
             for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
             __syncthreads();
-            for (int v = 0; v < NV; ++v) ut[li][v] = bapply<DIM, K>(S.tmp[le][v], c, 1, n, T.R);
+            for (int v = 0; v < NV; ++v) ut[v] = bapply<DIM, K>(S.tmp[le][v], c, 1, n, T.R);
         } else {
             for (int v = 0; v < NV; ++v) S.GS[le][0][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
             __syncthreads();
             for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.GS[le][0][v], c, 1, n, T.R);
             __syncthreads();
-            for (int v = 0; v < NV; ++v) ut[li][v] = bapply<DIM, K>(S.tmp[le][v], c, 2, n, T.R);
+            for (int v = 0; v < NV; ++v) ut[v] = bapply<DIM, K>(S.tmp[le][v], c, 2, n, T.R);
         }
-        const int s = sidx[li];
-        const double b = S.be[le][LV::off(li) + s];
-        for (int v = 0; v < NV; ++v) ut[li][v] = (1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * ut[li][v];
+        for (int v = 0; v < NV; ++v) ut[v] = (1.0 - b) * S.mean[le][v][LV::off(li) + sidx[li]] + b * ut[v];
+        double gut[NV];
+        for (int v = 0; v < NV; ++v) gut[v] = 0.0;
+        for (int a = 0; a < DIM; ++a) {
+            const double sc = K / (n * P.dx[a]);
+            double gv[NV];
+            for (int v = 0; v < NV; ++v) gv[v] = sc * thn * S.lam[le][v][c];
+            for (int bax = 0; bax < DIM; ++bax) {
+                if (bax == a) continue;
+                __syncthreads();
+                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = gv[v];
+                __syncthreads();
+                for (int v = 0; v < NV; ++v) gv[v] = bapply<DIM, K>(S.tmp[le][v], c, bax, n, T.PT);
+            }
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = gv[v];
+            __syncthreads();
+            double gfl[NV], gj[NV];
+            for (int v = 0; v < NV; ++v) gfl[v] = bapply<DIM, K>(S.tmp[le][v], c, a, n, T.DhatT);
+            if (thn != 0.0) {
+                euler_flux_adj<DIM>(ut, a, gam, gfl, gj);
+                for (int v = 0; v < NV; ++v) gut[v] += gj[v];
+            }
+        }
+        double y[NV];
+        for (int v = 0; v < NV; ++v) y[v] = gut[v];
+        for (int ax = DIM - 1; ax >= 0; --ax) {
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = y[v];
+            __syncthreads();
+            for (int v = 0; v < NV; ++v) y[v] = bapply<DIM, K>(S.tmp[le][v], c, ax, n, T.RT);
+        }
+        const double nd = (DIM == 2) ? n * n : n * n * n;
+        double ms[NV];
+        for (int v = 0; v < NV; ++v) ms[v] = subreduce<DIM, K>(gut[v], ln, S.wsL, OpSum());
+        if (thn != 0.0)
+            for (int v = 0; v < NV; ++v) gu[v] += b * y[v] + (1.0 - b) * ms[v] / nd;
         __syncthreads();
-    }
-
-    double gu[NV], gut[LV::NLEV][NV], gm[LV::NLEV][NV];
-    for (int v = 0; v < NV; ++v) {
-        gu[v] = 0.0;
-        for (int li = 0; li < LV::NLEV; ++li) { gut[li][v] = 0.0; gm[li][v] = 0.0; }
     }
 
     for (int a = 0; a < DIM; ++a) {
@@ -1825,70 +1862,24 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) adjoint_kernel(KArgs 
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
                 const double thn = th[1 + li];
-                if (thn == 0.0) continue;
                 const sedg_level_tab &T = P.tabs[li];
-                const int n = LV::n(li);
+                const int n = LV::n(li), ln = ilog2i(n);
                 const double b = S.be[le][LV::off(li) + sidx[li]];
+                const double nd = (DIM == 2) ? n * n : n * n * n;
                 for (int v = 0; v < NV; ++v) {
-                    double tr = bapply<DIM, K>(S.GS[le][0][v], c, a, n, T.EmT) + bapply<DIM, K>(S.GS[le][1][v], c, a, n, T.EpT);
-                    gu[v] += thn * b * tr;
-                    gm[li][v] += thn * gs[v];
+                    // the trace part through E^T along a; the squeeze-mean part summed over the sub-element
+                    const double ms = subreduce<DIM, K>(thn * gs[v], ln, S.wsL, OpSum());
+                    if (thn != 0.0) {
+                        const double tr = bapply<DIM, K>(S.GS[le][0][v], c, a, n, T.EmT) +
+                                          bapply<DIM, K>(S.GS[le][1][v], c, a, n, T.EpT);
+                        gu[v] += thn * b * tr + (1.0 - b) * ms / nd;
+                    }
                 }
-            }
-        }
-
-        // ---------------- (4) DG volume terms along a ----------------
-#pragma unroll
-        for (int li = 0; li < LV::NLEV; ++li) {
-            if (!__syncthreads_or(actv[1 + li])) continue;
-            const sedg_level_tab &T = P.tabs[li];
-            const int n = LV::n(li);
-            const double thn = th[1 + li];
-            const double sc = K / (n * P.dx[a]);
-            double gv[NV];
-            for (int v = 0; v < NV; ++v) gv[v] = sc * thn * S.lam[le][v][c];
-            for (int bax = 0; bax < DIM; ++bax) {
-                if (bax == a) continue;
-                __syncthreads();
-                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = gv[v];
-                __syncthreads();
-                for (int v = 0; v < NV; ++v) gv[v] = bapply<DIM, K>(S.tmp[le][v], c, bax, n, T.PT);
-            }
-            __syncthreads();
-            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = gv[v];
-            __syncthreads();
-            double gfl[NV], gj[NV];
-            for (int v = 0; v < NV; ++v) gfl[v] = bapply<DIM, K>(S.tmp[le][v], c, a, n, T.DhatT);
-            if (thn != 0.0) {
-                euler_flux_adj<DIM>(ut[li], a, gam, gfl, gj);
-                for (int v = 0; v < NV; ++v) gut[li][v] += gj[v];
             }
         }
         __syncthreads();
     }
 
-    // ---------------- reverse of the squeezed reconstructions ----------------
-#pragma unroll
-    for (int li = 0; li < LV::NLEV; ++li) {
-        if (!__syncthreads_or(actv[1 + li])) continue;
-        const sedg_level_tab &T = P.tabs[li];
-        const int n = LV::n(li), ln = ilog2i(n);
-        double y[NV];
-        for (int v = 0; v < NV; ++v) y[v] = gut[li][v];
-        for (int ax = DIM - 1; ax >= 0; --ax) {
-            for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = y[v];
-            __syncthreads();
-            for (int v = 0; v < NV; ++v) y[v] = bapply<DIM, K>(S.tmp[le][v], c, ax, n, T.RT);
-            __syncthreads();
-        }
-        double nd = (DIM == 2) ? n * n : n * n * n;
-        double ms[NV];
-        for (int v = 0; v < NV; ++v) ms[v] = subreduce<DIM, K>(gut[li][v] + gm[li][v], ln, S.wsL, OpSum());
-        if (th[1 + li] != 0.0) {
-            const double b = S.be[le][LV::off(li) + sidx[li]];
-            for (int v = 0; v < NV; ++v) gu[v] += b * y[v] + (1.0 - b) * ms[v] / nd;
-        }
-    }
     if (!act) return;
     if (P.stage == 0) {
         for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = gu[v];
@@ -2324,6 +2315,12 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
     if (it != C->graphs.end()) {
         exec = it->second;
     } else {
+        // bounded cache: a caller cycling through many state buffers re-captures
+        if (C->graphs.size() >= 16) {
+            if (hipStreamSynchronize(s) != hipSuccess) return SEDG_EHIP;
+            for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
+            C->graphs.clear();
+        }
         hipStream_t cs;
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SEDG_EHIP;
         hipGraph_t graph;

@@ -239,23 +239,6 @@ def test_tape_step_reproduces_rk_step():
 # checkpointed autograd evolution vs central differences of the frozen map
 # ---------------------------------------------------------------------------
 
-def _frozen_evolve(s, u0, tapes, dts):
-    """The frozen forward map: every stage with the recorded factors and step sizes."""
-    ns, na = s.state_len, s.alpha_len
-    u = u0.clone()
-    d = torch.zeros_like(u)
-    for tape, dt in zip(tapes, dts):
-        al = [tape[3 * ns + k * na:3 * ns + (k + 1) * na] for k in range(3)]
-        be = [tape[3 * ns + (3 + k) * na:3 * ns + (4 + k) * na] for k in range(3)]
-        s.rhs_frozen(u, al[0], be[0], d)
-        u1 = u + dt * d
-        s.rhs_frozen(u1, al[1], be[1], d)
-        u2 = 0.75 * u + 0.25 * (u1 + dt * d)
-        s.rhs_frozen(u2, al[2], be[2], d)
-        u = (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + dt * d)
-    return u
-
-
 def test_autograd_evolution_finite_differences():
     """Pulse workload (periodic, K = 8) on 8x8 elements, 25 steps with a checkpoint
     every 7 steps (ragged last segment).  J = sum of rho^2 |cell| over the centre
@@ -281,16 +264,8 @@ def test_autograd_evolution_finite_differences():
     J(uT).backward()
     grad = x.grad.detach()
     dts = ADJ.dt_log_of(uT)[:nsteps].clone()
-    # the frozen factors: replay with tapes from the initial state
-    tapes = []
-    u = u0.clone()
-    for j in range(nsteps):
-        t = torch.zeros(s.tape_len, dtype=torch.float64, device=DEV)
-        s.rk_step_tape(u, dts[j:j + 1], t)
-        tapes.append(t)
-    assert torch.equal(u, uT.detach())
-    dtl = [float(v) for v in dts.cpu()]
-    assert torch.allclose(_frozen_evolve(s, u0, tapes, dtl), uT.detach(), rtol=0, atol=1e-12)
+    frozen = ADJ.record_frozen(s, u0, dts)
+    assert torch.allclose(ADJ.frozen_evolve(s, u0, frozen, dts), uT.detach(), rtol=0, atol=1e-12)
     rng = np.random.default_rng(17)
     scale = u0.abs()
     errs = []
@@ -298,11 +273,12 @@ def test_autograd_evolution_finite_differences():
         v = _t(rng.standard_normal(u0.shape[0])) * scale
         v = v / v.norm()
         eps = 1e-6 * u0.norm()
-        jp = J(_frozen_evolve(s, u0 + eps * v, tapes, dtl))
-        jm = J(_frozen_evolve(s, u0 - eps * v, tapes, dtl))
+        jp = J(ADJ.frozen_evolve(s, u0 + eps * v, frozen, dts))
+        jm = J(ADJ.frozen_evolve(s, u0 - eps * v, frozen, dts))
         fd = float((jp - jm) / (2 * eps))
         ad = float((grad * v).sum())
         errs.append(abs(fd - ad) / abs(ad))
     say("  autograd FD rel errors: " + " ".join("%.1e" % e for e in errs))
-    assert max(errs) <= 1e-5
+    # central differences at this step carry ~1e-7..1e-6 of truncation and rounding
+    assert max(errs) <= 2e-6
     s.close()
