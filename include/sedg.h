@@ -181,6 +181,55 @@ int sedg_rk_step_tape(sedg_ctx *ctx, double *u, const double *dt_dev, double *ta
  * Same support and allocation rules as sedg_adjoint_rhs. */
 int sedg_adjoint_rk_step(sedg_ctx *ctx, const double *tape, const double *dt_dev, double *lam, void *stream);
 
+/* ---- batched ensembles -------------------------------------------------------
+ * Many independent 2-D problems of the scheme above, each with its own mesh
+ * (element counts, box, boundary conditions, K = 4 or 8) and its own CFL step,
+ * sharing the scheme parameters (params->top_level must be 0; EXTERNAL mode is
+ * not available), the ratio of specific heats and the node family.  Their states
+ * sit back to back in one device array: problem p occupies
+ * [sedg_batch_state_offset(p), + 4 * its DOF) in the single-problem layout.
+ * One step advances every problem by one SSP-RK3 step with one launch of the
+ * analyse kernel and one of the residual kernel per stage for the whole
+ * ensemble (plus a per-problem step-size kernel), captured once per
+ * (u, dt_log, fixed) into a HIP graph and replayed. */
+typedef struct sedg_batch sedg_batch;
+
+/* Launch shape of the batched kernels (chosen by an autotuner):
+ *   epb4, epb8     elements per workgroup for K = 4 and K = 8: (4, 1) or (8, 2)
+ *                  (64 or 128 threads)
+ *   blocks_per_cu  0: one workgroup per tile; n > 0: a persistent grid of n
+ *                  workgroups per compute unit, each taking a contiguous run of
+ *                  tiles (at most 64)
+ *   xcd_map        1: workgroups remapped so that each XCD takes a contiguous
+ *                  range of tiles (neighbour face data stay in its L2); 0: none */
+typedef struct sedg_batch_tuning {
+    int epb4, epb8, blocks_per_cu, xcd_map;
+} sedg_batch_tuning;
+
+/* Create an ensemble of count problems (meshes[0..count-1], dim 2).  Returns
+ * SEDG_EUNSUPPORTED for dim != 2 or K not in {4, 8}, SEDG_EINVAL for mixed gamma
+ * or node family, a bad mesh, top_level != 0 or EXTERNAL mode; SEDG_ENOMEM. */
+int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *params, sedg_batch **out);
+int sedg_batch_destroy(sedg_batch *batch);
+
+/* Doubles in the ensemble state; offset of problem p's state (negative on error). */
+long sedg_batch_state_len(const sedg_batch *batch);
+long sedg_batch_state_offset(const sedg_batch *batch, int p);
+
+/* Set / read the launch shape (synchronises the device; drops captured graphs). */
+int sedg_batch_set_tuning(sedg_batch *batch, const sedg_batch_tuning *tuning);
+int sedg_batch_get_tuning(const sedg_batch *batch, sedg_batch_tuning *tuning);
+
+/* Advance every problem by nsteps SSP-RK3 steps in place.  dt_fixed > 0: that step
+ * for all problems; otherwise each problem's own CFL step of each step's initial
+ * state.  dt_log_dev (device, optional, CFL steps only) receives nsteps * count
+ * step sizes, step-major. */
+int sedg_batch_rk_step(sedg_batch *batch, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream);
+
+/* Synchronise and report a non-permissible or non-finite mean value: SEDG_ESTATE
+ * with the problem index and its element index, else SEDG_OK and -1, -1. */
+int sedg_batch_check(sedg_batch *batch, int *bad_problem, long *bad_elem);
+
 /* Host-only: the library's own operator tables of level n (2, 4, 8) for node
  * family fam, in the order xi[n], w[n], Dcal[n*n], D[n*n], bm[n], bp[n],
  * P[n*n], R[n*n], Dhat[n*n], Bhat_left[n], Bhat_right[n], Iplus[n*n],

@@ -43,6 +43,8 @@
 // kernel arguments
 // ---------------------------------------------------------------------------
 
+struct ProbDesc;
+
 struct KArgs {
     const double *u;        // stage state (read)
     const double *u0;       // u^n for RK stages 2, 3
@@ -60,6 +62,14 @@ struct KArgs {
     const double *lam;      // adjoint: input adjoint state
     double *gfb;            // adjoint: per element, its own share of the flux adjoints on its faces
     double *acc;            // adjoint RK: running adjoint of the step's initial state
+    int lam_mask;           // CFL slots - 1 (slot = tile & lam_mask)
+    int err_base;           // added to the element index reported through err
+    // batched ensembles
+    const ProbDesc *probs;  // per problem
+    const int *tile_prob;   // problem of every tile
+    int ntiles;             // tiles of the whole ensemble
+    int chunk;              // consecutive tiles per workgroup
+    int xcd_map;            // remap workgroups to contiguous tile ranges per XCD
     long long dof;
     int nel;
     int ne[3];
@@ -76,9 +86,39 @@ struct KArgs {
     double gamma, tau_A, tau_S, alpha_H, alpha_L, beta_L;
 };
 
+// Per-axis mesh data by run-time axis.  A kernel may hold its arguments in a local
+// copy, which must only be read at constant offsets to stay in registers; a plain
+// select of the three fields is folded by the optimiser into one load at a
+// selected offset, so the fields are blended arithmetically (exact: the other
+// terms are multiplied by zero and every value is finite).
+__device__ __forceinline__ int arg_ne(const KArgs &P, int a)
+{
+    return (a == 0) * P.ne[0] + (a == 1) * P.ne[1] + (a == 2) * P.ne[2];
+}
+__device__ __forceinline__ int arg_bc(const KArgs &P, int a)
+{
+    return (a == 0) * P.bc[0] + (a == 1) * P.bc[1] + (a == 2) * P.bc[2];
+}
+__device__ __forceinline__ double arg_dx(const KArgs &P, int a)
+{
+    return (a == 0 ? 1.0 : 0.0) * P.dx[0] + (a == 1 ? 1.0 : 0.0) * P.dx[1] + (a == 2 ? 1.0 : 0.0) * P.dx[2];
+}
+
 // ---------------------------------------------------------------------------
 // physics (Sec. 3.1) - same formulas as the HLL-Einfeldt flux of Sec. 3
 // ---------------------------------------------------------------------------
+
+// The axis a is a run-time value in the kernels: components along a are picked and
+// scattered with selects over the unrolled component loop, never by indexing a
+// register array with a.
+template <int DIM>
+__device__ __forceinline__ double pick(const double *x, int a)
+{
+    double r = x[0];
+#pragma unroll
+    for (int b = 1; b < DIM; ++b) r = (b == a) ? x[b] : r;
+    return r;
+}
 
 template <int DIM>
 __device__ __forceinline__ double pressure(const double *u, double g)
@@ -112,8 +152,9 @@ template <int DIM>
 __device__ __forceinline__ void euler_flux(const double *u, int a, double g, double *f)
 {
     double p = pressure<DIM>(u, g);
-    double va = u[1 + a] / u[0];
-    f[0] = u[1 + a];
+    const double ma = pick<DIM>(u + 1, a);
+    double va = ma / u[0];
+    f[0] = ma;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) f[1 + b] = u[1 + b] * va + (a == b ? p : 0.0);
     f[DIM + 1] = va * (u[DIM + 1] + p);
@@ -127,7 +168,7 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
     euler_flux<DIM>(uL, a, g, fL);
     euler_flux<DIM>(uR, a, g, fR);
     double pL = pressure<DIM>(uL, g), pR = pressure<DIM>(uR, g);
-    double vL = uL[1 + a] / uL[0], vR = uR[1 + a] / uR[0];
+    double vL = pick<DIM>(uL + 1, a) / uL[0], vR = pick<DIM>(uR + 1, a) / uR[0];
     double cL = sqrt(fmax(g * pL / uL[0], 0.0)), cR = sqrt(fmax(g * pR / uR[0], 0.0));
     double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
     double HL = (uL[DIM + 1] + pL) / uL[0], HR = (uR[DIM + 1] + pR) / uR[0];
@@ -152,18 +193,6 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
 // ---------------------------------------------------------------------------
 // reverse-mode building blocks of the adjoint (vector-Jacobian products)
 // ---------------------------------------------------------------------------
-
-// The axis a is a run-time value in the kernels: components along a are picked and
-// scattered with selects over the unrolled component loop, never by indexing a
-// register array with a.
-template <int DIM>
-__device__ __forceinline__ double pick(const double *x, int a)
-{
-    double r = x[0];
-#pragma unroll
-    for (int b = 1; b < DIM; ++b) r = (b == a) ? x[b] : r;
-    return r;
-}
 
 // gu = (d f_a / d u)^T gf for the Euler flux of eqn. comp-euler-conservative
 template <int DIM>
@@ -524,9 +553,10 @@ __device__ __forceinline__ int neighbour(const KArgs &P, const int *e3, int a, i
     int f[3] = {e3[0], e3[1], e3[2]};
     int d = side ? 1 : -1;
     f[a] += d;
-    if (f[a] < 0 || f[a] >= P.ne[a]) {
-        if (P.bc[a] != SEDG_PERIODIC) return -1;
-        f[a] = (f[a] + P.ne[a]) % P.ne[a];
+    const int na = arg_ne(P, a);
+    if (f[a] < 0 || f[a] >= na) {
+        if (arg_bc(P, a) != SEDG_PERIODIC) return -1;
+        f[a] = (f[a] + na) % na;
     }
     return f[0] + P.ne[0] * (f[1] + P.ne[1] * f[2]);
 }
@@ -537,6 +567,16 @@ __device__ __forceinline__ long long fb_index(int e, int a, int side, int v, int
 {
     constexpr int NV = DIM + 2, KF = Geo<DIM, K>::KF;
     return ((((long long)e * DIM + a) * 2 + side) * NV + v) * KF + t;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i on XCD i mod 8),
+// each XCD with its own L2.  The kernels that read their neighbours' face data
+// remap workgroups so that every XCD works on one contiguous range of tiles: an
+// element's x-neighbours are then on the same XCD and their face data in its L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // ---------------------------------------------------------------------------
@@ -585,17 +625,16 @@ __device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, EPB> &S, int le,
     __syncthreads();
 }
 
+// one tile (EPB elements) of the analyse kernel; every thread of the workgroup calls it
 template <int DIM, int K, int TOP, int EPB>
-__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
-analyse_kernel(KArgs P)
+__device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSmem<DIM, K, EPB> &S)
 {
     typedef Geo<DIM, K> G;
     typedef Lv<DIM, K, TOP> LV;
     constexpr int NV = G::NV, KD = G::KD;
-    __shared__ AnalyseSmem<DIM, K, EPB> S;
     const int tid = threadIdx.x;
     const int le = tid / KD, c = tid % KD;
-    const int e = blockIdx.x * EPB + le;
+    const int e = tile * EPB + le;
     const bool act = e < P.nel;
     const int ee = act ? e : P.nel - 1;
     int e3[3];
@@ -613,7 +652,7 @@ analyse_kernel(KArgs P)
         bool fin = true;
         for (int v = 0; v < NV; ++v) fin = fin && isfinite(ub[v]);
         bool ok = fin && permissible<DIM>(ub, gam);
-        if (act && !ok) atomicMin(P.err, e);
+        if (act && !ok) atomicMin(P.err, P.err_base + e);
         if (P.lam_part) {
             double lam = 0.0;
             if (act && ok) {
@@ -628,7 +667,7 @@ analyse_kernel(KArgs P)
                 double m = 0.0;
                 for (int wv = 0; wv < (EPB * KD + 63) / 64; ++wv) m = fmax(m, S.lam[wv]);
                 // non-negative doubles order like their bit patterns: an integer max is exact
-                atomicMax((unsigned long long *)&P.lam_part[blockIdx.x & (LAM_SLOTS - 1)],
+                atomicMax((unsigned long long *)&P.lam_part[tile & P.lam_mask],
                           (unsigned long long)__double_as_longlong(m));
             }
         }
@@ -837,6 +876,13 @@ analyse_kernel(KArgs P)
     }
 }
 
+template <int DIM, int K, int TOP, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) analyse_kernel(KArgs P)
+{
+    __shared__ AnalyseSmem<DIM, K, EPB> S;
+    analyse_body<DIM, K, TOP, EPB>(P, blockIdx.x, S);
+}
+
 // ---------------------------------------------------------------------------
 // residual kernel
 // ---------------------------------------------------------------------------
@@ -897,18 +943,17 @@ __device__ __forceinline__ void face_at(int a0, int na, int step, int fidx, int 
     }
 }
 
+// one tile (EPB elements) of the residual kernel; every thread of the workgroup calls it
 template <int DIM, int K, int TOP, int EPB>
-__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
-__attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
+__device__ __forceinline__ void residual_body(const KArgs &P, int tile, ResidualSmem<DIM, K, TOP, EPB> &S)
 {
     typedef Geo<DIM, K> G;
     typedef Lv<DIM, K, TOP> LV;
     typedef ResidualSmem<DIM, K, TOP, EPB> SM;
     constexpr int NV = G::NV, KD = G::KD, KF = G::KF;
-    __shared__ SM S;
     const int tid = threadIdx.x;
     const int le = tid / KD, c = tid % KD;
-    const int e = blockIdx.x * EPB + le;
+    const int e = tile * EPB + le;
     const bool act = e < P.nel;
     const int ee = act ? e : P.nel - 1;
     int e3[3];
@@ -1179,7 +1224,7 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
             for (int a = a0; a < a1; ++a) {
                 const int axs = SM::AXO ? 0 : a;
                 const int pos = G::coord(c, a), tr = G::trans(c, a);
-                double sc = K / P.dx[a];
+                double sc = K / arg_dx(P, a);
                 for (int v = 0; v < NV; ++v)
                     rfv[v] -= sc * (S.F[le][axs][v][(pos + 1) * KF + tr] - S.F[le][axs][v][pos * KF + tr]);
             }
@@ -1234,7 +1279,7 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
                     const int pos = G::coord(c, a), tr = G::trans(c, a);
                     const int lo = pos & (n - 1);
                     const int kl = pos - lo, kr = kl + n;
-                    const double sc = K / (n * P.dx[a]);
+                    const double sc = K / (n * arg_dx(P, a));
                     for (int v = 0; v < NV; ++v) {
                         double surf = T.Bhl[lo] * S.F[le][axs][v][kl * KF + tr] + T.Bhr[lo] * S.F[le][axs][v][kr * KF + tr];
                         lrl[v] += sc * (vol[v] - surf);
@@ -1277,6 +1322,14 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
     }
 }
 
+template <int DIM, int K, int TOP, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
+__attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
+{
+    __shared__ ResidualSmem<DIM, K, TOP, EPB> S;
+    residual_body<DIM, K, TOP, EPB>(P, xcd_tile(blockIdx.x, gridDim.x), S);
+}
+
 // ---------------------------------------------------------------------------
 // frozen blending factors: preparation kernel
 // ---------------------------------------------------------------------------
@@ -1300,7 +1353,7 @@ __device__ void own_face_adjoint(const KArgs &P, const double *al, const double 
     typedef Geo<DIM, K> G;
     constexpr int NV = G::NV;
     for (int v = 0; v < NV; ++v) gf[v] = 0.0;
-    const double sc = K / P.dx[a];
+    const double sc = K / arg_dx(P, a);
     const int st = G::stride(a);
     double th[MAXLEV + 1];
     if (k > 0) {
@@ -1313,7 +1366,7 @@ __device__ void own_face_adjoint(const KArgs &P, const double *al, const double 
             const int n = LV::n(li);
             if (k % n != 0 || th[1 + li] == 0.0) continue;
             const sedg_level_tab &T = P.tabs[li];
-            const double w = (K / (n * P.dx[a])) * th[1 + li];
+            const double w = (K / (n * arg_dx(P, a))) * th[1 + li];
             for (int lo = 0; lo < n; ++lo) {
                 const int cell = cl - (n - 1 - lo) * st;
                 for (int v = 0; v < NV; ++v) gf[v] -= w * T.Bhr[lo] * lam[v][cell];
@@ -1330,7 +1383,7 @@ __device__ void own_face_adjoint(const KArgs &P, const double *al, const double 
             const int n = LV::n(li);
             if (k % n != 0 || th[1 + li] == 0.0) continue;
             const sedg_level_tab &T = P.tabs[li];
-            const double w = (K / (n * P.dx[a])) * th[1 + li];
+            const double w = (K / (n * arg_dx(P, a))) * th[1 + li];
             for (int lo = 0; lo < n; ++lo) {
                 const int cell = cr + lo * st;
                 for (int v = 0; v < NV; ++v) gf[v] -= w * T.Bhl[lo] * lam[v][cell];
@@ -1400,7 +1453,7 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
         fin = fin && isfinite(ub[v]);
         if (adj) S.lam[le][v][c] = P.lam[v * P.dof + g];
     }
-    if (act && !(fin && permissible<DIM>(ub, gam))) atomicMin(P.err, e);
+    if (act && !(fin && permissible<DIM>(ub, gam))) atomicMin(P.err, P.err_base + e);
     {
         double sr = subreduce<DIM, K>(ub[0], G::LOGK, S.x, OpMax());
         double se = subreduce<DIM, K>(fabs(ub[NV - 1]), G::LOGK, S.x, OpMax());
@@ -1514,7 +1567,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     __shared__ AdjointSmem<DIM, K, TOP, EPB> S;
     const int tid = threadIdx.x;
     const int le = tid / KD, c = tid % KD;
-    const int e = blockIdx.x * EPB + le;
+    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = e < P.nel;
     const int ee = act ? e : P.nel - 1;
     int e3[3];
@@ -1582,7 +1635,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
         double gut[NV];
         for (int v = 0; v < NV; ++v) gut[v] = 0.0;
         for (int a = 0; a < DIM; ++a) {
-            const double sc = K / (n * P.dx[a]);
+            const double sc = K / (n * arg_dx(P, a));
             double gv[NV];
             for (int v = 0; v < NV; ++v) gv[v] = sc * thn * S.lam[le][v][c];
             for (int bax = 0; bax < DIM; ++bax) {
@@ -1902,6 +1955,162 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     }
 }
 
+// ---------------------------------------------------------------------------
+// batched ensembles of independent 2-D problems
+// ---------------------------------------------------------------------------
+//
+// The problems of an ensemble share the scheme parameters but not the mesh:
+// each has its own element counts, boundary conditions, spacing, K (4 or 8) and
+// step size.  Their states, blending factors, face buffers and scales sit back to
+// back in ensemble-wide arrays; a tile is EPB consecutive elements of one problem
+// and the tiles of all problems are numbered consecutively.  One launch of the
+// analyse kernel and one of the residual kernel per RK stage cover the whole
+// ensemble: each workgroup takes a range of tiles, reads its problem's
+// descriptor and runs the K = 4 or K = 8 body (a workgroup-uniform branch; both
+// bodies use the same workgroup size and share one LDS allocation).
+
+#define BATCH_SLOTS 16      // CFL slots per problem
+
+struct ProbDesc {
+    long long state_off;    // doubles before the problem's state (nvar * dof each)
+    long long alpha_off;    // doubles before its blending factors (nel * A each)
+    long long fbuf_off;     // doubles before its face buffer
+    long long elem_off;     // elements before it
+    long long dof;
+    int nel, K, tile_off, ntiles;
+    int ne[2], G[2], bc[2];
+    double dx[2];
+    double cfl_num;         // numerator of its CFL step
+};
+
+// Workgroup-uniform values loaded from memory: readfirstlane tells the compiler they
+// are uniform, so they and everything derived from them stay in scalar registers.
+__device__ __forceinline__ int wg_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long wg_uniform(long long v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wg_uniform(double v) { return __longlong_as_double(wg_uniform(__double_as_longlong(v))); }
+
+// the kernel arguments of one problem of the ensemble (D read with uniform loads)
+__device__ __forceinline__ KArgs problem_args(const KArgs &P, const ProbDesc &Dm, int p)
+{
+    ProbDesc D;
+    D.state_off = wg_uniform(Dm.state_off);
+    D.alpha_off = wg_uniform(Dm.alpha_off);
+    D.fbuf_off = wg_uniform(Dm.fbuf_off);
+    D.elem_off = wg_uniform(Dm.elem_off);
+    D.dof = wg_uniform(Dm.dof);
+    D.nel = wg_uniform(Dm.nel);
+    D.K = wg_uniform(Dm.K);
+    for (int a = 0; a < 2; ++a) {
+        D.ne[a] = wg_uniform(Dm.ne[a]);
+        D.G[a] = wg_uniform(Dm.G[a]);
+        D.bc[a] = wg_uniform(Dm.bc[a]);
+        D.dx[a] = wg_uniform(Dm.dx[a]);
+    }
+    KArgs Q = P;
+    Q.u = P.u + D.state_off;
+    Q.u0 = P.u0 ? P.u0 + D.state_off : nullptr;
+    Q.out = P.out + D.state_off;
+    Q.alpha = P.alpha + D.alpha_off;
+    Q.beta = P.beta + D.alpha_off;
+    Q.mean = P.mean + 4 * D.alpha_off;      // nvar = 4 in 2-D
+    Q.fbuf = P.fbuf + D.fbuf_off;
+    Q.scale = P.scale + 2 * D.elem_off;
+    Q.lam_part = P.lam_part ? P.lam_part + (long long)p * BATCH_SLOTS : nullptr;
+    Q.dt = P.dt ? P.dt + p : nullptr;
+    Q.tabs = (D.K == 4) ? P.tabs + 1 : P.tabs;   // level tables 8, 4, 2: K = 4 starts at 4
+    Q.err_base = (int)D.elem_off;
+    Q.lam_mask = BATCH_SLOTS - 1;
+    Q.dof = D.dof;
+    Q.nel = D.nel;
+    Q.ne[0] = D.ne[0]; Q.ne[1] = D.ne[1]; Q.ne[2] = 1;
+    Q.G[0] = D.G[0]; Q.G[1] = D.G[1]; Q.G[2] = 1;
+    Q.bc[0] = D.bc[0]; Q.bc[1] = D.bc[1]; Q.bc[2] = SEDG_PERIODIC;
+    Q.dx[0] = D.dx[0]; Q.dx[1] = D.dx[1]; Q.dx[2] = 1.0;
+    return Q;
+}
+
+template <int EPB4, int EPB8, bool PERSIST>
+__global__ void __launch_bounds__(64 * EPB8) analyse_batch_kernel(KArgs P)
+{
+    static_assert(16 * EPB4 == 64 * EPB8, "one workgroup size for both K");
+    __shared__ union {
+        AnalyseSmem<2, 4, EPB4> k4;
+        AnalyseSmem<2, 8, EPB8> k8;
+    } U;
+    const int L = P.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int t0 = PERSIST ? L * P.chunk : L;
+    const int t1 = PERSIST ? min(P.ntiles, (L + 1) * P.chunk) : L + 1;
+    for (int t = t0; t < t1; ++t) {
+        const int p = wg_uniform(P.tile_prob[t]);
+        const ProbDesc &D = P.probs[p];
+        const KArgs Q = problem_args(P, D, p);
+        const int tl = t - wg_uniform(D.tile_off);
+        if (wg_uniform(D.K) == 4) analyse_body<2, 4, 4, EPB4>(Q, tl, U.k4);
+        else analyse_body<2, 8, 8, EPB8>(Q, tl, U.k8);
+        __syncthreads();
+    }
+}
+
+template <int EPB4, int EPB8, bool PERSIST>
+__global__ void __launch_bounds__(64 * EPB8)
+__attribute__((amdgpu_waves_per_eu(3, 8))) residual_batch_kernel(KArgs P)
+{
+    static_assert(16 * EPB4 == 64 * EPB8, "one workgroup size for both K");
+    __shared__ union {
+        ResidualSmem<2, 4, 4, EPB4> k4;
+        ResidualSmem<2, 8, 8, EPB8> k8;
+    } U;
+    const int L = P.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int t0 = PERSIST ? L * P.chunk : L;
+    const int t1 = PERSIST ? min(P.ntiles, (L + 1) * P.chunk) : L + 1;
+    for (int t = t0; t < t1; ++t) {
+        const int p = wg_uniform(P.tile_prob[t]);
+        const ProbDesc &D = P.probs[p];
+        const KArgs Q = problem_args(P, D, p);
+        const int tl = t - wg_uniform(D.tile_off);
+        if (wg_uniform(D.K) == 4) residual_body<2, 4, 4, EPB4>(Q, tl, U.k4);
+        else residual_body<2, 8, 8, EPB8>(Q, tl, U.k8);
+        __syncthreads();
+    }
+}
+
+// per-problem CFL steps: one workgroup of BATCH_SLOTS threads per problem, which
+// also clears the problem's slots for the next step
+__global__ void __launch_bounds__(BATCH_SLOTS) finalize_batch_kernel(double *lam_part, const ProbDesc *probs, int nprob,
+                                                                     double *dt, double *dt_log, const int *step_ctr)
+{
+    __shared__ double s[BATCH_SLOTS];
+    const int p = blockIdx.x, i = threadIdx.x;
+    s[i] = lam_part[(long long)p * BATCH_SLOTS + i];
+    lam_part[(long long)p * BATCH_SLOTS + i] = 0.0;
+    __syncthreads();
+    for (int w = BATCH_SLOTS / 2; w > 0; w >>= 1) {
+        if (i < w) s[i] = fmax(s[i], s[i + w]);
+        __syncthreads();
+    }
+    if (i == 0) {
+        const double d = probs[p].cfl_num / s[0];
+        dt[p] = d;
+        if (dt_log) dt_log[(long long)step_ctr[0] * nprob + p] = d;
+    }
+}
+
+__global__ void fill_kernel(double *x, int n, double v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ void count_step_kernel(int *ctr)
+{
+    if (threadIdx.x == 0) ctr[0] += 1;
+}
+
 // CFL step from the eigenvalue maxima folded into LAM_SLOTS slots (eq. cfl-condition);
 // one block of LAM_SLOTS threads, which also clears the slots for the next step.
 __global__ void __launch_bounds__(LAM_SLOTS) finalize_dt_kernel(double *lam_part, int nparts, double num, double *dt,
@@ -2039,6 +2248,7 @@ KArgs base_args(const sedg_ctx *C)
     P.mean = C->d_mean;
     P.tabs = C->d_tabs;
     P.err = C->d_err;
+    P.lam_mask = LAM_SLOTS - 1;
     P.dof = C->dof;
     P.nel = C->nel;
     for (int a = 0; a < 3; ++a) {
@@ -2516,6 +2726,339 @@ int sedg_adjoint_rk_step(sedg_ctx *C, const double *tape, const double *dt_dev, 
     }
     C->last = s;
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched ensembles: host side
+// ---------------------------------------------------------------------------
+
+struct sedg_batch {
+    int nprob;
+    sedg_params params;
+    double gamma;
+    int family;
+    int ncu;
+    std::vector<sedg_mesh> meshes;
+    std::vector<ProbDesc> probs;
+    long long state_len, alpha_len, fbuf_len, nel;
+    sedg_batch_tuning tun;
+    int ntiles, grid, chunk;
+    sedg_level_tab *d_tabs;
+    ProbDesc *d_probs;
+    int *d_tile_prob;
+    double *d_alpha, *d_beta, *d_mean, *d_scale, *d_fbuf, *d_u1, *d_u2, *d_dt, *d_lam;
+    int *d_err, *d_ctr;
+    hipStream_t last;
+    std::map<std::tuple<double *, double *, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+void batch_drop_graphs(sedg_batch *B)
+{
+    for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+    B->graphs.clear();
+}
+
+// tiles of every problem for the current elements-per-workgroup choice, and the grid
+int batch_layout(sedg_batch *B)
+{
+    std::vector<int> tp;
+    int t = 0;
+    for (int p = 0; p < B->nprob; ++p) {
+        ProbDesc &D = B->probs[p];
+        const int epb = D.K == 4 ? B->tun.epb4 : B->tun.epb8;
+        D.tile_off = t;
+        D.ntiles = (D.nel + epb - 1) / epb;
+        t += D.ntiles;
+        for (int i = 0; i < D.ntiles; ++i) tp.push_back(p);
+    }
+    B->ntiles = t;
+    if (B->tun.blocks_per_cu > 0) {
+        long long g = (long long)B->ncu * B->tun.blocks_per_cu;
+        B->grid = (int)(g < t ? g : t);
+    } else {
+        B->grid = t;
+    }
+    B->chunk = (t + B->grid - 1) / B->grid;
+    if (B->d_tile_prob) (void)hipFree(B->d_tile_prob);
+    B->d_tile_prob = nullptr;
+    if (hipMalloc(&B->d_tile_prob, sizeof(int) * (size_t)t) != hipSuccess) return SEDG_ENOMEM;
+    if (hipMemcpy(B->d_tile_prob, tp.data(), sizeof(int) * (size_t)t, hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    if (hipMemcpy(B->d_probs, B->probs.data(), sizeof(ProbDesc) * (size_t)B->nprob, hipMemcpyHostToDevice) != hipSuccess)
+        return SEDG_EHIP;
+    batch_drop_graphs(B);
+    return SEDG_OK;
+}
+
+KArgs batch_args(const sedg_batch *B)
+{
+    KArgs P;
+    std::memset(&P, 0, sizeof(P));
+    P.alpha = B->d_alpha;
+    P.beta = B->d_beta;
+    P.mean = B->d_mean;
+    P.scale = B->d_scale;
+    P.fbuf = B->d_fbuf;
+    P.tabs = B->d_tabs;
+    P.err = B->d_err;
+    P.dt = B->d_dt;
+    P.probs = B->d_probs;
+    P.tile_prob = B->d_tile_prob;
+    P.ntiles = B->ntiles;
+    P.chunk = B->chunk;
+    P.xcd_map = B->tun.xcd_map;
+    P.mode = B->params.mode;
+    P.level_mask = B->params.level_mask;
+    P.gamma = B->gamma;
+    P.tau_A = B->params.tau_A;
+    P.tau_S = B->params.tau_S;
+    P.alpha_H = B->params.alpha_H;
+    P.alpha_L = B->params.alpha_L;
+    P.beta_L = B->params.beta_L;
+    return P;
+}
+
+template <int EPB4, int EPB8, bool PERSIST>
+void batch_launch_t(int which, const sedg_batch *B, const KArgs &P, hipStream_t s)
+{
+    if (which == 0) hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
+    else hipLaunchKernelGGL((residual_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
+}
+
+void batch_launch(int which, const sedg_batch *B, const KArgs &P, hipStream_t s)
+{
+    const bool persist = B->tun.blocks_per_cu > 0;
+    if (B->tun.epb8 == 2) {
+        if (persist) batch_launch_t<8, 2, true>(which, B, P, s);
+        else batch_launch_t<8, 2, false>(which, B, P, s);
+    } else {
+        if (persist) batch_launch_t<4, 1, true>(which, B, P, s);
+        else batch_launch_t<4, 1, false>(which, B, P, s);
+    }
+}
+
+void enqueue_batch_step(sedg_batch *B, double *u, bool fixed, double *dt_log, hipStream_t s)
+{
+    KArgs P = batch_args(B);
+    P.u = u;
+    P.out = B->d_u1;
+    P.stage = 1;
+    P.lam_part = fixed ? nullptr : B->d_lam;
+    batch_launch(0, B, P, s);
+    if (!fixed)
+        hipLaunchKernelGGL(finalize_batch_kernel, dim3(B->nprob), dim3(BATCH_SLOTS), 0, s, B->d_lam,
+                           (const ProbDesc *)B->d_probs, B->nprob, B->d_dt, dt_log, (const int *)B->d_ctr);
+    batch_launch(1, B, P, s);
+    P.lam_part = nullptr;
+    P.u = B->d_u1;
+    P.u0 = u;
+    P.out = B->d_u2;
+    P.stage = 2;
+    batch_launch(0, B, P, s);
+    batch_launch(1, B, P, s);
+    P.u = B->d_u2;
+    P.u0 = u;
+    P.out = u;
+    P.stage = 3;
+    batch_launch(0, B, P, s);
+    batch_launch(1, B, P, s);
+    if (dt_log && !fixed) hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, s, B->d_ctr);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedg_batch_destroy(sedg_batch *B)
+{
+    if (!B) return SEDG_OK;
+    (void)hipDeviceSynchronize();
+    batch_drop_graphs(B);
+    void *ptrs[] = {B->d_tabs, B->d_probs, B->d_tile_prob, B->d_alpha, B->d_beta, B->d_mean, B->d_scale,
+                    B->d_fbuf, B->d_u1, B->d_u2, B->d_dt, B->d_lam, B->d_err, B->d_ctr};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete B;
+    return SEDG_OK;
+}
+
+int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *params, sedg_batch **out)
+{
+    if (!meshes || count < 1 || !params || !out) return SEDG_EINVAL;
+    *out = nullptr;
+    if (params->top_level != 0 || params->mode == SEDG_EXTERNAL || params->mode < 0 || params->mode > 3)
+        return SEDG_EINVAL;
+    for (int p = 0; p < count; ++p) {
+        const sedg_mesh &m = meshes[p];
+        if (m.dim != 2) return SEDG_EUNSUPPORTED;
+        if (m.K != 4 && m.K != 8) return SEDG_EUNSUPPORTED;
+        if (m.gamma != meshes[0].gamma || m.family != meshes[0].family) return SEDG_EINVAL;
+        if (!(m.gamma > 1.0) || (m.family != SEDG_GAUSS && m.family != SEDG_LGL)) return SEDG_EINVAL;
+        for (int a = 0; a < 2; ++a) {
+            if (m.nelem[a] < 1 || !(m.hi[a] > m.lo[a])) return SEDG_EINVAL;
+            if (m.bc[a] != SEDG_PERIODIC && m.bc[a] != SEDG_OUTFLOW) return SEDG_EINVAL;
+        }
+    }
+    sedg_batch *B = new sedg_batch();
+    B->nprob = count;
+    B->params = *params;
+    B->gamma = meshes[0].gamma;
+    B->family = meshes[0].family;
+    B->meshes.assign(meshes, meshes + count);
+    B->tun.epb4 = 4;
+    B->tun.epb8 = 1;
+    B->tun.blocks_per_cu = 0;
+    B->tun.xcd_map = 1;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) { delete B; return SEDG_EHIP; }
+    B->ncu = prop.multiProcessorCount;
+    long long so = 0, ao = 0, fo = 0, eo = 0;
+    for (int p = 0; p < count; ++p) {
+        const sedg_mesh &m = meshes[p];
+        ProbDesc D;
+        std::memset(&D, 0, sizeof(D));
+        D.K = m.K;
+        D.nel = m.nelem[0] * m.nelem[1];
+        D.dof = (long long)D.nel * m.K * m.K;
+        D.state_off = so;
+        D.alpha_off = ao;
+        D.fbuf_off = fo;
+        D.elem_off = eo;
+        const int A = m.K == 8 ? 21 : 5;
+        for (int a = 0; a < 2; ++a) {
+            D.ne[a] = m.nelem[a];
+            D.G[a] = m.nelem[a] * m.K;
+            D.bc[a] = m.bc[a];
+            D.dx[a] = (m.hi[a] - m.lo[a]) / m.nelem[a];
+        }
+        const double dxm = D.dx[0] < D.dx[1] ? D.dx[0] : D.dx[1];
+        D.cfl_num = params->cfl * dxm / (2.0 * (2.0 * m.K - 1.0));
+        so += 4 * D.dof;
+        ao += (long long)D.nel * A;
+        fo += (long long)D.nel * 2 * 2 * 4 * m.K;
+        eo += D.nel;
+        B->probs.push_back(D);
+    }
+    if (eo > INT_MAX) { delete B; return SEDG_EINVAL; }
+    B->state_len = so;
+    B->alpha_len = ao;
+    B->fbuf_len = fo;
+    B->nel = eo;
+    bool ok = true;
+    ok = ok && hipMalloc(&B->d_tabs, sizeof(sedg_level_tab) * MAXLEV) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_probs, sizeof(ProbDesc) * (size_t)count) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_alpha, sizeof(double) * (size_t)ao) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_beta, sizeof(double) * (size_t)ao) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_mean, sizeof(double) * 4 * (size_t)ao) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_scale, sizeof(double) * 2 * (size_t)eo) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_fbuf, sizeof(double) * (size_t)fo) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_u1, sizeof(double) * (size_t)so) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_u2, sizeof(double) * (size_t)so) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_dt, sizeof(double) * (size_t)count) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_lam, sizeof(double) * BATCH_SLOTS * (size_t)count) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_err, sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_ctr, sizeof(int)) == hipSuccess;
+    if (!ok) { sedg_batch_destroy(B); return SEDG_ENOMEM; }
+    sedg_level_tab h[MAXLEV];
+    std::memset(h, 0, sizeof(h));
+    for (int li = 0; li < 3; ++li)
+        if (sedg_build_level(8 >> li, B->family, &h[li])) { sedg_batch_destroy(B); return SEDG_EINVAL; }
+    int big = INT_MAX;
+    ok = hipMemcpy(B->d_tabs, h, sizeof(h), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(B->d_err, &big, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(B->d_lam, 0, sizeof(double) * BATCH_SLOTS * (size_t)count) == hipSuccess;
+    if (!ok) { sedg_batch_destroy(B); return SEDG_EHIP; }
+    int rc = batch_layout(B);
+    if (rc) { sedg_batch_destroy(B); return rc; }
+    B->last = nullptr;
+    *out = B;
+    return SEDG_OK;
+}
+
+long sedg_batch_state_len(const sedg_batch *B) { return B ? (long)B->state_len : SEDG_EINVAL; }
+
+long sedg_batch_state_offset(const sedg_batch *B, int p)
+{
+    if (!B || p < 0 || p >= B->nprob) return SEDG_EINVAL;
+    return (long)B->probs[p].state_off;
+}
+
+int sedg_batch_set_tuning(sedg_batch *B, const sedg_batch_tuning *t)
+{
+    if (!B || !t) return SEDG_EINVAL;
+    const bool shape_ok = (t->epb4 == 4 && t->epb8 == 1) || (t->epb4 == 8 && t->epb8 == 2);
+    if (!shape_ok || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 || (t->xcd_map != 0 && t->xcd_map != 1))
+        return SEDG_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return SEDG_EHIP;
+    B->tun = *t;
+    return batch_layout(B);
+}
+
+int sedg_batch_get_tuning(const sedg_batch *B, sedg_batch_tuning *t)
+{
+    if (!B || !t) return SEDG_EINVAL;
+    *t = B->tun;
+    return SEDG_OK;
+}
+
+int sedg_batch_rk_step(sedg_batch *B, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream)
+{
+    if (!B || !u || nsteps < 0) return SEDG_EINVAL;
+    if (nsteps == 0) return SEDG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fixed = dt_fixed > 0.0;
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, (double *)nullptr, 0.0, B->d_ctr);
+    if (fixed)
+        hipLaunchKernelGGL(fill_kernel, dim3((B->nprob + 255) / 256), dim3(256), 0, s, B->d_dt, B->nprob, dt_fixed);
+    auto key = std::make_tuple(u, dt_log_dev, fixed ? 1 : 0);
+    hipGraphExec_t exec = nullptr;
+    auto it = B->graphs.find(key);
+    if (it != B->graphs.end()) {
+        exec = it->second;
+    } else {
+        if (B->graphs.size() >= 16) {
+            if (hipStreamSynchronize(s) != hipSuccess) return SEDG_EHIP;
+            batch_drop_graphs(B);
+        }
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SEDG_EHIP;
+        hipGraph_t graph;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
+        enqueue_batch_step(B, u, fixed, dt_log_dev, cs);
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return SEDG_EHIP;
+        B->graphs[key] = exec;
+    }
+    for (int st = 0; st < nsteps; ++st)
+        if (hipGraphLaunch(exec, s) != hipSuccess) return SEDG_EHIP;
+    B->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+int sedg_batch_check(sedg_batch *B, int *bad_problem, long *bad_elem)
+{
+    if (!B || !bad_problem || !bad_elem) return SEDG_EINVAL;
+    if (hipStreamSynchronize(B->last) != hipSuccess) return SEDG_EHIP;
+    int h = INT_MAX;
+    if (hipMemcpy(&h, B->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SEDG_EHIP;
+    *bad_problem = -1;
+    *bad_elem = -1;
+    if (h == INT_MAX) return SEDG_OK;
+    for (int p = 0; p < B->nprob; ++p)
+        if (h >= B->probs[p].elem_off && h < B->probs[p].elem_off + B->probs[p].nel) {
+            *bad_problem = p;
+            *bad_elem = (long)(h - B->probs[p].elem_off);
+        }
+    int big = INT_MAX;
+    if (hipMemcpy(B->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    return SEDG_ESTATE;
 }
 
 }  // extern "C"

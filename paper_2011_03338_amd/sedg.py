@@ -5,8 +5,9 @@ the stream from torch's current stream.
 
 The functions mirror the C entry points declared in include/sedg.h:
 sedg_create / sedg_destroy / sedg_rhs / sedg_max_dt / sedg_rk_step / sedg_check
-/ sedg_tables, and the frozen map with its adjoint: sedg_rhs_frozen /
-sedg_adjoint_rhs / sedg_tape_len / sedg_rk_step_tape / sedg_adjoint_rk_step.  A missing or unloadable library raises at first use; there is
+/ sedg_tables, the frozen map with its adjoint: sedg_rhs_frozen /
+sedg_adjoint_rhs / sedg_tape_len / sedg_rk_step_tape / sedg_adjoint_rk_step, and
+batched ensembles: sedg_batch_*.  A missing or unloadable library raises at first use; there is
 no fallback path.
 """
 from __future__ import annotations
@@ -24,7 +25,9 @@ SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED = 0
 EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "sedg_set_params",
             "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror",
             "sedg_profile", "sedg_profile_read", "sedg_rhs_frozen", "sedg_adjoint_rhs", "sedg_tape_len",
-            "sedg_rk_step_tape", "sedg_adjoint_rk_step"]
+            "sedg_rk_step_tape", "sedg_adjoint_rk_step", "sedg_batch_create", "sedg_batch_destroy",
+            "sedg_batch_state_len", "sedg_batch_state_offset", "sedg_batch_set_tuning", "sedg_batch_get_tuning",
+            "sedg_batch_rk_step", "sedg_batch_check"]
 
 
 class SedgError(RuntimeError):
@@ -43,6 +46,11 @@ class Params_c(ctypes.Structure):
     _fields_ = [("tau_A", ctypes.c_double), ("tau_S", ctypes.c_double), ("alpha_H", ctypes.c_double),
                 ("alpha_L", ctypes.c_double), ("beta_L", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int)]
+
+
+class Tuning_c(ctypes.Structure):
+    _fields_ = [("epb4", ctypes.c_int), ("epb8", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
+                ("xcd_map", ctypes.c_int)]
 
 
 _lib = None
@@ -77,6 +85,16 @@ def load():
     lib.sedg_tape_len.restype = ctypes.c_long
     lib.sedg_rk_step_tape.argtypes = [vp, vp, vp, vp, vp]
     lib.sedg_adjoint_rk_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.sedg_batch_create.argtypes = [ctypes.POINTER(Mesh_c), ctypes.c_int, ctypes.POINTER(Params_c), ctypes.POINTER(vp)]
+    lib.sedg_batch_destroy.argtypes = [vp]
+    lib.sedg_batch_state_len.argtypes = [vp]
+    lib.sedg_batch_state_len.restype = ctypes.c_long
+    lib.sedg_batch_state_offset.argtypes = [vp, ctypes.c_int]
+    lib.sedg_batch_state_offset.restype = ctypes.c_long
+    lib.sedg_batch_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning_c)]
+    lib.sedg_batch_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning_c)]
+    lib.sedg_batch_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
+    lib.sedg_batch_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_long)]
     lib.sedg_strerror.argtypes = [ctypes.c_int]
     lib.sedg_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -221,3 +239,72 @@ class Solver:
             raise SedgError(rc, "sedg_check: element %d" % bad.value)
         _check(rc, "sedg_check")
         return -1
+
+
+class BatchSolver:
+    """An ensemble of independent 2-D problems advanced together (sedg_batch_*)."""
+
+    def __init__(self, meshes, params):
+        lib = load()
+        self.meshes, self.params = list(meshes), params
+        arr = (Mesh_c * len(self.meshes))(*[mesh_c(m) for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(lib.sedg_batch_create(arr, len(self.meshes), ctypes.byref(params_c(params)), ctypes.byref(h)),
+               "sedg_batch_create")
+        self._h = h
+        self.state_len = lib.sedg_batch_state_len(h)
+        self.offsets = [lib.sedg_batch_state_offset(h, p) for p in range(len(self.meshes))]
+
+    @property
+    def count(self) -> int:
+        return len(self.meshes)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sedg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1):
+        t = Tuning_c(epb4, epb8, blocks_per_cu, xcd_map)
+        _check(load().sedg_batch_set_tuning(self._h, ctypes.byref(t)), "sedg_batch_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning_c()
+        _check(load().sedg_batch_get_tuning(self._h, ctypes.byref(t)), "sedg_batch_get_tuning")
+        return {"epb4": t.epb4, "epb8": t.epb8, "blocks_per_cu": t.blocks_per_cu, "xcd_map": t.xcd_map}
+
+    def pack(self, states):
+        """One ensemble state (GPU tensor) from per-problem states (arrays or tensors)."""
+        import torch
+        parts = [torch.as_tensor(x, dtype=torch.float64).reshape(-1) for x in states]
+        return torch.cat(parts).to("cuda").contiguous()
+
+    def views(self, u):
+        """Per-problem views of an ensemble state, each shaped (nvar, gz, gy, gx)."""
+        out = []
+        for m, o in zip(self.meshes, self.offsets):
+            n = m.nvar * m.dof
+            out.append(u[o:o + n].view(*m.shape()))
+        return out
+
+    def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, stream=None):
+        _check(load().sedg_batch_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log),
+                                         _stream(stream)), "sedg_batch_rk_step")
+
+    def check(self):
+        """Returns None, or raises SedgError(SEDG_ESTATE) naming the problem and element."""
+        p = ctypes.c_int(-1)
+        e = ctypes.c_long(-1)
+        rc = load().sedg_batch_check(self._h, ctypes.byref(p), ctypes.byref(e))
+        if rc == SEDG_ESTATE:
+            err = SedgError(rc, "sedg_batch_check: problem %d element %d" % (p.value, e.value))
+            err.problem, err.element = p.value, e.value
+            raise err
+        _check(rc, "sedg_batch_check")
+        return None

@@ -263,3 +263,10 @@ def ensemble(seed: int = 0, count: int = 256, sides=(32, 48, 64, 96, 128), Ks=(4
         sub_seed = int(rng.integers(0, 2 ** 31 - 1))
         out.append({"side": side, "K": K, "E": E, "seed": sub_seed})
     return out
+
+
+def ensemble_problem(desc):
+    """The mesh and initial state of one ensemble member: the 2-D blast of sedov()
+    on desc["side"]^2 elements with K = desc["K"], energy desc["E"] and a seeded
+    centre within 0.2 of the origin."""
+    return sedov(desc["seed"], desc["side"], desc["K"], E=desc["E"], rc=0.2)

@@ -86,9 +86,11 @@ def test_frozen_rhs_matches_oracle(case):
 
 
 @pytest.mark.parametrize("K,ne", [(4, 16), (8, 8)])
-def test_frozen_rhs_equals_adaptive_bitwise(K, ne):
+def test_frozen_rhs_equals_adaptive(K, ne):
     """With the factors the adaptive evaluation chose, the frozen map reproduces it
-    bit for bit (same means, same face data, same residual kernel)."""
+    up to rounding: the residual kernel is the same, but the element-face states
+    and means come from the preparation kernel instead of the analyse kernel, where
+    the compiler may fuse multiply-adds differently."""
     mesh, u, _ = W.sedov(0, ne, K, L=0.3, sigma=0.03)
     s = sedg.Solver(mesh, W.Params())
     ug = _t(u)
@@ -99,7 +101,9 @@ def test_frozen_rhs_equals_adaptive_bitwise(K, ne):
     d2 = torch.zeros_like(ug)
     s.rhs_frozen(ug, al, be, d2)
     s.check()
-    assert torch.equal(d1, d2)
+    err = float((d1 - d2).abs().max() / d1.abs().max())
+    say("  frozen vs adaptive K%d: rel %.2e" % (K, err))
+    assert err <= 1e-13
     s.close()
 
 

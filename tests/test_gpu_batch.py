@@ -1,0 +1,136 @@
+"""Batched ensembles: many independent 2-D problems (mixed K, mesh sizes and
+boundary conditions) advanced by one launch per kernel and stage must give, for
+every problem and every launch shape, bit for bit the states and step sizes of
+the single-problem path (the same element arithmetic), and match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_03338_amd import sedg, workloads as W
+from tests.parity import DEV, STATE_TOL, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+TUNINGS = [dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1), dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=0),
+           dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=1), dict(epb4=4, epb8=1, blocks_per_cu=2, xcd_map=1),
+           dict(epb4=8, epb8=2, blocks_per_cu=1, xcd_map=0)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sedg.load()
+    yield
+
+
+def _problems():
+    out = []
+    out.append(W.sedov(3, 5, 8, E=1.5, rc=0.2)[:2])
+    out.append(W.config0(1, 8, 4)[:2])
+    out.append(W.sedov(4, 7, 4, E=0.7, rc=0.2)[:2])
+    out.append(W.config0(2, 3, 8)[:2])
+    out.append(W.pressure_pulse(2, 4, 8)[:2])
+    m = W.Mesh(2, 8, [1, 1], [0, 0], [1, 1], [0, 0])
+    out.append((m, W.density_wave(m, vel=(0.3, -0.2, 0), amp=0.2)))
+    out.append(W.sedov(5, 6, 4, E=2.0, rc=0.2, L=0.5, sigma=0.05)[:2])
+    return out
+
+
+def _single(mesh, u, nsteps, dt_fixed=0.0):
+    s = sedg.Solver(mesh, W.Params())
+    ug = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
+    log = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=DEV)
+    s.rk_step(ug, nsteps, dt_fixed, None if dt_fixed > 0 else log)
+    s.check()
+    out = ug.cpu().numpy(), log.cpu().numpy()[:nsteps]
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("tuning", range(len(TUNINGS)))
+def test_batch_matches_single_problem_bitwise(tuning):
+    probs = _problems()
+    nsteps = 3
+    B = sedg.BatchSolver([m for m, _ in probs], W.Params())
+    B.set_tuning(**TUNINGS[tuning])
+    u = B.pack([x for _, x in probs])
+    log = torch.zeros(nsteps * B.count, dtype=torch.float64, device=DEV)
+    B.rk_step(u, nsteps, 0.0, log)
+    B.check()
+    logs = log.view(nsteps, B.count).cpu().numpy()
+    views = B.views(u)
+    for p, (m, x) in enumerate(probs):
+        ref, ref_log = _single(m, x, nsteps)
+        got = views[p].cpu().numpy()
+        assert np.array_equal(got, ref), (tuning, p, np.abs(got - ref).max())
+        assert np.array_equal(logs[:, p], ref_log), (tuning, p)
+    say("  batch tuning %s: %d problems bitwise equal" % (TUNINGS[tuning], B.count))
+    B.close()
+
+
+def test_batch_fixed_step_bitwise():
+    probs = _problems()
+    B = sedg.BatchSolver([m for m, _ in probs], W.Params())
+    u = B.pack([x for _, x in probs])
+    B.rk_step(u, 2, 2e-5)
+    B.check()
+    views = B.views(u)
+    for p, (m, x) in enumerate(probs):
+        ref, _ = _single(m, x, 2, 2e-5)
+        assert np.array_equal(views[p].cpu().numpy(), ref), p
+    B.close()
+
+
+def test_batch_matches_oracle():
+    """Two members after 5 steps against the oracle's own SSP-RK3 (state 1e-9, steps 1e-14)."""
+    probs = _problems()
+    B = sedg.BatchSolver([m for m, _ in probs], W.Params())
+    u = B.pack([x for _, x in probs])
+    nsteps = 5
+    log = torch.zeros(nsteps * B.count, dtype=torch.float64, device=DEV)
+    B.rk_step(u, nsteps, 0.0, log)
+    B.check()
+    logs = log.view(nsteps, B.count).cpu().numpy()
+    views = B.views(u)
+    for p in (1, 2):
+        m, x = probs[p]
+        uo, dto = O.rk3(m, W.Params(), x, nsteps)
+        err = rel_err(views[p].cpu().numpy(), uo)
+        say("  batch member %d vs oracle after %d steps: rel_err=%.3e" % (p, nsteps, err))
+        assert err <= STATE_TOL
+        assert np.abs(logs[:, p] - dto).max() <= 1e-14 * dto.max()
+    B.close()
+
+
+def test_batch_reports_bad_state():
+    probs = _problems()
+    # a negative density in element 0 of member 3 (whose elements follow 138 others);
+    # within the step the bad state reaches the face neighbours, so the smallest bad
+    # element index over the step is that element's
+    x = probs[3][1].copy()
+    x[0, 0, 3, 5] = -1.0
+    probs[3] = (probs[3][0], x)
+    B = sedg.BatchSolver([m for m, _ in probs], W.Params())
+    u = B.pack([x for _, x in probs])
+    B.rk_step(u, 1, 1e-6)
+    with pytest.raises(sedg.SedgError) as ei:
+        B.check()
+    assert ei.value.problem == 3 and ei.value.element == 0
+    B.close()
+
+
+def test_batch_invalid_arguments():
+    m2 = W.config0(0, 4, 4)[0]
+    m3 = W.Mesh(3, 4, [2, 2, 2], [0.0] * 3, [1.0] * 3, [0, 0, 0])
+    with pytest.raises(sedg.SedgError) as ei:
+        sedg.BatchSolver([m2, m3], W.Params())
+    assert ei.value.code == sedg.SEDG_EUNSUPPORTED
+    mg = W.Mesh(2, 4, [4, 4], [0, 0], [1, 1], [0, 0], gamma=1.3)
+    with pytest.raises(sedg.SedgError) as ei:
+        sedg.BatchSolver([m2, mg], W.Params())
+    assert ei.value.code == sedg.SEDG_EINVAL
+    B = sedg.BatchSolver([m2], W.Params())
+    with pytest.raises(sedg.SedgError):
+        B.set_tuning(epb4=8, epb8=1)
+    B.close()
