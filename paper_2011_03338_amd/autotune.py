@@ -1,0 +1,94 @@
+"""Autotuner of the batched ensemble's launch shape.
+
+Times a short run of every candidate launch shape (elements per workgroup for
+K = 4 and K = 8, a persistent grid of n workgroups per compute unit or one
+workgroup per tile, XCD-contiguous tile ranges or not) on a scratch copy of the
+ensemble state, keeps the fastest and caches the choice as JSON, keyed by the
+device and the ensemble's element counts per K.  The cache file is
+$SEDG_TUNING_CACHE, else ~/.cache/sedg/batch_tuning.json.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import torch
+
+CANDIDATES = [
+    dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1),
+    dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=0),
+    dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=1),
+    dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=0),
+    dict(epb4=4, epb8=1, blocks_per_cu=4, xcd_map=1),
+    dict(epb4=4, epb8=1, blocks_per_cu=8, xcd_map=1),
+    dict(epb4=8, epb8=2, blocks_per_cu=2, xcd_map=1),
+    dict(epb4=8, epb8=2, blocks_per_cu=4, xcd_map=1),
+]
+
+
+def cache_path() -> str:
+    return os.environ.get("SEDG_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "sedg",
+                                                            "batch_tuning.json"))
+
+
+def signature(batch) -> str:
+    """Device name plus the ensemble's element counts per K (order independent)."""
+    counts = {}
+    for m in batch.meshes:
+        counts[m.K] = counts.get(m.K, 0) + m.nel
+    text = json.dumps([torch.cuda.get_device_name(), sorted(counts.items()), len(batch.meshes)])
+    return hashlib.sha1(text.encode()).hexdigest()[:16]
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time(batch, u0, steps):
+    u = u0.clone()
+    batch.rk_step(u, 1)                      # capture the step graph
+    batch.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    batch.rk_step(u, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    batch.check()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(batch, u, steps: int = 2, use_cache: bool = True, candidates=None):
+    """Pick and set the fastest launch shape for `batch` (state u is not modified).
+    Returns (tuning, {candidate index: ms per step}, from_cache)."""
+    key = signature(batch)
+    path = cache_path()
+    cache = _load_cache(path) if use_cache else {}
+    if key in cache:
+        batch.set_tuning(**cache[key]["tuning"])
+        return cache[key]["tuning"], cache[key].get("timings", {}), True
+    cands = candidates or CANDIDATES
+    timings = {}
+    for i, c in enumerate(cands):
+        batch.set_tuning(**c)
+        timings[i] = _time(batch, u, steps)
+    best = min(timings, key=timings.get)
+    batch.set_tuning(**cands[best])
+    entry = {"tuning": cands[best], "timings": {str(i): t for i, t in timings.items()},
+             "candidates": cands}
+    if use_cache:
+        cache[key] = entry
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1)
+            os.replace(tmp, path)
+        except OSError:
+            pass
+    return cands[best], timings, False

@@ -280,10 +280,14 @@ class BatchSolver:
         return {"epb4": t.epb4, "epb8": t.epb8, "blocks_per_cu": t.blocks_per_cu, "xcd_map": t.xcd_map}
 
     def pack(self, states):
-        """One ensemble state (GPU tensor) from per-problem states (arrays or tensors)."""
+        """One ensemble state (GPU tensor) from per-problem states (arrays or tensors),
+        copied piece by piece."""
         import torch
-        parts = [torch.as_tensor(x, dtype=torch.float64).reshape(-1) for x in states]
-        return torch.cat(parts).to("cuda").contiguous()
+        u = torch.empty(self.state_len, dtype=torch.float64, device="cuda")
+        for x, m, o in zip(states, self.meshes, self.offsets):
+            n = m.nvar * m.dof
+            u[o:o + n].copy_(torch.as_tensor(x, dtype=torch.float64).reshape(-1))
+        return u
 
     def views(self, u):
         """Per-problem views of an ensemble state, each shaped (nvar, gz, gy, gx)."""

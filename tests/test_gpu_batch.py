@@ -134,3 +134,20 @@ def test_batch_invalid_arguments():
     with pytest.raises(sedg.SedgError):
         B.set_tuning(epb4=8, epb8=1)
     B.close()
+
+
+def test_autotuner_picks_and_caches(tmp_path, monkeypatch):
+    from paper_2011_03338_amd import autotune
+    monkeypatch.setenv("SEDG_TUNING_CACHE", str(tmp_path / "tune.json"))
+    probs = _problems()
+    B = sedg.BatchSolver([m for m, _ in probs], W.Params())
+    u = B.pack([x for _, x in probs])
+    u_before = u.clone()
+    cands = autotune.CANDIDATES[:3]
+    tun, timings, cached = autotune.tune(B, u, steps=1, candidates=cands)
+    assert not cached and tun in cands and len(timings) == 3
+    assert torch.equal(u, u_before)                  # the state is not advanced
+    assert B.get_tuning() == tun
+    tun2, _, cached2 = autotune.tune(B, u, steps=1, candidates=cands)
+    assert cached2 and tun2 == tun
+    B.close()
