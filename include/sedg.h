@@ -170,16 +170,18 @@ int sedg_adjoint_rhs(sedg_ctx *ctx, const double *u, const double *alpha, const 
  * [u^n | u^(1) | u^(2) | alpha x 3 | beta x 3]. */
 long sedg_tape_len(const sedg_ctx *ctx);
 
-/* One SSP-RK3 step of u in place with the step size *dt_dev (device scalar),
- * recording the step's tape (device, sedg_tape_len doubles, caller-owned).  The
- * arithmetic is that of sedg_rk_step, so a step replayed from a checkpoint with
- * the logged step size reproduces the original step bit for bit. */
-int sedg_rk_step_tape(sedg_ctx *ctx, double *u, const double *dt_dev, double *tape, void *stream);
+/* nsteps SSP-RK3 steps of u in place, step j with the step size dt_dev[j] (device),
+ * recording step j's tape at tapes + j * sedg_tape_len (device, caller-owned).  The
+ * arithmetic is that of sedg_rk_step, so steps replayed from a checkpoint with the
+ * logged step sizes reproduce the original steps bit for bit. */
+int sedg_rk_step_tape(sedg_ctx *ctx, double *u, int nsteps, const double *dt_dev, double *tapes, void *stream);
 
-/* Transposed SSP-RK3 step: on entry lam holds dJ/du^(n+1); on return dJ/du^n for
- * the step recorded in tape, with alpha, beta and the step size frozen.
- * Same support and allocation rules as sedg_adjoint_rhs. */
-int sedg_adjoint_rk_step(sedg_ctx *ctx, const double *tape, const double *dt_dev, double *lam, void *stream);
+/* Transposed SSP-RK3 steps: on entry lam holds dJ/du after the nsteps steps recorded in
+ * tapes (step j at tapes + j * sedg_tape_len, step size dt_dev[j]); on return dJ/du
+ * before them, with alpha, beta and the step sizes frozen.  Same support and
+ * allocation rules as sedg_adjoint_rhs. */
+int sedg_adjoint_rk_step(sedg_ctx *ctx, const double *tapes, int nsteps, const double *dt_dev, double *lam,
+                         void *stream);
 
 /* ---- batched ensembles -------------------------------------------------------
  * Many independent 2-D problems of the scheme above, each with its own mesh

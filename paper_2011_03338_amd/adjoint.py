@@ -63,10 +63,8 @@ class RK3Evolve(torch.autograd.Function):
             s0 = seg * every
             m = min(every, nsteps - s0)
             u = ctx.checkpoints[seg].clone()
-            for j in range(m):
-                solver.rk_step_tape(u, ctx.dt_log[s0 + j:s0 + j + 1], tapes[j])
-            for j in reversed(range(m)):
-                solver.adjoint_rk_step(tapes[j], ctx.dt_log[s0 + j:s0 + j + 1], lam)
+            solver.rk_step_tape(u, ctx.dt_log[s0:s0 + m], tapes)
+            solver.adjoint_rk_step(tapes, ctx.dt_log[s0:s0 + m], lam)
         solver.check()
         return lam, None, None, None
 

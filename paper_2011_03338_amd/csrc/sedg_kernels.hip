@@ -2661,68 +2661,74 @@ Tape tape_view(const sedg_ctx *C, double *tape)
 
 extern "C" {
 
-int sedg_rk_step_tape(sedg_ctx *C, double *u, const double *dt_dev, double *tape, void *stream)
+int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, double *tapes, void *stream)
 {
-    if (!C || !u || !dt_dev || !tape) return SEDG_EINVAL;
+    if (!C || !u || nsteps < 0 || (nsteps > 0 && (!dt_dev || !tapes))) return SEDG_EINVAL;
     if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    Tape T = tape_view(C, tape);
-    if (hipMemcpyAsync(T.u[0], u, sizeof(double) * (size_t)C->nv * C->dof, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return SEDG_EHIP;
-    KArgs P = base_args(C);
-    P.dt = dt_dev;
-    // the three stages of one step, as in sedg_rk_step, with the stage states and the
-    // blending factors and squeezing parameters of every stage kept on the tape
-    P.u = u;
-    P.out = T.u[1];
-    P.alpha = T.alpha[0];
-    P.beta = T.beta[0];
-    P.stage = 1;
-    launch_analyse_any(C, P, s);
-    launch_residual_any(C, P, s);
-    P.u = T.u[1];
-    P.u0 = u;
-    P.out = T.u[2];
-    P.alpha = T.alpha[1];
-    P.beta = T.beta[1];
-    P.stage = 2;
-    launch_analyse_any(C, P, s);
-    launch_residual_any(C, P, s);
-    P.u = T.u[2];
-    P.u0 = u;
-    P.out = u;
-    P.alpha = T.alpha[2];
-    P.beta = T.beta[2];
-    P.stage = 3;
-    launch_analyse_any(C, P, s);
-    launch_residual_any(C, P, s);
+    const long tl = sedg_tape_len(C);
+    for (int j = 0; j < nsteps; ++j) {
+        Tape T = tape_view(C, tapes + (size_t)j * tl);
+        if (hipMemcpyAsync(T.u[0], u, sizeof(double) * (size_t)C->nv * C->dof, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return SEDG_EHIP;
+        KArgs P = base_args(C);
+        P.dt = dt_dev + j;
+        // the three stages of one step, as in sedg_rk_step, with the stage states and the
+        // blending factors and squeezing parameters of every stage kept on the tape
+        P.u = u;
+        P.out = T.u[1];
+        P.alpha = T.alpha[0];
+        P.beta = T.beta[0];
+        P.stage = 1;
+        launch_analyse_any(C, P, s);
+        launch_residual_any(C, P, s);
+        P.u = T.u[1];
+        P.u0 = u;
+        P.out = T.u[2];
+        P.alpha = T.alpha[1];
+        P.beta = T.beta[1];
+        P.stage = 2;
+        launch_analyse_any(C, P, s);
+        launch_residual_any(C, P, s);
+        P.u = T.u[2];
+        P.u0 = u;
+        P.out = u;
+        P.alpha = T.alpha[2];
+        P.beta = T.beta[2];
+        P.stage = 3;
+        launch_analyse_any(C, P, s);
+        launch_residual_any(C, P, s);
+    }
     C->last = s;
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
 }
 
-int sedg_adjoint_rk_step(sedg_ctx *C, const double *tape, const double *dt_dev, double *lam, void *stream)
+int sedg_adjoint_rk_step(sedg_ctx *C, const double *tapes, int nsteps, const double *dt_dev, double *lam, void *stream)
 {
-    if (!C || !tape || !dt_dev || !lam) return SEDG_EINVAL;
+    if (!C || !lam || nsteps < 0 || (nsteps > 0 && (!tapes || !dt_dev))) return SEDG_EINVAL;
     if (!adjoint_supported(C)) return SEDG_EUNSUPPORTED;
     int rc = ensure_adjoint_buffers(C);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    Tape T = tape_view(C, const_cast<double *>(tape));
-    KArgs P = base_args(C);
-    P.dt = dt_dev;
-    P.gfb = C->d_gfb;
-    P.acc = C->d_acc;
-    const double *lin[3] = {C->d_l1, C->d_l2, lam};   // adjoint entering reverse stage 1, 2, 3
-    double *lout[3] = {lam, C->d_l1, C->d_l2};
-    for (int st = 2; st >= 0; --st) {
-        P.u = T.u[st];
-        P.alpha = T.alpha[st];
-        P.beta = T.beta[st];
-        P.lam = lin[st];
-        P.out = lout[st];
-        P.stage = 11 + st;
-        launch_prep_any(C, P, s);
-        launch_adjoint_any(C, P, s);
+    const long tl = sedg_tape_len(C);
+    for (int j = nsteps - 1; j >= 0; --j) {
+        Tape T = tape_view(C, const_cast<double *>(tapes) + (size_t)j * tl);
+        KArgs P = base_args(C);
+        P.dt = dt_dev + j;
+        P.gfb = C->d_gfb;
+        P.acc = C->d_acc;
+        const double *lin[3] = {C->d_l1, C->d_l2, lam};   // adjoint entering reverse stage 1, 2, 3
+        double *lout[3] = {lam, C->d_l1, C->d_l2};
+        for (int st = 2; st >= 0; --st) {
+            P.u = T.u[st];
+            P.alpha = T.alpha[st];
+            P.beta = T.beta[st];
+            P.lam = lin[st];
+            P.out = lout[st];
+            P.stage = 11 + st;
+            launch_prep_any(C, P, s);
+            launch_adjoint_any(C, P, s);
+        }
     }
     C->last = s;
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;

@@ -83,8 +83,8 @@ def load():
     lib.sedg_adjoint_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.sedg_tape_len.argtypes = [vp]
     lib.sedg_tape_len.restype = ctypes.c_long
-    lib.sedg_rk_step_tape.argtypes = [vp, vp, vp, vp, vp]
-    lib.sedg_adjoint_rk_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.sedg_rk_step_tape.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+    lib.sedg_adjoint_rk_step.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
     lib.sedg_batch_create.argtypes = [ctypes.POINTER(Mesh_c), ctypes.c_int, ctypes.POINTER(Params_c), ctypes.POINTER(vp)]
     lib.sedg_batch_destroy.argtypes = [vp]
     lib.sedg_batch_state_len.argtypes = [vp]
@@ -210,15 +210,19 @@ class Solver:
     def tape_len(self) -> int:
         return load().sedg_tape_len(self._h)
 
-    def rk_step_tape(self, u, dt_dev, tape, stream=None):
-        """One SSP-RK3 step of u in place with step size dt_dev (a one-element GPU tensor
-        or a view into a step-size log), recording the step's tape."""
-        _check(load().sedg_rk_step_tape(self._h, _ptr(u), _ptr(dt_dev), _ptr(tape), _stream(stream)),
+    def rk_step_tape(self, u, dt_dev, tapes, stream=None):
+        """len(dt_dev) SSP-RK3 steps of u in place, step j with step size dt_dev[j] (GPU
+        tensor, e.g. a slice of a step-size log), recording tapes[j] (rows of tape_len)."""
+        n = dt_dev.numel()
+        assert tapes.numel() >= n * self.tape_len
+        _check(load().sedg_rk_step_tape(self._h, _ptr(u), n, _ptr(dt_dev), _ptr(tapes), _stream(stream)),
                "sedg_rk_step_tape")
 
-    def adjoint_rk_step(self, tape, dt_dev, lam, stream=None):
-        """lam <- (du^(n+1)/du^n)^T lam for the step recorded in tape."""
-        _check(load().sedg_adjoint_rk_step(self._h, _ptr(tape), _ptr(dt_dev), _ptr(lam), _stream(stream)),
+    def adjoint_rk_step(self, tapes, dt_dev, lam, stream=None):
+        """lam <- (du_end/du_start)^T lam over the len(dt_dev) steps recorded in tapes."""
+        n = dt_dev.numel()
+        assert tapes.numel() >= n * self.tape_len
+        _check(load().sedg_adjoint_rk_step(self._h, _ptr(tapes), n, _ptr(dt_dev), _ptr(lam), _stream(stream)),
                "sedg_adjoint_rk_step")
 
     def profile(self, on: bool):

@@ -224,18 +224,22 @@ def test_adjoint_rk_step_matches_oracle(name):
 
 
 def test_tape_step_reproduces_rk_step():
-    """A taped step with the logged step size reproduces sedg_rk_step bit for bit."""
+    """Taped steps with the logged step sizes reproduce sedg_rk_step bit for bit."""
     mesh, u0, _ = W.sedov(0, 8, 8, L=0.3, sigma=0.03)
     s = sedg.Solver(mesh, W.Params())
     ua = _t(u0).reshape(-1)
     ub = ua.clone()
     log = torch.zeros(3, dtype=torch.float64, device=DEV)
     s.rk_step(ua, 3, 0.0, log)
-    tape = torch.zeros(s.tape_len, dtype=torch.float64, device=DEV)
-    for j in range(3):
-        s.rk_step_tape(ub, log[j:j + 1], tape)
+    tapes = torch.zeros((3, s.tape_len), dtype=torch.float64, device=DEV)
+    s.rk_step_tape(ub, log, tapes)
     s.check()
     assert torch.equal(ua, ub)
+    # the last tape's initial state is the state after two steps
+    uc = _t(u0).reshape(-1)
+    s.rk_step(uc, 2, 0.0, None)
+    s.check()
+    assert torch.equal(tapes[2, :uc.numel()], uc)
     s.close()
 
 
