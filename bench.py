@@ -171,6 +171,43 @@ def adjoint_bench(args, dev):
             "finite_differences": fd, "pulse_center": info["pulse_center"]}
 
 
+def fwd3d_bench(args, dev):
+    """3-D forward: Kelvin-Helmholtz shear layer, 64^3 periodic elements over [-1, 1]^3,
+    K = 8 (degree 7, O(8) -> O(4) -> O(2) -> FV), 134 M DOF, CFL 0.5; means of the
+    initial state by a 3^3 Gauss rule per subcell, computed on the GPU; `steps3d`
+    timed SSP-RK3 steps after one warm-up step, with per-launch events."""
+    import torch
+    from paper_2011_03338_amd import sedg, workloads as W
+    mesh, u0, _ = W.shear_layer_3d(args.seed, 64, 8, nq=3, device="cuda")
+    params = W.Params(cfl=0.5)
+    s = sedg.Solver(mesh, params)
+    u = u0.contiguous().reshape(-1)
+    del u0
+    s.rk_step(u, 1)
+    s.check()
+    s.profile(True)
+    s.profile_read()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.rk_step(u, args.steps3d)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = s.profile_read()
+    s.profile(False)
+    s.check()
+    kb = kernel_bytes_per_launch(mesh, W.alpha_len(mesh, params))
+    kernels = {k: {"avg_ms": (prof[k][0] / prof[k][1]) if prof[k][1] else None, "launches": prof[k][1],
+                   "algorithmic_GBs": (kb[k] / ((prof[k][0] / prof[k][1]) * 1e-3) / 1e9) if k in kb and prof[k][1] else None}
+               for k in prof}
+    s.close()
+    return {"workload": "3-D Kelvin-Helmholtz shear layer, 64^3 periodic elements, K=8, SSP-RK3 CFL 0.5",
+            "value": mesh.dof * 3 * args.steps3d / (ms * 1e-3), "unit": "DOF-updates/s",
+            "steps": args.steps3d, "ms_per_step": ms / args.steps3d, "dof": mesh.dof, "kernels": kernels}
+
+
 def batch_bench(args, dev):
     """Batched ensemble: 256 independent 2-D Sedov-type blasts ([-1.5, 1.5]^2,
     outflow), mesh side drawn from {32, 48, 64, 96, 128} elements, K from {4, 8},
@@ -238,6 +275,8 @@ def main():
     # K = 8 lose positivity between steps 55 and 100 (the oracle too)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--steps3d", type=int, default=5)
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run an untimed device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -297,6 +336,7 @@ def main():
 
     adj = None if args.no_adjoint else adjoint_bench(args, dev)
     batch = None if args.no_batch else batch_bench(args, dev)
+    fwd3d = None if args.no_3d else fwd3d_bench(args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -324,6 +364,7 @@ def main():
         "cpu_baseline": cpu,
         "adjoint": adj,
         "batched": batch,
+        "fwd_3d": fwd3d,
     }
     print(json.dumps(out), flush=True)
 

@@ -590,9 +590,10 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // the minima of the check set are reduced only on levels where some
 // sub-element fails the permissibility check (beta = 1 needs neither).
 
-template <int DIM, int K, int EPB>
+template <int DIM, int K, int TOP, int EPB>
 struct AnalyseSmem {
     typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
     double u[EPB][G::NV][G::KD];
     double r[EPB][2][G::NV][G::KD];         // reconstructions of the current level and of its children
     double t[EPB][G::NV][G::KD];            // temporary
@@ -600,14 +601,14 @@ struct AnalyseSmem {
     double x[EPB * G::KD];                  // reduction exchange
     int ix[EPB * G::KD];
     double lam[EPB * G::KD / 64 + 1];
-    double al[EPB][73];                     // per sub-element: blending factor,
-    double be[EPB][73];                     //   squeezing parameter,
-    double mean[EPB][G::NV][73];            //   mean value
+    double al[EPB][LV::A];                  // per sub-element: blending factor,
+    double be[EPB][LV::A];                  //   squeezing parameter,
+    double mean[EPB][G::NV][LV::A];         //   mean value
 };
 
 // unlimited reconstruction of level li of every variable into dst: u x_1 R x_2 R (x_3 R)
-template <int DIM, int K, int EPB>
-__device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, EPB> &S, int le, int c, const sedg_level_tab &T, int n,
+template <int DIM, int K, int TOP, int EPB>
+__device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, TOP, EPB> &S, int le, int c, const sedg_level_tab &T, int n,
                                             double (*dst)[Geo<DIM, K>::KD])
 {
     constexpr int NV = Geo<DIM, K>::NV;
@@ -627,7 +628,7 @@ __device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, EPB> &S, int le,
 
 // one tile (EPB elements) of the analyse kernel; every thread of the workgroup calls it
 template <int DIM, int K, int TOP, int EPB>
-__device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSmem<DIM, K, EPB> &S)
+__device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSmem<DIM, K, TOP, EPB> &S)
 {
     typedef Geo<DIM, K> G;
     typedef Lv<DIM, K, TOP> LV;
@@ -706,7 +707,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         }
         const sedg_level_tab &T = P.tabs[li];
         if (have_rec != li) {
-            recon_level<DIM, K, EPB>(S, le, c, T, n, S.r[le][li & 1]);
+            recon_level<DIM, K, TOP, EPB>(S, le, c, T, n, S.r[le][li & 1]);
             have_rec = li;
         }
         double (*R0)[KD] = S.r[le][li & 1];
@@ -759,7 +760,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         const bool need_next = (li + 1 < LV::NLEV) &&
                                (P.mode == SEDG_EXTERNAL || (P.mode == SEDG_ADAPTIVE && n >= 4));
         if (__syncthreads_or(visit && need_next)) {
-            recon_level<DIM, K, EPB>(S, le, c, P.tabs[li + 1], n / 2, S.r[le][(li + 1) & 1]);
+            recon_level<DIM, K, TOP, EPB>(S, le, c, P.tabs[li + 1], n / 2, S.r[le][(li + 1) & 1]);
             have_rec = li + 1;
         }
         if (P.mode != SEDG_ADAPTIVE) continue;
@@ -879,7 +880,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
 template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) analyse_kernel(KArgs P)
 {
-    __shared__ AnalyseSmem<DIM, K, EPB> S;
+    __shared__ AnalyseSmem<DIM, K, TOP, EPB> S;
     analyse_body<DIM, K, TOP, EPB>(P, blockIdx.x, S);
 }
 
@@ -2039,8 +2040,8 @@ __global__ void __launch_bounds__(64 * EPB8) analyse_batch_kernel(KArgs P)
 {
     static_assert(16 * EPB4 == 64 * EPB8, "one workgroup size for both K");
     __shared__ union {
-        AnalyseSmem<2, 4, EPB4> k4;
-        AnalyseSmem<2, 8, EPB8> k8;
+        AnalyseSmem<2, 4, 4, EPB4> k4;
+        AnalyseSmem<2, 8, 8, EPB8> k8;
     } U;
     const int L = P.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int t0 = PERSIST ? L * P.chunk : L;
