@@ -457,6 +457,21 @@ __device__ __forceinline__ double lane_xor(double v, int mask)
     return __hiloint2double(hi, lo);
 }
 
+// OR of a predicate over the workgroup, ordered like a barrier.  A one-wavefront
+// workgroup (every 2-D kernel) takes a wave vote after the barrier; the library's
+// workgroup reduction behind __syncthreads_or keeps an LDS buffer of its own, which
+// would cost the residual kernel one resident workgroup per CU.
+template <int NT>
+__device__ __forceinline__ bool block_or(bool pred)
+{
+    if constexpr (NT <= 64) {
+        __syncthreads();
+        return __any(pred ? 1 : 0) != 0;
+    } else {
+        return __syncthreads_or(pred ? 1 : 0) != 0;
+    }
+}
+
 // xor-butterfly reduction over the cells of one level-n sub-element (ln = log2 n;
 // ln = LOGK gives the whole element).  Bits inside a wavefront use lane exchanges,
 // higher bits exchange through LDS; every lane ends with the same value.
@@ -596,8 +611,7 @@ struct AnalyseSmem {
     typedef Lv<DIM, K, TOP> LV;
     double u[EPB][G::NV][G::KD];
     double r[EPB][2][G::NV][G::KD];         // reconstructions of the current level and of its children
-    double t[EPB][G::NV][G::KD];            // temporary
-    double w[EPB][G::NV][G::KD];            // primitive variables
+    double t[EPB][G::NV][G::KD];            // temporary; primitive variables in the indicator
     double x[EPB * G::KD];                  // reduction exchange
     int ix[EPB * G::KD];
     double lam[EPB * G::KD / 64 + 1];
@@ -701,8 +715,8 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         else if (P.mode == SEDG_FORCE_DG) visit = (li == 0);
         else if (P.mode == SEDG_FORCE_FV) visit = false;
         else visit = enabled && !broke;
-        if (!__syncthreads_or(visit)) {
-            if (P.mode != SEDG_ADAPTIVE || !__syncthreads_or(!broke)) break;
+        if (!block_or<EPB * KD>(visit)) {
+            if (P.mode != SEDG_ADAPTIVE || !block_or<EPB * KD>(!broke)) break;
             continue;
         }
         const sedg_level_tab &T = P.tabs[li];
@@ -738,7 +752,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         double b = 1.0;
         const int sub = G::subelem(c, n);
         const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
-        if (__syncthreads_or(visit && !ok)) {
+        if (block_or<EPB * KD>(visit && !ok)) {
             double nd = (DIM == 2) ? n * n : n * n * n;
             double mn[NV];
             for (int v = 0; v < NV; ++v) mn[v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
@@ -759,7 +773,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         // children reconstruction = next level's reconstruction
         const bool need_next = (li + 1 < LV::NLEV) &&
                                (P.mode == SEDG_EXTERNAL || (P.mode == SEDG_ADAPTIVE && n >= 4));
-        if (__syncthreads_or(visit && need_next)) {
+        if (block_or<EPB * KD>(visit && need_next)) {
             recon_level<DIM, K, TOP, EPB>(S, le, c, P.tabs[li + 1], n / 2, S.r[le][(li + 1) & 1]);
             have_rec = li + 1;
         }
@@ -778,7 +792,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             wv[0] = pt[0];
             for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
             wv[DIM + 1] = pressure<DIM>(pt, gam);
-            for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
+            for (int v = 0; v < NV; ++v) S.t[le][v][c] = wv[v];
             __syncthreads();
             double sn[NV], sh[NV];
             {
@@ -786,7 +800,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 for (int d = 0; d < DIM; ++d) wq *= T.w[G::coord(c, d) & (n - 1)];
                 for (int v = 0; v < NV; ++v) {
                     double s = 0.0;
-                    for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, n, T.Dcal));
+                    for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.t[le][v], c, d, n, T.Dcal));
                     sn[v] = wq * s;
                 }
             }
@@ -796,14 +810,14 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             wv[0] = pt[0];
             for (int d = 0; d < DIM; ++d) wv[1 + d] = pt[1 + d] / pt[0];
             wv[DIM + 1] = pressure<DIM>(pt, gam);
-            for (int v = 0; v < NV; ++v) S.w[le][v][c] = wv[v];
+            for (int v = 0; v < NV; ++v) S.t[le][v][c] = wv[v];
             __syncthreads();
             {
                 double wq = (DIM == 2) ? 0.5 : 0.25;   // child measure in parent coordinates
                 for (int d = 0; d < DIM; ++d) wq *= H.w[G::coord(c, d) & (h - 1)];
                 for (int v = 0; v < NV; ++v) {
                     double s = 0.0;
-                    for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.w[le][v], c, d, h, H.Dcal));
+                    for (int d = 0; d < DIM; ++d) s += fabs(bapply<DIM, K>(S.t[le][v], c, d, h, H.Dcal));
                     sh[v] = wq * s;
                 }
             }
@@ -1105,7 +1119,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
                 // uniform skip: no element of the block has this level active on a needed face
-                if (!__syncthreads_or(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+                if (!block_or<EPB * KD>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
                     continue;
                 const sedg_level_tab &T = P.tabs[li];
                 const int n = LV::n(li), ln = ilog2i(n);
@@ -1236,7 +1250,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         // ---------------- DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat) ----------------
 #pragma unroll
         for (int li = 0; li < LV::NLEV; ++li) {
-            if (!__syncthreads_or(actv[1 + li])) continue;
+            if (!block_or<EPB * KD>(actv[1 + li])) continue;
             const sedg_level_tab &T = P.tabs[li];
             const int n = LV::n(li);
             const bool on = th[1 + li] != 0.0;
@@ -1615,7 +1629,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     // x_a Dhat^T); then gu += b (gut x_all R^T) + (1 - b) / n^DIM * (sum of gut over the sub-element)
 #pragma unroll
     for (int li = 0; li < LV::NLEV; ++li) {
-        if (!__syncthreads_or(actv[1 + li])) continue;
+        if (!block_or<EPB * KD>(actv[1 + li])) continue;
         const sedg_level_tab &T = P.tabs[li];
         const int n = LV::n(li), ln = ilog2i(n);
         const double thn = th[1 + li];
@@ -1797,7 +1811,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
             const int sbase = slot * KF;
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
-                if (!__syncthreads_or(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+                if (!block_or<EPB * KD>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
                     continue;
                 const sedg_level_tab &T = P.tabs[li];
                 const int n = LV::n(li), ln = ilog2i(n);
