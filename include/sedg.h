@@ -165,9 +165,11 @@ int sedg_rhs_frozen(sedg_ctx *ctx, const double *u, const double *alpha, const d
 int sedg_adjoint_rhs(sedg_ctx *ctx, const double *u, const double *alpha, const double *beta, const double *lam,
                      double *lam_out, void *stream);
 
-/* Doubles in one step tape: the three stage states of one SSP-RK3 step and the
- * blending factors and squeezing parameters of each stage,
- * [u^n | u^(1) | u^(2) | alpha x 3 | beta x 3]. */
+/* Doubles in one step tape: the three stage states of one SSP-RK3 step and, for
+ * each stage, its blending factors, squeezing parameters, element-face states,
+ * sub-element means and element data scales,
+ * [u^n | u^(1) | u^(2) | alpha x 3 | beta x 3 | face states x 3 | means x 3 | scales x 3]
+ * (alpha and beta in the layout above). */
 long sedg_tape_len(const sedg_ctx *ctx);
 
 /* nsteps SSP-RK3 steps of u in place, step j with the step size dt_dev[j] (device),

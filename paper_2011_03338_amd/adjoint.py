@@ -7,9 +7,9 @@ parameters and step sizes of every stage are those of the forward evolution
 the forward keeps the state at the start of every segment of `every` steps;
 the backward replays one segment at a time from its checkpoint with the logged
 step sizes, recording a tape per step (the three stage states with their
-blending factors and squeezing parameters, bit-identical to the forward since
-the same kernels run on the same inputs), then walks the segment backwards with
-the transposed RK3 step.  Peak extra memory: one checkpoint per segment plus
+blending factors, squeezing parameters, face states, means and scales,
+bit-identical to the forward since the same kernels run on the same inputs),
+then walks the segment backwards with the transposed RK3 step.  Peak extra memory: one checkpoint per segment plus
 `every` tapes.
 
 Every arithmetic step runs in the library (sedg_rk_step, sedg_rk_step_tape,
@@ -88,7 +88,7 @@ def record_frozen(solver: sedg.Solver, u0: torch.Tensor, dt_log: torch.Tensor):
     out = []
     for j in range(dt_log.numel()):
         solver.rk_step_tape(u, dt_log[j:j + 1], tape)
-        out.append(tape[3 * ns:].view(2, 3, na).transpose(0, 1).clone(memory_format=torch.contiguous_format))
+        out.append(tape[3 * ns:3 * ns + 6 * na].view(2, 3, na).transpose(0, 1).clone(memory_format=torch.contiguous_format))
     solver.check()
     return out
 

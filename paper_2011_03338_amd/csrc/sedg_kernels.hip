@@ -1532,6 +1532,40 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
     }
 }
 
+// Each element's own share of the flux adjoints on its element faces, alone: for the
+// transposed RK stages, whose face states, means and scales were recorded on the
+// tape by the analysis that produced the stage.
+template <int DIM, int K, int TOP, int EPB>
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) face_adjoint_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int NV = G::NV, KD = G::KD;
+    __shared__ double s_lam[EPB][NV][KD];
+    __shared__ double s_al[EPB][LV::A];
+    const int tid = threadIdx.x;
+    const int le = tid / KD, c = tid % KD;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = e < P.nel;
+    const int ee = act ? e : P.nel - 1;
+    int e3[3];
+    elem3(P, ee, e3);
+    const long long g = gindex<DIM, K>(P, e3, c);
+    for (int v = 0; v < NV; ++v) s_lam[le][v][c] = P.lam[v * P.dof + g];
+    for (int q = c; q < LV::A; q += KD) s_al[le][q] = P.alpha[(long long)ee * LV::A + q];
+    __syncthreads();
+    if (!act) return;
+    for (int a = 0; a < DIM; ++a) {
+        const int pos = G::coord(c, a);
+        for (int sd = 0; sd < 2; ++sd) {
+            if (pos != (sd ? K - 1 : 0)) continue;
+            double gf[NV];
+            own_face_adjoint<DIM, K, LV>(P, s_al[le], s_lam[le], a, sd ? K : 0, G::trans(c, a), gf);
+            for (int v = 0; v < NV; ++v) P.gfb[fb_index<DIM, K>(e, a, sd, v, G::trans(c, a))] = gf[v];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // adjoint kernel: lam_out = (dL/du)^T lam of the frozen right-hand side
 // ---------------------------------------------------------------------------
@@ -1688,9 +1722,17 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
 
     for (int a = 0; a < DIM; ++a) {
         const int nbL = neighbour<DIM>(P, e3, a, 0), nbR = neighbour<DIM>(P, e3, a, 1);
-        // ---------------- (1) flux adjoints on every face of axis a ----------------
+        // the faces the forward evaluated: every face when the FV level is active, else
+        // the multiples of the smallest active DG level (the element faces at least)
+        int step = K;
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li)
+            if (actv[1 + li]) step = min(step, LV::n(li));
+        if (actv[0]) step = 1;
+        // ---------------- (1) flux adjoints on those faces of axis a ----------------
         for (int q = c; q < (K + 1) * KF; q += KD) {
             const int k = q / KF, t = q % KF;
+            if (k % step != 0) continue;    // never read
             double gf[NV];
             if (k == 0 || k == K) {
                 const int sd = (k == K) ? 1 : 0;
@@ -1712,11 +1754,6 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
         __syncthreads();
 
         // ---------------- (2) reverse of the common fluxes ----------------
-        int step = K;
-#pragma unroll
-        for (int li = 0; li < LV::NLEV; ++li)
-            if (actv[1 + li]) step = min(step, LV::n(li));
-        if (actv[0]) step = 1;
         const int nfaces = face_count<K>(1, step);
         int nfmax = nfaces;
         if (EPB > 1) {
@@ -1929,6 +1966,9 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
             }
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
+                // a level the element does not use contributes nothing (the flag is uniform
+                // over the element's lanes, and the reduction stays inside the element)
+                if (!actv[1 + li]) continue;
                 const double thn = th[1 + li];
                 const sedg_level_tab &T = P.tabs[li];
                 const int n = LV::n(li), ln = ilog2i(n);
@@ -2203,6 +2243,7 @@ void launch_kernel(int which, const KArgs &P, int nblocks, hipStream_t s)
     if (which == 0) hipLaunchKernelGGL((analyse_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
     else if (which == 1) hipLaunchKernelGGL((residual_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
     else if (which == 2) hipLaunchKernelGGL((frozen_prep_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else if (which == 5) hipLaunchKernelGGL((face_adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
     else if constexpr (!(DIM == 3 && K == 8))  // one element's adjoint data exceed the LDS at 3-D K = 8
         hipLaunchKernelGGL((adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
 }
@@ -2228,6 +2269,7 @@ void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { laun
 void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(1, C, P, s); }
 void launch_prep_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(2, C, P, s); }
 void launch_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(3, C, P, s); }
+void launch_face_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(5, C, P, s); }
 
 bool adjoint_supported(const sedg_ctx *C) { return !(C->mesh.dim == 3 && C->mesh.K == 8); }
 
@@ -2649,25 +2691,39 @@ int sedg_adjoint_rhs(sedg_ctx *C, const double *u, const double *alpha, const do
 long sedg_tape_len(const sedg_ctx *C)
 {
     if (!C) return SEDG_EINVAL;
-    return 3L * C->nv * C->dof + 6L * C->A * C->nel;
+    long kf = 1;
+    for (int a = 1; a < C->mesh.dim; ++a) kf *= C->mesh.K;
+    const long nfb = (long)C->nel * C->mesh.dim * 2 * C->nv * kf;
+    return 3L * C->nv * C->dof + 6L * C->A * C->nel + 3L * (nfb + (long)C->nel * C->nv * C->A + 2L * C->nel);
 }
 
 }  // extern "C"
 
 namespace {
 
+// one step's tape: [u^n | u^(1) | u^(2) | alpha x 3 | beta x 3 | face states x 3 |
+// sub-element means x 3 | element scales x 3] (the last three as the analyse kernel
+// writes them, so that a transposed stage needs no second analysis)
 struct Tape {
-    double *u[3], *alpha[3], *beta[3];
+    double *u[3], *alpha[3], *beta[3], *fbuf[3], *mean[3], *scale[3];
 };
 
 Tape tape_view(const sedg_ctx *C, double *tape)
 {
     Tape T;
     const long ns = (long)C->nv * C->dof, na = (long)C->A * C->nel;
+    long kf = 1;
+    for (int a = 1; a < C->mesh.dim; ++a) kf *= C->mesh.K;
+    const long nfb = (long)C->nel * C->mesh.dim * 2 * C->nv * kf, nmn = (long)C->nel * C->nv * C->A,
+               nsc = 2L * C->nel;
+    double *q = tape + 3 * ns + 6 * na;
     for (int k = 0; k < 3; ++k) {
         T.u[k] = tape + k * ns;
         T.alpha[k] = tape + 3 * ns + k * na;
         T.beta[k] = tape + 3 * ns + (3 + k) * na;
+        T.fbuf[k] = q + k * nfb;
+        T.mean[k] = q + 3 * nfb + k * nmn;
+        T.scale[k] = q + 3 * nfb + 3 * nmn + k * nsc;
     }
     return T;
 }
@@ -2694,6 +2750,9 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
         P.out = T.u[1];
         P.alpha = T.alpha[0];
         P.beta = T.beta[0];
+        P.fbuf = T.fbuf[0];
+        P.mean = T.mean[0];
+        P.scale = T.scale[0];
         P.stage = 1;
         launch_analyse_any(C, P, s);
         launch_residual_any(C, P, s);
@@ -2702,6 +2761,9 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
         P.out = T.u[2];
         P.alpha = T.alpha[1];
         P.beta = T.beta[1];
+        P.fbuf = T.fbuf[1];
+        P.mean = T.mean[1];
+        P.scale = T.scale[1];
         P.stage = 2;
         launch_analyse_any(C, P, s);
         launch_residual_any(C, P, s);
@@ -2710,6 +2772,9 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
         P.out = u;
         P.alpha = T.alpha[2];
         P.beta = T.beta[2];
+        P.fbuf = T.fbuf[2];
+        P.mean = T.mean[2];
+        P.scale = T.scale[2];
         P.stage = 3;
         launch_analyse_any(C, P, s);
         launch_residual_any(C, P, s);
@@ -2738,10 +2803,13 @@ int sedg_adjoint_rk_step(sedg_ctx *C, const double *tapes, int nsteps, const dou
             P.u = T.u[st];
             P.alpha = T.alpha[st];
             P.beta = T.beta[st];
+            P.fbuf = T.fbuf[st];
+            P.mean = T.mean[st];
+            P.scale = T.scale[st];
             P.lam = lin[st];
             P.out = lout[st];
             P.stage = 11 + st;
-            launch_prep_any(C, P, s);
+            launch_face_adjoint_any(C, P, s);
             launch_adjoint_any(C, P, s);
         }
     }
