@@ -151,3 +151,39 @@ def test_autotuner_picks_and_caches(tmp_path, monkeypatch):
     tun2, _, cached2 = autotune.tune(B, u, steps=1, candidates=cands)
     assert cached2 and tun2 == tun
     B.close()
+
+
+VARIANTS = [dict(family=W.LGL), dict(mode=W.FORCE_DG), dict(mode=W.FORCE_FV), dict(level_mask=1 << 2),
+            dict(family=W.LGL, level_mask=(1 << 3) | (1 << 1))]
+
+
+@pytest.mark.parametrize("variant", range(len(VARIANTS)))
+def test_batch_variants_match_single_problem_bitwise(variant):
+    """LGL nodes, forced DG or FV, and reduced level sets: the ensemble path must still
+    reproduce the single-problem path bit for bit."""
+    import dataclasses
+    v = VARIANTS[variant]
+    family = v.get("family", W.GAUSS)
+    prm = W.Params(**{k: x for k, x in v.items() if k != "family"})
+    probs = [(dataclasses.replace(m, family=family), x) for m, x in _problems()]
+    if prm.mode == W.FORCE_DG:
+        probs = [probs[i] for i in (1, 3, 4, 5)]      # smooth members only
+    nsteps = 2
+    B = sedg.BatchSolver([m for m, _ in probs], prm)
+    u = B.pack([x for _, x in probs])
+    log = torch.zeros(nsteps * B.count, dtype=torch.float64, device=DEV)
+    B.rk_step(u, nsteps, 0.0, log)
+    B.check()
+    logs = log.view(nsteps, B.count).cpu().numpy()
+    views = B.views(u)
+    for p, (m, x) in enumerate(probs):
+        s = sedg.Solver(m, prm)
+        ug = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+        ref_log = torch.zeros(nsteps, dtype=torch.float64, device=DEV)
+        s.rk_step(ug, nsteps, 0.0, ref_log)
+        s.check()
+        assert np.array_equal(views[p].cpu().numpy(), ug.cpu().numpy()), (v, p)
+        assert np.array_equal(logs[:, p], ref_log.cpu().numpy()), (v, p)
+        s.close()
+    say("  batch variant %s: %d problems bitwise equal" % (v, B.count))
+    B.close()

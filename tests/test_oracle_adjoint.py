@@ -69,6 +69,21 @@ def test_adjoint_directional_blast_with_squeezes():
     assert _dot_check(mesh, u, np.zeros_like(al), be) < 1e-6
 
 
+@pytest.mark.parametrize("K", [4, 8])
+@pytest.mark.parametrize("mode", ["random", "dg"])
+def test_adjoint_directional_lgl(K, mode):
+    """LGL sub-cells.  The config-0 state gets seeded 1e-3 relative noise: LGL nodes on
+    the element faces sample its jump where the modulation vanishes, a pure contact
+    whose two Einfeldt speed estimates coincide (a kink of the frozen map)."""
+    import dataclasses
+    mesh, u, _ = W.config0(1, 3, K)
+    mesh = dataclasses.replace(mesh, family=W.LGL)
+    u = u * (1.0 + 1e-3 * np.random.default_rng(7).standard_normal(u.shape))
+    _, al, be = _base(mesh, u)
+    al = np.random.default_rng(2).uniform(0, 1, al.shape) if mode == "random" else np.ones_like(al)
+    assert _dot_check(mesh, u, al, be) < 1e-6
+
+
 @pytest.mark.parametrize("dim,K", [(1, 8), (3, 4)])
 def test_adjoint_directional_other_dims(dim, K):
     ne = {1: [5], 3: [2, 2, 2]}[dim]
