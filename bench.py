@@ -114,7 +114,10 @@ def adjoint_bench(args, dev):
     checkpointed autograd evolution (checkpoint every 20 steps, frozen factors and
     step sizes).  Reports the forward time, the backward time (replay of every
     segment from its checkpoint plus the transposed steps) and their ratio, and
-    central differences of the frozen map along seeded unit directions."""
+    central differences of the frozen map along seeded unit directions.  The
+    difference error is truncation-dominated at steps of 1e-6 |u0| (the frozen map
+    has kinks where Einfeldt speed estimates tie) and rounding-dominated below
+    1e-9 |u0|; 1e-7 |u0| sits between the two."""
     import numpy as np
     import torch
     from paper_2011_03338_amd import adjoint as ADJ, sedg, workloads as W
@@ -150,7 +153,7 @@ def adjoint_bench(args, dev):
         dts = ADJ.dt_log_of(uT)[:args.adj_steps].clone()
         frozen = ADJ.record_frozen(s, u0, dts)
         rng = np.random.default_rng(args.seed + 1000)
-        eps = 1e-6 * float(u0.norm())
+        eps = args.adj_fd_eps * float(u0.norm())
         errs = []
         for _ in range(args.adj_fd):
             v = torch.from_numpy(rng.standard_normal(u0.numel())).to(dev)
@@ -160,8 +163,8 @@ def adjoint_bench(args, dev):
             fdv = float((jp - jm) / (2 * eps))
             ad = float((grad * v).sum())
             errs.append(abs(fdv - ad) / max(abs(ad), 1e-300))
-        fd = {"directions": args.adj_fd, "eps_relative_to_norm": 1e-6, "max_rel_err": max(errs),
-              "rel_errs": errs}
+        fd = {"directions": args.adj_fd, "eps_relative_to_norm": args.adj_fd_eps, "max_rel_err": max(errs),
+              "within_1e-6": max(errs) <= 1e-6, "rel_errs": errs}
     s.check()
     dof = mesh.dof
     return {"workload": "2-D Euler pressure pulse, 128x128 periodic elements, K=8, %d SSP-RK3 steps, "
@@ -269,7 +272,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--adj-steps", type=int, default=200)
-    ap.add_argument("--adj-fd", type=int, default=2, help="finite-difference directions of the adjoint check")
+    ap.add_argument("--adj-fd", type=int, default=32, help="finite-difference directions of the adjoint check")
+    ap.add_argument("--adj-fd-eps", type=float, default=1e-7,
+                    help="central-difference step along unit directions, relative to the initial state's norm")
     ap.add_argument("--no-adjoint", action="store_true")
     # 50: every member stays permissible; 25 of the 31 members with 32^2 elements at
     # K = 8 lose positivity between steps 55 and 100 (the oracle too)
