@@ -939,6 +939,57 @@ __device__ __forceinline__ void theta_cell_of(const double *al, int cell, double
     theta_from_alpha<LV>(al, sidx, th);
 }
 
+// The two sides of an element face for the lane at transverse position t: the
+// element's own face state and weights, the neighbour's (nb < 0: a domain boundary,
+// where the outflow copy mirrors the own side), the data scales of the pair and the
+// cells whose means replace a non-admissible FV input (element -1: own element).
+// The face-buffer and scale loads of both sides are issued together, unconditionally
+// (a boundary lane reads its own element), so that one memory latency covers them.
+template <int DIM, int K, class LV>
+__device__ __forceinline__ void element_face_sides(const KArgs &P, int ee, int fa, int t, bool high, int nb,
+                                                   const double *al_own, const double *al_nb, double own_sr,
+                                                   double own_se, double *uL, double *uR, double *thL, double *thR,
+                                                   int &mLe, int &mLc, int &mRe, int &mRc, double &srho, double &sE)
+{
+    constexpr int NV = DIM + 2;
+    typedef Geo<DIM, K> G;
+    const int sdo = high ? 1 : 0;
+    const int nbc = nb >= 0 ? nb : ee;
+    double uo[NV], un[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        uo[v] = P.fbuf[fb_index<DIM, K>(ee, fa, sdo, v, t)];
+        un[v] = P.fbuf[fb_index<DIM, K>(nbc, fa, 1 - sdo, v, t)];
+    }
+    const double nsr = P.scale[2 * (long long)nbc], nse = P.scale[2 * (long long)nbc + 1];
+    const int co = G::from_trans(t, fa, high ? K - 1 : 0), cn = G::from_trans(t, fa, high ? 0 : K - 1);
+    double tho[MAXLEV + 1], thn[MAXLEV + 1];
+    theta_cell_of<DIM, K, LV>(al_own, co, tho);
+    if (nb >= 0) {
+        theta_cell_of<DIM, K, LV>(al_nb, cn, thn);
+        srho = fmax(nsr, own_sr);
+        sE = fmax(nse, own_se);
+    } else {
+        for (int l = 0; l <= LV::NLEV; ++l) thn[l] = tho[l];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) un[v] = uo[v];
+    }
+    const int me = nb >= 0 ? nb : -1, mc = nb >= 0 ? cn : co;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        uL[v] = high ? uo[v] : un[v];
+        uR[v] = high ? un[v] : uo[v];
+    }
+    for (int l = 0; l <= LV::NLEV; ++l) {
+        thL[l] = high ? tho[l] : thn[l];
+        thR[l] = high ? thn[l] : tho[l];
+    }
+    mLe = high ? -1 : me;
+    mLc = high ? co : mc;
+    mRe = high ? me : -1;
+    mRc = high ? mc : co;
+}
+
 // The needed faces of na axes starting at a0: first the two element faces of each
 // axis, then the interior faces at multiples of 'step' (1 when the FV level is
 // active, else the smallest active DG level; K leaves none).
@@ -1043,42 +1094,10 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
             // cells whose means replace a non-admissible FV input (element -1: own element)
             int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
             double srho = own_sr, sE = own_se;
-            if (lowface) {
-                int cr = G::from_trans(t, fa, 0), cl = G::from_trans(t, fa, K - 1);
-                for (int v = 0; v < NV; ++v) {
-                    uR[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 0, v, t)];
-                    uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, fa, 1, v, t)] : uR[v];
-                }
-                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
-                mRc = cr;
-                if (nbL >= 0) {
-                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 0], cl, thL);
-                    mLe = nbL;
-                    mLc = cl;
-                    srho = fmax(P.scale[2 * (long long)nbL], own_sr);
-                    sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
-                } else {
-                    for (int l = 0; l <= LV::NLEV; ++l) thL[l] = thR[l];
-                    mLc = cr;
-                }
-            } else if (highface) {
-                int cl = G::from_trans(t, fa, K - 1), cr = G::from_trans(t, fa, 0);
-                for (int v = 0; v < NV; ++v) {
-                    uL[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 1, v, t)];
-                    uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, fa, 0, v, t)] : uL[v];
-                }
-                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
-                mLc = cl;
-                if (nbR >= 0) {
-                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 1], cr, thR);
-                    mRe = nbR;
-                    mRc = cr;
-                    srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
-                    sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
-                } else {
-                    for (int l = 0; l <= LV::NLEV; ++l) thR[l] = thL[l];
-                    mRc = cl;
-                }
+            if (lowface || highface) {
+                element_face_sides<DIM, K, LV>(P, ee, fa, t, highface, highface ? nbR : nbL, S.al[le],
+                                               S.nal[le][2 * fa + (highface ? 1 : 0)], own_sr, own_se, uL, uR, thL,
+                                               thR, mLe, mLc, mRe, mRc, srho, sE);
             } else {
                 // interior face: blended interface states of the two adjacent cells
                 int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
@@ -1772,42 +1791,10 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
             double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
             int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
             double srho = own_sr, sE = own_se;
-            if (lowface) {
-                int cr = G::from_trans(t, fa, 0), cl = G::from_trans(t, fa, K - 1);
-                for (int v = 0; v < NV; ++v) {
-                    uR[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 0, v, t)];
-                    uL[v] = (nbL >= 0) ? P.fbuf[fb_index<DIM, K>(nbL, fa, 1, v, t)] : uR[v];
-                }
-                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
-                mRc = cr;
-                if (nbL >= 0) {
-                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 0], cl, thL);
-                    mLe = nbL;
-                    mLc = cl;
-                    srho = fmax(P.scale[2 * (long long)nbL], own_sr);
-                    sE = fmax(P.scale[2 * (long long)nbL + 1], own_se);
-                } else {
-                    for (int l = 0; l <= LV::NLEV; ++l) thL[l] = thR[l];
-                    mLc = cr;
-                }
-            } else if (highface) {
-                int cl = G::from_trans(t, fa, K - 1), cr = G::from_trans(t, fa, 0);
-                for (int v = 0; v < NV; ++v) {
-                    uL[v] = P.fbuf[fb_index<DIM, K>(ee, fa, 1, v, t)];
-                    uR[v] = (nbR >= 0) ? P.fbuf[fb_index<DIM, K>(nbR, fa, 0, v, t)] : uL[v];
-                }
-                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
-                mLc = cl;
-                if (nbR >= 0) {
-                    theta_cell_of<DIM, K, LV>(S.nal[le][2 * fa + 1], cr, thR);
-                    mRe = nbR;
-                    mRc = cr;
-                    srho = fmax(own_sr, P.scale[2 * (long long)nbR]);
-                    sE = fmax(own_se, P.scale[2 * (long long)nbR + 1]);
-                } else {
-                    for (int l = 0; l <= LV::NLEV; ++l) thR[l] = thL[l];
-                    mRc = cl;
-                }
+            if (lowface || highface) {
+                element_face_sides<DIM, K, LV>(P, ee, fa, t, highface, highface ? nbR : nbL, S.al[le],
+                                               S.nal[le][2 * fa + (highface ? 1 : 0)], own_sr, own_se, uL, uR, thL,
+                                               thR, mLe, mLc, mRe, mRc, srho, sE);
             } else {
                 int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
                 theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
