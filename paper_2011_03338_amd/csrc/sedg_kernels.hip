@@ -990,6 +990,55 @@ __device__ __forceinline__ void element_face_sides(const KArgs &P, int ee, int f
     mRc = high ? mc : co;
 }
 
+// Stage an element's state (and, for the adjoint, its adjoint state), blending
+// factors, squeezing parameters, sub-element means and the face neighbours'
+// blending factors in LDS.  Every global load is issued before the first LDS store,
+// so that one memory latency covers them all (each lane holds at most one entry of
+// the per-element vectors: A <= K^d).
+template <int DIM, int K, class LV, bool LAM, class SM>
+__device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, int c, int ee, const int *e3,
+                                                long long g)
+{
+    constexpr int NV = DIM + 2, NB = 2 * DIM;
+    static_assert(LV::A <= Geo<DIM, K>::KD, "one factor per lane");
+    double uv[NV], lv[NV], mv[NV], an[NB], ao = 0.0, bo = 0.0;
+    int src[NB];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const int nbs = neighbour<DIM>(P, e3, a, sd);
+            src[2 * a + sd] = nbs >= 0 ? nbs : ee;
+        }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        uv[v] = P.u[v * P.dof + g];
+        if constexpr (LAM) lv[v] = P.lam[v * P.dof + g];
+    }
+    const bool hq = c < LV::A;
+    if (hq) {
+        ao = P.alpha[(long long)ee * LV::A + c];
+        bo = P.beta[(long long)ee * LV::A + c];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) mv[v] = P.mean[((long long)ee * NV + v) * LV::A + c];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) an[j] = P.alpha[(long long)src[j] * LV::A + c];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        S.u[le][v][c] = uv[v];
+        if constexpr (LAM) S.lam[le][v][c] = lv[v];
+    }
+    if (hq) {
+        S.al[le][c] = ao;
+        S.be[le][c] = bo;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.mean[le][v][c] = mv[v];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) S.nal[le][j][c] = an[j];
+    }
+}
+
 // The needed faces of na axes starting at a0: first the two element faces of each
 // axis, then the interior faces at multiples of 'step' (1 when the FV level is
 // active, else the smallest active DG level; K leaves none).
@@ -1027,18 +1076,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    for (int v = 0; v < NV; ++v) S.u[le][v][c] = P.u[v * P.dof + g];
-    for (int q = c; q < LV::A; q += KD) {
-        S.al[le][q] = P.alpha[(long long)ee * LV::A + q];
-        S.be[le][q] = P.beta[(long long)ee * LV::A + q];
-        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * LV::A + q];
-    }
-    for (int a = 0; a < DIM; ++a)
-        for (int sd = 0; sd < 2; ++sd) {
-            const int nbs = neighbour<DIM>(P, e3, a, sd);
-            const int src = nbs >= 0 ? nbs : ee;
-            for (int q = c; q < LV::A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * LV::A + q];
-        }
+    preload_element<DIM, K, LV, false>(P, S, le, c, ee, e3, g);
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
@@ -1343,14 +1381,18 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = out[v];
     } else {
         double dt = *P.dt;
-        double ub[NV];
+        double ub[NV], u0[NV];
         for (int v = 0; v < NV; ++v) ub[v] = S.u[le][v][c];
+        // all loads of u^n before the first store (the output may alias nothing, but
+        // the compiler cannot know it, and would otherwise wait once per variable)
+        if (P.stage != 1)
+            for (int v = 0; v < NV; ++v) u0[v] = P.u0[v * P.dof + g];
         for (int v = 0; v < NV; ++v) {
             long long i = v * P.dof + g;
             double r;
             if (P.stage == 1) r = ub[v] + dt * out[v];
-            else if (P.stage == 2) r = 0.75 * P.u0[i] + 0.25 * (ub[v] + dt * out[v]);
-            else r = (1.0 / 3.0) * P.u0[i] + (2.0 / 3.0) * (ub[v] + dt * out[v]);
+            else if (P.stage == 2) r = 0.75 * u0[v] + 0.25 * (ub[v] + dt * out[v]);
+            else r = (1.0 / 3.0) * u0[v] + (2.0 / 3.0) * (ub[v] + dt * out[v]);
             P.out[i] = r;
         }
     }
@@ -1643,21 +1685,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    for (int v = 0; v < NV; ++v) {
-        S.u[le][v][c] = P.u[v * P.dof + g];
-        S.lam[le][v][c] = P.lam[v * P.dof + g];
-    }
-    for (int q = c; q < LV::A; q += KD) {
-        S.al[le][q] = P.alpha[(long long)ee * LV::A + q];
-        S.be[le][q] = P.beta[(long long)ee * LV::A + q];
-        for (int v = 0; v < NV; ++v) S.mean[le][v][q] = P.mean[((long long)ee * NV + v) * LV::A + q];
-    }
-    for (int a = 0; a < DIM; ++a)
-        for (int sd = 0; sd < 2; ++sd) {
-            const int nbs = neighbour<DIM>(P, e3, a, sd);
-            const int src = nbs >= 0 ? nbs : ee;
-            for (int q = c; q < LV::A; q += KD) S.nal[le][2 * a + sd][q] = P.alpha[(long long)src * LV::A + q];
-        }
+    preload_element<DIM, K, LV, true>(P, S, le, c, ee, e3, g);
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
@@ -1982,6 +2010,9 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     }
     // transposed SSP-RK3 stages (stage codes 13, 12, 11 reverse stages 3, 2, 1)
     const double dt = *P.dt;
+    double ac[NV];
+    if (P.stage != 13)
+        for (int v = 0; v < NV; ++v) ac[v] = P.acc[v * P.dof + g];
     for (int v = 0; v < NV; ++v) {
         const long long i = v * P.dof + g;
         const double l = S.lam[le][v][c];
@@ -1990,9 +2021,9 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
             P.acc[i] = (1.0 / 3.0) * l;
         } else if (P.stage == 12) {
             P.out[i] = 0.25 * (l + dt * gu[v]);
-            P.acc[i] += 0.75 * l;
+            P.acc[i] = ac[v] + 0.75 * l;
         } else {
-            P.out[i] = P.acc[i] + l + dt * gu[v];
+            P.out[i] = ac[v] + l + dt * gu[v];
         }
     }
 }
