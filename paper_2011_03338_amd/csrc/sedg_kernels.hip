@@ -45,6 +45,13 @@
 
 struct ProbDesc;
 
+// Level tables are read-only for the lifetime of every launch.  Kernels read them
+// through the constant address space, so that the compiler may treat the loads as
+// invariant: reads of a wave-uniform address become scalar loads, and per-lane
+// reads may be scheduled across barriers.
+typedef const __attribute__((address_space(4))) sedg_level_tab CTab;
+typedef const __attribute__((address_space(4))) double CDbl;
+
 struct KArgs {
     const double *u;        // stage state (read)
     const double *u0;       // u^n for RK stages 2, 3
@@ -55,7 +62,7 @@ struct KArgs {
     double *fbuf;           // face buffer
     double *scale;          // nel * 2: largest mean density and |mean energy| per element
     double *mean;           // nel * NV * A: sub-element means per level
-    const sedg_level_tab *tabs;  // per level index
+    CTab *tabs;                  // per level index
     double *lam_part;       // per-block CFL eigenvalue maxima (nullable)
     const double *dt;       // device scalar step (RK stages)
     int *err;               // smallest bad element index (INT_MAX = none)
@@ -510,13 +517,13 @@ struct OpOr { __device__ int operator()(int a, int b) const { return a | b; } };
 // blocked n-mode product: out = sum_m M[lo][m] * src[base + m*stride] along axis a
 // for level n (lo = position of c inside its level-n sub-element along a)
 template <int DIM, int K>
-__device__ __forceinline__ double bapply(const double *src, int c, int a, int n, const double *M)
+__device__ __forceinline__ double bapply(const double *src, int c, int a, int n, CDbl *M)
 {
     typedef Geo<DIM, K> G;
     int st = G::stride(a);
     int lo = G::coord(c, a) & (n - 1);
     int base = c - lo * st;
-    const double *row = M + lo * n;
+    CDbl *row = M + lo * n;
     double acc = 0.0;
     for (int m = 0; m < n; ++m) acc += row[m] * src[base + m * st];
     return acc;
@@ -622,7 +629,7 @@ struct AnalyseSmem {
 
 // unlimited reconstruction of level li of every variable into dst: u x_1 R x_2 R (x_3 R)
 template <int DIM, int K, int TOP, int EPB>
-__device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, TOP, EPB> &S, int le, int c, const sedg_level_tab &T, int n,
+__device__ __forceinline__ void recon_level(AnalyseSmem<DIM, K, TOP, EPB> &S, int le, int c, CTab &T, int n,
                                             double (*dst)[Geo<DIM, K>::KD])
 {
     constexpr int NV = Geo<DIM, K>::NV;
@@ -719,7 +726,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             if (P.mode != SEDG_ADAPTIVE || !block_or<EPB * KD>(!broke)) break;
             continue;
         }
-        const sedg_level_tab &T = P.tabs[li];
+        CTab &T = P.tabs[li];
         if (have_rec != li) {
             recon_level<DIM, K, TOP, EPB>(S, le, c, T, n, S.r[le][li & 1]);
             have_rec = li;
@@ -735,7 +742,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             int lo = G::coord(c, a) & (n - 1);
             for (int sd = 0; sd < 2; ++sd) {
                 if (lo != (sd ? n - 1 : 0)) continue;
-                const double *bv = sd ? T.bp : T.bm;
+                CDbl *bv = sd ? T.bp : T.bm;
                 int st = G::stride(a), base = c - lo * st;
                 for (int v = 0; v < NV; ++v) {
                     double s = 0.0;
@@ -783,7 +790,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (n == 2) {
             a = (b < P.beta_L) ? 0.0 : b;
         } else {
-            const sedg_level_tab &H = P.tabs[li + 1];
+            CTab &H = P.tabs[li + 1];
             double (*R1)[KD] = S.r[le][(li + 1) & 1];
             const int h = n / 2;
             double wv[NV];
@@ -875,9 +882,9 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
                 if (th[1 + li] == 0.0) continue;
-                const sedg_level_tab &T = P.tabs[li];
+                CTab &T = P.tabs[li];
                 int n = LV::n(li);
-                const double *E = sd ? T.Ep : T.Em;
+                CDbl *E = sd ? T.Ep : T.Em;
                 const int q = LV::off(li) + sidx[li];
                 double b = S.be[le][q];
                 for (int v = 0; v < NV; ++v) {
@@ -1149,7 +1156,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 }
 #pragma unroll
                 for (int li = 0; li < LV::NLEV; ++li) {
-                    const sedg_level_tab &T = P.tabs[li];
+                    CTab &T = P.tabs[li];
                     int n = LV::n(li);
                     if (thL[1 + li] != 0.0) {
                         int s = G::subelem(cl, n);
@@ -1178,7 +1185,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 // uniform skip: no element of the block has this level active on a needed face
                 if (!block_or<EPB * KD>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
                     continue;
-                const sedg_level_tab &T = P.tabs[li];
+                CTab &T = P.tabs[li];
                 const int n = LV::n(li), ln = ilog2i(n);
                 const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
                 const bool need = has && (k % n == 0) && (tb != 0.0);
@@ -1308,7 +1315,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
 #pragma unroll
         for (int li = 0; li < LV::NLEV; ++li) {
             if (!block_or<EPB * KD>(actv[1 + li])) continue;
-            const sedg_level_tab &T = P.tabs[li];
+            CTab &T = P.tabs[li];
             const int n = LV::n(li);
             const bool on = th[1 + li] != 0.0;
             // squeezed reconstruction at this cell's node
@@ -1441,7 +1448,7 @@ __device__ void own_face_adjoint(const KArgs &P, const double *al, const double 
         for (int li = 0; li < LV::NLEV; ++li) {
             const int n = LV::n(li);
             if (k % n != 0 || th[1 + li] == 0.0) continue;
-            const sedg_level_tab &T = P.tabs[li];
+            CTab &T = P.tabs[li];
             const double w = (K / (n * arg_dx(P, a))) * th[1 + li];
             for (int lo = 0; lo < n; ++lo) {
                 const int cell = cl - (n - 1 - lo) * st;
@@ -1458,7 +1465,7 @@ __device__ void own_face_adjoint(const KArgs &P, const double *al, const double 
         for (int li = 0; li < LV::NLEV; ++li) {
             const int n = LV::n(li);
             if (k % n != 0 || th[1 + li] == 0.0) continue;
-            const sedg_level_tab &T = P.tabs[li];
+            CTab &T = P.tabs[li];
             const double w = (K / (n * arg_dx(P, a))) * th[1 + li];
             for (int lo = 0; lo < n; ++lo) {
                 const int cell = cr + lo * st;
@@ -1472,7 +1479,7 @@ __device__ void own_face_adjoint(const KArgs &P, const double *al, const double 
 // M[lo][m] src(m) (2-D), or M[lo0][m0] M[lo1][m1] src(m0, m1) (3-D); src is a
 // face-plane array of K^(DIM-1) values
 template <int DIM, int K>
-__device__ __forceinline__ double seg_apply(const double *src, int t, int n, const double *M)
+__device__ __forceinline__ double seg_apply(const double *src, int t, int n, CDbl *M)
 {
     if (DIM == 2) {
         const int lo0 = t & (n - 1), tb0 = t - lo0;
@@ -1571,9 +1578,9 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
                 if (th[1 + li] == 0.0) continue;
-                const sedg_level_tab &T = P.tabs[li];
+                CTab &T = P.tabs[li];
                 int n = LV::n(li);
-                const double *E = sd ? T.Ep : T.Em;
+                CDbl *E = sd ? T.Ep : T.Em;
                 const int q = LV::off(li) + sidx[li];
                 double b = S.be[le][q];
                 for (int v = 0; v < NV; ++v) {
@@ -1711,7 +1718,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
 #pragma unroll
     for (int li = 0; li < LV::NLEV; ++li) {
         if (!block_or<EPB * KD>(actv[1 + li])) continue;
-        const sedg_level_tab &T = P.tabs[li];
+        CTab &T = P.tabs[li];
         const int n = LV::n(li), ln = ilog2i(n);
         const double thn = th[1 + li];
         const double b = S.be[le][LV::off(li) + sidx[li]];
@@ -1835,7 +1842,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
                 }
 #pragma unroll
                 for (int li = 0; li < LV::NLEV; ++li) {
-                    const sedg_level_tab &T = P.tabs[li];
+                    CTab &T = P.tabs[li];
                     int n = LV::n(li);
                     if (thL[1 + li] != 0.0) {
                         int s = G::subelem(cl, n);
@@ -1865,7 +1872,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
             for (int li = 0; li < LV::NLEV; ++li) {
                 if (!block_or<EPB * KD>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
                     continue;
-                const sedg_level_tab &T = P.tabs[li];
+                CTab &T = P.tabs[li];
                 const int n = LV::n(li), ln = ilog2i(n);
                 const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
                 const bool need = has && (k % n == 0) && (tb != 0.0);
@@ -1985,7 +1992,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
                 // over the element's lanes, and the reduction stays inside the element)
                 if (!actv[1 + li]) continue;
                 const double thn = th[1 + li];
-                const sedg_level_tab &T = P.tabs[li];
+                CTab &T = P.tabs[li];
                 const int n = LV::n(li), ln = ilog2i(n);
                 const double b = S.be[le][LV::off(li) + sidx[li]];
                 const double nd = (DIM == 2) ? n * n : n * n * n;
@@ -2321,7 +2328,7 @@ KArgs base_args(const sedg_ctx *C)
     P.fbuf = C->d_fbuf;
     P.scale = C->d_scale;
     P.mean = C->d_mean;
-    P.tabs = C->d_tabs;
+    P.tabs = (CTab *)C->d_tabs;
     P.err = C->d_err;
     P.lam_mask = LAM_SLOTS - 1;
     P.dof = C->dof;
@@ -2909,7 +2916,7 @@ KArgs batch_args(const sedg_batch *B)
     P.mean = B->d_mean;
     P.scale = B->d_scale;
     P.fbuf = B->d_fbuf;
-    P.tabs = B->d_tabs;
+    P.tabs = (CTab *)B->d_tabs;
     P.err = B->d_err;
     P.dt = B->d_dt;
     P.probs = B->d_probs;
