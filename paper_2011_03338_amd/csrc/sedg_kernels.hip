@@ -1198,32 +1198,42 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                     lo0 = t0 & (n - 1); tb0 = t0 - lo0;
                     lo1 = t1 & (n - 1); tb1 = t1 - lo1;
                 }
+                const int t0 = t - K * (t >> G::LOGK), t1 = t >> G::LOGK;   // 3-D face coordinates
                 for (int v = 0; v < NV; ++v) {
                     S.wsL[le * KD + c] = uL[v];
                     S.wsR[le * KD + c] = uR[v];
                     __syncthreads();
                     double sl = 0.0, sr = 0.0;
-                    if (need) {
-                        if (DIM == 2) {
+                    if (DIM == 2) {
+                        if (need)
                             for (int m = 0; m < n; ++m) {
                                 double Rm = T.R[lo0 * n + m];
                                 sl += Rm * S.wsL[le * KD + sbase + tb0 + m];
                                 sr += Rm * S.wsR[le * KD + sbase + tb0 + m];
                             }
-                        } else {
-                            for (int m1 = 0; m1 < n; ++m1) {
-                                double al0 = 0.0, ar0 = 0.0;
-                                for (int m0 = 0; m0 < n; ++m0) {
-                                    double Rm = T.R[lo0 * n + m0];
-                                    int q = sbase + (tb0 + m0) + K * (tb1 + m1);
-                                    al0 += Rm * S.wsL[le * KD + q];
-                                    ar0 += Rm * S.wsR[le * KD + q];
-                                }
-                                double Rm1 = T.R[lo1 * n + m1];
-                                sl += Rm1 * al0;
-                                sr += Rm1 * ar0;
+                    } else {
+                        // separable: along t0 for the lane's own row, through LDS, then along t1
+                        // (the row sums the lane (t0, tb1 + m1) leaves are exactly the inner sums
+                        // of R x R; need is uniform over a level-n segment)
+                        double al0 = 0.0, ar0 = 0.0;
+                        if (need)
+                            for (int m0 = 0; m0 < n; ++m0) {
+                                double Rm = T.R[lo0 * n + m0];
+                                int q = sbase + (tb0 + m0) + K * t1;
+                                al0 += Rm * S.wsL[le * KD + q];
+                                ar0 += Rm * S.wsR[le * KD + q];
                             }
-                        }
+                        __syncthreads();
+                        S.wsL[le * KD + c] = al0;
+                        S.wsR[le * KD + c] = ar0;
+                        __syncthreads();
+                        if (need)
+                            for (int m1 = 0; m1 < n; ++m1) {
+                                double Rm1 = T.R[lo1 * n + m1];
+                                int q = sbase + t0 + K * (tb1 + m1);
+                                sl += Rm1 * S.wsL[le * KD + q];
+                                sr += Rm1 * S.wsR[le * KD + q];
+                            }
                     }
                     nl[v] = sl;
                     nr[v] = sr;
@@ -1250,17 +1260,21 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                     S.wsL[le * KD + c] = fnod[v];
                     __syncthreads();
                     double sacc = 0.0;
-                    if (need && okf) {
-                        if (DIM == 2) {
+                    if (DIM == 2) {
+                        if (need && okf)
                             for (int m = 0; m < n; ++m) sacc += T.P[lo0 * n + m] * S.wsL[le * KD + sbase + tb0 + m];
-                        } else {
-                            for (int m1 = 0; m1 < n; ++m1) {
-                                double a0s = 0.0;
-                                for (int m0 = 0; m0 < n; ++m0)
-                                    a0s += T.P[lo0 * n + m0] * S.wsL[le * KD + sbase + (tb0 + m0) + K * (tb1 + m1)];
-                                sacc += T.P[lo1 * n + m1] * a0s;
-                            }
-                        }
+                    } else {
+                        // separable, as for R above (okf is uniform over a level-n segment too)
+                        double a0s = 0.0;
+                        if (need && okf)
+                            for (int m0 = 0; m0 < n; ++m0)
+                                a0s += T.P[lo0 * n + m0] * S.wsL[le * KD + sbase + (tb0 + m0) + K * t1];
+                        __syncthreads();
+                        S.wsL[le * KD + c] = a0s;
+                        __syncthreads();
+                        if (need && okf)
+                            for (int m1 = 0; m1 < n; ++m1)
+                                sacc += T.P[lo1 * n + m1] * S.wsL[le * KD + sbase + t0 + K * (tb1 + m1)];
                     }
                     if (need && okf) F[v] += tb * sacc;
                     __syncthreads();
