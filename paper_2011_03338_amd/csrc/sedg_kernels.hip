@@ -935,6 +935,9 @@ struct ResidualSmem {
     double nal[EPB][2 * DIM][LV::A];
     double wsL[EPB * G::KD], wsR[EPB * G::KD];
     int act[EPB][MAXLEV + 1];
+    // 3-D: the squeezed nodal values of every level, reconstructed in the first axis pass
+    // and reused by the other two
+    double nodc[AXO ? EPB : 1][AXO ? LV::NLEV : 1][AXO ? G::NV : 1][AXO ? G::KD : 1];
 };
 
 // theta of the cell across an element face, from the neighbour's alpha
@@ -1103,14 +1106,12 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
 
     double out[NV];
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
-    double rfv[NV];
-    for (int v = 0; v < NV; ++v) rfv[v] = 0.0;
-    double lr[SM::AXO ? MAXLEV : 1][NV];
-    for (int li = 0; li < (SM::AXO ? MAXLEV : 1); ++li)
-        for (int v = 0; v < NV; ++v) lr[li][v] = 0.0;
-
     constexpr int NPASS = SM::AXO ? DIM : 1;
     for (int pass = 0; pass < NPASS; ++pass) {
+        // each pass adds its axes' FV part, then its levels' parts from the top (blend of
+        // eq. blending-weights, summed axis pass by axis pass in 3-D)
+        double rfv[NV];
+        for (int v = 0; v < NV; ++v) rfv[v] = 0.0;
         const int a0 = SM::AXO ? pass : 0, a1 = SM::AXO ? pass + 1 : DIM;
         // ---------------- common fluxes on the needed faces of axes [a0, a1) ----------------
         int step = K;
@@ -1321,8 +1322,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 for (int v = 0; v < NV; ++v)
                     rfv[v] -= sc * (S.F[le][axs][v][(pos + 1) * KF + tr] - S.F[le][axs][v][pos * KF + tr]);
             }
-            if (!SM::AXO)
-                for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
+            for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
         }
 
         // ---------------- DG levels: (K/(n dx_a)) (f~_a x_a Dhat x_perp P - F*_a x_a Bhat) ----------------
@@ -1338,20 +1338,25 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
                 __syncthreads();
                 for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(S.tmp[le][v], c, 1, n, T.R);
-            } else {
+            } else if (pass == 0) {
                 for (int v = 0; v < NV; ++v) S.nod[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
                 __syncthreads();
                 for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.nod[le][v], c, 1, n, T.R);
                 __syncthreads();
                 for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(S.tmp[le][v], c, 2, n, T.R);
+            } else {
+                for (int v = 0; v < NV; ++v) nodal[v] = S.nodc[SM::AXO ? le : 0][SM::AXO ? li : 0][SM::AXO ? v : 0][SM::AXO ? c : 0];
             }
-            {
+            if (!SM::AXO || pass == 0) {
                 int s = sidx[li];
                 double b = S.be[le][LV::off(li) + s];
                 for (int v = 0; v < NV; ++v) nodal[v] = (1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * nodal[v];
+                if (SM::AXO)
+                    for (int v = 0; v < NV; ++v)
+                        S.nodc[SM::AXO ? le : 0][SM::AXO ? li : 0][SM::AXO ? v : 0][SM::AXO ? c : 0] = nodal[v];
             }
             double lrl[NV];
-            for (int v = 0; v < NV; ++v) lrl[v] = SM::AXO ? lr[li][v] : 0.0;
+            for (int v = 0; v < NV; ++v) lrl[v] = 0.0;
             for (int a = a0; a < a1; ++a) {
                 const int axs = SM::AXO ? 0 : a;
                 double f[NV];
@@ -1379,24 +1384,12 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                     }
                 }
             }
-            if (SM::AXO) {
-                for (int v = 0; v < NV; ++v) lr[li][v] = lrl[v];
-            } else if (on) {
+            if (on)
                 for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lrl[v];
-            }
             __syncthreads();
         }
     }
 
-    // blend (eq. blending-weights): FV first, then the levels from the top
-    if (SM::AXO) {
-        if (th[0] != 0.0)
-            for (int v = 0; v < NV; ++v) out[v] += th[0] * rfv[v];
-#pragma unroll
-        for (int li = 0; li < LV::NLEV; ++li)
-            if (th[1 + li] != 0.0)
-                for (int v = 0; v < NV; ++v) out[v] += th[1 + li] * lr[li][v];
-    }
     if (!act) return;
     if (P.stage == 0) {
         for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = out[v];
