@@ -916,8 +916,9 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) analyse_kernel(KArgs 
 // face subcell; (3) the FV part, then for each active DG level the squeezed
 // reconstruction, nodal fluxes, Dhat along the flux axis, P along the others
 // and the Bhat surface term; (4) blend and store (SSP-RK3 stage fused).
-// In 3-D the flux buffer holds one axis at a time (LDS budget), so the
-// reconstruction is repeated per axis; in 2-D all axes are held.
+// In 3-D the flux buffer holds one axis at a time (LDS budget): the element is
+// processed in one pass per axis, the squeezed nodal values of each level are
+// reconstructed in the first pass and kept for the others; in 2-D all axes are held.
 
 template <int DIM, int K, int TOP, int EPB>
 struct ResidualSmem {
