@@ -227,6 +227,47 @@ def test_full_size_sedov_windows():
         assert err <= tol
 
 
+def test_full_size_shear3d_windows():
+    """64^3 elements, K = 8 (the 3-D benchmark's launch configuration): the right-hand
+    side of sampled 3x3x3-element windows equals the oracle's on the window cut out with
+    one ring of neighbours (outflow edges on the cut, interior compared), at windows on
+    the two shear layers (y = -1/2, +1/2), on the mid-plane and at seeded positions."""
+    mesh, ud, _ = W.shear_layer_3d(0, 64, 8, nq=3, device=DEV)
+    p = W.Params()
+    s = sedg.Solver(mesh, p)
+    ug = ud.contiguous()
+    del ud
+    dg = torch.zeros_like(ug)
+    s.rhs(ug, dg)
+    s.check()
+    s.close()
+    K, ne, h = 8, 64, 2.0 / 64
+    rng = np.random.default_rng(5)
+    centres = [(10, 16, 20), (40, 48, 33), (31, 32, 31), (5, 15, 58)]
+    centres += [(int(rng.integers(2, 62)), int(rng.choice([15, 16, 47, 48])), int(rng.integers(2, 62))) for _ in range(2)]
+    for (ex, ey, ez) in centres:
+        x0, y0, z0 = ex - 2, ey - 2, ez - 2
+        sub = np.ascontiguousarray(ug[:, z0 * K:(z0 + 5) * K, y0 * K:(y0 + 5) * K, x0 * K:(x0 + 5) * K].cpu().numpy())
+        wm = W.Mesh(3, K, [5, 5, 5], [-1.0 + x0 * h, -1.0 + y0 * h, -1.0 + z0 * h],
+                    [-1.0 + (x0 + 5) * h, -1.0 + (y0 + 5) * h, -1.0 + (z0 + 5) * h], [1, 1, 1])
+        do = O.rhs(wm, p, sub)
+        go = dg[:, (z0 + 1) * K:(z0 + 4) * K, (y0 + 1) * K:(y0 + 4) * K, (x0 + 1) * K:(x0 + 4) * K].cpu().numpy()
+        oo = do[:, K:4 * K, K:4 * K, K:4 * K]
+        noise = 0.0
+        for t in range(2):
+            sgn = np.random.default_rng(200 + t).choice([-1.0, 1.0], size=sub.shape)
+            dp = O.rhs(wm, p, np.ascontiguousarray(sub * (1.0 + sgn * 2.220446049250313e-16)))
+            noise = max(noise, np.abs(dp - do)[:, K:4 * K, K:4 * K, K:4 * K].max())
+        scale = np.abs(oo).max()
+        err = np.abs(go - oo).max()
+        tol = max(RHS_TOL * scale, 4.0 * noise)
+        say("  3-D window (%d,%d,%d) |g-o|=%.3e  max|o|=%.3e  rel=%.3e  oracle 1-ulp noise=%.3e"
+            % (ex, ey, ez, err, scale, err / scale, noise))
+        assert err <= tol
+    del ug, dg
+    torch.cuda.empty_cache()
+
+
 def test_full_size_conservation_periodic():
     """128x128 elements, K = 8, periodic: the domain sum of the right-hand side
     vanishes to round-off for adaptive and random blending factors."""
