@@ -187,3 +187,47 @@ def test_batch_variants_match_single_problem_bitwise(variant):
         s.close()
     say("  batch variant %s: %d problems bitwise equal" % (v, B.count))
     B.close()
+
+
+def test_full_size_ensemble_members():
+    """The benchmark's ensemble (256 blasts, sides {32..128}^2, K in {4, 8}, 74.6 M DOF)
+    in two launch shapes: after 2 steps, sampled members equal the single-problem path
+    bit for bit (states and step sizes), and a small member matches the oracle."""
+    from paper_2011_03338_amd import autotune
+    descs = W.ensemble(0, 256)
+    meshes, states = [], []
+    for d in descs:
+        m, x, _ = W.ensemble_problem(d)
+        meshes.append(m)
+        states.append(x)
+    prm = W.Params(cfl=0.5)
+    rng = np.random.default_rng(9)
+    dofs = np.array([m.dof for m in meshes])
+    sample = sorted({int(np.argmax(dofs)), int(np.argmin(dofs))} | {int(i) for i in rng.choice(256, 4, replace=False)})
+    nsteps = 2
+    for tun in (autotune.CANDIDATES[0], autotune.CANDIDATES[5]):
+        B = sedg.BatchSolver(meshes, prm)
+        B.set_tuning(**tun)
+        u = B.pack(states)
+        log = torch.zeros(nsteps * B.count, dtype=torch.float64, device=DEV)
+        B.rk_step(u, nsteps, 0.0, log)
+        B.check()
+        logs = log.view(nsteps, B.count).cpu().numpy()
+        views = B.views(u)
+        for p in sample:
+            s = sedg.Solver(meshes[p], prm)
+            ug = torch.from_numpy(np.ascontiguousarray(states[p])).to(DEV)
+            rl = torch.zeros(nsteps, dtype=torch.float64, device=DEV)
+            s.rk_step(ug, nsteps, 0.0, rl)
+            s.check()
+            assert np.array_equal(views[p].cpu().numpy(), ug.cpu().numpy()), (tun, p)
+            assert np.array_equal(logs[:, p], rl.cpu().numpy()), (tun, p)
+            s.close()
+        say("  full ensemble, tuning %s: members %s bitwise equal to single solves" % (tun, sample))
+        small = int(np.argmin(dofs))
+        uo, dto = O.rk3(meshes[small], prm, states[small], nsteps)
+        err = rel_err(views[small].cpu().numpy(), uo)
+        assert err <= STATE_TOL and np.abs(logs[:, small] - dto).max() <= 1e-14 * dto.max()
+        B.close()
+        del u
+    torch.cuda.empty_cache()
