@@ -344,3 +344,43 @@ def test_autograd_evolution_finite_differences():
     # central differences at this step carry ~1e-7..1e-6 of truncation and rounding
     assert max(errs) <= 2e-6
     s.close()
+
+
+def test_full_size_adjoint_windows():
+    """The adjoint workload's size and state (128x128 periodic elements, K = 8, pressure
+    pulse): the adjoint right-hand side at the adaptive factors, with a seeded adjoint
+    state, against the oracle's on 5x5-element windows (the factors and squeezing
+    parameters cut out of the full-size ones, outflow edges on the cut); the interior
+    3x3 elements only see fluxes between window elements."""
+    mesh, u, _ = W.pressure_pulse(0, 128, 8)
+    p = W.Params()
+    s = sedg.Solver(mesh, p)
+    ug = _t(u)
+    d = torch.zeros_like(ug)
+    al = torch.zeros(s.alpha_len, dtype=torch.float64, device=DEV)
+    be = torch.zeros_like(al)
+    s.rhs(ug, d, al, be)
+    lam = np.random.default_rng(41).standard_normal(u.shape)
+    out = torch.zeros_like(ug)
+    s.adjoint_rhs(ug, al, be, _t(lam), out)
+    s.check()
+    s.close()
+    A = W.alpha_len(mesh, p)
+    aln = al.cpu().numpy().reshape(128, 128, A)
+    ben = be.cpu().numpy().reshape(128, 128, A)
+    g = out.cpu().numpy()
+    K, h = 8, 1.0 / 128
+    rng = np.random.default_rng(3)
+    centres = [(72, 49), (64, 64), (56, 40)] + [tuple(int(x) for x in rng.integers(2, 126, 2)) for _ in range(3)]
+    for (ex, ey) in centres:
+        x0, y0 = ex - 2, ey - 2
+        wm = W.Mesh(2, K, [5, 5], [x0 * h, y0 * h], [(x0 + 5) * h, (y0 + 5) * h], [1, 1])
+        sl = (slice(None), slice(None), slice(y0 * K, (y0 + 5) * K), slice(x0 * K, (x0 + 5) * K))
+        wal = np.ascontiguousarray(aln[y0:y0 + 5, x0:x0 + 5].reshape(25, A))
+        wbe = np.ascontiguousarray(ben[y0:y0 + 5, x0:x0 + 5].reshape(25, A))
+        o = O.adjoint_rhs(wm, p, np.ascontiguousarray(u[sl]), wal, wbe, np.ascontiguousarray(lam[sl]))
+        oi = o[:, :, K:4 * K, K:4 * K]
+        gi = g[:, :, (y0 + 1) * K:(y0 + 4) * K, (x0 + 1) * K:(x0 + 4) * K]
+        err = np.abs(gi - oi).max() / np.abs(oi).max()
+        say("  adjoint window (%d,%d) rel_err=%.3e" % (ex, ey, err))
+        assert err <= ADJ_TOL
