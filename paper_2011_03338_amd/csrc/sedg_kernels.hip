@@ -867,18 +867,23 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             P.beta[(long long)e * LV::A + q] = S.be[le][q];
             for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * LV::A + q] = S.mean[le][v][q];
         }
-    int sidx[MAXLEV];
-    subidx_all<DIM, K, LV>(c, sidx);
-    double th[MAXLEV + 1];
-    theta_from_alpha<LV>(S.al[le], sidx, th);
     // blended interface states on the element faces: theta_FV * mean + sum_n theta_n *
-    // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation)
-    for (int a = 0; a < DIM; ++a) {
-        int pos = G::coord(c, a);
-        for (int sd = 0; sd < 2; ++sd) {
-            if (pos != (sd ? K - 1 : 0)) continue;
+    // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation).
+    // One task per (element, face, face cell), spread over the workgroup's lanes, rather
+    // than each boundary lane looping over the faces its cell touches.
+    {
+        constexpr int NF = 2 * DIM, KF = G::KF;
+        for (int tsk = tid; tsk < EPB * NF * KF; tsk += EPB * KD) {
+            const int tle = tsk / (NF * KF), rem = tsk - tle * (NF * KF), f = rem / KF, t = rem - f * KF;
+            const int a = f >> 1, sd = f & 1;
+            const int cc = G::from_trans(t, a, sd ? K - 1 : 0);
+            const int te = tile * EPB + tle;
+            int sidx[MAXLEV];
+            subidx_all<DIM, K, LV>(cc, sidx);
+            double th[MAXLEV + 1];
+            theta_from_alpha<LV>(S.al[tle], sidx, th);
             double st[NV];
-            for (int v = 0; v < NV; ++v) st[v] = th[0] * ub[v];
+            for (int v = 0; v < NV; ++v) st[v] = th[0] * S.u[tle][v][cc];
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
                 if (th[1 + li] == 0.0) continue;
@@ -886,14 +891,14 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 int n = LV::n(li);
                 CDbl *E = sd ? T.Ep : T.Em;
                 const int q = LV::off(li) + sidx[li];
-                double b = S.be[le][q];
+                double b = S.be[tle][q];
                 for (int v = 0; v < NV; ++v) {
-                    double tr = bapply<DIM, K>(S.u[le][v], c, a, n, E);
-                    st[v] += th[1 + li] * ((1.0 - b) * S.mean[le][v][q] + b * tr);
+                    double tr = bapply<DIM, K>(S.u[tle][v], cc, a, n, E);
+                    st[v] += th[1 + li] * ((1.0 - b) * S.mean[tle][v][q] + b * tr);
                 }
             }
-            if (act)
-                for (int v = 0; v < NV; ++v) P.fbuf[fb_index<DIM, K>(e, a, sd, v, G::trans(c, a))] = st[v];
+            if (te < P.nel)
+                for (int v = 0; v < NV; ++v) P.fbuf[fb_index<DIM, K>(te, a, sd, v, t)] = st[v];
         }
     }
 }
