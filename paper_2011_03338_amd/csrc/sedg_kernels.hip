@@ -739,21 +739,21 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         int ok = (pt[0] > 0.0 && pp > 0.0) ? 1 : 0;
         double rmin = pt[0], pmin = pp;
         for (int a = 0; a < DIM; ++a) {
-            int lo = G::coord(c, a) & (n - 1);
-            for (int sd = 0; sd < 2; ++sd) {
-                if (lo != (sd ? n - 1 : 0)) continue;
-                CDbl *bv = sd ? T.bp : T.bm;
-                int st = G::stride(a), base = c - lo * st;
-                for (int v = 0; v < NV; ++v) {
-                    double s = 0.0;
-                    for (int m = 0; m < n; ++m) s += bv[m] * R0[v][base + m * st];
-                    pt[v] = s;
-                }
-                double q = pressure<DIM>(pt, gam);
-                if (!(pt[0] > 0.0 && q > 0.0)) ok = 0;
-                rmin = fmin(rmin, pt[0]);
-                pmin = fmin(pmin, q);
+            // a lane on the low face of its sub-element takes the trace with b^-, one on
+            // the high face the trace with b^+ (both sides in one pass; n >= 2)
+            const int lo = G::coord(c, a) & (n - 1);
+            const bool hi = (lo == n - 1);
+            if (!(lo == 0 || hi)) continue;
+            const int st = G::stride(a), base = c - lo * st;
+            for (int v = 0; v < NV; ++v) {
+                double s = 0.0;
+                for (int m = 0; m < n; ++m) s += (hi ? T.bp[m] : T.bm[m]) * R0[v][base + m * st];
+                pt[v] = s;
             }
+            double q = pressure<DIM>(pt, gam);
+            if (!(pt[0] > 0.0 && q > 0.0)) ok = 0;
+            rmin = fmin(rmin, pt[0]);
+            pmin = fmin(pmin, q);
         }
         ok = subreduce<DIM, K>(ok, ln, S.ix, OpAnd());
         double b = 1.0;
