@@ -1635,15 +1635,16 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) face_adjoint_kernel(K
     for (int v = 0; v < NV; ++v) s_lam[le][v][c] = P.lam[v * P.dof + g];
     for (int q = c; q < LV::A; q += KD) s_al[le][q] = P.alpha[(long long)ee * LV::A + q];
     __syncthreads();
-    if (!act) return;
-    for (int a = 0; a < DIM; ++a) {
-        const int pos = G::coord(c, a);
-        for (int sd = 0; sd < 2; ++sd) {
-            if (pos != (sd ? K - 1 : 0)) continue;
-            double gf[NV];
-            own_face_adjoint<DIM, K, LV>(P, s_al[le], s_lam[le], a, sd ? K : 0, G::trans(c, a), gf);
-            for (int v = 0; v < NV; ++v) P.gfb[fb_index<DIM, K>(e, a, sd, v, G::trans(c, a))] = gf[v];
-        }
+    // one task per (element, face, face cell) over the workgroup's lanes
+    constexpr int NF = 2 * DIM, KF = G::KF;
+    for (int tsk = tid; tsk < EPB * NF * KF; tsk += EPB * KD) {
+        const int tle = tsk / (NF * KF), rem = tsk - tle * (NF * KF), f = rem / KF, t = rem - f * KF;
+        const int te = blockIdx.x * EPB + tle;
+        if (te >= P.nel) continue;
+        const int a = f >> 1, sd = f & 1;
+        double gf[NV];
+        own_face_adjoint<DIM, K, LV>(P, s_al[tle], s_lam[tle], a, sd ? K : 0, t, gf);
+        for (int v = 0; v < NV; ++v) P.gfb[fb_index<DIM, K>(te, a, sd, v, t)] = gf[v];
     }
 }
 
