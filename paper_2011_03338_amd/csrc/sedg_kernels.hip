@@ -1798,17 +1798,23 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
             if (actv[1 + li]) step = min(step, LV::n(li));
         if (actv[0]) step = 1;
         // ---------------- (1) flux adjoints on those faces of axis a ----------------
-        for (int q = c; q < (K + 1) * KF; q += KD) {
-            const int k = q / KF, t = q % KF;
-            if (k % step != 0) continue;    // never read
+        // only the faces at multiples of step are read: one lane per (such face, face cell)
+        const int nk = K / step + 1;
+        for (int j = c; j < nk * KF; j += KD) {
+            const int k = (j / KF) * step, t = j % KF, q = k * KF + t;
             double gf[NV];
             if (k == 0 || k == K) {
+                // both shares loaded together, unconditionally (a boundary lane reads its
+                // own element's and drops it)
                 const int sd = (k == K) ? 1 : 0;
                 const int nb = sd ? nbR : nbL;
+                const int nbc = nb >= 0 ? nb : ee;
+                double go[NV], gn[NV];
                 for (int v = 0; v < NV; ++v) {
-                    double o = nb >= 0 ? P.gfb[fb_index<DIM, K>(nb, a, 1 - sd, v, t)] : 0.0;
-                    gf[v] = P.gfb[fb_index<DIM, K>(ee, a, sd, v, t)] + o;
+                    go[v] = P.gfb[fb_index<DIM, K>(ee, a, sd, v, t)];
+                    gn[v] = P.gfb[fb_index<DIM, K>(nbc, a, 1 - sd, v, t)];
                 }
+                for (int v = 0; v < NV; ++v) gf[v] = go[v] + (nb >= 0 ? gn[v] : 0.0);
             } else {
                 own_face_adjoint<DIM, K, LV>(P, S.al[le], S.lam[le], a, k, t, gf);
             }
