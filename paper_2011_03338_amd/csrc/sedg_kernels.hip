@@ -1139,7 +1139,6 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
             int fa = 0, k = 0;
             const bool has = fidx < nfaces;
             if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k);
-            const int st = G::stride(fa);
             const bool lowface = (k == 0), highface = (k == K);
             const int nbL = neighbour<DIM>(P, e3, fa, 0), nbR = neighbour<DIM>(P, e3, fa, 1);
             double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
@@ -1420,7 +1419,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
 
 template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
-__attribute__((amdgpu_waves_per_eu(3, 8))) residual_kernel(KArgs P)
+__attribute__((amdgpu_waves_per_eu(DIM == 3 ? 2 : 3, 8))) residual_kernel(KArgs P)
 {
     __shared__ ResidualSmem<DIM, K, TOP, EPB> S;
     residual_body<DIM, K, TOP, EPB>(P, xcd_tile(blockIdx.x, gridDim.x), S);
@@ -2222,7 +2221,7 @@ __global__ void __launch_bounds__(LAM_SLOTS) finalize_dt_kernel(double *lam_part
     lam_part[threadIdx.x] = 0.0;
     __syncthreads();
     for (int w = LAM_SLOTS / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+        if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
