@@ -31,23 +31,27 @@ METRIC = "FP64 DOF-updates/sec on 1 MI355X (fwd, batched, adjoint/fwd cost ratio
 
 
 def kernel_bytes_per_launch(mesh, A):
-    """Algorithmic HBM bytes of one launch of each kernel (minimal I/O of the
-    decomposition): state in/out, stage base state (2 of 3 stages),
-    blending factors and squeezing parameters, neighbour blending factors,
-    element-face states (own write; own + neighbour read) and element scales."""
+    """Algorithmic HBM bytes of one launch of each stage kernel (minimal I/O of the
+    decomposition): the analysis (state in; factors, sub-element means, face states and
+    scales out), the element-face fluxes and the residual (state in and out, stage base
+    state, own factors and means, element-face fluxes, scales)."""
     d, K, nv = mesh.dim, mesh.K, mesh.nvar
     nel = mesh.nel
     kd, kf = K ** d, K ** (d - 1)
     per_el = {
-        "analyse": 8 * (nv * kd + 2 * A + 2 * d * nv * kf + 2),
-        "residual": 8 * (nv * kd + nv * kd + (2.0 / 3.0) * nv * kd + 2 * A + 2 * d * A
-                         + 2 * (2 * d * nv * kf) + 2 * (1 + 2 * d)),
+        "analyse": 8 * (nv * kd + 2 * A + nv * A + 2 * d * nv * kf + 2),
+        # element-face fluxes, once per face: the element's d low faces (face states of
+        # both sides, both elements' factors and scales in; F* out)
+        "faces": 8 * (d * (2 * nv * kf + 2 * A + 4) + d * nv * kf),
+        # state in, out, stage base state (2 of 3 stages), own factors and sub-element
+        # means, the fluxes on its 2d element faces, own scales
+        "residual": 8 * (nv * kd + nv * kd + (2.0 / 3.0) * nv * kd + 2 * A + nv * A + 2 * d * nv * kf + 2),
     }
     return {k: v * nel for k, v in per_el.items()}
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2011_03338_amd", "csrc", "sedg_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "residual_sedov2d_256x256_K8_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernels_sedov2d_256x256_K8_hbm_traffic.txt")
 
 
 def kernel_source_sha1():
@@ -68,9 +72,9 @@ def measured_traffic(kernel):
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("kernel_role") != kernel or kv.get("source_sha1") != kernel_source_sha1():
+        if kv.get("source_sha1") != kernel_source_sha1():
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["%s_hbm_bytes_per_launch" % kernel])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -335,7 +339,7 @@ def main():
 
     # roofline of the dominant kernel
     kb = kernel_bytes_per_launch(mesh, A)
-    dom = max(("analyse", "residual"), key=lambda k: prof[k][0])
+    dom = max(("analyse", "residual", "faces"), key=lambda k: prof[k][0])
     avg_ms = prof[dom][0] / max(prof[dom][1], 1)
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

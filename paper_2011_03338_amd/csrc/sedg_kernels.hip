@@ -60,6 +60,7 @@ struct KArgs {
     double *beta;           // nel * A
     const double *alpha_in; // EXTERNAL mode
     double *fbuf;           // face buffer
+    double *ef;             // common fluxes on the element faces (face-buffer layout), or null
     double *scale;          // nel * 2: largest mean density and |mean energy| per element
     double *mean;           // nel * NV * A: sub-element means per level
     CTab *tabs;                  // per level index
@@ -907,7 +908,9 @@ template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) analyse_kernel(KArgs P)
 {
     __shared__ AnalyseSmem<DIM, K, TOP, EPB> S;
-    analyse_body<DIM, K, TOP, EPB>(P, blockIdx.x, S);
+    // XCD-contiguous tiles: horizontally adjacent elements share the 128-B lines of the
+    // state, and an XCD's L2 then serves the second element its half
+    analyse_body<DIM, K, TOP, EPB>(P, xcd_tile(blockIdx.x, gridDim.x), S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,7 +1014,7 @@ __device__ __forceinline__ void element_face_sides(const KArgs &P, int ee, int f
 // blending factors in LDS.  Every global load is issued before the first LDS store,
 // so that one memory latency covers them all (each lane holds at most one entry of
 // the per-element vectors: A <= K^d).
-template <int DIM, int K, class LV, bool LAM, class SM>
+template <int DIM, int K, class LV, bool LAM, class SM, bool NBA = true>
 __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, int c, int ee, const int *e3,
                                                 long long g)
 {
@@ -1037,8 +1040,10 @@ __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, i
         bo = P.beta[(long long)ee * LV::A + c];
 #pragma unroll
         for (int v = 0; v < NV; ++v) mv[v] = P.mean[((long long)ee * NV + v) * LV::A + c];
+        // the neighbours' factors serve the element faces, unless their fluxes come precomputed
+        if constexpr (NBA)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) an[j] = P.alpha[(long long)src[j] * LV::A + c];
+            for (int j = 0; j < NB; ++j) an[j] = P.alpha[(long long)src[j] * LV::A + c];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1050,8 +1055,9 @@ __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, i
         S.be[le][c] = bo;
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.mean[le][v][c] = mv[v];
+        if constexpr (NBA)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) S.nal[le][j][c] = an[j];
+            for (int j = 0; j < NB; ++j) S.nal[le][j][c] = an[j];
     }
 }
 
@@ -1059,23 +1065,176 @@ __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, i
 // axis, then the interior faces at multiples of 'step' (1 when the FV level is
 // active, else the smallest active DG level; K leaves none).
 template <int K>
-__device__ __forceinline__ int face_count(int na, int step) { return na * (2 + K / step - 1); }
+__device__ __forceinline__ int face_count(int na, int step, bool skip_elem = false)
+{
+    return na * ((skip_elem ? 0 : 2) + K / step - 1);
+}
 
 template <int K>
-__device__ __forceinline__ void face_at(int a0, int na, int step, int fidx, int *fa, int *fk)
+__device__ __forceinline__ void face_at(int a0, int na, int step, int fidx, int *fa, int *fk, bool skip_elem = false)
 {
-    if (fidx < 2 * na) {
+    if (!skip_elem && fidx < 2 * na) {
         *fa = a0 + (fidx >> 1);
         *fk = (fidx & 1) * K;
     } else {
-        int j = fidx - 2 * na, cnt = K / step - 1;
+        int j = fidx - (skip_elem ? 0 : 2 * na), cnt = K / step - 1;
         *fa = a0 + j / cnt;
         *fk = step * (1 + j % cnt);
     }
 }
 
-// one tile (EPB elements) of the residual kernel; every thread of the workgroup calls it
-template <int DIM, int K, int TOP, int EPB>
+// The common flux F* at the face subcells of one face per group of KF lanes (the
+// lane's face node t; the group's face cells start at sbase in the exchange buffers):
+// the DG candidates of every level whose sub-element boundary contains the face, then
+// the FV candidate with the remaining weight (R4, R17).  uL, uR, thL, thR: the blended
+// interface states and weights on both sides; srho, sE: the data scales of the two
+// elements; (mLe, mLc), (mRe, mRc): the cells whose means replace a non-admissible FV
+// input (element -1: own element ee, read from uown in LDS when given, else from
+// global memory).  wsL, wsR: LDS exchange buffers of the element's lanes (lane c);
+// every lane of the workgroup (NT threads) calls it with the same face count.
+template <int DIM, int K, class LV, int NT>
+__device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double *wsR, int c, int sbase, int t, bool has,
+                                            int fa, int k, const double *uL, const double *uR, const double *thL,
+                                            const double *thR, double srho, double sE, int mLe, int mLc, int mRe,
+                                            int mRc, const double *uown, int ee, double *F)
+{
+    typedef Geo<DIM, K> G;
+    constexpr int NV = G::NV, KD = G::KD;
+    const double gam = P.gamma;
+    // DG candidates level by level: R along the face, HLLE at the face nodes, P back
+    double thFV = 1.0;
+    for (int v = 0; v < NV; ++v) F[v] = 0.0;
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        // uniform skip: no element of the block has this level active on a needed face
+        if (!block_or<NT>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+            continue;
+        CTab &T = P.tabs[li];
+        const int n = LV::n(li), ln = ilog2i(n);
+        const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
+        const bool need = has && (k % n == 0) && (tb != 0.0);
+        double nl[NV], nr[NV];
+        int lo0, lo1 = 0, tb0, tb1 = 0;
+        if (DIM == 2) { lo0 = t & (n - 1); tb0 = t - lo0; }
+        else {
+            int t0 = t & (K - 1), t1 = t >> G::LOGK;
+            lo0 = t0 & (n - 1); tb0 = t0 - lo0;
+            lo1 = t1 & (n - 1); tb1 = t1 - lo1;
+        }
+        const int t0 = t - K * (t >> G::LOGK), t1 = t >> G::LOGK;   // 3-D face coordinates
+        for (int v = 0; v < NV; ++v) {
+            wsL[c] = uL[v];
+            wsR[c] = uR[v];
+            __syncthreads();
+            double sl = 0.0, sr = 0.0;
+            if (DIM == 2) {
+                if (need)
+                    for (int m = 0; m < n; ++m) {
+                        double Rm = T.R[lo0 * n + m];
+                        sl += Rm * wsL[sbase + tb0 + m];
+                        sr += Rm * wsR[sbase + tb0 + m];
+                    }
+            } else {
+                // separable: along t0 for the lane's own row, through LDS, then along t1
+                // (the row sums the lane (t0, tb1 + m1) leaves are exactly the inner sums
+                // of R x R; need is uniform over a level-n segment)
+                double al0 = 0.0, ar0 = 0.0;
+                if (need)
+                    for (int m0 = 0; m0 < n; ++m0) {
+                        double Rm = T.R[lo0 * n + m0];
+                        int q = sbase + (tb0 + m0) + K * t1;
+                        al0 += Rm * wsL[q];
+                        ar0 += Rm * wsR[q];
+                    }
+                __syncthreads();
+                wsL[c] = al0;
+                wsR[c] = ar0;
+                __syncthreads();
+                if (need)
+                    for (int m1 = 0; m1 < n; ++m1) {
+                        double Rm1 = T.R[lo1 * n + m1];
+                        int q = sbase + t0 + K * (tb1 + m1);
+                        sl += Rm1 * wsL[q];
+                        sr += Rm1 * wsR[q];
+                    }
+            }
+            nl[v] = sl;
+            nr[v] = sr;
+            __syncthreads();
+        }
+        int okf = need ? ((flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0) : 1;
+        // segment-wide admissibility (transverse bits of the level-n block of this face)
+        for (int q = 0; q < DIM - 1; ++q)
+            for (int bb = 0; bb < ln; ++bb) {
+                int bit = q * G::LOGK + bb;
+                int mask = 1 << bit;
+                if (bit < 6) okf &= lane_xor(okf, mask);
+                else {
+                    ((int *)wsL)[c] = okf;
+                    __syncthreads();
+                    okf &= ((int *)wsL)[c ^ mask];
+                    __syncthreads();
+                }
+            }
+        double fnod[NV];
+        if (need && okf) hlle<DIM>(nl, nr, fa, gam, fnod);
+        else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
+        for (int v = 0; v < NV; ++v) {
+            wsL[c] = fnod[v];
+            __syncthreads();
+            double sacc = 0.0;
+            if (DIM == 2) {
+                if (need && okf)
+                    for (int m = 0; m < n; ++m) sacc += T.P[lo0 * n + m] * wsL[sbase + tb0 + m];
+            } else {
+                // separable, as for R above (okf is uniform over a level-n segment too)
+                double a0s = 0.0;
+                if (need && okf)
+                    for (int m0 = 0; m0 < n; ++m0)
+                        a0s += T.P[lo0 * n + m0] * wsL[sbase + (tb0 + m0) + K * t1];
+                __syncthreads();
+                wsL[c] = a0s;
+                __syncthreads();
+                if (need && okf)
+                    for (int m1 = 0; m1 < n; ++m1)
+                        sacc += T.P[lo1 * n + m1] * wsL[sbase + t0 + K * (tb1 + m1)];
+            }
+            if (need && okf) F[v] += tb * sacc;
+            __syncthreads();
+        }
+        if (need && okf) thFV -= tb;
+    }
+    if (has) {
+        if (thFV != 0.0) {
+            double aL[NV], aR[NV], fs[NV];
+            for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
+            if (!flux_admissible<DIM>(aL, gam, srho, sE)) {
+                if (mLe < 0 && uown) for (int v = 0; v < NV; ++v) aL[v] = uown[v * KD + mLc];
+                else {
+                    int n3[3];
+                    elem3(P, mLe < 0 ? ee : mLe, n3);
+                    long long gn = gindex<DIM, K>(P, n3, mLc);
+                    for (int v = 0; v < NV; ++v) aL[v] = P.u[v * P.dof + gn];
+                }
+            }
+            if (!flux_admissible<DIM>(aR, gam, srho, sE)) {
+                if (mRe < 0 && uown) for (int v = 0; v < NV; ++v) aR[v] = uown[v * KD + mRc];
+                else {
+                    int n3[3];
+                    elem3(P, mRe < 0 ? ee : mRe, n3);
+                    long long gn = gindex<DIM, K>(P, n3, mRc);
+                    for (int v = 0; v < NV; ++v) aR[v] = P.u[v * P.dof + gn];
+                }
+            }
+            hlle<DIM>(aL, aR, fa, gam, fs);
+            for (int v = 0; v < NV; ++v) F[v] += thFV * fs[v];
+        }
+    }
+}
+
+// one tile (EPB elements) of the residual kernel; every thread of the workgroup calls it.
+// EF: the common fluxes on the element faces come precomputed in P.ef (eface_kernel)
+template <int DIM, int K, int TOP, int EPB, bool EF = false>
 __device__ __forceinline__ void residual_body(const KArgs &P, int tile, ResidualSmem<DIM, K, TOP, EPB> &S)
 {
     typedef Geo<DIM, K> G;
@@ -1092,7 +1251,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    preload_element<DIM, K, LV, false>(P, S, le, c, ee, e3, g);
+    preload_element<DIM, K, LV, false, SM, !EF>(P, S, le, c, ee, e3, g);
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
@@ -1125,7 +1284,19 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         for (int li = 0; li < LV::NLEV; ++li)
             if (actv[1 + li]) step = min(step, LV::n(li));
         if (actv[0]) step = 1;
-        const int nfaces = face_count<K>(a1 - a0, step);
+        // with the element-face fluxes precomputed (once per face), only interior faces
+        // are left to this kernel: copy the element faces' rows of the flux buffer first
+        constexpr bool efb = EF;
+        if (efb)
+            for (int q = c; q < (a1 - a0) * 2 * KF; q += KD) {
+                const int fa = a0 + q / (2 * KF), sd = (q / KF) & 1, tt = q % KF;
+                const int nb = sd ? neighbour<DIM>(P, e3, fa, 1) : -1;
+                const int src = nb >= 0 ? nb : ee, ssd = nb >= 0 ? 0 : sd;
+                double fv[NV];
+                for (int v = 0; v < NV; ++v) fv[v] = P.ef[fb_index<DIM, K>(src, fa, ssd, v, tt)];
+                for (int v = 0; v < NV; ++v) S.F[le][SM::AXO ? 0 : fa][v][(sd ? K : 0) * KF + tt] = fv[v];
+            }
+        const int nfaces = face_count<K>(a1 - a0, step, efb);
         int nfmax = nfaces;
         if (EPB > 1) {
             S.wsL[tid] = (double)nfaces;
@@ -1138,7 +1309,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
             const int fidx = r0 + slot;
             int fa = 0, k = 0;
             const bool has = fidx < nfaces;
-            if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k);
+            if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k, efb);
             const bool lowface = (k == 0), highface = (k == K);
             const int nbL = neighbour<DIM>(P, e3, fa, 0), nbR = neighbour<DIM>(P, e3, fa, 1);
             double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
@@ -1182,136 +1353,10 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                     }
                 }
             }
-            // DG candidates level by level: R along the face, HLLE at the face nodes, P back
-            double thFV = 1.0;
             double F[NV];
-            for (int v = 0; v < NV; ++v) F[v] = 0.0;
-#pragma unroll
-            for (int li = 0; li < LV::NLEV; ++li) {
-                // uniform skip: no element of the block has this level active on a needed face
-                if (!block_or<EPB * KD>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
-                    continue;
-                CTab &T = P.tabs[li];
-                const int n = LV::n(li), ln = ilog2i(n);
-                const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
-                const bool need = has && (k % n == 0) && (tb != 0.0);
-                double nl[NV], nr[NV];
-                const int sbase = slot * KF;
-                int lo0, lo1 = 0, tb0, tb1 = 0;
-                if (DIM == 2) { lo0 = t & (n - 1); tb0 = t - lo0; }
-                else {
-                    int t0 = t & (K - 1), t1 = t >> G::LOGK;
-                    lo0 = t0 & (n - 1); tb0 = t0 - lo0;
-                    lo1 = t1 & (n - 1); tb1 = t1 - lo1;
-                }
-                const int t0 = t - K * (t >> G::LOGK), t1 = t >> G::LOGK;   // 3-D face coordinates
-                for (int v = 0; v < NV; ++v) {
-                    S.wsL[le * KD + c] = uL[v];
-                    S.wsR[le * KD + c] = uR[v];
-                    __syncthreads();
-                    double sl = 0.0, sr = 0.0;
-                    if (DIM == 2) {
-                        if (need)
-                            for (int m = 0; m < n; ++m) {
-                                double Rm = T.R[lo0 * n + m];
-                                sl += Rm * S.wsL[le * KD + sbase + tb0 + m];
-                                sr += Rm * S.wsR[le * KD + sbase + tb0 + m];
-                            }
-                    } else {
-                        // separable: along t0 for the lane's own row, through LDS, then along t1
-                        // (the row sums the lane (t0, tb1 + m1) leaves are exactly the inner sums
-                        // of R x R; need is uniform over a level-n segment)
-                        double al0 = 0.0, ar0 = 0.0;
-                        if (need)
-                            for (int m0 = 0; m0 < n; ++m0) {
-                                double Rm = T.R[lo0 * n + m0];
-                                int q = sbase + (tb0 + m0) + K * t1;
-                                al0 += Rm * S.wsL[le * KD + q];
-                                ar0 += Rm * S.wsR[le * KD + q];
-                            }
-                        __syncthreads();
-                        S.wsL[le * KD + c] = al0;
-                        S.wsR[le * KD + c] = ar0;
-                        __syncthreads();
-                        if (need)
-                            for (int m1 = 0; m1 < n; ++m1) {
-                                double Rm1 = T.R[lo1 * n + m1];
-                                int q = sbase + t0 + K * (tb1 + m1);
-                                sl += Rm1 * S.wsL[le * KD + q];
-                                sr += Rm1 * S.wsR[le * KD + q];
-                            }
-                    }
-                    nl[v] = sl;
-                    nr[v] = sr;
-                    __syncthreads();
-                }
-                int okf = need ? ((flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0) : 1;
-                // segment-wide admissibility (transverse bits of the level-n block of this face)
-                for (int q = 0; q < DIM - 1; ++q)
-                    for (int bb = 0; bb < ln; ++bb) {
-                        int bit = q * G::LOGK + bb;
-                        int mask = 1 << bit;
-                        if (bit < 6) okf &= lane_xor(okf, mask);
-                        else {
-                            ((int *)S.wsL)[tid] = okf;
-                            __syncthreads();
-                            okf &= ((int *)S.wsL)[tid ^ mask];
-                            __syncthreads();
-                        }
-                    }
-                double fnod[NV];
-                if (need && okf) hlle<DIM>(nl, nr, fa, gam, fnod);
-                else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
-                for (int v = 0; v < NV; ++v) {
-                    S.wsL[le * KD + c] = fnod[v];
-                    __syncthreads();
-                    double sacc = 0.0;
-                    if (DIM == 2) {
-                        if (need && okf)
-                            for (int m = 0; m < n; ++m) sacc += T.P[lo0 * n + m] * S.wsL[le * KD + sbase + tb0 + m];
-                    } else {
-                        // separable, as for R above (okf is uniform over a level-n segment too)
-                        double a0s = 0.0;
-                        if (need && okf)
-                            for (int m0 = 0; m0 < n; ++m0)
-                                a0s += T.P[lo0 * n + m0] * S.wsL[le * KD + sbase + (tb0 + m0) + K * t1];
-                        __syncthreads();
-                        S.wsL[le * KD + c] = a0s;
-                        __syncthreads();
-                        if (need && okf)
-                            for (int m1 = 0; m1 < n; ++m1)
-                                sacc += T.P[lo1 * n + m1] * S.wsL[le * KD + sbase + t0 + K * (tb1 + m1)];
-                    }
-                    if (need && okf) F[v] += tb * sacc;
-                    __syncthreads();
-                }
-                if (need && okf) thFV -= tb;
-            }
+            common_flux<DIM, K, LV, EPB * KD>(P, &S.wsL[le * KD], &S.wsR[le * KD], c, slot * KF, t, has, fa, k, uL, uR,
+                                             thL, thR, srho, sE, mLe, mLc, mRe, mRc, &S.u[le][0][0], ee, F);
             if (has) {
-                if (thFV != 0.0) {
-                    double aL[NV], aR[NV], fs[NV];
-                    for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
-                    if (!flux_admissible<DIM>(aL, gam, srho, sE)) {
-                        if (mLe < 0) for (int v = 0; v < NV; ++v) aL[v] = S.u[le][v][mLc];
-                        else {
-                            int n3[3];
-                            elem3(P, mLe, n3);
-                            long long gn = gindex<DIM, K>(P, n3, mLc);
-                            for (int v = 0; v < NV; ++v) aL[v] = P.u[v * P.dof + gn];
-                        }
-                    }
-                    if (!flux_admissible<DIM>(aR, gam, srho, sE)) {
-                        if (mRe < 0) for (int v = 0; v < NV; ++v) aR[v] = S.u[le][v][mRc];
-                        else {
-                            int n3[3];
-                            elem3(P, mRe, n3);
-                            long long gn = gindex<DIM, K>(P, n3, mRc);
-                            for (int v = 0; v < NV; ++v) aR[v] = P.u[v * P.dof + gn];
-                        }
-                    }
-                    hlle<DIM>(aL, aR, fa, gam, fs);
-                    for (int v = 0; v < NV; ++v) F[v] += thFV * fs[v];
-                }
                 const int axs = SM::AXO ? 0 : fa;
                 for (int v = 0; v < NV; ++v) S.F[le][axs][v][k * KF + t] = F[v];
             }
@@ -1417,12 +1462,48 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     }
 }
 
+// Common fluxes on the element faces, once per face (the residual kernel would otherwise
+// evaluate each on both sides): a workgroup of 64 lanes takes 64 / K^{d-1} (element,
+// axis) tasks, each the element's low face along the axis (the element is the right
+// side, its low neighbour the left), plus the high face of an element at an outflow
+// boundary, which no neighbour takes.  F* goes to P.ef in the face-buffer layout.
+template <int DIM, int K, int TOP>
+__global__ void __launch_bounds__(64) eface_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int NV = G::NV, KF = G::KF, NS = 64 / KF;
+    __shared__ double wsL[64], wsR[64];
+    const int c = threadIdx.x, slot = c / KF, t = c % KF;
+    const long long task = (long long)xcd_tile(blockIdx.x, gridDim.x) * NS + slot;
+    const bool valid = task < (long long)P.nel * DIM;
+    const int e = valid ? (int)(task / DIM) : 0, a = valid ? (int)(task % DIM) : 0;
+    int e3[3];
+    elem3(P, e, e3);
+    const double own_sr = P.scale[2 * (long long)e], own_se = P.scale[2 * (long long)e + 1];
+    for (int sd = 0; sd < 2; ++sd) {
+        const int nb = neighbour<DIM>(P, e3, a, sd);
+        const bool has = valid && (sd == 0 || nb < 0);
+        if (!block_or<64>(has)) continue;
+        double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1], srho = own_sr, sE = own_se;
+        int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
+        element_face_sides<DIM, K, LV>(P, e, a, t, sd == 1, nb, P.alpha + (long long)e * LV::A,
+                                       P.alpha + (long long)(nb >= 0 ? nb : e) * LV::A, own_sr, own_se, uL, uR,
+                                       thL, thR, mLe, mLc, mRe, mRc, srho, sE);
+        double F[NV];
+        common_flux<DIM, K, LV, 64>(P, wsL, wsR, c, slot * KF, t, has, a, sd ? K : 0, uL, uR, thL, thR, srho, sE, mLe,
+                                    mLc, mRe, mRc, nullptr, e, F);
+        if (has)
+            for (int v = 0; v < NV; ++v) P.ef[fb_index<DIM, K>(e, a, sd, v, t)] = F[v];
+    }
+}
+
 template <int DIM, int K, int TOP, int EPB>
 __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
 __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 2 : 3, 8))) residual_kernel(KArgs P)
 {
     __shared__ ResidualSmem<DIM, K, TOP, EPB> S;
-    residual_body<DIM, K, TOP, EPB>(P, xcd_tile(blockIdx.x, gridDim.x), S);
+    residual_body<DIM, K, TOP, EPB, true>(P, xcd_tile(blockIdx.x, gridDim.x), S);
 }
 
 // ---------------------------------------------------------------------------
@@ -2257,6 +2338,7 @@ struct sedg_ctx {
     double dx[3];
     sedg_level_tab *d_tabs;
     double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale, *d_mean;
+    double *d_ef;                          // element-face common fluxes
     double *d_gfb, *d_l1, *d_l2, *d_acc;   // adjoint (allocated on first use)
     int *d_err, *d_ctr;
     int nblocks;
@@ -2288,6 +2370,11 @@ void launch_kernel(int which, const KArgs &P, int nblocks, hipStream_t s)
     else if (which == 1) hipLaunchKernelGGL((residual_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
     else if (which == 2) hipLaunchKernelGGL((frozen_prep_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
     else if (which == 5) hipLaunchKernelGGL((face_adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else if (which == 6) {
+        constexpr int NS = 64 / Geo<DIM, K>::KF;   // face tasks per workgroup
+        const long long tasks = (long long)P.nel * DIM;
+        hipLaunchKernelGGL((eface_kernel<DIM, K, TOP>), dim3((unsigned)((tasks + NS - 1) / NS)), dim3(64), 0, s, P);
+    }
     else if constexpr (!(DIM == 3 && K == 8))  // one element's adjoint data exceed the LDS at 3-D K = 8
         hipLaunchKernelGGL((adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
 }
@@ -2310,7 +2397,14 @@ void launch_any(int which, const sedg_ctx *C, const KArgs &P, hipStream_t s)
 }
 
 void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(0, C, P, s); }
-void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(1, C, P, s); }
+// the residual kernel reads the element-face fluxes of the face kernel launched before it
+void launch_faces_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(6, C, P, s); }
+void launch_residual_only_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(1, C, P, s); }
+void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s)
+{
+    launch_faces_any(C, P, s);
+    launch_residual_only_any(C, P, s);
+}
 void launch_prep_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(2, C, P, s); }
 void launch_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(3, C, P, s); }
 void launch_face_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(5, C, P, s); }
@@ -2345,6 +2439,7 @@ KArgs base_args(const sedg_ctx *C)
     P.alpha = C->d_alpha;
     P.beta = C->d_beta;
     P.fbuf = C->d_fbuf;
+    P.ef = C->d_ef;
     P.scale = C->d_scale;
     P.mean = C->d_mean;
     P.tabs = (CTab *)C->d_tabs;
@@ -2469,6 +2564,7 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     ok = ok && hipMalloc(&C->d_fbuf, sizeof(double) * (size_t)C->nel * mesh->dim * 2 * C->nv * kf) == hipSuccess;
     ok = ok && hipMalloc(&C->d_lam, sizeof(double) * LAM_SLOTS) == hipSuccess;
     ok = ok && hipMalloc(&C->d_scale, sizeof(double) * 2 * (size_t)C->nel) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_ef, sizeof(double) * (size_t)C->nel * mesh->dim * 2 * C->nv * kf) == hipSuccess;
     ok = ok && hipMalloc(&C->d_mean, sizeof(double) * (size_t)C->nel * C->nv * maxA) == hipSuccess;
     ok = ok && hipMalloc(&C->d_dt, sizeof(double) * 2) == hipSuccess;
     ok = ok && hipMalloc(&C->d_u1, sizeof(double) * nst) == hipSuccess;
@@ -2495,7 +2591,7 @@ int sedg_destroy(sedg_ctx *C)
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
     void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr,
-                    C->d_scale, C->d_mean, C->d_gfb, C->d_l1, C->d_l2, C->d_acc};
+                    C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_l1, C->d_l2, C->d_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
@@ -2587,7 +2683,8 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
             hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
                                cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
         });
-    timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
+    timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+    timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
     // stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1))
     P.lam_part = nullptr;
     P.u = C->d_u1;
@@ -2595,14 +2692,16 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     P.out = C->d_u2;
     P.stage = 2;
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
-    timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
+    timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+    timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
     // stage 3: u = 1/3 u + 2/3 (u2 + dt L(u2))
     P.u = C->d_u2;
     P.u0 = u;
     P.out = u;
     P.stage = 3;
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
-    timed(C, 1, s, [&] { launch_residual_any(C, P, s); });
+    timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+    timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
 }
 
 extern "C" {
@@ -2661,7 +2760,7 @@ int sedg_profile_read(sedg_ctx *C, double *ms, long *count)
 {
     if (!C || !ms || !count) return SEDG_EINVAL;
     if (hipStreamSynchronize(C->last) != hipSuccess) return SEDG_EHIP;
-    for (int k = 0; k < 3; ++k) { ms[k] = 0.0; count[k] = 0; }
+    for (int k = 0; k < 4; ++k) { ms[k] = 0.0; count[k] = 0; }
     for (auto &m : C->marks) {
         float t = 0.0f;
         if (hipEventElapsedTime(&t, m.second.first, m.second.second) != hipSuccess) return SEDG_EHIP;

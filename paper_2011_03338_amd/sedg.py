@@ -229,11 +229,11 @@ class Solver:
         _check(load().sedg_profile(self._h, 1 if on else 0), "sedg_profile")
 
     def profile_read(self):
-        """{kernel: (total_ms, launches)} for analyse, residual, step_size."""
-        ms = (ctypes.c_double * 3)()
-        cnt = (ctypes.c_long * 3)()
+        """{kernel: (total_ms, launches)} for analyse, residual, step_size, faces."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_long * 4)()
         _check(load().sedg_profile_read(self._h, ms, cnt), "sedg_profile_read")
-        return {k: (ms[i], cnt[i]) for i, k in enumerate(["analyse", "residual", "step_size"])}
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(["analyse", "residual", "step_size", "faces"])}
 
     def check(self):
         """Returns -1, or raises SedgError(SEDG_ESTATE) naming the bad element."""
