@@ -75,6 +75,7 @@ struct KArgs {
     // batched ensembles
     const ProbDesc *probs;  // per problem
     const int *tile_prob;   // problem of every tile
+    const int *ftile_prob;  // problem of every element-face tile
     int ntiles;             // tiles of the whole ensemble
     int chunk;              // consecutive tiles per workgroup
     int xcd_map;            // remap workgroups to contiguous tile ranges per XCD
@@ -1468,14 +1469,13 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
 // side, its low neighbour the left), plus the high face of an element at an outflow
 // boundary, which no neighbour takes.  F* goes to P.ef in the face-buffer layout.
 template <int DIM, int K, int TOP>
-__global__ void __launch_bounds__(64) eface_kernel(KArgs P)
+__device__ __forceinline__ void eface_body(const KArgs &P, int tile, double *wsL, double *wsR)
 {
     typedef Geo<DIM, K> G;
     typedef Lv<DIM, K, TOP> LV;
     constexpr int NV = G::NV, KF = G::KF, NS = 64 / KF;
-    __shared__ double wsL[64], wsR[64];
     const int c = threadIdx.x, slot = c / KF, t = c % KF;
-    const long long task = (long long)xcd_tile(blockIdx.x, gridDim.x) * NS + slot;
+    const long long task = (long long)tile * NS + slot;
     const bool valid = task < (long long)P.nel * DIM;
     const int e = valid ? (int)(task / DIM) : 0, a = valid ? (int)(task % DIM) : 0;
     int e3[3];
@@ -1496,6 +1496,13 @@ __global__ void __launch_bounds__(64) eface_kernel(KArgs P)
         if (has)
             for (int v = 0; v < NV; ++v) P.ef[fb_index<DIM, K>(e, a, sd, v, t)] = F[v];
     }
+}
+
+template <int DIM, int K, int TOP>
+__global__ void __launch_bounds__(64) eface_kernel(KArgs P)
+{
+    __shared__ double wsL[64], wsR[64];
+    eface_body<DIM, K, TOP>(P, xcd_tile(blockIdx.x, gridDim.x), wsL, wsR);
 }
 
 template <int DIM, int K, int TOP, int EPB>
@@ -2158,6 +2165,7 @@ struct ProbDesc {
     long long elem_off;     // elements before it
     long long dof;
     int nel, K, tile_off, ntiles;
+    int ftile_off;          // element-face tiles before it
     int ne[2], G[2], bc[2];
     double dx[2];
     double cfl_num;         // numerator of its CFL step
@@ -2199,6 +2207,7 @@ __device__ __forceinline__ KArgs problem_args(const KArgs &P, const ProbDesc &Dm
     Q.beta = P.beta + D.alpha_off;
     Q.mean = P.mean + 4 * D.alpha_off;      // nvar = 4 in 2-D
     Q.fbuf = P.fbuf + D.fbuf_off;
+    Q.ef = P.ef ? P.ef + D.fbuf_off : nullptr;
     Q.scale = P.scale + 2 * D.elem_off;
     Q.lam_part = P.lam_part ? P.lam_part + (long long)p * BATCH_SLOTS : nullptr;
     Q.dt = P.dt ? P.dt + p : nullptr;
@@ -2253,10 +2262,24 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_batch_kernel(KArgs P)
         const ProbDesc &D = P.probs[p];
         const KArgs Q = problem_args(P, D, p);
         const int tl = t - wg_uniform(D.tile_off);
-        if (wg_uniform(D.K) == 4) residual_body<2, 4, 4, EPB4>(Q, tl, U.k4);
-        else residual_body<2, 8, 8, EPB8>(Q, tl, U.k8);
+        if (wg_uniform(D.K) == 4) residual_body<2, 4, 4, EPB4, true>(Q, tl, U.k4);
+        else residual_body<2, 8, 8, EPB8, true>(Q, tl, U.k8);
         __syncthreads();
     }
+}
+
+// element-face fluxes of the ensemble: every face tile (64 / K face tasks of one problem)
+// is one workgroup of 64 lanes
+__global__ void __launch_bounds__(64) eface_batch_kernel(KArgs P)
+{
+    __shared__ double wsL[64], wsR[64];
+    const int L = P.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int p = wg_uniform(P.ftile_prob[L]);
+    const ProbDesc &D = P.probs[p];
+    const KArgs Q = problem_args(P, D, p);
+    const int tl = L - wg_uniform(D.ftile_off);
+    if (wg_uniform(D.K) == 4) eface_body<2, 4, 4>(Q, tl, wsL, wsR);
+    else eface_body<2, 8, 8>(Q, tl, wsL, wsR);
 }
 
 // per-problem CFL steps: one workgroup of BATCH_SLOTS threads per problem, which
@@ -2976,11 +2999,11 @@ struct sedg_batch {
     std::vector<ProbDesc> probs;
     long long state_len, alpha_len, fbuf_len, nel;
     sedg_batch_tuning tun;
-    int ntiles, grid, chunk;
+    int ntiles, grid, chunk, nftiles;
     sedg_level_tab *d_tabs;
     ProbDesc *d_probs;
-    int *d_tile_prob;
-    double *d_alpha, *d_beta, *d_mean, *d_scale, *d_fbuf, *d_u1, *d_u2, *d_dt, *d_lam;
+    int *d_tile_prob, *d_ftile_prob;
+    double *d_alpha, *d_beta, *d_mean, *d_scale, *d_fbuf, *d_ef, *d_u1, *d_u2, *d_dt, *d_lam;
     int *d_err, *d_ctr;
     hipStream_t last;
     std::map<std::tuple<double *, double *, int>, hipGraphExec_t> graphs;
@@ -3008,6 +3031,18 @@ int batch_layout(sedg_batch *B)
         for (int i = 0; i < D.ntiles; ++i) tp.push_back(p);
     }
     B->ntiles = t;
+    // element-face tiles: 64 / K tasks (element, axis) each
+    std::vector<int> ftp;
+    int ft = 0;
+    for (int p = 0; p < B->nprob; ++p) {
+        ProbDesc &D = B->probs[p];
+        const int ns = 64 / D.K;
+        D.ftile_off = ft;
+        const int n = (2 * D.nel + ns - 1) / ns;
+        ft += n;
+        for (int i = 0; i < n; ++i) ftp.push_back(p);
+    }
+    B->nftiles = ft;
     if (B->tun.blocks_per_cu > 0) {
         long long g = (long long)B->ncu * B->tun.blocks_per_cu;
         B->grid = (int)(g < t ? g : t);
@@ -3019,6 +3054,11 @@ int batch_layout(sedg_batch *B)
     B->d_tile_prob = nullptr;
     if (hipMalloc(&B->d_tile_prob, sizeof(int) * (size_t)t) != hipSuccess) return SEDG_ENOMEM;
     if (hipMemcpy(B->d_tile_prob, tp.data(), sizeof(int) * (size_t)t, hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    if (B->d_ftile_prob) (void)hipFree(B->d_ftile_prob);
+    B->d_ftile_prob = nullptr;
+    if (hipMalloc(&B->d_ftile_prob, sizeof(int) * (size_t)ft) != hipSuccess) return SEDG_ENOMEM;
+    if (hipMemcpy(B->d_ftile_prob, ftp.data(), sizeof(int) * (size_t)ft, hipMemcpyHostToDevice) != hipSuccess)
+        return SEDG_EHIP;
     if (hipMemcpy(B->d_probs, B->probs.data(), sizeof(ProbDesc) * (size_t)B->nprob, hipMemcpyHostToDevice) != hipSuccess)
         return SEDG_EHIP;
     batch_drop_graphs(B);
@@ -3034,11 +3074,13 @@ KArgs batch_args(const sedg_batch *B)
     P.mean = B->d_mean;
     P.scale = B->d_scale;
     P.fbuf = B->d_fbuf;
+    P.ef = B->d_ef;
     P.tabs = (CTab *)B->d_tabs;
     P.err = B->d_err;
     P.dt = B->d_dt;
     P.probs = B->d_probs;
     P.tile_prob = B->d_tile_prob;
+    P.ftile_prob = B->d_ftile_prob;
     P.ntiles = B->ntiles;
     P.chunk = B->chunk;
     P.xcd_map = B->tun.xcd_map;
@@ -3057,7 +3099,11 @@ template <int EPB4, int EPB8, bool PERSIST>
 void batch_launch_t(int which, const sedg_batch *B, const KArgs &P, hipStream_t s)
 {
     if (which == 0) hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
-    else hipLaunchKernelGGL((residual_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
+    else {
+        // the residual reads the element-face fluxes of the face kernel launched before it
+        hipLaunchKernelGGL(eface_batch_kernel, dim3(B->nftiles), dim3(64), 0, s, P);
+        hipLaunchKernelGGL((residual_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
+    }
 }
 
 void batch_launch(int which, const sedg_batch *B, const KArgs &P, hipStream_t s)
@@ -3109,8 +3155,8 @@ int sedg_batch_destroy(sedg_batch *B)
     if (!B) return SEDG_OK;
     (void)hipDeviceSynchronize();
     batch_drop_graphs(B);
-    void *ptrs[] = {B->d_tabs, B->d_probs, B->d_tile_prob, B->d_alpha, B->d_beta, B->d_mean, B->d_scale,
-                    B->d_fbuf, B->d_u1, B->d_u2, B->d_dt, B->d_lam, B->d_err, B->d_ctr};
+    void *ptrs[] = {B->d_tabs, B->d_probs, B->d_tile_prob, B->d_ftile_prob, B->d_alpha, B->d_beta, B->d_mean,
+                    B->d_scale, B->d_fbuf, B->d_ef, B->d_u1, B->d_u2, B->d_dt, B->d_lam, B->d_err, B->d_ctr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete B;
@@ -3188,6 +3234,7 @@ int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *par
     ok = ok && hipMalloc(&B->d_mean, sizeof(double) * 4 * (size_t)ao) == hipSuccess;
     ok = ok && hipMalloc(&B->d_scale, sizeof(double) * 2 * (size_t)eo) == hipSuccess;
     ok = ok && hipMalloc(&B->d_fbuf, sizeof(double) * (size_t)fo) == hipSuccess;
+    ok = ok && hipMalloc(&B->d_ef, sizeof(double) * (size_t)fo) == hipSuccess;
     ok = ok && hipMalloc(&B->d_u1, sizeof(double) * (size_t)so) == hipSuccess;
     ok = ok && hipMalloc(&B->d_u2, sizeof(double) * (size_t)so) == hipSuccess;
     ok = ok && hipMalloc(&B->d_dt, sizeof(double) * (size_t)count) == hipSuccess;
