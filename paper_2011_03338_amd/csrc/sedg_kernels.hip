@@ -439,10 +439,12 @@ struct Lv {
     static constexpr int A = off(NLEV);
 };
 
-// Exact lane exchange v <- v[lane ^ mask] inside a wavefront.  Masks below 16 use
-// DPP lane permutations (xor 1 / xor 2: quad permutes; xor 4: half-row mirror then
-// quad reverse; xor 8: rotation by 8 inside a 16-lane row); 16 and 32 cross rows
-// through ds_bpermute.
+// Exact lane exchange v <- v[lane ^ mask] inside a wavefront, on the VALU (no LDS
+// traffic).  Masks below 16 use DPP lane permutations (xor 1 / xor 2: quad permutes;
+// xor 4: half-row mirror then quad reverse; xor 8: rotation by 8 inside a 16-lane
+// row).  16 and 32 use the row swaps of gfx950: with both operands v, the first
+// result holds the lower partner of every pair of 16- (32-) lane halves in both
+// halves and the second the upper one, so a lane in the upper half takes the first.
 __device__ __forceinline__ int lane_xor_i(int v, int mask)
 {
     switch (mask) {
@@ -453,6 +455,14 @@ __device__ __forceinline__ int lane_xor_i(int v, int mask)
         return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);
     }
     case 8: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    case 16: {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? (int)r[0] : (int)r[1];
+    }
+    case 32: {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? (int)r[0] : (int)r[1];
+    }
     default: return __shfl_xor(v, mask, 64);
     }
 }
