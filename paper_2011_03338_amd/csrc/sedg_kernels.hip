@@ -882,10 +882,14 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
     // blended interface states on the element faces: theta_FV * mean + sum_n theta_n *
     // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation).
     // One task per (element, face, face cell), spread over the workgroup's lanes, rather
-    // than each boundary lane looping over the faces its cell touches.
+    // than each boundary lane looping over the faces its cell touches; with at least
+    // twice as many lanes as tasks (2-D, K = 8) the variables of a task are split over
+    // two lanes.
     {
-        constexpr int NF = 2 * DIM, KF = G::KF;
-        for (int tsk = tid; tsk < EPB * NF * KF; tsk += EPB * KD) {
+        constexpr int NF = 2 * DIM, KF = G::KF, NT = EPB * NF * KF;
+        constexpr int VS = (EPB * KD >= 2 * NT) ? 2 : 1, VPL = (NV + VS - 1) / VS;
+        for (int w = tid; w < NT * VS; w += EPB * KD) {
+            const int tsk = w % NT, v0 = (w / NT) * VPL;
             const int tle = tsk / (NF * KF), rem = tsk - tle * (NF * KF), f = rem / KF, t = rem - f * KF;
             const int a = f >> 1, sd = f & 1;
             const int cc = G::from_trans(t, a, sd ? K - 1 : 0);
@@ -894,8 +898,8 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             subidx_all<DIM, K, LV>(cc, sidx);
             double th[MAXLEV + 1];
             theta_from_alpha<LV>(S.al[tle], sidx, th);
-            double st[NV];
-            for (int v = 0; v < NV; ++v) st[v] = th[0] * S.u[tle][v][cc];
+            double st[VPL];
+            for (int j = 0; j < VPL; ++j) st[j] = (v0 + j < NV) ? th[0] * S.u[tle][v0 + j][cc] : 0.0;
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
                 if (th[1 + li] == 0.0) continue;
@@ -904,13 +908,15 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 CDbl *E = sd ? T.Ep : T.Em;
                 const int q = LV::off(li) + sidx[li];
                 double b = S.be[tle][q];
-                for (int v = 0; v < NV; ++v) {
-                    double tr = bapply<DIM, K>(S.u[tle][v], cc, a, n, E);
-                    st[v] += th[1 + li] * ((1.0 - b) * S.mean[tle][v][q] + b * tr);
+                for (int j = 0; j < VPL; ++j) {
+                    if (v0 + j >= NV) break;
+                    double tr = bapply<DIM, K>(S.u[tle][v0 + j], cc, a, n, E);
+                    st[j] += th[1 + li] * ((1.0 - b) * S.mean[tle][v0 + j][q] + b * tr);
                 }
             }
             if (te < P.nel)
-                for (int v = 0; v < NV; ++v) P.fbuf[fb_index<DIM, K>(te, a, sd, v, t)] = st[v];
+                for (int j = 0; j < VPL; ++j)
+                    if (v0 + j < NV) P.fbuf[fb_index<DIM, K>(te, a, sd, v0 + j, t)] = st[j];
         }
     }
 }
