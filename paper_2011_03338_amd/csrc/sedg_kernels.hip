@@ -69,6 +69,7 @@ struct KArgs {
     int *err;               // smallest bad element index (INT_MAX = none)
     const double *lam;      // adjoint: input adjoint state
     double *gfb;            // adjoint: per element, its own share of the flux adjoints on its faces
+    double *gsb, *gdb;      // adjoint: interface-state and mean-fallback adjoints of the element faces
     double *acc;            // adjoint RK: running adjoint of the step's initial state
     int lam_mask;           // CFL slots - 1 (slot = tile & lam_mask)
     int err_base;           // added to the element index reported through err
@@ -1751,6 +1752,113 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) face_adjoint_kernel(K
     }
 }
 
+// Reverse of common_flux on one face per group of KF lanes: from the flux adjoint on
+// the face (the group's KF face values of variable v at gseg[v * gstride + 0 .. KF - 1])
+// to the adjoints of the blended interface states (guL, guR) and of the subcell states
+// whose means replaced a non-admissible FV input (gdL, gdR).  The other arguments are
+// those of common_flux; every lane of the workgroup (NT threads) calls it with the same
+// face count.
+template <int DIM, int K, class LV, int NT>
+__device__ __forceinline__ void common_flux_adj(const KArgs &P, double *wsL, double *wsR, int c, int sbase, int t,
+                                                bool has, int fa, int k, const double *uL, const double *uR,
+                                                const double *thL, const double *thR, double srho, double sE, int mLe,
+                                                int mLc, int mRe, int mRc, const double *uown, int ee,
+                                                const double *gseg, int gstride, double *guL, double *guR, double *gdL,
+                                                double *gdR)
+{
+    typedef Geo<DIM, K> G;
+    constexpr int NV = G::NV, KD = G::KD;
+    const double gam = P.gamma;
+    double gFv[NV];
+    for (int v = 0; v < NV; ++v) gFv[v] = gseg[v * gstride + t];
+    for (int v = 0; v < NV; ++v) { guL[v] = 0.0; guR[v] = 0.0; gdL[v] = 0.0; gdR[v] = 0.0; }
+    double thFV = 1.0;
+#pragma unroll
+    for (int li = 0; li < LV::NLEV; ++li) {
+        if (!block_or<NT>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
+            continue;
+        CTab &T = P.tabs[li];
+        const int n = LV::n(li), ln = ilog2i(n);
+        const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
+        const bool need = has && (k % n == 0) && (tb != 0.0);
+        // nodal face states R_perp uL, R_perp uR
+        double nl[NV], nr[NV];
+        for (int v = 0; v < NV; ++v) {
+            wsL[c] = uL[v];
+            wsR[c] = uR[v];
+            __syncthreads();
+            nl[v] = need ? seg_apply<DIM, K>(&wsL[sbase], t, n, T.R) : 0.0;
+            nr[v] = need ? seg_apply<DIM, K>(&wsR[sbase], t, n, T.R) : 0.0;
+            __syncthreads();
+        }
+        int okf = need ? ((flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0) : 1;
+        for (int q = 0; q < DIM - 1; ++q)
+            for (int bb = 0; bb < ln; ++bb) {
+                int bit = q * G::LOGK + bb;
+                int mask = 1 << bit;
+                if (bit < 6) okf &= lane_xor(okf, mask);
+                else {
+                    ((int *)wsL)[c] = okf;
+                    __syncthreads();
+                    okf &= ((int *)wsL)[c ^ mask];
+                    __syncthreads();
+                }
+            }
+        const bool use = need && okf;
+        // face-node flux adjoints tb * P_perp^T gF, then the HLLE Jacobian^T
+        double gnl[NV], gnr[NV];
+        for (int v = 0; v < NV; ++v) { gnl[v] = 0.0; gnr[v] = 0.0; }
+        if (use) {
+            double gh[NV];
+            for (int v = 0; v < NV; ++v) gh[v] = tb * seg_apply<DIM, K>(&gseg[v * gstride], t, n, T.PT);
+            hlle_adj<DIM>(nl, nr, fa, gam, gh, gnl, gnr);
+        }
+        // back to face means: R_perp^T
+        for (int v = 0; v < NV; ++v) {
+            wsL[c] = gnl[v];
+            wsR[c] = gnr[v];
+            __syncthreads();
+            if (use) {
+                guL[v] += seg_apply<DIM, K>(&wsL[sbase], t, n, T.RT);
+                guR[v] += seg_apply<DIM, K>(&wsR[sbase], t, n, T.RT);
+            }
+            __syncthreads();
+        }
+        if (use) thFV -= tb;
+    }
+    if (has && thFV != 0.0) {
+        double aL[NV], aR[NV];
+        for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
+        const bool fbL = !flux_admissible<DIM>(aL, gam, srho, sE);
+        const bool fbR = !flux_admissible<DIM>(aR, gam, srho, sE);
+        if (fbL) {
+            if (mLe < 0 && uown) for (int v = 0; v < NV; ++v) aL[v] = uown[v * KD + mLc];
+            else {
+                int n3[3];
+                elem3(P, mLe < 0 ? ee : mLe, n3);
+                long long gn = gindex<DIM, K>(P, n3, mLc);
+                for (int v = 0; v < NV; ++v) aL[v] = P.u[v * P.dof + gn];
+            }
+        }
+        if (fbR) {
+            if (mRe < 0 && uown) for (int v = 0; v < NV; ++v) aR[v] = uown[v * KD + mRc];
+            else {
+                int n3[3];
+                elem3(P, mRe < 0 ? ee : mRe, n3);
+                long long gn = gindex<DIM, K>(P, n3, mRc);
+                for (int v = 0; v < NV; ++v) aR[v] = P.u[v * P.dof + gn];
+            }
+        }
+        double gfs[NV], gaL[NV], gaR[NV];
+        for (int v = 0; v < NV; ++v) { gfs[v] = thFV * gFv[v]; gaL[v] = 0.0; gaR[v] = 0.0; }
+        hlle_adj<DIM>(aL, aR, fa, gam, gfs, gaL, gaR);
+        for (int v = 0; v < NV; ++v) {
+            if (fbL) gdL[v] += gaL[v]; else guL[v] += gaL[v];
+            if (fbR) gdR[v] += gaR[v]; else guR[v] += gaR[v];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // adjoint kernel: lam_out = (dL/du)^T lam of the frozen right-hand side
 // ---------------------------------------------------------------------------
@@ -1760,14 +1868,13 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) face_adjoint_kernel(K
 // Dhat^T along each axis, Euler-flux Jacobian^T at the squeezed nodal values),
 // taken back through the squeezed reconstruction (R^T on every axis plus the
 // sub-element mean).  Then, axis by axis:
-//   (1) flux adjoints gF at every face of the axis: interior faces from the
-//       element's own adjoint state; element faces from the two elements' shares
-//       published by the preparation kernel (so both sides see the same sum);
-//   (2) reverse of the common fluxes on the faces the forward evaluated: the FV
-//       candidate and the level DG candidates (P_perp^T, HLLE Jacobian^T,
+//   (1) flux adjoints gF at the interior faces of the axis, from the element's own
+//       adjoint state;
+//   (2) reverse of the common fluxes on the interior faces the forward evaluated:
+//       the FV candidate and the level DG candidates (P_perp^T, HLLE Jacobian^T,
 //       R_perp^T), giving adjoints of the blended interface states (GS) and of
-//       subcell means that replaced a flux input (GD); at an element face only the
-//       element's own side is kept, the neighbour does the other;
+//       subcell means that replaced a flux input (GD); those of the element faces
+//       come from the element-face adjoint kernel (eface_adjoint_kernel);
 //   (3) interface-state adjoints -> state adjoints: theta_FV directly, the level-n
 //       traces through E^T along the axis and the squeeze mean.
 // Only the state adjoint stays live across the face loop.  The RK variants fuse
@@ -1786,7 +1893,6 @@ struct AdjointSmem {
     double al[EPB][LV::A];
     double be[EPB][LV::A];
     double mean[EPB][G::NV][LV::A];
-    double nal[EPB][2 * DIM][LV::A];
     double wsL[EPB * G::KD], wsR[EPB * G::KD];
     int act[EPB][MAXLEV + 1];
 };
@@ -1809,7 +1915,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    preload_element<DIM, K, LV, true>(P, S, le, c, ee, e3, g);
+    preload_element<DIM, K, LV, true, AdjointSmem<DIM, K, TOP, EPB>, false>(P, S, le, c, ee, e3, g);
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
@@ -1892,46 +1998,49 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     }
 
     for (int a = 0; a < DIM; ++a) {
-        const int nbL = neighbour<DIM>(P, e3, a, 0), nbR = neighbour<DIM>(P, e3, a, 1);
         // the faces the forward evaluated: every face when the FV level is active, else
-        // the multiples of the smallest active DG level (the element faces at least)
+        // the multiples of the smallest active DG level (the element faces at least;
+        // their reverse comes precomputed from the element-face adjoint kernel)
         int step = K;
 #pragma unroll
         for (int li = 0; li < LV::NLEV; ++li)
             if (actv[1 + li]) step = min(step, LV::n(li));
         if (actv[0]) step = 1;
-        // ---------------- (1) flux adjoints on those faces of axis a ----------------
+        // ---------------- (1) flux adjoints on the interior faces of axis a ----------------
         // only the faces at multiples of step are read: one lane per (such face, face cell)
-        const int nk = K / step + 1;
-        for (int j = c; j < nk * KF; j += KD) {
-            const int k = (j / KF) * step, t = j % KF, q = k * KF + t;
+        const int nki = K / step - 1;
+        for (int j = c; j < nki * KF; j += KD) {
+            const int k = (j / KF + 1) * step, t = j % KF, q = k * KF + t;
             double gf[NV];
-            if (k == 0 || k == K) {
-                // both shares loaded together, unconditionally (a boundary lane reads its
-                // own element's and drops it)
-                const int sd = (k == K) ? 1 : 0;
-                const int nb = sd ? nbR : nbL;
-                const int nbc = nb >= 0 ? nb : ee;
-                double go[NV], gn[NV];
-                for (int v = 0; v < NV; ++v) {
-                    go[v] = P.gfb[fb_index<DIM, K>(ee, a, sd, v, t)];
-                    gn[v] = P.gfb[fb_index<DIM, K>(nbc, a, 1 - sd, v, t)];
-                }
-                for (int v = 0; v < NV; ++v) gf[v] = go[v] + (nb >= 0 ? gn[v] : 0.0);
-            } else {
-                own_face_adjoint<DIM, K, LV>(P, S.al[le], S.lam[le], a, k, t, gf);
-            }
+            own_face_adjoint<DIM, K, LV>(P, S.al[le], S.lam[le], a, k, t, gf);
             for (int v = 0; v < NV; ++v) S.gF[le][v][q] = gf[v];
         }
-        for (int sd = 0; sd < 2; ++sd)
+        // the element faces' interface-state and mean adjoints of the element's own cells
+        {
+            const int pos = G::coord(c, a), tt = G::trans(c, a);
+            double gs0[NV], gs1[NV], gd0[NV], gd1[NV];
             for (int v = 0; v < NV; ++v) {
-                S.GS[le][sd][v][c] = 0.0;
-                S.GD[le][sd][v][c] = 0.0;
+                gs0[v] = gs1[v] = gd0[v] = gd1[v] = 0.0;
+                if (act && pos == 0) {
+                    gs0[v] = P.gsb[fb_index<DIM, K>(ee, a, 0, v, tt)];
+                    gd0[v] = P.gdb[fb_index<DIM, K>(ee, a, 0, v, tt)];
+                }
+                if (act && pos == K - 1) {
+                    gs1[v] = P.gsb[fb_index<DIM, K>(ee, a, 1, v, tt)];
+                    gd1[v] = P.gdb[fb_index<DIM, K>(ee, a, 1, v, tt)];
+                }
             }
+            for (int v = 0; v < NV; ++v) {
+                S.GS[le][0][v][c] = gs0[v];
+                S.GS[le][1][v][c] = gs1[v];
+                S.GD[le][0][v][c] = gd0[v];
+                S.GD[le][1][v][c] = gd1[v];
+            }
+        }
         __syncthreads();
 
-        // ---------------- (2) reverse of the common fluxes ----------------
-        const int nfaces = face_count<K>(1, step);
+        // ---------------- (2) reverse of the common fluxes on the interior faces ----------------
+        const int nfaces = face_count<K>(1, step, true);
         int nfmax = nfaces;
         if (EPB > 1) {
             S.wsL[tid] = (double)nfaces;
@@ -1942,163 +2051,50 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
         const int slot = c / KF, t = c % KF;
         for (int r0 = 0; r0 < nfmax; r0 += K) {
             const int fidx = r0 + slot;
-            int fa = a, k = 0;
+            // an idle lane takes face 1, so that every cell it reads lies in the element
+            int fa = a, k = 1;
             const bool has = fidx < nfaces;
-            if (has) face_at<K>(a, 1, step, fidx, &fa, &k);
-            const bool lowface = (k == 0), highface = (k == K);
+            if (has) face_at<K>(a, 1, step, fidx, &fa, &k, true);
             double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
-            int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
-            double srho = own_sr, sE = own_se;
-            if (lowface || highface) {
-                element_face_sides<DIM, K, LV>(P, ee, fa, t, highface, highface ? nbR : nbL, S.al[le],
-                                               S.nal[le][2 * fa + (highface ? 1 : 0)], own_sr, own_se, uL, uR, thL,
-                                               thR, mLe, mLc, mRe, mRc, srho, sE);
-            } else {
-                int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
-                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
-                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
-                mLc = cl;
-                mRc = cr;
-                for (int v = 0; v < NV; ++v) {
-                    uL[v] = thL[0] * S.u[le][v][cl];
-                    uR[v] = thR[0] * S.u[le][v][cr];
-                }
-#pragma unroll
-                for (int li = 0; li < LV::NLEV; ++li) {
-                    CTab &T = P.tabs[li];
-                    int n = LV::n(li);
-                    if (thL[1 + li] != 0.0) {
-                        int s = G::subelem(cl, n);
-                        double b = S.be[le][LV::off(li) + s];
-                        for (int v = 0; v < NV; ++v) {
-                            double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
-                            uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
-                        }
-                    }
-                    if (thR[1 + li] != 0.0) {
-                        int s = G::subelem(cr, n);
-                        double b = S.be[le][LV::off(li) + s];
-                        for (int v = 0; v < NV; ++v) {
-                            double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
-                            uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
-                        }
-                    }
-                }
+            const int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
+            theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
+            theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
+            for (int v = 0; v < NV; ++v) {
+                uL[v] = thL[0] * S.u[le][v][cl];
+                uR[v] = thR[0] * S.u[le][v][cr];
             }
-            double gFv[NV];
-            for (int v = 0; v < NV; ++v) gFv[v] = S.gF[le][v][k * KF + t];
-            double guL[NV], guR[NV], gdL[NV], gdR[NV];
-            for (int v = 0; v < NV; ++v) { guL[v] = 0.0; guR[v] = 0.0; gdL[v] = 0.0; gdR[v] = 0.0; }
-            double thFV = 1.0;
-            const int sbase = slot * KF;
 #pragma unroll
             for (int li = 0; li < LV::NLEV; ++li) {
-                if (!block_or<EPB * KD>(has && (k % LV::n(li) == 0) && (thL[1 + li] != 0.0 || thR[1 + li] != 0.0)))
-                    continue;
                 CTab &T = P.tabs[li];
-                const int n = LV::n(li), ln = ilog2i(n);
-                const double tb = 0.5 * (thL[1 + li] + thR[1 + li]);
-                const bool need = has && (k % n == 0) && (tb != 0.0);
-                // nodal face states R_perp uL, R_perp uR
-                double nl[NV], nr[NV];
-                for (int v = 0; v < NV; ++v) {
-                    S.wsL[le * KD + c] = uL[v];
-                    S.wsR[le * KD + c] = uR[v];
-                    __syncthreads();
-                    nl[v] = need ? seg_apply<DIM, K>(&S.wsL[le * KD + sbase], t, n, T.R) : 0.0;
-                    nr[v] = need ? seg_apply<DIM, K>(&S.wsR[le * KD + sbase], t, n, T.R) : 0.0;
-                    __syncthreads();
-                }
-                int okf = need ? ((flux_admissible<DIM>(nl, gam, srho, sE) && flux_admissible<DIM>(nr, gam, srho, sE)) ? 1 : 0) : 1;
-                for (int q = 0; q < DIM - 1; ++q)
-                    for (int bb = 0; bb < ln; ++bb) {
-                        int bit = q * G::LOGK + bb;
-                        int mask = 1 << bit;
-                        if (bit < 6) okf &= lane_xor(okf, mask);
-                        else {
-                            ((int *)S.wsL)[tid] = okf;
-                            __syncthreads();
-                            okf &= ((int *)S.wsL)[tid ^ mask];
-                            __syncthreads();
-                        }
-                    }
-                const bool use = need && okf;
-                // face-node flux adjoints tb * P_perp^T gF, then the HLLE Jacobian^T
-                double gnl[NV], gnr[NV];
-                for (int v = 0; v < NV; ++v) { gnl[v] = 0.0; gnr[v] = 0.0; }
-                if (use) {
-                    double gh[NV];
-                    for (int v = 0; v < NV; ++v) gh[v] = tb * seg_apply<DIM, K>(&S.gF[le][v][k * KF], t, n, T.PT);
-                    hlle_adj<DIM>(nl, nr, fa, gam, gh, gnl, gnr);
-                }
-                // back to face means: R_perp^T
-                for (int v = 0; v < NV; ++v) {
-                    S.wsL[le * KD + c] = gnl[v];
-                    S.wsR[le * KD + c] = gnr[v];
-                    __syncthreads();
-                    if (use) {
-                        guL[v] += seg_apply<DIM, K>(&S.wsL[le * KD + sbase], t, n, T.RT);
-                        guR[v] += seg_apply<DIM, K>(&S.wsR[le * KD + sbase], t, n, T.RT);
-                    }
-                    __syncthreads();
-                }
-                if (use) thFV -= tb;
-            }
-            if (has && thFV != 0.0) {
-                double aL[NV], aR[NV];
-                for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
-                const bool fbL = !flux_admissible<DIM>(aL, gam, srho, sE);
-                const bool fbR = !flux_admissible<DIM>(aR, gam, srho, sE);
-                if (fbL) {
-                    if (mLe < 0) for (int v = 0; v < NV; ++v) aL[v] = S.u[le][v][mLc];
-                    else {
-                        int n3[3];
-                        elem3(P, mLe, n3);
-                        long long gn = gindex<DIM, K>(P, n3, mLc);
-                        for (int v = 0; v < NV; ++v) aL[v] = P.u[v * P.dof + gn];
-                    }
-                }
-                if (fbR) {
-                    if (mRe < 0) for (int v = 0; v < NV; ++v) aR[v] = S.u[le][v][mRc];
-                    else {
-                        int n3[3];
-                        elem3(P, mRe, n3);
-                        long long gn = gindex<DIM, K>(P, n3, mRc);
-                        for (int v = 0; v < NV; ++v) aR[v] = P.u[v * P.dof + gn];
-                    }
-                }
-                double gfs[NV], gaL[NV], gaR[NV];
-                for (int v = 0; v < NV; ++v) { gfs[v] = thFV * gFv[v]; gaL[v] = 0.0; gaR[v] = 0.0; }
-                hlle_adj<DIM>(aL, aR, fa, gam, gfs, gaL, gaR);
-                for (int v = 0; v < NV; ++v) {
-                    if (fbL) gdL[v] += gaL[v]; else guL[v] += gaL[v];
-                    if (fbR) gdR[v] += gaR[v]; else guR[v] += gaR[v];
-                }
-            }
-            if (has) {
-                if (lowface) {
-                    // own side = right; an outflow mirror feeds both sides from it
-                    const int cr = G::from_trans(t, fa, 0);
+                int n = LV::n(li);
+                if (thL[1 + li] != 0.0) {
+                    int s = G::subelem(cl, n);
+                    double b = S.be[le][LV::off(li) + s];
                     for (int v = 0; v < NV; ++v) {
-                        S.GS[le][0][v][cr] = guR[v] + (nbL < 0 ? guL[v] : 0.0);
-                        S.GD[le][0][v][cr] = gdR[v] + (nbL < 0 ? gdL[v] : 0.0);
+                        double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
+                        uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
                     }
-                } else if (highface) {
-                    const int cl = G::from_trans(t, fa, K - 1);
+                }
+                if (thR[1 + li] != 0.0) {
+                    int s = G::subelem(cr, n);
+                    double b = S.be[le][LV::off(li) + s];
                     for (int v = 0; v < NV; ++v) {
-                        S.GS[le][1][v][cl] = guL[v] + (nbR < 0 ? guR[v] : 0.0);
-                        S.GD[le][1][v][cl] = gdL[v] + (nbR < 0 ? gdR[v] : 0.0);
-                    }
-                } else {
-                    const int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
-                    for (int v = 0; v < NV; ++v) {
-                        S.GS[le][1][v][cl] = guL[v];
-                        S.GS[le][0][v][cr] = guR[v];
-                        S.GD[le][1][v][cl] = gdL[v];
-                        S.GD[le][0][v][cr] = gdR[v];
+                        double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
+                        uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
                     }
                 }
             }
+            double guL[NV], guR[NV], gdL[NV], gdR[NV];
+            common_flux_adj<DIM, K, LV, EPB * KD>(P, &S.wsL[le * KD], &S.wsR[le * KD], c, slot * KF, t, has, fa, k, uL,
+                                                  uR, thL, thR, own_sr, own_se, -1, cl, -1, cr, &S.u[le][0][0], ee,
+                                                  &S.gF[le][0][k * KF], (K + 1) * KF, guL, guR, gdL, gdR);
+            if (has)
+                for (int v = 0; v < NV; ++v) {
+                    S.GS[le][1][v][cl] = guL[v];
+                    S.GS[le][0][v][cr] = guR[v];
+                    S.GD[le][1][v][cl] = gdL[v];
+                    S.GD[le][0][v][cr] = gdR[v];
+                }
         }
         __syncthreads();
 
@@ -2155,6 +2151,70 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
         } else {
             P.out[i] = ac[v] + l + dt * gu[v];
         }
+    }
+}
+
+// Reverse of the common fluxes on the element faces, once per face (the transpose of
+// eface_kernel): face tasks (element, axis) of KF lanes, 64 / KF per workgroup, each
+// the element's low face along the axis plus its high face at an outflow boundary.
+// The flux adjoint on a face is the sum of the two elements' shares (P.gfb); the
+// interface-state adjoints (P.gsb) and mean-fallback adjoints (P.gdb) of each side go
+// to the element owning that side, in the face-buffer layout (at an outflow boundary
+// the mirrored side adds to the own one).
+template <int DIM, int K, int TOP>
+__global__ void __launch_bounds__(64) eface_adjoint_kernel(KArgs P)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int NV = G::NV, KF = G::KF, NS = 64 / KF;
+    __shared__ double wsL[64], wsR[64], wsG[NV * 64];
+    const int c = threadIdx.x, slot = c / KF, t = c % KF;
+    const long long task = (long long)xcd_tile(blockIdx.x, gridDim.x) * NS + slot;
+    const bool valid = task < (long long)P.nel * DIM;
+    const int e = valid ? (int)(task / DIM) : 0, a = valid ? (int)(task % DIM) : 0;
+    int e3[3];
+    elem3(P, e, e3);
+    const double own_sr = P.scale[2 * (long long)e], own_se = P.scale[2 * (long long)e + 1];
+    for (int sd = 0; sd < 2; ++sd) {
+        const int nb = neighbour<DIM>(P, e3, a, sd);
+        const bool has = valid && (sd == 0 || nb < 0);
+        if (!block_or<64>(has)) continue;
+        const int nbc = nb >= 0 ? nb : e;
+        double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1], srho = own_sr, sE = own_se;
+        int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
+        double go[NV], gn[NV];
+        for (int v = 0; v < NV; ++v) {
+            go[v] = P.gfb[fb_index<DIM, K>(e, a, sd, v, t)];
+            gn[v] = P.gfb[fb_index<DIM, K>(nbc, a, 1 - sd, v, t)];
+        }
+        element_face_sides<DIM, K, LV>(P, e, a, t, sd == 1, nb, P.alpha + (long long)e * LV::A,
+                                       P.alpha + (long long)nbc * LV::A, own_sr, own_se, uL, uR, thL, thR, mLe, mLc,
+                                       mRe, mRc, srho, sE);
+        for (int v = 0; v < NV; ++v) wsG[v * 64 + c] = go[v] + (nb >= 0 ? gn[v] : 0.0);
+        __syncthreads();
+        double guL[NV], guR[NV], gdL[NV], gdR[NV];
+        common_flux_adj<DIM, K, LV, 64>(P, wsL, wsR, c, slot * KF, t, has, a, sd ? K : 0, uL, uR, thL, thR, srho, sE,
+                                        mLe, mLc, mRe, mRc, nullptr, e, wsG + slot * KF, 64, guL, guR, gdL, gdR);
+        if (has) {
+            if (sd == 0) {
+                // own side: the right one; the left belongs to the low neighbour's high face
+                for (int v = 0; v < NV; ++v) {
+                    P.gsb[fb_index<DIM, K>(e, a, 0, v, t)] = guR[v] + (nb < 0 ? guL[v] : 0.0);
+                    P.gdb[fb_index<DIM, K>(e, a, 0, v, t)] = gdR[v] + (nb < 0 ? gdL[v] : 0.0);
+                }
+                if (nb >= 0)
+                    for (int v = 0; v < NV; ++v) {
+                        P.gsb[fb_index<DIM, K>(nb, a, 1, v, t)] = guL[v];
+                        P.gdb[fb_index<DIM, K>(nb, a, 1, v, t)] = gdL[v];
+                    }
+            } else {
+                for (int v = 0; v < NV; ++v) {
+                    P.gsb[fb_index<DIM, K>(e, a, 1, v, t)] = guL[v] + guR[v];
+                    P.gdb[fb_index<DIM, K>(e, a, 1, v, t)] = gdL[v] + gdR[v];
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -2379,6 +2439,7 @@ struct sedg_ctx {
     double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale, *d_mean;
     double *d_ef;                          // element-face common fluxes
     double *d_gfb, *d_l1, *d_l2, *d_acc;   // adjoint (allocated on first use)
+    double *d_gsb, *d_gdb;
     int *d_err, *d_ctr;
     int nblocks;
     hipStream_t last;
@@ -2414,8 +2475,16 @@ void launch_kernel(int which, const KArgs &P, int nblocks, hipStream_t s)
         const long long tasks = (long long)P.nel * DIM;
         hipLaunchKernelGGL((eface_kernel<DIM, K, TOP>), dim3((unsigned)((tasks + NS - 1) / NS)), dim3(64), 0, s, P);
     }
-    else if constexpr (!(DIM == 3 && K == 8))  // one element's adjoint data exceed the LDS at 3-D K = 8
-        hipLaunchKernelGGL((adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+    else if constexpr (!(DIM == 3 && K == 8)) {  // one element's adjoint data exceed the LDS at 3-D K = 8
+        if (which == 7) {
+            constexpr int NS = 64 / Geo<DIM, K>::KF;
+            const long long tasks = (long long)P.nel * DIM;
+            hipLaunchKernelGGL((eface_adjoint_kernel<DIM, K, TOP>), dim3((unsigned)((tasks + NS - 1) / NS)), dim3(64), 0,
+                               s, P);
+        } else {
+            hipLaunchKernelGGL((adjoint_kernel<DIM, K, TOP, EPBv>), dim3(nblocks), dim3(threads), 0, s, P);
+        }
+    }
 }
 
 template <int DIM, int K>
@@ -2447,6 +2516,8 @@ void launch_residual_any(const sedg_ctx *C, const KArgs &P, hipStream_t s)
 void launch_prep_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(2, C, P, s); }
 void launch_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(3, C, P, s); }
 void launch_face_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(5, C, P, s); }
+// the adjoint kernel reads the element-face reverse of the kernel launched before it
+void launch_eface_adjoint_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(7, C, P, s); }
 
 bool adjoint_supported(const sedg_ctx *C) { return !(C->mesh.dim == 3 && C->mesh.K == 8); }
 
@@ -2457,15 +2528,18 @@ int ensure_adjoint_buffers(sedg_ctx *C)
     size_t kf = 1;
     for (int a = 1; a < C->mesh.dim; ++a) kf *= C->mesh.K;
     size_t nst = (size_t)C->nv * C->dof;
-    bool ok = hipMalloc(&C->d_gfb, sizeof(double) * (size_t)C->nel * C->mesh.dim * 2 * C->nv * kf) == hipSuccess;
+    const size_t nfb = (size_t)C->nel * C->mesh.dim * 2 * C->nv * kf;
+    bool ok = hipMalloc(&C->d_gfb, sizeof(double) * nfb) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_gsb, sizeof(double) * nfb) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_gdb, sizeof(double) * nfb) == hipSuccess;
     ok = ok && hipMalloc(&C->d_l1, sizeof(double) * nst) == hipSuccess;
     ok = ok && hipMalloc(&C->d_l2, sizeof(double) * nst) == hipSuccess;
     ok = ok && hipMalloc(&C->d_acc, sizeof(double) * nst) == hipSuccess;
     if (!ok) {
-        void *ptrs[] = {C->d_gfb, C->d_l1, C->d_l2, C->d_acc};
+        void *ptrs[] = {C->d_gfb, C->d_gsb, C->d_gdb, C->d_l1, C->d_l2, C->d_acc};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
-        C->d_gfb = C->d_l1 = C->d_l2 = C->d_acc = nullptr;
+        C->d_gfb = C->d_gsb = C->d_gdb = C->d_l1 = C->d_l2 = C->d_acc = nullptr;
         return SEDG_ENOMEM;
     }
     return SEDG_OK;
@@ -2630,7 +2704,7 @@ int sedg_destroy(sedg_ctx *C)
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
     void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr,
-                    C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_l1, C->d_l2, C->d_acc};
+                    C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_gsb, C->d_gdb, C->d_l1, C->d_l2, C->d_acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
@@ -2863,8 +2937,11 @@ int sedg_adjoint_rhs(sedg_ctx *C, const double *u, const double *alpha, const do
     P.alpha = const_cast<double *>(alpha);
     P.beta = const_cast<double *>(beta);
     P.gfb = C->d_gfb;
+    P.gsb = C->d_gsb;
+    P.gdb = C->d_gdb;
     P.stage = 0;
     launch_prep_any(C, P, s);
+    launch_eface_adjoint_any(C, P, s);
     launch_adjoint_any(C, P, s);
     C->last = s;
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
@@ -2978,6 +3055,8 @@ int sedg_adjoint_rk_step(sedg_ctx *C, const double *tapes, int nsteps, const dou
         KArgs P = base_args(C);
         P.dt = dt_dev + j;
         P.gfb = C->d_gfb;
+        P.gsb = C->d_gsb;
+        P.gdb = C->d_gdb;
         P.acc = C->d_acc;
         const double *lin[3] = {C->d_l1, C->d_l2, lam};   // adjoint entering reverse stage 1, 2, 3
         double *lout[3] = {lam, C->d_l1, C->d_l2};
@@ -2992,6 +3071,7 @@ int sedg_adjoint_rk_step(sedg_ctx *C, const double *tapes, int nsteps, const dou
             P.out = lout[st];
             P.stage = 11 + st;
             launch_face_adjoint_any(C, P, s);
+            launch_eface_adjoint_any(C, P, s);
             launch_adjoint_any(C, P, s);
         }
     }
