@@ -45,6 +45,21 @@ def test_rhs_sedov_resolved():
     compare_rhs(mesh, W.Params(), u, "sedov resolved")
 
 
+@pytest.mark.parametrize("K,ne,bc", [(8, [1, 3], [0, 1]), (4, [1, 1], [0, 0]), (8, [2, 1], [1, 0])])
+def test_rhs_single_element_periodic_axis(K, ne, bc):
+    """One periodic element along an axis: its low and high element faces are the same
+    face, whose common flux is computed once and read by both sides."""
+    mesh = W.Mesh(2, K, ne, [0, 0], [0.3 * ne[0], 0.3 * ne[1]], bc)
+    rng = np.random.default_rng(21 + K)
+    u = np.zeros(mesh.shape())
+    g = mesh.grid
+    u[0] = 1.0 + 0.5 * rng.uniform(size=(1, g[1], g[0]))
+    u[1] = 0.3 * u[0]
+    u[2] = 0.1 * u[0]
+    u[3] = (1.0 + 0.5 * rng.uniform(size=(1, g[1], g[0]))) / 0.4 + 0.5 * 0.1 * u[0]
+    compare_rhs(mesh, W.Params(), u, "single periodic element K=%d %s" % (K, ne))
+
+
 def test_rhs_nonsquare_ragged():
     mesh, u0, _ = W.config0(4, 6, 8)
     mesh = W.Mesh(2, 8, [5, 3], [0, 0], [1.0, 0.6], [0, 1])
