@@ -448,14 +448,16 @@ struct Lv {
 // halves and the second the upper one, so a lane in the upper half takes the first.
 __device__ __forceinline__ int lane_xor_i(int v, int mask)
 {
+    // every lane reads a valid source lane, so no prior destination value is kept
+    // (mov_dpp instead of update_dpp with a zero, which costs a register clear each)
     switch (mask) {
-    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
     case 4: {
-        int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
-        return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);
+        int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);
     }
-    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
     case 16: {
         const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         return (threadIdx.x & 16) ? (int)r[0] : (int)r[1];
@@ -475,6 +477,46 @@ __device__ __forceinline__ double lane_xor(double v, int mask)
     int lo = lane_xor_i(__double2loint(v), mask);
     int hi = lane_xor_i(__double2hiint(v), mask);
     return __hiloint2double(hi, lo);
+}
+
+// One butterfly step of a reduction with a commutative operation: op(v, v[lane ^ mask]).
+// Across 16- and 32-lane halves the row swap of v with itself leaves the lower half's
+// values in one result and the upper half's in the other, in every lane, so op of the
+// two results is the step's value without a select (and the same in both halves).
+__device__ __forceinline__ void swap_halves(int v, int mask, int &lo, int &hi)
+{
+    if (mask == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        lo = (int)r[0];
+        hi = (int)r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        lo = (int)r[0];
+        hi = (int)r[1];
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ int lane_step(int v, int mask, Op op)
+{
+    if (mask == 16 || mask == 32) {
+        int lo, hi;
+        swap_halves(v, mask, lo, hi);
+        return op(lo, hi);
+    }
+    return op(v, lane_xor(v, mask));
+}
+
+template <class Op>
+__device__ __forceinline__ double lane_step(double v, int mask, Op op)
+{
+    if (mask == 16 || mask == 32) {
+        int l0, h0, l1, h1;
+        swap_halves(__double2loint(v), mask, l0, h0);
+        swap_halves(__double2hiint(v), mask, l1, h1);
+        return op(__hiloint2double(l1, l0), __hiloint2double(h1, h0));
+    }
+    return op(v, lane_xor(v, mask));
 }
 
 // OR of a predicate over the workgroup, ordered like a barrier.  A one-wavefront
@@ -508,8 +550,7 @@ __device__ T subreduce(T v, int ln, T *s_x, Op op)
             int bit = a * LOGK + b;
             int mask = 1 << bit;
             if (bit < 6) {
-                T o = lane_xor(v, mask);
-                v = op(v, o);
+                v = lane_step(v, mask, op);
             } else {
                 s_x[tid] = v;
                 __syncthreads();
@@ -695,7 +736,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
             }
             #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) lam = fmax(lam, lane_xor(lam, off));
+            for (int off = 32; off >= 1; off >>= 1) lam = lane_step(lam, off, OpMax());
             if ((tid & 63) == 0) S.lam[tid >> 6] = lam;
             __syncthreads();
             if (tid == 0) {
@@ -923,7 +964,8 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
 }
 
 template <int DIM, int K, int TOP, int EPB>
-__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) analyse_kernel(KArgs P)
+__global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
+__attribute__((amdgpu_waves_per_eu(DIM == 2 ? 4 : 2, 8))) analyse_kernel(KArgs P)
 {
     __shared__ AnalyseSmem<DIM, K, TOP, EPB> S;
     // XCD-contiguous tiles: horizontally adjacent elements share the 128-B lines of the
@@ -1186,7 +1228,7 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
             for (int bb = 0; bb < ln; ++bb) {
                 int bit = q * G::LOGK + bb;
                 int mask = 1 << bit;
-                if (bit < 6) okf &= lane_xor(okf, mask);
+                if (bit < 6) okf = lane_step(okf, mask, OpAnd());
                 else {
                     ((int *)wsL)[c] = okf;
                     __syncthreads();
@@ -1796,7 +1838,7 @@ __device__ __forceinline__ void common_flux_adj(const KArgs &P, double *wsL, dou
             for (int bb = 0; bb < ln; ++bb) {
                 int bit = q * G::LOGK + bb;
                 int mask = 1 << bit;
-                if (bit < 6) okf &= lane_xor(okf, mask);
+                if (bit < 6) okf = lane_step(okf, mask, OpAnd());
                 else {
                     ((int *)wsL)[c] = okf;
                     __syncthreads();
