@@ -1001,7 +1001,6 @@ struct ResidualSmem {
     double al[EPB][LV::A];
     double mean[EPB][G::NV][LV::A];
     double be[EPB][LV::A];
-    double nal[EPB][2 * DIM][LV::A];
     double wsL[EPB * G::KD], wsR[EPB * G::KD];
     int act[EPB][MAXLEV + 1];
     // 3-D: the squeezed nodal values of every level, reconstructed in the first axis pass
@@ -1070,25 +1069,15 @@ __device__ __forceinline__ void element_face_sides(const KArgs &P, int ee, int f
 }
 
 // Stage an element's state (and, for the adjoint, its adjoint state), blending
-// factors, squeezing parameters, sub-element means and the face neighbours'
-// blending factors in LDS.  Every global load is issued before the first LDS store,
-// so that one memory latency covers them all (each lane holds at most one entry of
-// the per-element vectors: A <= K^d).
-template <int DIM, int K, class LV, bool LAM, class SM, bool NBA = true>
-__device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, int c, int ee, const int *e3,
-                                                long long g)
+// factors, squeezing parameters and sub-element means in LDS.  Every global load is
+// issued before the first LDS store, so that one memory latency covers them all (each
+// lane holds at most one entry of the per-element vectors: A <= K^d).
+template <int DIM, int K, class LV, bool LAM, class SM>
+__device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, int c, int ee, long long g)
 {
-    constexpr int NV = DIM + 2, NB = 2 * DIM;
+    constexpr int NV = DIM + 2;
     static_assert(LV::A <= Geo<DIM, K>::KD, "one factor per lane");
-    double uv[NV], lv[NV], mv[NV], an[NB], ao = 0.0, bo = 0.0;
-    int src[NB];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-        for (int sd = 0; sd < 2; ++sd) {
-            const int nbs = neighbour<DIM>(P, e3, a, sd);
-            src[2 * a + sd] = nbs >= 0 ? nbs : ee;
-        }
+    double uv[NV], lv[NV], mv[NV], ao = 0.0, bo = 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         uv[v] = P.u[v * P.dof + g];
@@ -1100,10 +1089,6 @@ __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, i
         bo = P.beta[(long long)ee * LV::A + c];
 #pragma unroll
         for (int v = 0; v < NV; ++v) mv[v] = P.mean[((long long)ee * NV + v) * LV::A + c];
-        // the neighbours' factors serve the element faces, unless their fluxes come precomputed
-        if constexpr (NBA)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) an[j] = P.alpha[(long long)src[j] * LV::A + c];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1115,9 +1100,6 @@ __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, i
         S.be[le][c] = bo;
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.mean[le][v][c] = mv[v];
-        if constexpr (NBA)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) S.nal[le][j][c] = an[j];
     }
 }
 
@@ -1293,8 +1275,8 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
 }
 
 // one tile (EPB elements) of the residual kernel; every thread of the workgroup calls it.
-// EF: the common fluxes on the element faces come precomputed in P.ef (eface_kernel)
-template <int DIM, int K, int TOP, int EPB, bool EF = false>
+// The common fluxes on the element faces come precomputed in P.ef (eface_kernel).
+template <int DIM, int K, int TOP, int EPB>
 __device__ __forceinline__ void residual_body(const KArgs &P, int tile, ResidualSmem<DIM, K, TOP, EPB> &S)
 {
     typedef Geo<DIM, K> G;
@@ -1311,7 +1293,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    preload_element<DIM, K, LV, false, SM, !EF>(P, S, le, c, ee, e3, g);
+    preload_element<DIM, K, LV, false, SM>(P, S, le, c, ee, g);
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
@@ -1344,19 +1326,17 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         for (int li = 0; li < LV::NLEV; ++li)
             if (actv[1 + li]) step = min(step, LV::n(li));
         if (actv[0]) step = 1;
-        // with the element-face fluxes precomputed (once per face), only interior faces
+        // the element-face fluxes come precomputed (once per face), only interior faces
         // are left to this kernel: copy the element faces' rows of the flux buffer first
-        constexpr bool efb = EF;
-        if (efb)
-            for (int q = c; q < (a1 - a0) * 2 * KF; q += KD) {
-                const int fa = a0 + q / (2 * KF), sd = (q / KF) & 1, tt = q % KF;
-                const int nb = sd ? neighbour<DIM>(P, e3, fa, 1) : -1;
-                const int src = nb >= 0 ? nb : ee, ssd = nb >= 0 ? 0 : sd;
-                double fv[NV];
-                for (int v = 0; v < NV; ++v) fv[v] = P.ef[fb_index<DIM, K>(src, fa, ssd, v, tt)];
-                for (int v = 0; v < NV; ++v) S.F[le][SM::AXO ? 0 : fa][v][(sd ? K : 0) * KF + tt] = fv[v];
-            }
-        const int nfaces = face_count<K>(a1 - a0, step, efb);
+        for (int q = c; q < (a1 - a0) * 2 * KF; q += KD) {
+            const int fa = a0 + q / (2 * KF), sd = (q / KF) & 1, tt = q % KF;
+            const int nb = sd ? neighbour<DIM>(P, e3, fa, 1) : -1;
+            const int src = nb >= 0 ? nb : ee, ssd = nb >= 0 ? 0 : sd;
+            double fv[NV];
+            for (int v = 0; v < NV; ++v) fv[v] = P.ef[fb_index<DIM, K>(src, fa, ssd, v, tt)];
+            for (int v = 0; v < NV; ++v) S.F[le][SM::AXO ? 0 : fa][v][(sd ? K : 0) * KF + tt] = fv[v];
+        }
+        const int nfaces = face_count<K>(a1 - a0, step, true);
         int nfmax = nfaces;
         if (EPB > 1) {
             S.wsL[tid] = (double)nfaces;
@@ -1367,55 +1347,45 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         const int slot = c / KF, t = c % KF;
         for (int r0 = 0; r0 < nfmax; r0 += K) {
             const int fidx = r0 + slot;
-            int fa = 0, k = 0;
+            // an idle lane takes face 1 of the first axis, so that every cell it reads lies
+            // in the element
+            int fa = a0, k = 1;
             const bool has = fidx < nfaces;
-            if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k, efb);
-            const bool lowface = (k == 0), highface = (k == K);
-            const int nbL = neighbour<DIM>(P, e3, fa, 0), nbR = neighbour<DIM>(P, e3, fa, 1);
+            if (has) face_at<K>(a0, a1 - a0, step, fidx, &fa, &k, true);
             double uL[NV], uR[NV], thL[MAXLEV + 1], thR[MAXLEV + 1];
-            // cells whose means replace a non-admissible FV input (element -1: own element)
-            int mLe = -1, mLc = 0, mRe = -1, mRc = 0;
-            double srho = own_sr, sE = own_se;
-            if (lowface || highface) {
-                element_face_sides<DIM, K, LV>(P, ee, fa, t, highface, highface ? nbR : nbL, S.al[le],
-                                               S.nal[le][2 * fa + (highface ? 1 : 0)], own_sr, own_se, uL, uR, thL,
-                                               thR, mLe, mLc, mRe, mRc, srho, sE);
-            } else {
-                // interior face: blended interface states of the two adjacent cells
-                int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
-                theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
-                theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
-                mLc = cl;
-                mRc = cr;
-                for (int v = 0; v < NV; ++v) {
-                    uL[v] = thL[0] * S.u[le][v][cl];
-                    uR[v] = thR[0] * S.u[le][v][cr];
-                }
+            // interior face: blended interface states of the two adjacent cells; a cell
+            // whose mean replaces a non-admissible FV input is the cell itself
+            const int cl = G::from_trans(t, fa, k - 1), cr = G::from_trans(t, fa, k);
+            theta_cell_of<DIM, K, LV>(S.al[le], cl, thL);
+            theta_cell_of<DIM, K, LV>(S.al[le], cr, thR);
+            for (int v = 0; v < NV; ++v) {
+                uL[v] = thL[0] * S.u[le][v][cl];
+                uR[v] = thR[0] * S.u[le][v][cr];
+            }
 #pragma unroll
-                for (int li = 0; li < LV::NLEV; ++li) {
-                    CTab &T = P.tabs[li];
-                    int n = LV::n(li);
-                    if (thL[1 + li] != 0.0) {
-                        int s = G::subelem(cl, n);
-                        double b = S.be[le][LV::off(li) + s];
-                        for (int v = 0; v < NV; ++v) {
-                            double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
-                            uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
-                        }
+            for (int li = 0; li < LV::NLEV; ++li) {
+                CTab &T = P.tabs[li];
+                int n = LV::n(li);
+                if (thL[1 + li] != 0.0) {
+                    int s = G::subelem(cl, n);
+                    double b = S.be[le][LV::off(li) + s];
+                    for (int v = 0; v < NV; ++v) {
+                        double tr = bapply<DIM, K>(S.u[le][v], cl, fa, n, T.Ep);
+                        uL[v] += thL[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
                     }
-                    if (thR[1 + li] != 0.0) {
-                        int s = G::subelem(cr, n);
-                        double b = S.be[le][LV::off(li) + s];
-                        for (int v = 0; v < NV; ++v) {
-                            double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
-                            uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
-                        }
+                }
+                if (thR[1 + li] != 0.0) {
+                    int s = G::subelem(cr, n);
+                    double b = S.be[le][LV::off(li) + s];
+                    for (int v = 0; v < NV; ++v) {
+                        double tr = bapply<DIM, K>(S.u[le][v], cr, fa, n, T.Em);
+                        uR[v] += thR[1 + li] * ((1.0 - b) * S.mean[le][v][LV::off(li) + s] + b * tr);
                     }
                 }
             }
             double F[NV];
             common_flux<DIM, K, LV, EPB * KD>(P, &S.wsL[le * KD], &S.wsR[le * KD], c, slot * KF, t, has, fa, k, uL, uR,
-                                             thL, thR, srho, sE, mLe, mLc, mRe, mRc, &S.u[le][0][0], ee, F);
+                                             thL, thR, own_sr, own_se, -1, cl, -1, cr, &S.u[le][0][0], ee, F);
             if (has) {
                 const int axs = SM::AXO ? 0 : fa;
                 for (int v = 0; v < NV; ++v) S.F[le][axs][v][k * KF + t] = F[v];
@@ -1569,7 +1539,7 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD))
 __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 2 : 3, 8))) residual_kernel(KArgs P)
 {
     __shared__ ResidualSmem<DIM, K, TOP, EPB> S;
-    residual_body<DIM, K, TOP, EPB, true>(P, xcd_tile(blockIdx.x, gridDim.x), S);
+    residual_body<DIM, K, TOP, EPB>(P, xcd_tile(blockIdx.x, gridDim.x), S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1957,7 +1927,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     const long long g = gindex<DIM, K>(P, e3, c);
     const double gam = P.gamma;
 
-    preload_element<DIM, K, LV, true, AdjointSmem<DIM, K, TOP, EPB>, false>(P, S, le, c, ee, e3, g);
+    preload_element<DIM, K, LV, true, AdjointSmem<DIM, K, TOP, EPB>>(P, S, le, c, ee, g);
     int sidx[MAXLEV];
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
@@ -2380,8 +2350,8 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_batch_kernel(KArgs P)
         const ProbDesc &D = P.probs[p];
         const KArgs Q = problem_args(P, D, p);
         const int tl = t - wg_uniform(D.tile_off);
-        if (wg_uniform(D.K) == 4) residual_body<2, 4, 4, EPB4, true>(Q, tl, U.k4);
-        else residual_body<2, 8, 8, EPB8, true>(Q, tl, U.k8);
+        if (wg_uniform(D.K) == 4) residual_body<2, 4, 4, EPB4>(Q, tl, U.k4);
+        else residual_body<2, 8, 8, EPB8>(Q, tl, U.k8);
         __syncthreads();
     }
 }
