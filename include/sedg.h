@@ -134,7 +134,9 @@ int sedg_check(sedg_ctx *ctx, long *bad_elem);
 
 /* Per-kernel timing with HIP events, for benchmarking.  After sedg_profile(ctx, 1)
  * sedg_rk_step enqueues its kernels directly (no graph replay) and records an event
- * pair around every launch on the caller's stream; sedg_profile_read synchronises
+ * on the caller's stream before its first launch and after every launch, so that a
+ * launch is timed from the end of the one before it (within the call) to its own
+ * end, one event marker per launch; sedg_profile_read synchronises
  * that stream and returns, for the analyse, residual, step-size and element-face
  * flux kernels (arrays of 4, in that order), the summed milliseconds and the launch
  * counts, then clears them.  sedg_profile(ctx, 0) returns to graph replay. */

@@ -2461,6 +2461,7 @@ struct sedg_ctx {
     std::vector<hipEvent_t> pool;
     size_t pool_used;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    hipEvent_t prev;        // the event closing the last timed launch of the current call
 };
 
 namespace {
@@ -2781,16 +2782,23 @@ static hipEvent_t prof_event(sedg_ctx *C)
     return C->pool[C->pool_used++];
 }
 
-// launch f() on s, bracketed by an event pair of kind 'kind' when profiling
+// launch f() on s and, when profiling, time it as kind 'kind': one event at every
+// boundary between timed launches (the event closing one launch opens the next), so
+// that the stream carries one marker per launch rather than two
 template <typename F>
 static void timed(sedg_ctx *C, int kind, hipStream_t s, F f)
 {
     if (!C->prof) { f(); return; }
-    hipEvent_t a = prof_event(C), b = prof_event(C);
-    if (a) (void)hipEventRecord(a, s);
+    hipEvent_t a = C->prev;
+    if (!a) {
+        a = prof_event(C);
+        if (a) (void)hipEventRecord(a, s);
+    }
     f();
+    hipEvent_t b = prof_event(C);
     if (b) (void)hipEventRecord(b, s);
     if (a && b) C->marks.push_back({kind, {a, b}});
+    C->prev = b;
 }
 
 static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log, hipStream_t s)
@@ -2840,6 +2848,7 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
     // step counter / fixed step
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, C->d_dt, dt_fixed > 0.0 ? dt_fixed : 0.0, C->d_ctr);
     if (C->prof) {
+        C->prev = nullptr;
         for (int st = 0; st < nsteps; ++st) enqueue_step(C, u, dt_fixed, dt_log_dev, s);
         C->last = s;
         return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
@@ -2878,6 +2887,7 @@ int sedg_profile(sedg_ctx *C, int on)
 {
     if (!C) return SEDG_EINVAL;
     C->prof = on != 0;
+    C->prev = nullptr;
     return SEDG_OK;
 }
 
@@ -2894,6 +2904,7 @@ int sedg_profile_read(sedg_ctx *C, double *ms, long *count)
     }
     C->marks.clear();
     C->pool_used = 0;
+    C->prev = nullptr;
     return SEDG_OK;
 }
 
