@@ -792,6 +792,28 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         double pp = pressure<DIM>(pt, gam);
         int ok = (pt[0] > 0.0 && pp > 0.0) ? 1 : 0;
         double rmin = pt[0], pmin = pp;
+        if (DIM == 2 && n >= 4) {
+            // the sub-element's 4n face-node traces, one per cell of the sub-element: the
+            // cell at local (lx, ly) with ly < 4 takes face ly (x low, x high, y low, y high)
+            // at face node lx, so that one pass covers both axes and both sides, and every
+            // trace lies in the sub-element whose reductions below take it
+            const int lx = G::coord(c, 0) & (n - 1), ly = G::coord(c, 1) & (n - 1);
+            if (ly < 4) {
+                const int a = ly >> 1;
+                const bool hi = (ly & 1) != 0;
+                const int b0 = c - lx - K * ly;     // low corner of the sub-element
+                const int base = a == 0 ? b0 + K * lx : b0 + lx, st = a == 0 ? 1 : K;
+                for (int v = 0; v < NV; ++v) {
+                    double s = 0.0;
+                    for (int m = 0; m < n; ++m) s += (hi ? T.bp[m] : T.bm[m]) * R0[v][base + m * st];
+                    pt[v] = s;
+                }
+                double q = pressure<DIM>(pt, gam);
+                if (!(pt[0] > 0.0 && q > 0.0)) ok = 0;
+                rmin = fmin(rmin, pt[0]);
+                pmin = fmin(pmin, q);
+            }
+        } else
         for (int a = 0; a < DIM; ++a) {
             // a lane on the low face of its sub-element takes the trace with b^-, one on
             // the high face the trace with b^+ (both sides in one pass; n >= 2)
