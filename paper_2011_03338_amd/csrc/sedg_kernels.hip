@@ -1018,12 +1018,14 @@ struct ResidualSmem {
     static constexpr int NAX = AXO ? 1 : DIM;
     double u[EPB][G::NV][G::KD];
     double F[EPB][NAX][G::NV][(K + 1) * G::KF];
-    double nod[EPB][G::NV][G::KD];
+    // temporary of the contraction passes; between them (active-level vote, face
+    // fluxes) its first two variables serve as the lane exchange buffers
     double tmp[EPB][G::NV][G::KD];
+    // 3-D: the reconstruction's first pass and the nodal fluxes (2-D stages both in tmp)
+    double nod[AXO ? EPB : 1][AXO ? G::NV : 1][AXO ? G::KD : 1];
     double al[EPB][LV::A];
     double mean[EPB][G::NV][LV::A];
     double be[EPB][LV::A];
-    double wsL[EPB * G::KD], wsR[EPB * G::KD];
     int act[EPB][MAXLEV + 1];
     // 3-D: the squeezed nodal values of every level, reconstructed in the first axis pass
     // and reused by the other two
@@ -1324,7 +1326,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     {
         int flags = 0;
         for (int l = 0; l <= LV::NLEV; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
-        flags = subreduce<DIM, K>(flags, G::LOGK, (int *)S.wsL, OpOr());
+        flags = subreduce<DIM, K>(flags, G::LOGK, (int *)&S.tmp[0][0][0], OpOr());
         if (c == 0)
             for (int l = 0; l <= MAXLEV; ++l) S.act[le][l] = (flags >> l) & 1;
     }
@@ -1332,6 +1334,12 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     __syncthreads();
     int actv[MAXLEV + 1];
     for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
+    // lane exchange buffers of the face fluxes (the temporary is free then)
+    double *const wsx = &S.tmp[0][0][0];
+    double *const wsL = &S.tmp[le][0][0], *const wsR = &S.tmp[le][1][0];
+    // staging of the nodal fluxes: its own array in 3-D (the temporary holds the
+    // transverse passes), the temporary in 2-D
+    double *const fst = SM::AXO ? &S.nod[SM::AXO ? le : 0][0][0] : &S.tmp[le][0][0];
 
     double out[NV];
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
@@ -1361,9 +1369,9 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         const int nfaces = face_count<K>(a1 - a0, step, true);
         int nfmax = nfaces;
         if (EPB > 1) {
-            S.wsL[tid] = (double)nfaces;
+            wsx[tid] = (double)nfaces;
             __syncthreads();
-            for (int q = 0; q < EPB; ++q) nfmax = max(nfmax, (int)S.wsL[q * KD]);
+            for (int q = 0; q < EPB; ++q) nfmax = max(nfmax, (int)wsx[q * KD]);
             __syncthreads();
         }
         const int slot = c / KF, t = c % KF;
@@ -1406,7 +1414,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 }
             }
             double F[NV];
-            common_flux<DIM, K, LV, EPB * KD>(P, &S.wsL[le * KD], &S.wsR[le * KD], c, slot * KF, t, has, fa, k, uL, uR,
+            common_flux<DIM, K, LV, EPB * KD>(P, wsL, wsR, c, slot * KF, t, has, fa, k, uL, uR,
                                              thL, thR, own_sr, own_se, -1, cl, -1, cr, &S.u[le][0][0], ee, F);
             if (has) {
                 const int axs = SM::AXO ? 0 : fa;
@@ -1441,9 +1449,9 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 __syncthreads();
                 for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(S.tmp[le][v], c, 1, n, T.R);
             } else if (pass == 0) {
-                for (int v = 0; v < NV; ++v) S.nod[le][v][c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
+                for (int v = 0; v < NV; ++v) fst[v * KD + c] = bapply<DIM, K>(S.u[le][v], c, 0, n, T.R);
                 __syncthreads();
-                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(S.nod[le][v], c, 1, n, T.R);
+                for (int v = 0; v < NV; ++v) S.tmp[le][v][c] = bapply<DIM, K>(fst + v * KD, c, 1, n, T.R);
                 __syncthreads();
                 for (int v = 0; v < NV; ++v) nodal[v] = bapply<DIM, K>(S.tmp[le][v], c, 2, n, T.R);
             } else {
@@ -1464,10 +1472,10 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
                 double f[NV];
                 euler_flux<DIM>(nodal, a, gam, f);
                 __syncthreads();
-                for (int v = 0; v < NV; ++v) S.nod[le][v][c] = f[v];
+                for (int v = 0; v < NV; ++v) fst[v * KD + c] = f[v];
                 __syncthreads();
                 double vol[NV];
-                for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(S.nod[le][v], c, a, n, T.Dhat);
+                for (int v = 0; v < NV; ++v) vol[v] = bapply<DIM, K>(fst + v * KD, c, a, n, T.Dhat);
                 for (int bax = 0; bax < DIM; ++bax) {
                     if (bax == a) continue;
                     __syncthreads();
