@@ -260,3 +260,88 @@ def ml1d_rhs(K, nelem, dx, ubar, alphas, levels, periodic=True, g=GAMMA):
         al = np.repeat(alphas[n], n, axis=1)[None]
         acc = (1.0 - al) * acc + al * rhs[n]
     return acc.reshape(nv, nelem * K)
+
+
+def ml2d_rhs(K, ne, dx, ubar, alpha, levels, g=GAMMA):
+    """Dense brute force of the 2-D multi-level blended scheme on a periodic mesh of
+    ne x ne square elements of width dx (Sec. 2.6 in two dimensions; App. eqs.
+    3D-interface-fluxes and 3D-blend-interface-fluxes reduced to d = 2).
+
+    ubar: (4, G, G) subcell means indexed [v, y, x], G = ne*K.  alpha: (ne*ne, A)
+    per element (x fastest), levels listed from the top (K, K/2, ..., 2), level n's
+    sub-elements at offsets sum_{m > n} (K/m)^2, x fastest inside the element.
+    Every operator is a dense G x G matrix on one global axis, block-diagonal over
+    the level-n sub-elements (Kronecker product with the identity).  Squeezing and the
+    interface safety rule are not modelled: the caller checks that neither acts."""
+    dim, nv, G = 2, 4, ne * K
+    U = ubar
+    tabs = {n: np_tables(n) for n in levels}
+
+    def blk(M, n):
+        return np.kron(np.eye(G // n), M)
+
+    def along(X, M, a):          # contract M with spatial axis a (0 = x, 1 = y)
+        return np.einsum("ij,vyj->vyi", M, X) if a == 0 else np.einsum("ij,vjx->vix", M, X)
+
+    # per-cell blending weights (eq. blending-weights)
+    iy, ix = np.meshgrid(np.arange(G), np.arange(G), indexing="ij")
+    elem = (ix // K) + ne * (iy // K)
+    th, prod, off = {}, np.ones((G, G)), 0
+    for n in levels:
+        ns = K // n
+        a_n = alpha[elem, off + (ix % K) // n + ns * ((iy % K) // n)]
+        th[n] = a_n * prod
+        prod = prod * (1.0 - a_n)
+        off += ns * ns
+    th1 = prod
+
+    rhs = {1: np.zeros_like(U)}
+    rhs.update({n: np.zeros_like(U) for n in levels})
+    nodal = {n: along(along(U, blk(tabs[n]["R"], n), 0), blk(tabs[n]["R"], n), 1) for n in levels}
+    for a in range(dim):
+        b = 1 - a
+        # interface states of every cell at its high (+) and low (-) face along a: cascade
+        up, um = th1[None] * U, th1[None] * U
+        for n in levels:
+            T = tabs[n]
+            up = up + th[n][None] * along(U, blk(T["Ip"] @ T["R"], n), a)
+            um = um + th[n][None] * along(U, blk(T["Im"] @ T["R"], n), a)
+        # face f along a lies between cell f-1 (left) and cell f (right), periodic
+        ax = 2 - a
+        uL = np.roll(up, 1, axis=ax)
+        uR = um
+        F = hlle(uL, uR, dim, a, g)
+        wsum = np.zeros((G, G))
+        acc = np.zeros_like(U)
+        fidx = np.arange(G)
+        for n in levels:
+            T = tabs[n]
+            cand = along(hlle(along(uL, blk(T["R"], n), b), along(uR, blk(T["R"], n), b), dim, a, g),
+                         blk(T["P"], n), b)
+            tbar = 0.5 * (np.roll(th[n], 1, axis=ax - 1) + th[n])
+            on = (fidx % n == 0)
+            mask = on[None, :] if a == 0 else on[:, None]
+            wn = np.where(mask, tbar, 0.0)
+            acc = acc + wn[None] * cand
+            wsum = wsum + wn
+        F = acc + (1.0 - wsum)[None] * F
+        # first-order finite volumes
+        rhs[1] = rhs[1] - (K / dx) * (np.roll(F, -1, axis=ax) - F)
+        # DG levels: (K / (n dx)) (f(nodal) x_a Dhat x_b P - F* x_a Bhat)
+        for n in levels:
+            T = tabs[n]
+            Dhat = T["P"] @ T["D"]
+            B0 = np.zeros((n, n + 1))
+            B0[:, 0] = -T["bm"] / T["w"]
+            B0[:, n] = T["bp"] / T["w"]
+            Bhat = T["P"] @ B0
+            Bbig = np.zeros((G, G))
+            for s in range(G // n):
+                Bbig[s * n:(s + 1) * n, s * n] += Bhat[:, 0]
+                Bbig[s * n:(s + 1) * n, ((s + 1) * n) % G] += Bhat[:, n]
+            vol = along(along(flux(nodal[n], dim, a, g), blk(Dhat, n), a), blk(T["P"], n), b)
+            rhs[n] = rhs[n] + (K / (n * dx)) * (vol - along(F, Bbig, a))
+    out = th1[None] * rhs[1]
+    for n in levels:
+        out = out + th[n][None] * rhs[n]
+    return out
