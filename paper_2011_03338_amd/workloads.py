@@ -270,3 +270,17 @@ def ensemble_problem(desc):
     on desc["side"]^2 elements with K = desc["K"], energy desc["E"] and a seeded
     centre within 0.2 of the origin."""
     return sedov(desc["seed"], desc["side"], desc["K"], E=desc["E"], rc=0.2)
+
+
+def sod_tube(nelem: int = 32, K: int = 8):
+    """Sod shock tube on [0, 1] (diaphragm at x = 0.5; (rho, v, p) = (1, 0, 1) left,
+    (0.125, 0, 0.1) right), laid out as a 2-D strip of nelem x 1 elements, outflow
+    in x and periodic in y, so every row of subcells evolves as the 1-D problem.
+    The diaphragm falls on a subcell edge, so the means are exact."""
+    mesh = Mesh(2, K, [nelem, 1], [0.0, 0.0], [1.0, 1.0 / nelem], [OUTFLOW, PERIODIC])
+    xc = 0.5 * (mesh.edges(0)[1:] + mesh.edges(0)[:-1])
+    left = xc < 0.5
+    u = np.zeros(mesh.shape())
+    u[0, 0] = np.where(left, 1.0, 0.125)[None, :]
+    u[3, 0] = (np.where(left, 1.0, 0.1) / (mesh.gamma - 1.0))[None, :]
+    return mesh, u, {"x_diaphragm": 0.5, "T": 0.2}
