@@ -13,10 +13,12 @@ from tests.test_oracle_sod import exact_density_means, run_to
 pytestmark = pytest.mark.gpu
 
 
-def test_sod_gpu_matches_oracle_and_exact():
+@pytest.mark.parametrize("mask,bound", [(0, 3e-3), (1 << 3, 4e-3)])
+def test_sod_gpu_matches_oracle_and_exact(mask, bound):
+    """mask 0: all levels O(8) -> O(4) -> O(2) -> FV; 1 << 3: single level O(8) -> FV."""
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     mesh, u0, info = W.sod_tube(nelem=32, K=8)
-    p = W.Params()
+    p = W.Params(level_mask=mask)
     dts = []
     u_o = run_to(mesh, p, u0, info["T"], dts)
     s = sedg.Solver(mesh, p)
@@ -31,6 +33,6 @@ def test_sod_gpu_matches_oracle_and_exact():
     diff = float(np.max(np.abs(u_g - u_o)))
     rho = u_g[0, 0].mean(axis=0)
     l1 = float(np.mean(np.abs(rho - exact_density_means(mesh.edges(0), info["T"]))))
-    say("  sod %d steps max|gpu-oracle|=%.3e density L1 vs exact=%.3e" % (len(dts), diff, l1))
+    say("  sod mask %d %d steps max|gpu-oracle|=%.3e density L1 vs exact=%.3e" % (mask, len(dts), diff, l1))
     assert diff < 1e-3
-    assert l1 < 3e-3
+    assert l1 < bound
