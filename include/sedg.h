@@ -55,7 +55,8 @@ enum {
     SEDG_EHIP = -2,        /* HIP runtime error */
     SEDG_ENOMEM = -3,      /* device allocation failed */
     SEDG_ESTATE = -4,      /* non-permissible or non-finite mean value detected */
-    SEDG_EUNSUPPORTED = -5 /* configuration not compiled (dim, K) */
+    SEDG_EUNSUPPORTED = -5,/* configuration not compiled (dim, K) */
+    SEDG_ESCRATCH = -6     /* problem larger than the static work space of sedg_rhs_noalloc */
 };
 
 enum { SEDG_PERIODIC = 0, SEDG_OUTFLOW = 1 };
@@ -241,6 +242,33 @@ int sedg_batch_check(sedg_batch *batch, int *bad_problem, long *bad_elem);
  * P[n*n], R[n*n], Dhat[n*n], Bhat_left[n], Bhat_right[n], Iplus[n*n],
  * Iminus[n*n] (row-major).  Returns the count written or SEDG_EINVAL. */
 int sedg_tables(int n, int family, double *out, int cap);
+
+/* ---- right-hand side without device allocation ------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Computes what sedg_rhs
+ * computes (same kernels, same results bit for bit) for the given mesh and
+ * parameters, with no context: every work array (blending factors, squeezing
+ * parameters, sub-element means, face states, element-face fluxes, data scales,
+ * the error flag) and the operator tables live in one static device array of
+ * 64 MiB per device, held from the first call until the process ends.
+ *   mesh, params  host; modes SEDG_ADAPTIVE, SEDG_FORCE_DG and SEDG_FORCE_FV
+ *                 (SEDG_EINVAL otherwise)
+ *   u             device, state (read only)
+ *   dudt          device, output state-shaped array (must not alias u)
+ *   bad_dev       device int, optional (NULL): receives the index of an element
+ *                 holding a non-permissible or non-finite mean value, INT_MAX if none
+ *   stream        hipStream_t or NULL
+ * Returns SEDG_ESCRATCH when the work arrays of the mesh exceed the static space
+ * (per element 8 * ((2 + nvar) * A + 4 * dim * nvar * K^(dim-1) + 2) bytes: 2-D
+ * K = 8 about 21 800 elements, 3-D K = 8 about 1 900).  It calls no hipMalloc or
+ * hipFree.  The first call on a device locates that device's array and copies the
+ * operator tables into it synchronously, so it must not be made under stream
+ * capture; later calls only enqueue kernels.  All calls on one device share its
+ * array and leave the last call's contents there: calls that overlap in time on
+ * one device (different streams or threads) race and must be serialised by the
+ * caller. */
+int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const double *u, double *dudt, int *bad_dev,
+                     void *stream);
 
 /* Text of a return code. */
 const char *sedg_strerror(int code);

@@ -30,6 +30,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -2538,13 +2539,17 @@ void launch_top(int which, int top, const KArgs &P, int nblocks, hipStream_t s)
     else launch_kernel<DIM, K, (K >= 8 ? 8 : 4)>(which, P, nblocks, s);
 }
 
+void launch_shape(int which, int d, int K, int top, int nblocks, const KArgs &P, hipStream_t s)
+{
+    if (d == 2 && K == 4) launch_top<2, 4>(which, top, P, nblocks, s);
+    else if (d == 2 && K == 8) launch_top<2, 8>(which, top, P, nblocks, s);
+    else if (d == 3 && K == 4) launch_top<3, 4>(which, top, P, nblocks, s);
+    else launch_top<3, 8>(which, top, P, nblocks, s);
+}
+
 void launch_any(int which, const sedg_ctx *C, const KArgs &P, hipStream_t s)
 {
-    int d = C->mesh.dim, K = C->mesh.K, top = C->lev_n[0];
-    if (d == 2 && K == 4) launch_top<2, 4>(which, top, P, C->nblocks, s);
-    else if (d == 2 && K == 8) launch_top<2, 8>(which, top, P, C->nblocks, s);
-    else if (d == 3 && K == 4) launch_top<3, 4>(which, top, P, C->nblocks, s);
-    else launch_top<3, 8>(which, top, P, C->nblocks, s);
+    launch_shape(which, C->mesh.dim, C->mesh.K, C->lev_n[0], C->nblocks, P, s);
 }
 
 void launch_analyse_any(const sedg_ctx *C, const KArgs &P, hipStream_t s) { launch_any(0, C, P, s); }
@@ -2672,6 +2677,7 @@ const char *sedg_strerror(int code)
     case SEDG_ENOMEM: return "device allocation failed";
     case SEDG_ESTATE: return "non-permissible or non-finite mean value";
     case SEDG_EUNSUPPORTED: return "unsupported configuration";
+    case SEDG_ESCRATCH: return "problem larger than the static work space of sedg_rhs_noalloc";
     default: return "unknown error";
     }
 }
@@ -3487,6 +3493,160 @@ int sedg_batch_check(sedg_batch *B, int *bad_problem, long *bad_elem)
     int big = INT_MAX;
     if (hipMemcpy(B->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
     return SEDG_ESTATE;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// right-hand side without device allocation
+// ---------------------------------------------------------------------------
+// Every buffer beyond the caller's input and output lives in one file-scope device
+// array: the operator tables of both node families (levels 8, 4, 2 each), the error
+// flag and the per-element work arrays of one right-hand side (factors, squeezing
+// parameters, sub-element means, face states, element-face fluxes, data scales).
+// Each device the library runs on holds its own copy for the lifetime of the process.
+
+#define SEDG_SCRATCH_BYTES (64ull << 20)
+#define SEDG_MAX_DEVICES 64
+
+static __device__ __align__(256) unsigned char scratch[SEDG_SCRATCH_BYTES];
+
+namespace {
+
+// byte offsets inside the scratch array
+constexpr size_t NA_TABS = 0;                                            // 2 families x levels 8, 4, 2
+constexpr size_t NA_ERR = ((2 * 3 * sizeof(sedg_level_tab) + 255) / 256) * 256;
+constexpr size_t NA_WORK = NA_ERR + 256;
+
+std::mutex na_mu;
+unsigned char *na_ptr[SEDG_MAX_DEVICES];   // device address of each device's scratch
+
+// set-up on the current device, once: the device address of its scratch array and the
+// operator tables copied into it (a synchronous copy; the first call on a device must
+// therefore not be made under stream capture)
+int na_setup(int dev, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lk(na_mu);
+    if (na_ptr[dev]) { *out = na_ptr[dev]; return SEDG_OK; }
+    unsigned char *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SEDG_EHIP;
+    sedg_level_tab h[6];
+    std::memset(h, 0, sizeof(h));
+    for (int fam = 0; fam < 2; ++fam)
+        for (int li = 0; li < 3; ++li)
+            if (sedg_build_level(8 >> li, fam, &h[3 * fam + li])) return SEDG_EINVAL;
+    if (hipMemcpy(ptr + NA_TABS, h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    na_ptr[dev] = ptr;
+    *out = ptr;
+    return SEDG_OK;
+}
+
+__global__ void na_set_int_kernel(int *x, int v)
+{
+    if (threadIdx.x == 0) x[0] = v;
+}
+
+__global__ void na_copy_int_kernel(const int *src, int *dst)
+{
+    if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const double *u, double *dudt, int *bad_dev,
+                     void *stream)
+{
+    if (!mesh || !params || !u || !dudt || u == dudt) return SEDG_EINVAL;
+    if (!supported(mesh->dim, mesh->K)) return SEDG_EUNSUPPORTED;
+    if (!(mesh->gamma > 1.0) || (mesh->family != SEDG_GAUSS && mesh->family != SEDG_LGL)) return SEDG_EINVAL;
+    if (params->mode != SEDG_ADAPTIVE && params->mode != SEDG_FORCE_DG && params->mode != SEDG_FORCE_FV)
+        return SEDG_EINVAL;
+    const int d = mesh->dim, K = mesh->K, nv = d + 2;
+    const int top = params->top_level > 0 ? params->top_level : K;
+    if (top < 2 || top > K || (top & (top - 1))) return SEDG_EINVAL;
+    // geometry, as sedg_create validates it
+    KArgs P;
+    std::memset(&P, 0, sizeof(P));
+    long long nel = 1, dof = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < d) {
+            if (mesh->nelem[a] < 1 || !(mesh->hi[a] > mesh->lo[a])) return SEDG_EINVAL;
+            if (mesh->bc[a] != SEDG_PERIODIC && mesh->bc[a] != SEDG_OUTFLOW) return SEDG_EINVAL;
+            P.ne[a] = mesh->nelem[a];
+            P.G[a] = mesh->nelem[a] * K;
+            P.bc[a] = mesh->bc[a];
+            P.dx[a] = (mesh->hi[a] - mesh->lo[a]) / mesh->nelem[a];
+        } else {
+            P.ne[a] = 1;
+            P.G[a] = 1;
+            P.bc[a] = SEDG_PERIODIC;
+            P.dx[a] = 1.0;
+        }
+        nel *= P.ne[a];
+        dof *= P.G[a];
+    }
+    // level hierarchy and per-element work sizes
+    int off = 0;
+    for (int n = top; n >= 2; n /= 2) {
+        int li = P.nlev++;
+        P.lev_n[li] = n;
+        P.lev_off[li] = off;
+        int per = 1;
+        for (int a = 0; a < d; ++a) per *= K / n;
+        off += per;
+    }
+    for (int li = P.nlev; li < MAXLEV; ++li) { P.lev_n[li] = 2; P.lev_off[li] = 0; }
+    P.A = off;
+    long long kf = 1;
+    for (int a = 1; a < d; ++a) kf *= K;
+    const long long nfb = (long long)d * 2 * nv * kf;
+    const long long per_el = 2LL * P.A + (long long)nv * P.A + 2 * nfb + 2;
+    if (nel > INT_MAX / 8 || per_el * nel * (long long)sizeof(double) > (long long)(SEDG_SCRATCH_BYTES - NA_WORK))
+        return SEDG_ESCRATCH;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SEDG_EHIP;
+    if (dev < 0 || dev >= SEDG_MAX_DEVICES) return SEDG_EUNSUPPORTED;
+    unsigned char *base = nullptr;
+    int rc = na_setup(dev, &base);
+    if (rc) return rc;
+
+    double *w = (double *)(base + NA_WORK);
+    P.alpha = w;
+    P.beta = P.alpha + nel * P.A;
+    P.mean = P.beta + nel * P.A;
+    P.fbuf = P.mean + nel * nv * P.A;
+    P.ef = P.fbuf + nel * nfb;
+    P.scale = P.ef + nel * nfb;
+    int li_top = top == 8 ? 0 : top == 4 ? 1 : 2;
+    P.tabs = (CTab *)((sedg_level_tab *)(base + NA_TABS) + 3 * mesh->family + li_top);
+    P.err = (int *)(base + NA_ERR);
+    P.lam_mask = LAM_SLOTS - 1;
+    P.dof = dof;
+    P.nel = (int)nel;
+    P.mode = params->mode;
+    P.level_mask = params->level_mask;
+    P.gamma = mesh->gamma;
+    P.tau_A = params->tau_A;
+    P.tau_S = params->tau_S;
+    P.alpha_H = params->alpha_H;
+    P.alpha_L = params->alpha_L;
+    P.beta_L = params->beta_L;
+    P.u = u;
+    P.out = dudt;
+    P.stage = 0;
+
+    hipStream_t s = (hipStream_t)stream;
+    const int epb = epb_for(d, K);
+    const int nblocks = (int)((nel + epb - 1) / epb);
+    hipLaunchKernelGGL(na_set_int_kernel, dim3(1), dim3(64), 0, s, P.err, INT_MAX);
+    launch_shape(0, d, K, top, nblocks, P, s);
+    launch_shape(6, d, K, top, nblocks, P, s);
+    launch_shape(1, d, K, top, nblocks, P, s);
+    if (bad_dev) hipLaunchKernelGGL(na_copy_int_kernel, dim3(1), dim3(64), 0, s, P.err, bad_dev);
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
 }
 
 }  // extern "C"

@@ -20,14 +20,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsedg.so")
 
-SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED, SEDG_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "sedg_set_params",
             "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror",
             "sedg_profile", "sedg_profile_read", "sedg_rhs_frozen", "sedg_adjoint_rhs", "sedg_tape_len",
             "sedg_rk_step_tape", "sedg_adjoint_rk_step", "sedg_batch_create", "sedg_batch_destroy",
             "sedg_batch_state_len", "sedg_batch_state_offset", "sedg_batch_set_tuning", "sedg_batch_get_tuning",
-            "sedg_batch_rk_step", "sedg_batch_check"]
+            "sedg_batch_rk_step", "sedg_batch_check", "sedg_rhs_noalloc"]
 
 
 class SedgError(RuntimeError):
@@ -95,6 +95,7 @@ def load():
     lib.sedg_batch_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning_c)]
     lib.sedg_batch_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
     lib.sedg_batch_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_long)]
+    lib.sedg_rhs_noalloc.argtypes = [ctypes.POINTER(Mesh_c), ctypes.POINTER(Params_c), vp, vp, vp, vp]
     lib.sedg_strerror.argtypes = [ctypes.c_int]
     lib.sedg_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -155,6 +156,18 @@ def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def rhs_noalloc(mesh, params, u, dudt, bad=None, stream=None):
+    """sedg_rhs_noalloc: the right-hand side without a context and without device
+    allocation (work arrays in the library's static device array).  bad: optional
+    int32 GPU tensor of one element receiving a bad element index (INT_MAX if none)."""
+    if bad is not None:
+        import torch
+        assert bad.dtype == torch.int32 and bad.is_cuda and bad.numel() >= 1
+    _check(load().sedg_rhs_noalloc(ctypes.byref(mesh_c(mesh)), ctypes.byref(params_c(params)), _ptr(u), _ptr(dudt),
+                                   None if bad is None else ctypes.c_void_p(bad.data_ptr()), _stream(stream)),
+           "sedg_rhs_noalloc")
 
 
 class Solver:

@@ -1,0 +1,103 @@
+"""The right-hand side without device allocation (sedg_rhs_noalloc) against the
+context-based sedg_rhs, through the C ABI: the same kernels run on the static work
+space, so the results must agree bit for bit (and so within the one-RHS bar of
+1e-12 relative).  Two calls in a row, the second on a smaller mesh with other
+tables, then a 3-D call; oversized meshes are rejected on the host."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_03338_amd import sedg, workloads as W
+from tests.parity import DEV, RHS_TOL, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+INT_MAX = 2 ** 31 - 1
+
+
+def _context_rhs(mesh, params, ug):
+    s = sedg.Solver(mesh, params)
+    d = torch.zeros_like(ug)
+    s.rhs(ug, d)
+    s.check()
+    s.close()
+    return d
+
+
+def _noalloc_rhs(mesh, params, ug):
+    d = torch.full_like(ug, float("nan"))
+    bad = torch.zeros(1, dtype=torch.int32, device=DEV)
+    sedg.rhs_noalloc(mesh, params, ug, d, bad)
+    torch.cuda.synchronize()
+    return d, int(bad.item())
+
+
+def test_noalloc_matches_context_rhs_two_calls():
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    sedg.load()
+    m_lgl = W.Mesh(2, 4, [5, 3], [0, 0], [1, 0.6], [0, 0], family=W.LGL)
+    u_lgl = W.density_wave(m_lgl)
+    cases = [
+        ("sedov 2-D K=8 12x10 elements", W.sedov(1, 12, 8, L=0.4, sigma=0.04)[:2], W.Params()),
+        ("density wave 2-D K=4 5x3 elements LGL", (m_lgl, u_lgl), W.Params()),
+        ("sedov 2-D K=8 4x4 elements top level 4", W.sedov(2, 4, 8, L=0.4, sigma=0.05)[:2], W.Params(top_level=4)),
+    ]
+    sizes = []
+    for name, (mesh, u), params in cases:
+        say("noalloc case", name)
+        ug = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
+        ref = _context_rhs(mesh, params, ug)
+        got, bad = _noalloc_rhs(mesh, params, ug)
+        assert bad == INT_MAX
+        assert torch.equal(got, ref), name
+        err = rel_err(got.cpu().numpy(), ref.cpu().numpy())
+        say("  max rel diff vs sedg_rhs", err)
+        assert err <= RHS_TOL
+        sizes.append(mesh.dof)
+    assert sizes[1] < sizes[0]
+
+
+def test_noalloc_3d_and_oracle():
+    mesh, u, _ = W.config0(0, 4, 4)
+    m3 = W.Mesh(3, 4, [3, 2, 2], [0, 0, 0], [1, 0.7, 0.7], [0, 1, 0])
+    rng = np.random.default_rng(5)
+    u3 = np.zeros(m3.shape())
+    u3[0] = 1.0 + 0.3 * rng.uniform(size=u3[0].shape)
+    u3[1] = 0.2 * u3[0]
+    u3[2] = -0.1 * u3[0]
+    u3[3] = 0.05 * u3[0]
+    u3[4] = 2.5 + 0.5 * rng.uniform(size=u3[0].shape)
+    for name, (m, x) in [("3-D K=4 3x2x2", (m3, u3)), ("config0 K=4 4x4", (mesh, u))]:
+        say("noalloc case", name)
+        ug = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+        got, bad = _noalloc_rhs(m, W.Params(), ug)
+        assert bad == INT_MAX
+        ref = _context_rhs(m, W.Params(), ug)
+        assert torch.equal(got, ref), name
+        o = O.rhs(m, W.Params(), x)
+        err = rel_err(got.cpu().numpy(), o)
+        say("  rel err vs oracle", err)
+        assert err <= RHS_TOL
+
+
+def test_noalloc_reports_bad_state_and_limits():
+    mesh, u, _ = W.config0(0, 8, 4)
+    u = u.copy()
+    u[0, 0, 13, 9] = -1.0     # subcell (9, 13) lies in element (2, 3) = 2 + 8 * 3
+    ug = torch.from_numpy(u).to(DEV)
+    _, bad = _noalloc_rhs(mesh, W.Params(), ug)
+    assert bad == 26
+    # a following good call clears the flag
+    mesh2, u2, _ = W.config0(1, 4, 4)
+    _, bad = _noalloc_rhs(mesh2, W.Params(), torch.from_numpy(u2).to(DEV))
+    assert bad == INT_MAX
+    # oversized meshes and unsupported modes are rejected before anything is enqueued
+    big = W.Mesh(2, 8, [256, 256], [0, 0], [1, 1], [0, 0])
+    dummy = torch.zeros(8, dtype=torch.float64, device=DEV)
+    with pytest.raises(sedg.SedgError) as ei:
+        sedg.rhs_noalloc(big, W.Params(), dummy, torch.zeros_like(dummy))
+    assert ei.value.code == sedg.SEDG_ESCRATCH
+    with pytest.raises(sedg.SedgError) as ei:
+        sedg.rhs_noalloc(mesh2, W.Params(mode=W.EXTERNAL), dummy, torch.zeros_like(dummy))
+    assert ei.value.code == sedg.SEDG_EINVAL
