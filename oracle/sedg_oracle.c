@@ -974,11 +974,9 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
         wdg[li] = tb;
         thFV -= tb;
     }
-    /* accumulation order: DG candidates level by level from the top, then the FV candidate */
+    /* the blend in the order eq. 3D-blend-interface-fluxes writes it: the FV candidate
+       with its weight, then the DG candidates level by level from the top */
     for (int v = 0; v < nv; v++) F[v] = 0.0;
-    for (int li = 0; li < c->nlev; li++)
-        if (wdg[li] != 0.0)
-            for (int v = 0; v < nv; v++) F[v] += wdg[li] * Fdg[li][v];
     if (thFV != 0.0) {
         double aL[MAXV], aR[MAXV], fs[MAXV];
         memcpy(aL, uL, sizeof(aL));
@@ -992,8 +990,11 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
             if (nfb) (*nfb)++;
         }
         hlle(dim, g, a, aL, aR, fs);
-        for (int v = 0; v < nv; v++) F[v] += thFV * fs[v];
+        for (int v = 0; v < nv; v++) F[v] = thFV * fs[v];
     }
+    for (int li = 0; li < c->nlev; li++)
+        if (wdg[li] != 0.0)
+            for (int v = 0; v < nv; v++) F[v] += wdg[li] * Fdg[li][v];
 }
 
 /* Pass 3, per element: level right-hand sides and their blend
