@@ -1,0 +1,263 @@
+"""Pins of two oracle parts against values worked by hand, with no operator table and
+no copy of the oracle's formulas:
+
+* the blending factor of Sec. 2.7 (eq. L1-norm-slope, eq. calc-blending-factor)
+  strictly between its clamps, on 1-D (and y-invariant 2-D) K = 4 elements whose
+  smoothness measures follow in closed form: the level-4 reconstruction of four
+  subcell means is the unique cubic with those means, and the level-2 children's are
+  the lines through their two means; where such a polynomial is monotone, the L1 norm
+  of its derivative is the difference of its end values (and the n-point Gauss rule of
+  the derivative's absolute value, a polynomial of degree <= 2n - 1, is exact);
+* the HLL flux with Einfeldt's signal speeds (Sec. 3) on the Sod states and on
+  supersonic pairs, extracted from first-order FV right-hand sides of piecewise
+  constant data (Sec. 2.1), against Roe averages and signal speeds worked by hand.
+"""
+from fractions import Fraction as Fr
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_03338_amd import workloads as W
+
+GAMMA = 1.4
+TAU_A, TAU_S = 100.0, 0.05
+
+
+# ---------------------------------------------------------------------------
+# indicator between its clamps
+# ---------------------------------------------------------------------------
+
+def _cubic_from_means(m):
+    """Coefficients c0..c3 (exact rationals) of the cubic on [0, 1] whose means over the
+    four subcells [i/4, (i+1)/4] are m."""
+    def mono_mean(k, a, b):
+        return (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a))
+    A = [[mono_mean(k, Fr(i, 4), Fr(i + 1, 4)) for k in range(4)] + [Fr(m[i])] for i in range(4)]
+    for c in range(4):
+        p = next(r for r in range(c, 4) if A[r][c] != 0)
+        A[c], A[p] = A[p], A[c]
+        for r in range(4):
+            if r != c and A[r][c] != 0:
+                f = A[r][c] / A[c][c]
+                A[r] = [x - f * y for x, y in zip(A[r], A[c])]
+    return [A[i][4] / A[i][i] for i in range(4)]
+
+
+def _monotone(c):
+    d = lambda x: c[1] + 2 * c[2] * x + 3 * c[3] * x * x
+    pts = [Fr(0), Fr(1)]
+    if c[3] != 0:
+        xv = -c[2] / (3 * c[3])
+        if 0 < xv < 1:
+            pts.append(xv)
+    vals = [d(x) for x in pts]
+    return all(v > 0 for v in vals) or all(v < 0 for v in vals)
+
+
+def _sigmas(m):
+    """(sigma_4, sigma_2) of four subcell means m (exact rationals): the total variation
+    of the level-4 cubic over the element and the sum over the two level-2 children of
+    the variation of their lines (a line through subcell means m_a, m_b at the subcell
+    centres, +-1/4 of the child, varies by 2 |m_b - m_a| over the child)."""
+    if all(Fr(x) == Fr(m[0]) for x in m):
+        return Fr(0), Fr(0)
+    c = _cubic_from_means(m)
+    assert _monotone(c)
+    s4 = abs(c[1] + c[2] + c[3])
+    s2 = 2 * abs(Fr(m[1]) - Fr(m[0])) + 2 * abs(Fr(m[3]) - Fr(m[2]))
+    return s4, s2
+
+
+def _alpha_of(s4, s2):
+    r = abs(s4 - s2) / max(s4, s2, Fr(1))
+    x = TAU_A * float(r) - TAU_A * TAU_S
+    return 1.0 - min(max(x, 0.0), 1.0), x
+
+
+# shapes with monotone cubics (searched over means 0, a/20, b/20, 1)
+SHAPE_A = [Fr(0), Fr(1, 20), Fr(6, 20), Fr(1)]      # sigma_4 = 19/12 > sigma_2 = 3/2
+SHAPE_B = [Fr(0), Fr(6, 20), Fr(14, 20), Fr(1)]     # sigma_4 = 17/15 < sigma_2 = 6/5
+SHAPE_C = [Fr(0), Fr(5, 20), Fr(7, 20), Fr(1)]      # relative difference 0.115: small amplitude case
+
+
+def _state_1d(rho_means, E_means):
+    mesh = W.Mesh(1, 4, [1], [0.0], [1.0], [W.PERIODIC])
+    u = np.zeros(mesh.shape())
+    u[0, 0, 0] = [float(x) for x in rho_means]
+    u[2, 0, 0] = [float(x) for x in E_means]
+    return mesh, u
+
+
+def _state_2d_y_invariant(rho_means, E_means, ny=4):
+    mesh = W.Mesh(2, 4, [1, 1], [0.0, 0.0], [1.0, 1.0], [W.PERIODIC, W.PERIODIC])
+    u = np.zeros(mesh.shape())
+    u[0, 0] = np.array([float(x) for x in rho_means])[None, :]
+    u[3, 0] = np.array([float(x) for x in E_means])[None, :]
+    return mesh, u
+
+
+CASES = {
+    # density varies (sigma >= 1, sigma_4 is the larger), pressure constant
+    "rho_A": ([1 + 2 * x for x in SHAPE_A], [Fr(5, 2)] * 4),
+    # density varies (sigma >= 1, sigma_2 is the larger)
+    "rho_B": ([1 + Fr(3, 2) * x for x in SHAPE_B], [Fr(5, 2)] * 4),
+    # small amplitude: both measures below 1, the floor of max(., ., 1) decides
+    "rho_C_small": ([1 + Fr(55, 233) * x for x in SHAPE_C], [Fr(5, 2)] * 4),
+    # pressure varies alone (p = 0.4 E at rest): the energy's measures exceed 1, the
+    # pressure's do not, so the primitive variable (not the conserved one) must decide
+    "p_B": ([Fr(1)] * 4, [2 + 2 * x for x in SHAPE_B]),
+    # both vary: the factor is the smaller of the two
+    "rho_A_p_B": ([1 + 2 * x for x in SHAPE_A], [2 + 5 * x for x in SHAPE_B]),
+}
+
+
+def _expected(name):
+    rho, E = CASES[name]
+    al, xs = [], []
+    for field, scale in ((rho, Fr(1)), ([Fr(2, 5) * e for e in E], Fr(1))):
+        s4, s2 = _sigmas(field)
+        a, x = _alpha_of(scale * s4, scale * s2)
+        al.append(a)
+        xs.append(x)
+    # the velocity (zero) has sigma = 0 on both levels: its factor is 1, its raw value -tau_A tau_S
+    xs.append(-TAU_A * TAU_S)
+    return min(al), max(xs)
+
+
+def test_indicator_cases_are_strictly_between_clamps():
+    for name in CASES:
+        a, _ = _expected(name)
+        assert 0.01 < a < 0.99, (name, a)
+        # every nodal density and pressure is positive (the cubics are monotone, so their
+        # extremes are their end values)
+        rho, E = CASES[name]
+        for f in (rho, E):
+            if any(Fr(x) != Fr(f[0]) for x in f):
+                c = _cubic_from_means(f)
+                assert c[0] > 0 and sum(c) > 0
+    # the energy of case p_B would give another factor than its pressure
+    s4, s2 = _sigmas(CASES["p_B"][1])
+    assert _alpha_of(s4, s2)[0] != _expected("p_B")[0]
+    # the floor matters in the small case: without it the factor would be clamped to 0
+    s4, s2 = _sigmas(CASES["rho_C_small"][0])
+    assert max(s4, s2) < 1 and abs(s4 - s2) / max(s4, s2) > TAU_S + 1 / TAU_A
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("dim", [1, 2])
+def test_indicator_between_clamps(name, dim):
+    rho, E = CASES[name]
+    mesh, u = (_state_1d if dim == 1 else _state_2d_y_invariant)(rho, E)
+    _, info = O.rhs(mesh, W.Params(), u, full=True)
+    a_exp, x_exp = _expected(name)
+    # level 4 (the element) first, then the level-2 sub-elements (alpha = beta = 1, snapped)
+    a = info["alpha"][0]
+    assert abs(a[0] - a_exp) <= 1e-11, (a[0], a_exp)
+    assert abs(info["araw"][0][0] - a_exp) <= 1e-11
+    assert abs(info["xraw"][0][0] - x_exp) <= 1e-11
+    assert np.all(a[1:] == 1.0)
+
+
+# ---------------------------------------------------------------------------
+# HLL flux with Einfeldt's signal speeds
+# ---------------------------------------------------------------------------
+
+def _cons(rho, v, p):
+    return np.array([rho, rho * v, p / (GAMMA - 1) + 0.5 * rho * v * v])
+
+
+def _phys_flux(rho, v, p):
+    E = p / (GAMMA - 1) + 0.5 * rho * v * v
+    return np.array([rho * v, rho * v * v + p, v * (E + p)])
+
+
+def _oracle_interface_flux(left, right, K=4, ne=2):
+    """F* at the interface between two constant states: a 1-D outflow mesh of two
+    elements in FORCE_FV mode; every other face carries f(u) (HLLE(u, u) = f(u),
+    outflow mirrors the state), so the right-hand side of the last left subcell is
+    -(K/dx) (F* - f(u_L))."""
+    mesh = W.Mesh(1, K, [ne], [0.0], [1.0], [W.OUTFLOW])
+    u = np.zeros(mesh.shape())
+    uL, uR = _cons(*left), _cons(*right)
+    half = K * ne // 2
+    for v in range(3):
+        u[v, 0, 0, :half] = uL[v]
+        u[v, 0, 0, half:] = uR[v]
+    d = O.rhs(mesh, W.Params(mode=W.FORCE_FV), u)
+    dx = 1.0 / (K * ne)
+    fL = _phys_flux(*left)
+    return fL - d[:, 0, 0, half - 1] * dx, d, u
+
+
+def test_hlle_sod_states_by_hand():
+    """Sod states (rho, v, p) = (1, 0, 1) | (0.125, 0, 0.1).  Both velocities vanish, so the
+    Roe velocity is 0 and the Roe sound speed is sqrt((gamma - 1) H~) with
+    H~ = (sqrt(rho_L) H_L + sqrt(rho_R) H_R) / (sqrt(rho_L) + sqrt(rho_R)),
+    H_L = (2.5 + 1) / 1 = 3.5, H_R = (0.25 + 0.1) / 0.125 = 2.8.
+    S_L = min(-c_L, -c~) = -sqrt(1.4) (c_L = 1.1832 > c~ = 1.1519),
+    S_R = max(c_R, c~) = c~ (c_R = sqrt(1.12) = 1.0583).
+    F* = (S_R f_L - S_L f_R + S_L S_R (u_R - u_L)) / (S_R - S_L) with f = (0, p, 0)."""
+    sq = math.sqrt(0.125)
+    H = (3.5 + sq * 2.8) / (1.0 + sq)
+    ct = math.sqrt(0.4 * H)
+    SL, SR = -math.sqrt(1.4), ct
+    assert SL < -ct and SR > math.sqrt(1.12)
+    den = SR - SL
+    exp_mass = SL * SR * (0.125 - 1.0) / den
+    exp_mom = (SR * 1.0 - SL * 0.1) / den
+    exp_en = SL * SR * (0.25 - 2.5) / den
+    # decimal values: c~ = 1.1518954, F* = (0.5107137, 0.5439642, 1.3132638)
+    assert abs(ct - 1.1518954) < 1e-7 and abs(exp_mass - 0.5107137) < 1e-7
+    assert abs(exp_mom - 0.5439642) < 1e-7 and abs(exp_en - 1.3132638) < 1e-7
+    F, _, _ = _oracle_interface_flux((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    np.testing.assert_allclose(F, [exp_mass, exp_mom, exp_en], rtol=0, atol=1e-13)
+
+
+def test_hlle_moving_states_by_hand():
+    """(rho, v, p) = (1, 0.75, 1) | (0.125, 0, 0.1): the Roe velocity
+    v~ = 0.75 / (1 + sqrt(0.125)) and enthalpy H~ weight the states by sqrt(rho);
+    c~^2 = (gamma - 1)(H~ - v~^2 / 2).  S_L = min(0.75 - c_L, v~ - c~),
+    S_R = max(c_R, v~ + c~), both picked by hand below."""
+    sq = math.sqrt(0.125)
+    vt = 0.75 / (1.0 + sq)
+    HL = (1.0 / 0.4 + 0.5 * 0.75 ** 2 + 1.0) / 1.0
+    HR = (0.1 / 0.4 + 0.1) / 0.125
+    Ht = (HL + sq * HR) / (1.0 + sq)
+    ct = math.sqrt(0.4 * (Ht - 0.5 * vt * vt))
+    cL, cR = math.sqrt(1.4), math.sqrt(1.12)
+    # which estimates bind (checked, then used)
+    assert vt - ct < 0.75 - cL        # the Roe estimate is the left speed
+    assert vt + ct > cR               # and the right one
+    SL, SR = vt - ct, vt + ct
+    uL, uR = _cons(1.0, 0.75, 1.0), _cons(0.125, 0.0, 0.1)
+    fL, fR = _phys_flux(1.0, 0.75, 1.0), _phys_flux(0.125, 0.0, 0.1)
+    exp = (SR * fL - SL * fR + SL * SR * (uR - uL)) / (SR - SL)
+    assert abs(vt - 0.5540971) < 1e-7
+    F, _, _ = _oracle_interface_flux((1.0, 0.75, 1.0), (0.125, 0.0, 0.1))
+    np.testing.assert_allclose(F, exp, rtol=0, atol=2e-13)
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_hlle_supersonic_upwinding(direction):
+    """Both states moving at Mach > 2 in one direction: every signal speed has that sign,
+    so the flux is the upwind state's physical flux exactly (S_L > 0 gives f(u_L),
+    S_R < 0 gives f(u_R))."""
+    left = (1.0, 3.0 * direction, 1.0)
+    right = (0.5, 2.6 * direction, 0.4)
+    F, _, _ = _oracle_interface_flux(left, right)
+    up = _phys_flux(*(left if direction > 0 else right))
+    np.testing.assert_allclose(F, up, rtol=1e-14, atol=1e-14)
+
+
+def test_hlle_consistency_and_contact():
+    """f*(u, u) = f(u); a contact at rest (equal pressure, v = 0, density jump) keeps the
+    momentum flux at p (the HLL momentum flux is (S_R p - S_L p)/(S_R - S_L) = p) and
+    diffuses mass with S_L S_R (rho_R - rho_L)/(S_R - S_L)."""
+    F, d, _ = _oracle_interface_flux((0.7, 0.3, 0.9), (0.7, 0.3, 0.9))
+    np.testing.assert_allclose(F, _phys_flux(0.7, 0.3, 0.9), rtol=1e-14, atol=1e-14)
+    assert np.abs(d).max() <= 1e-12
+    F, _, _ = _oracle_interface_flux((1.0, 0.0, 1.0), (0.25, 0.0, 1.0))
+    assert abs(F[1] - 1.0) <= 1e-14 and abs(F[2]) <= 1e-14
+    assert F[0] > 0.0
