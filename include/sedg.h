@@ -61,7 +61,7 @@ enum {
 
 enum { SEDG_PERIODIC = 0, SEDG_OUTFLOW = 1 };
 enum { SEDG_GAUSS = 0, SEDG_LGL = 1 };
-enum { SEDG_ADAPTIVE = 0, SEDG_FORCE_DG = 1, SEDG_FORCE_FV = 2, SEDG_EXTERNAL = 3 };
+enum { SEDG_ADAPTIVE = 0, SEDG_FORCE_DG = 1, SEDG_FORCE_FV = 2, SEDG_EXTERNAL = 3, SEDG_RANDOM = 4 };
 
 typedef struct sedg_mesh {
     int dim;            /* 2 or 3 */
@@ -81,7 +81,9 @@ typedef struct sedg_params {
     int top_level;           /* highest DG order used (DGFVn, Sec. 3.5); 0 = K */
     unsigned level_mask;     /* bit log2(n) enables DG level n; 0 = all levels */
     int mode;                /* SEDG_ADAPTIVE, SEDG_FORCE_DG (alpha_top = 1),
-                                SEDG_FORCE_FV (all alpha = 0), SEDG_EXTERNAL (alpha given) */
+                                SEDG_FORCE_FV (all alpha = 0), SEDG_EXTERNAL (alpha given),
+                                SEDG_RANDOM (alpha drawn afresh for every right-hand side) */
+    unsigned long long seed; /* SEDG_RANDOM: seed of the generator */
 } sedg_params;
 
 typedef struct sedg_ctx sedg_ctx;
@@ -101,11 +103,27 @@ int sedg_destroy(sedg_ctx *ctx);
 long sedg_state_len(const sedg_ctx *ctx);
 long sedg_alpha_len(const sedg_ctx *ctx);
 
-/* Replace the parameters of an existing context (same mesh). */
+/* Replace the parameters of an existing context (same mesh).  Restarts the
+ * SEDG_RANDOM draw counter at 0. */
 int sedg_set_params(sedg_ctx *ctx, const sedg_params *params);
+
+/* Copy a host state into the device array u_dev (nvar * DOF doubles, layout above)
+ * and check every mean value: SEDG_ESTATE with *bad_elem (optional) = the smallest
+ * index of an element holding a non-permissible (rho <= 0 or p <= 0) or non-finite
+ * mean value, else SEDG_OK and *bad_elem = -1.  Synchronous (the whole device); the
+ * host array is only read during the call.  Clears the context's state-error flag. */
+int sedg_init_state(sedg_ctx *ctx, double *u_dev, const double *u_host, long *bad_elem);
 
 /* One evaluation of the blended right-hand side d(u)/dt (eq.
  * multilevel-blending-scheme blended by eq. blending-weights).
+ * In SEDG_RANDOM mode (the conservation stress test of Sec. 3.3) every factor of
+ * every level and sub-element is uniform in [0, 1), drawn afresh for each
+ * right-hand side the context evaluates (sedg_rhs, every stage of the step
+ * functions, sedg_diagnose): factor q of element e in draw d is the k-th output of
+ * SplitMix64 (Steele, Lea & Flood 2014) seeded with params.seed, k = (d * nel + e)
+ * * A + q, as a double from its top 53 bits; d counts the draws since sedg_create
+ * or sedg_set_params.  Squeezing parameters are computed on every level, as in
+ * SEDG_EXTERNAL mode.
  *   u         device, state (read only)
  *   dudt      device, output state-shaped array (must not alias u)
  *   alpha_out device, optional (NULL): blending factors used, A per element
@@ -123,10 +141,32 @@ int sedg_max_dt(sedg_ctx *ctx, const double *u, double *dt_dev, void *stream);
 /* Advance u in place by nsteps steps of three-stage SSP-RK (Shu-Osher form).
  *   dt_fixed > 0: that step size; otherwise the CFL step of each step's
  *   initial state, computed on the device.
- *   dt_log_dev: device, optional, receives the nsteps step sizes.
- * The step sequence is captured once into a HIP graph per (u, dt_log, mode)
- * and replayed.  EXTERNAL mode is rejected (SEDG_EINVAL). */
-int sedg_rk_step(sedg_ctx *ctx, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream);
+ *   dt_log_dev: device, optional, receives the nsteps step sizes (fixed or CFL).
+ *   alpha_log_dev: device, optional, receives the blending factors of every stage,
+ *   3 * nsteps arrays of sedg_alpha_len doubles, step-major ([step][stage][...]).
+ * The step sequence is captured once into a HIP graph per (u, dt_log, alpha_log,
+ * fixed step) and replayed.  EXTERNAL mode is rejected (SEDG_EINVAL). */
+int sedg_rk_step(sedg_ctx *ctx, double *u, int nsteps, double dt_fixed, double *dt_log_dev, double *alpha_log_dev,
+                 void *stream);
+
+/* Diagnostics of one right-hand side at u (computed as sedg_rhs computes it, into
+ * dudt, device): the change of bulk of eq. change-of-bulk (Sec. 3.3), read as the
+ * sum over elements of |Omega_q| times the element mean of d(u)/dt, with the same
+ * sum of |d(u)/dt| as its scale; the weighted blending factor of eq. order-estimate
+ * per subcell (alpha_bar: device, optional, state-shaped for one variable) and its
+ * minimum, mean and maximum; the elements by the lowest order carrying weight
+ * anywhere in them (index 0: FV, 1: O(2), 2: O(4), 3: O(8)); the sub-elements
+ * squeezed (beta < 1) and rejected (beta < beta_L) on the levels evaluated; and the
+ * interface-safety fallbacks taken (an FV flux input replaced by the subcell mean,
+ * or a DG candidate handing its weight to FV, counted per face subcell).
+ * Synchronises the stream; *out is host memory.  Not in SEDG_EXTERNAL mode. */
+typedef struct sedg_diag {
+    double bulk_change[5], bulk_abs[5];
+    double alpha_bar_min, alpha_bar_mean, alpha_bar_max;
+    long elems_by_lowest_order[4];
+    long squeezed, beta_rejected, fallbacks;
+} sedg_diag;
+int sedg_diagnose(sedg_ctx *ctx, const double *u, double *dudt, double *alpha_bar, sedg_diag *out, void *stream);
 
 /* Synchronise the context's last stream and report device-side state errors:
  * SEDG_ESTATE with *bad_elem = index of an element holding a non-permissible
@@ -180,6 +220,14 @@ long sedg_tape_len(const sedg_ctx *ctx);
  * arithmetic is that of sedg_rk_step, so steps replayed from a checkpoint with the
  * logged step sizes reproduce the original steps bit for bit. */
 int sedg_rk_step_tape(sedg_ctx *ctx, double *u, int nsteps, const double *dt_dev, double *tapes, void *stream);
+
+/* The frozen forward map over nsteps SSP-RK3 steps, u in place: step j with step size
+ * dt_dev[j] and, in each stage k, the blending factors and squeezing parameters held at
+ * factors + j * 6 * A_len + k * A_len and + (3 + k) * A_len (A_len = sedg_alpha_len:
+ * exactly the factor block of a step tape, [alpha x 3 | beta x 3]); every other step
+ * of the right-hand side as in sedg_rhs_frozen.  The map the adjoint steps transpose. */
+int sedg_rk_step_frozen(sedg_ctx *ctx, double *u, int nsteps, const double *dt_dev, const double *factors,
+                        void *stream);
 
 /* Transposed SSP-RK3 steps: on entry lam holds dJ/du after the nsteps steps recorded in
  * tapes (step j at tapes + j * sedg_tape_len, step size dt_dev[j]); on return dJ/du

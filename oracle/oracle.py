@@ -35,7 +35,8 @@ class _Mesh(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("tau_A", ctypes.c_double), ("tau_S", ctypes.c_double), ("alpha_H", ctypes.c_double),
                 ("alpha_L", ctypes.c_double), ("beta_L", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int)]
+                ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong), ("draw", ctypes.c_longlong)]
 
 
 _lib = None
@@ -57,6 +58,8 @@ def lib():
         _lib.or_tables.restype = ctypes.c_int
         _lib.or_alpha_len.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params)]
         _lib.or_num_threads.restype = ctypes.c_int
+        _lib.or_alpha_bar.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), dp, dp]
+        _lib.or_alpha_bar.restype = ctypes.c_int
     return _lib
 
 
@@ -70,10 +73,12 @@ def _mesh(m) -> _Mesh:
     return s
 
 
-def _params(p) -> _Params:
+def _params(p, draw: int = 0) -> _Params:
     s = _Params()
     s.tau_A, s.tau_S, s.alpha_H, s.alpha_L, s.beta_L, s.cfl = p.tau_A, p.tau_S, p.alpha_H, p.alpha_L, p.beta_L, p.cfl
     s.top_level, s.level_mask, s.mode = p.top_level, p.level_mask, p.mode
+    s.seed = int(getattr(p, "seed", 0))
+    s.draw = int(draw)
     return s
 
 
@@ -107,9 +112,10 @@ def alpha_len(mesh, params) -> int:
     return lib().or_alpha_len(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)))
 
 
-def rhs(mesh, params, u, alpha_in=None, full: bool = False):
+def rhs(mesh, params, u, alpha_in=None, full: bool = False, draw: int = 0):
     """One right-hand side.  Returns dudt, or (dudt, info) with full=True where info
-    holds alpha, beta, xraw, araw (each nel x A) and the fallback count."""
+    holds alpha, beta, xraw, araw (each nel x A) and the fallback count.  draw: index
+    of the factor draw in RANDOM mode."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     A = alpha_len(mesh, params)
     nel = mesh.nel
@@ -120,7 +126,7 @@ def rhs(mesh, params, u, alpha_in=None, full: bool = False):
     ar = np.zeros((nel, A))
     ain = None if alpha_in is None else np.ascontiguousarray(alpha_in, dtype=np.float64).reshape(nel, A)
     nfb = ctypes.c_long(0)
-    rc = lib().or_rhs(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(u), _ptr(dudt),
+    rc = lib().or_rhs(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params, draw)), _ptr(u), _ptr(dudt),
                       _ptr(al), _ptr(be), _ptr(ain), _ptr(xr), _ptr(ar), ctypes.byref(nfb))
     if rc != 0:
         raise OracleError("or_rhs failed: %d" % rc)
@@ -137,14 +143,27 @@ def max_dt(mesh, params, u) -> float:
     return dt
 
 
-def rk3(mesh, params, u, nsteps: int, dt_fixed: float = 0.0):
-    """nsteps SSP-RK3 steps; returns (u_new, dt_log)."""
+def rk3(mesh, params, u, nsteps: int, dt_fixed: float = 0.0, draw: int = 0):
+    """nsteps SSP-RK3 steps; returns (u_new, dt_log).  In RANDOM mode the right-hand
+    sides use draws draw, draw + 1, ... (three per step)."""
     u = np.array(u, dtype=np.float64, order="C", copy=True)
     dts = np.zeros(max(nsteps, 1))
-    rc = lib().or_rk3(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(u), nsteps, dt_fixed, _ptr(dts))
+    rc = lib().or_rk3(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params, draw)), _ptr(u), nsteps, dt_fixed,
+                      _ptr(dts))
     if rc != 0:
         raise OracleError("or_rk3 failed: %d" % rc)
     return u, dts[:nsteps]
+
+
+def alpha_bar(mesh, params, alpha):
+    """Weighted blending factor of every subcell (eq. order-estimate), shaped (gz, gy, gx)."""
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    out = np.zeros(mesh.dof)
+    rc = lib().or_alpha_bar(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(al), _ptr(out))
+    if rc != 0:
+        raise OracleError("or_alpha_bar failed: %d" % rc)
+    g = mesh.grid
+    return out.reshape(g[2], g[1], g[0])
 
 
 def num_threads() -> int:

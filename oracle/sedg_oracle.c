@@ -15,6 +15,7 @@
 #include "sedg_oracle.h"
 
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -428,6 +429,23 @@ int or_alpha_len(const or_mesh *m, const or_params *p)
     return c.A;
 }
 
+/* Random blending factors of the conservation stress test (Sec. 3.3).  The generator
+   is SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+   generators", 2014): its k-th output for seed s is the output function
+   z -> (z ^ z>>31) after z = (z ^ z>>30) * 0xbf58476d1ce4e5b9,
+   z = (z ^ z>>27) * 0x94d049bb133111eb applied to s + (k+1) * 0x9e3779b97f4a7c15;
+   the factor is its top 53 bits times 2^-53.  Factor q of element e in draw d uses
+   k = (d * nel + e) * A + q. */
+static double random_factor(const ctx_t *c, long long draw, int e, int q)
+{
+    uint64_t k = (uint64_t)((draw * c->nel + e) * (long long)c->A + q);
+    uint64_t z = (uint64_t)c->p.seed + (k + 1u) * UINT64_C(0x9e3779b97f4a7c15);
+    z = (z ^ (z >> 30)) * UINT64_C(0xbf58476d1ce4e5b9);
+    z = (z ^ (z >> 27)) * UINT64_C(0x94d049bb133111eb);
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) / 9007199254740992.0;
+}
+
 static int level_enabled(const ctx_t *c, int li)
 {
     if (c->p.level_mask == 0) return 1;
@@ -678,6 +696,12 @@ static void analyse_element(const ctx_t *c, const double *u, int e, double *alph
     if (c->p.mode == OR_EXTERNAL) {
         for (int li = 0; li < c->nlev; li++) squeeze_level(c, ub, li, beta);
         for (int q = 0; q < c->A; q++) alpha[q] = alpha_in[q];
+        return;
+    }
+    if (c->p.mode == OR_RANDOM) {
+        /* every factor drawn, squeezing parameters on every level (as with given factors) */
+        for (int li = 0; li < c->nlev; li++) squeeze_level(c, ub, li, beta);
+        for (int q = 0; q < c->A; q++) alpha[q] = random_factor(c, c->p.draw, e, q);
         return;
     }
     if (c->p.mode == OR_FORCE_FV) return;
@@ -1252,22 +1276,57 @@ int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps, double d
     if (c->p.mode == OR_EXTERNAL || c->p.mode == OR_FROZEN) { free(c); return OR_EINVAL; }
     size_t n = (size_t)c->nv * c->dof;
     double *L = malloc(sizeof(double) * n), *u1 = malloc(sizeof(double) * n), *u2 = malloc(sizeof(double) * n);
+    /* in OR_RANDOM mode every right-hand side draws new factors: draw, draw + 1, ... */
     for (int st = 0; st < nsteps && rc == OR_OK; st++) {
         double dt = dt_fixed > 0.0 ? dt_fixed : max_dt_ctx(c, u);
         if (!(dt > 0.0)) { rc = OR_ESTATE; break; }
         if (dt_log) dt_log[st] = dt;
         rc = rhs_ctx(c, u, L, NULL, NULL, NULL, NULL, NULL, NULL);
+        c->p.draw++;
         if (rc) break;
         for (size_t i = 0; i < n; i++) u1[i] = u[i] + dt * L[i];
         rc = rhs_ctx(c, u1, L, NULL, NULL, NULL, NULL, NULL, NULL);
+        c->p.draw++;
         if (rc) break;
         for (size_t i = 0; i < n; i++) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * L[i]);
         rc = rhs_ctx(c, u2, L, NULL, NULL, NULL, NULL, NULL, NULL);
+        c->p.draw++;
         if (rc) break;
         for (size_t i = 0; i < n; i++) u[i] = (1.0 / 3.0) * u[i] + (2.0 / 3.0) * (u2[i] + dt * L[i]);
     }
     free(L); free(u1); free(u2); free(c);
     return rc;
+}
+
+/* Weighted blending factor (eq. order-estimate), in the nested form the paper writes:
+   starting from the FV order 1, each level n from the lowest up contributes
+   abar <- abar (1 - alpha^(n)) + n alpha^(n). */
+int or_alpha_bar(const or_mesh *m, const or_params *p, const double *alpha, double *abar)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return OR_EINVAL;
+    int rc = make_ctx(m, p, c);
+    if (rc) { free(c); return rc; }
+    int K = c->K, ky = c->dim > 1 ? K : 1, kz = c->dim > 2 ? K : 1;
+    for (int e = 0; e < c->nel; e++) {
+        int e3[3];
+        elem_coords(c, e, e3);
+        const double *al = alpha + (long)e * c->A;
+        for (int k = 0; k < kz; k++)
+            for (int j = 0; j < ky; j++)
+                for (int i = 0; i < K; i++) {
+                    double ab = 1.0;
+                    for (int li = c->nlev - 1; li >= 0; li--) {
+                        int n = c->lev_n[li], ns = K / n;
+                        int s = i / n + ns * ((c->dim > 1 ? j / n : 0) + ns * (c->dim > 2 ? k / n : 0));
+                        double a = al[c->lev_off[li] + s];
+                        ab = ab * (1.0 - a) + n * a;
+                    }
+                    abar[gidx(c, e3, i, j, k)] = ab;
+                }
+    }
+    free(c);
+    return OR_OK;
 }
 
 int or_num_threads(void)

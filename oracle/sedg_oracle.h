@@ -30,7 +30,7 @@ extern "C" {
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ESTATE = -4 };
 enum { OR_PERIODIC = 0, OR_OUTFLOW = 1 };
 enum { OR_GAUSS = 0, OR_LGL = 1 };
-enum { OR_ADAPTIVE = 0, OR_FORCE_DG = 1, OR_FORCE_FV = 2, OR_EXTERNAL = 3, OR_FROZEN = 4 };
+enum { OR_ADAPTIVE = 0, OR_FORCE_DG = 1, OR_FORCE_FV = 2, OR_EXTERNAL = 3, OR_RANDOM = 4, OR_FROZEN = 9 };
 
 typedef struct or_mesh {
     int dim;            /* 1, 2 or 3 */
@@ -49,7 +49,9 @@ typedef struct or_params {
     double cfl;
     int top_level;              /* highest DG order used (DGFVn); <= K */
     unsigned level_mask;        /* bit log2(n) enables DG level n; 0 = all */
-    int mode;                   /* OR_ADAPTIVE, OR_FORCE_DG, OR_FORCE_FV, OR_EXTERNAL */
+    int mode;                   /* OR_ADAPTIVE, OR_FORCE_DG, OR_FORCE_FV, OR_EXTERNAL, OR_RANDOM */
+    unsigned long long seed;    /* OR_RANDOM: generator seed */
+    long long draw;             /* OR_RANDOM: index of the (first) draw of factors */
 } or_params;
 
 /* Number of blending factors per element. */
@@ -94,6 +96,10 @@ int or_rhs_frozen(const or_mesh *m, const or_params *p, const double *u, const d
  * branches taken at u. */
 int or_adjoint_rhs(const or_mesh *m, const or_params *p, const double *u, const double *alpha,
                    const double *beta, const double *lam, double *lam_out);
+
+/* Weighted blending factor of every subcell (eq. order-estimate) from the blending
+ * factors alpha (nel * A): abar[dof] in the state layout of one variable. */
+int or_alpha_bar(const or_mesh *m, const or_params *p, const double *alpha, double *abar);
 
 /* Number of OpenMP threads the oracle runs with. */
 int or_num_threads(void);

@@ -13,7 +13,8 @@ then walks the segment backwards with the transposed RK3 step.  Peak extra memor
 `every` tapes.
 
 Every arithmetic step runs in the library (sedg_rk_step, sedg_rk_step_tape,
-sedg_adjoint_rk_step); this module only sequences the calls.
+sedg_adjoint_rk_step, and sedg_rk_step_frozen for the frozen forward map); this
+module only sequences the calls.
 """
 from __future__ import annotations
 
@@ -79,31 +80,23 @@ def dt_log_of(u_out: torch.Tensor) -> torch.Tensor:
     return u_out.grad_fn.dt_log
 
 
-def record_frozen(solver: sedg.Solver, u0: torch.Tensor, dt_log: torch.Tensor):
+def record_frozen(solver: sedg.Solver, u0: torch.Tensor, dt_log: torch.Tensor) -> torch.Tensor:
     """Replay the evolution from u0 with the logged step sizes and return, per step,
-    the (3, 2, alpha_len) blending factors and squeezing parameters of its stages."""
+    the factor block of its tape, [alpha x 3 | beta x 3] (nsteps x 6 x alpha_len)."""
     ns, na = solver.state_len, solver.alpha_len
     u = u0.detach().contiguous().clone()
     tape = torch.empty(solver.tape_len, dtype=torch.float64, device=u.device)
-    out = []
+    out = torch.empty((dt_log.numel(), 6, na), dtype=torch.float64, device=u.device)
     for j in range(dt_log.numel()):
         solver.rk_step_tape(u, dt_log[j:j + 1], tape)
-        out.append(tape[3 * ns:3 * ns + 6 * na].view(2, 3, na).transpose(0, 1).clone(memory_format=torch.contiguous_format))
+        out[j].copy_(tape[3 * ns:3 * ns + 6 * na].view(6, na))
     solver.check()
     return out
 
 
-def frozen_evolve(solver: sedg.Solver, u0: torch.Tensor, frozen, dt_log: torch.Tensor) -> torch.Tensor:
-    """The frozen forward map: SSP-RK3 with every stage's factors held at `frozen`
-    (from record_frozen) and the logged step sizes; no autograd."""
+def frozen_evolve(solver: sedg.Solver, u0: torch.Tensor, frozen: torch.Tensor, dt_log: torch.Tensor) -> torch.Tensor:
+    """The frozen forward map (sedg_rk_step_frozen): SSP-RK3 with every stage's factors
+    held at `frozen` (from record_frozen) and the logged step sizes; no autograd."""
     u = u0.detach().contiguous().clone()
-    d = torch.empty_like(u)
-    dts = [float(v) for v in dt_log.cpu()]
-    for fz, dt in zip(frozen, dts):
-        solver.rhs_frozen(u, fz[0, 0], fz[0, 1], d)
-        u1 = u + dt * d
-        solver.rhs_frozen(u1, fz[1, 0], fz[1, 1], d)
-        u2 = 0.75 * u + 0.25 * (u1 + dt * d)
-        solver.rhs_frozen(u2, fz[2, 0], fz[2, 1], d)
-        u = (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + dt * d)
+    solver.rk_step_frozen(u, dt_log.contiguous(), frozen.contiguous())
     return u

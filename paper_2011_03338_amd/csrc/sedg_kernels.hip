@@ -95,6 +95,10 @@ struct KArgs {
     unsigned level_mask;
     int stage;              // 0: write dudt; 1, 2, 3: SSP-RK3 stage
     double gamma, tau_A, tau_S, alpha_H, alpha_L, beta_L;
+    // RANDOM mode: generator seed and the device counter of right-hand-side draws
+    unsigned long long seed;
+    const long long *draw;
+    int *fbc;               // interface-safety fallback counter (diagnostics; nullable)
 };
 
 // Per-axis mesh data by run-time axis.  A kernel may hold its arguments in a local
@@ -113,6 +117,19 @@ __device__ __forceinline__ int arg_bc(const KArgs &P, int a)
 __device__ __forceinline__ double arg_dx(const KArgs &P, int a)
 {
     return (a == 0 ? 1.0 : 0.0) * P.dx[0] + (a == 1 ? 1.0 : 0.0) * P.dx[1] + (a == 2 ? 1.0 : 0.0) * P.dx[2];
+}
+
+// Random blending factors (stress test of Sec. 3.3): the k-th output of SplitMix64
+// (Steele, Lea & Flood, OOPSLA 2014) seeded with `seed`, i.e. its output function
+// applied to seed + (k + 1) * 0x9e3779b97f4a7c15, mapped to [0, 1) by its top 53 bits.
+// k = (draw * nel + element) * A + slot enumerates every factor of every draw.
+__device__ __forceinline__ double splitmix_u01(unsigned long long seed, unsigned long long k)
+{
+    unsigned long long z = seed + (k + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-53;
 }
 
 // ---------------------------------------------------------------------------
@@ -759,8 +776,14 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
     }
     __syncthreads();
 
+    const bool given = P.mode == SEDG_EXTERNAL || P.mode == SEDG_RANDOM;   // factors not from the indicator
+    const long long draw = (P.mode == SEDG_RANDOM) ? *P.draw : 0;
     for (int q = c; q < LV::A; q += KD) {
-        S.al[le][q] = (P.mode == SEDG_EXTERNAL) ? P.alpha_in[(long long)ee * LV::A + q] : 0.0;
+        double a0 = 0.0;
+        if (P.mode == SEDG_EXTERNAL) a0 = P.alpha_in[(long long)ee * LV::A + q];
+        else if (P.mode == SEDG_RANDOM)
+            a0 = splitmix_u01(P.seed, (unsigned long long)((draw * P.nel + ee) * LV::A + q));
+        S.al[le][q] = a0;
         S.be[le][q] = 1.0;
         for (int v = 0; v < NV; ++v) S.mean[le][v][q] = 0.0;
     }
@@ -773,7 +796,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         const int n = LV::n(li), ln = ilog2i(n);
         const bool enabled = (P.level_mask == 0) || ((P.level_mask >> ln) & 1u);
         bool visit;
-        if (P.mode == SEDG_EXTERNAL) visit = true;
+        if (given) visit = true;
         else if (P.mode == SEDG_FORCE_DG) visit = (li == 0);
         else if (P.mode == SEDG_FORCE_FV) visit = false;
         else visit = enabled && !broke;
@@ -856,7 +879,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (leader) S.be[le][LV::off(li) + sub] = b;
         // children reconstruction = next level's reconstruction
         const bool need_next = (li + 1 < LV::NLEV) &&
-                               (P.mode == SEDG_EXTERNAL || (P.mode == SEDG_ADAPTIVE && n >= 4));
+                               (given || (P.mode == SEDG_ADAPTIVE && n >= 4));
         if (block_or<EPB * KD>(visit && need_next)) {
             recon_level<DIM, K, TOP, EPB>(S, le, c, P.tabs[li + 1], n / 2, S.r[le][(li + 1) & 1]);
             have_rec = li + 1;
@@ -1243,6 +1266,7 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
                     __syncthreads();
                 }
             }
+        if (P.fbc && need && !okf) atomicAdd(P.fbc, 1);
         double fnod[NV];
         if (need && okf) hlle<DIM>(nl, nr, fa, gam, fnod);
         else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
@@ -1276,6 +1300,7 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
             double aL[NV], aR[NV], fs[NV];
             for (int v = 0; v < NV; ++v) { aL[v] = uL[v]; aR[v] = uR[v]; }
             if (!flux_admissible<DIM>(aL, gam, srho, sE)) {
+                if (P.fbc) atomicAdd(P.fbc, 1);
                 if (mLe < 0 && uown) for (int v = 0; v < NV; ++v) aL[v] = uown[v * KD + mLc];
                 else {
                     int n3[3];
@@ -1285,6 +1310,7 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
                 }
             }
             if (!flux_admissible<DIM>(aR, gam, srho, sE)) {
+                if (P.fbc) atomicAdd(P.fbc, 1);
                 if (mRe < 0 && uown) for (int v = 0; v < NV; ++v) aR[v] = uown[v * KD + mRc];
                 else {
                     int n3[3];
@@ -2450,12 +2476,132 @@ __global__ void __launch_bounds__(LAM_SLOTS) finalize_dt_kernel(double *lam_part
     if (threadIdx.x == 0) {
         double d = num / s[0];
         dt[0] = d;
-        if (dt_log) {
-            int k = step_ctr[0];
-            dt_log[k] = d;
-            step_ctr[0] = k + 1;
-        }
+        if (dt_log) dt_log[step_ctr[0]] = d;
     }
+}
+
+// RANDOM mode: the next right-hand side draws new factors
+__global__ void draw_advance_kernel(long long *draw)
+{
+    if (threadIdx.x == 0) draw[0] += 1;
+}
+
+// step-size log of a fixed-step run: dt_log[step] = dt
+__global__ void log_dt_kernel(const double *dt, double *dt_log, const int *step_ctr)
+{
+    if (threadIdx.x == 0) dt_log[step_ctr[0]] = dt[0];
+}
+
+// factor log: the factors of stage `stage` of step step_ctr go to
+// log[(3 * step + stage) * n ...]
+__global__ void log_alpha_kernel(const double *alpha, double *log, const int *step_ctr, int stage, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) log[(3LL * step_ctr[0] + stage) * n + i] = alpha[i];
+}
+
+// state check of sedg_init_state: the smallest element index holding a mean value that
+// is not finite or not permissible
+template <int DIM>
+__global__ void check_state_kernel(const double *u, long long dof, int G0, int G1, int K, int ne0, int ne1, int *err,
+                                   double gam)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dof) return;
+    constexpr int NV = DIM + 2;
+    double ub[NV];
+    bool fin = true;
+    for (int v = 0; v < NV; ++v) {
+        ub[v] = u[v * dof + i];
+        fin = fin && isfinite(ub[v]);
+    }
+    if (fin && permissible<DIM>(ub, gam)) return;
+    const long long gx = i % G0, r = i / G0, gy = r % G1, gz = r / G1;
+    const int e = (int)(gx / K + (long long)ne0 * (gy / K + (long long)ne1 * (gz / K)));
+    atomicMin(err, e);
+}
+
+// Diagnostics of one right-hand side, one thread per element: the element's share of
+// the change of bulk (eq. change-of-bulk, with |Omega_q| as a weight) and of its
+// absolute value, the weighted blending factor of every subcell (eq. order-estimate,
+// its nested form: start at 1 (FV) and take levels from the lowest up,
+// abar = abar (1 - alpha_n) + n alpha_n), the lowest order carrying weight in the
+// element, and its squeezed and rejected sub-elements.  Record per element:
+// [bulk x NV | |bulk| x NV | abar min, sum, max | lowest order | squeezed | rejected].
+struct DiagGeo {
+    int dim, K, nv, nlev, A;
+    int lev_n[MAXLEV], lev_off[MAXLEV];
+    int ne[3];
+    int G[3];
+    long long dof;
+    int nel;
+    double vol;            // |Omega_q| / K^dim: the weight of one subcell mean
+    double beta_L;
+};
+
+__global__ void diag_kernel(DiagGeo D, const double *dudt, const double *alpha, const double *beta, double *abar_out,
+                            double *rec)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D.nel) return;
+    const int R = 2 * D.nv + 6;
+    double *r = rec + (long long)e * R;
+    const int ex = e % D.ne[0], ey = (e / D.ne[0]) % D.ne[1], ez = e / (D.ne[0] * D.ne[1]);
+    const int ky = D.dim > 1 ? D.K : 1, kz = D.dim > 2 ? D.K : 1;
+    double bulk[5] = {0, 0, 0, 0, 0}, babs[5] = {0, 0, 0, 0, 0};
+    double amin = 1e300, asum = 0.0, amax = -1e300;
+    bool fv = false;
+    bool lvl[MAXLEV] = {false, false, false};
+    const double *al = alpha + (long long)e * D.A;
+    for (int k = 0; k < kz; ++k)
+        for (int j = 0; j < ky; ++j)
+            for (int i = 0; i < D.K; ++i) {
+                const long long g = (long long)ex * D.K + i +
+                                    (long long)D.G[0] * (((long long)ey * D.K + j) + (long long)D.G[1] * ((long long)ez * D.K + k));
+                for (int v = 0; v < D.nv; ++v) {
+                    const double x = dudt[v * D.dof + g];
+                    bulk[v] += D.vol * x;
+                    babs[v] += D.vol * fabs(x);
+                }
+                double a[MAXLEV], prod = 1.0;
+                for (int li = 0; li < D.nlev; ++li) {
+                    const int n = D.lev_n[li], ns = D.K / n;
+                    const int sx = i / n, sy = D.dim > 1 ? j / n : 0, sz = D.dim > 2 ? k / n : 0;
+                    a[li] = al[D.lev_off[li] + sx + ns * (sy + ns * sz)];
+                    if (a[li] * prod != 0.0) lvl[li] = true;
+                    prod *= 1.0 - a[li];
+                }
+                if (prod != 0.0) fv = true;
+                double ab = 1.0;
+                for (int li = D.nlev - 1; li >= 0; --li) ab = ab * (1.0 - a[li]) + D.lev_n[li] * a[li];
+                amin = fmin(amin, ab);
+                amax = fmax(amax, ab);
+                asum += ab;
+                if (abar_out) abar_out[g] = ab;
+            }
+    int low = 0;
+    if (fv) low = 1;
+    else
+        for (int li = 0; li < D.nlev; ++li)
+            if (lvl[li]) low = D.lev_n[li];
+    int sq = 0, rej = 0;
+    for (int q = 0; q < D.A; ++q) {
+        const double b = beta[(long long)e * D.A + q];
+        sq += b < 1.0 ? 1 : 0;
+        rej += b < D.beta_L ? 1 : 0;
+    }
+    for (int v = 0; v < D.nv; ++v) { r[v] = bulk[v]; r[D.nv + v] = babs[v]; }
+    r[2 * D.nv] = amin;
+    r[2 * D.nv + 1] = asum;
+    r[2 * D.nv + 2] = amax;
+    r[2 * D.nv + 3] = low;
+    r[2 * D.nv + 4] = sq;
+    r[2 * D.nv + 5] = rej;
+}
+
+__global__ void set_int_kernel(int *x, int v)
+{
+    if (threadIdx.x == 0) x[0] = v;
 }
 
 __global__ void set_scalars_kernel(double *dt, double val, int *step_ctr)
@@ -2484,9 +2630,12 @@ struct sedg_ctx {
     double *d_gfb, *d_l1, *d_l2, *d_acc;   // adjoint (allocated on first use)
     double *d_gsb, *d_gdb;
     int *d_err, *d_ctr;
+    long long *d_draw;                     // RANDOM mode: right-hand sides drawn so far
+    int *d_fbc;                            // diagnostics: interface-safety fallback counter
+    double *d_diag;                        // diagnostics: per-element records (first use)
     int nblocks;
     hipStream_t last;
-    std::map<std::tuple<double *, double *, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<double *, double *, double *, int>, hipGraphExec_t> graphs;
     // event timing (benchmark mode)
     bool prof;
     std::vector<hipEvent_t> pool;
@@ -2625,7 +2774,15 @@ KArgs base_args(const sedg_ctx *C)
     P.alpha_H = C->params.alpha_H;
     P.alpha_L = C->params.alpha_L;
     P.beta_L = C->params.beta_L;
+    P.seed = C->params.seed;
+    P.draw = C->d_draw;
     return P;
+}
+
+// after an analysis in RANDOM mode, the next one draws new factors
+void advance_draw(const sedg_ctx *C, hipStream_t s)
+{
+    if (C->params.mode == SEDG_RANDOM) hipLaunchKernelGGL(draw_advance_kernel, dim3(1), dim3(64), 0, s, C->d_draw);
 }
 
 double cfl_numerator(const sedg_ctx *C)
@@ -2640,8 +2797,9 @@ int set_levels(sedg_ctx *C, const sedg_params *p)
     int K = C->mesh.K;
     int top = p->top_level > 0 ? p->top_level : K;
     if (top < 2 || top > K || (top & (top - 1))) return SEDG_EINVAL;
-    if (p->mode < 0 || p->mode > 3) return SEDG_EINVAL;
+    if (p->mode < 0 || p->mode > SEDG_RANDOM) return SEDG_EINVAL;
     C->params = *p;
+    if (hipMemset(C->d_draw, 0, sizeof(long long)) != hipSuccess) return SEDG_EHIP;
     C->nlev = 0;
     int off = 0;
     for (int n = top; n >= 2; n /= 2) {
@@ -2733,6 +2891,8 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     ok = ok && hipMalloc(&C->d_u2, sizeof(double) * nst) == hipSuccess;
     ok = ok && hipMalloc(&C->d_err, sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc(&C->d_ctr, sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_draw, sizeof(long long)) == hipSuccess;
+    ok = ok && hipMalloc(&C->d_fbc, sizeof(int)) == hipSuccess;
     if (!ok) { sedg_destroy(C); return SEDG_ENOMEM; }
     int big = INT_MAX;
     if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) { sedg_destroy(C); return SEDG_EHIP; }
@@ -2753,7 +2913,8 @@ int sedg_destroy(sedg_ctx *C)
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
     void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr,
-                    C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_gsb, C->d_gdb, C->d_l1, C->d_l2, C->d_acc};
+                    C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_gsb, C->d_gdb, C->d_l1, C->d_l2, C->d_acc,
+                    C->d_draw, C->d_fbc, C->d_diag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
@@ -2782,6 +2943,7 @@ int sedg_rhs(sedg_ctx *C, const double *u, double *dudt, double *alpha_out, doub
     P.alpha_in = alpha_in;
     P.stage = 0;
     launch_analyse_any(C, P, s);
+    advance_draw(C, s);
     launch_residual_any(C, P, s);
     size_t na = sizeof(double) * (size_t)C->A * C->nel;
     if (alpha_out && hipMemcpyAsync(alpha_out, C->d_alpha, na, hipMemcpyDeviceToDevice, s) != hipSuccess) return SEDG_EHIP;
@@ -2837,21 +2999,31 @@ static void timed(sedg_ctx *C, int kind, hipStream_t s, F f)
     C->prev = b;
 }
 
-static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log, hipStream_t s)
+static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log, double *alpha_log, hipStream_t s)
 {
     KArgs P = base_args(C);
     P.dt = C->d_dt;
+    const long long na = (long long)C->A * C->nel;
+    auto log_alpha = [&](int stage) {
+        if (alpha_log)
+            hipLaunchKernelGGL(log_alpha_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, C->d_alpha,
+                               alpha_log, C->d_ctr, stage, na);
+    };
     // stage 1: u1 = u + dt L(u)
     P.u = u;
     P.out = C->d_u1;
     P.stage = 1;
     P.lam_part = dt_fixed > 0.0 ? nullptr : C->d_lam;
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+    advance_draw(C, s);
+    log_alpha(0);
     if (!(dt_fixed > 0.0))
         timed(C, 2, s, [&] {
             hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
                                cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
         });
+    else if (dt_log)
+        hipLaunchKernelGGL(log_dt_kernel, dim3(1), dim3(64), 0, s, (const double *)C->d_dt, dt_log, (const int *)C->d_ctr);
     timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
     timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
     // stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1))
@@ -2861,6 +3033,8 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     P.out = C->d_u2;
     P.stage = 2;
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+    advance_draw(C, s);
+    log_alpha(1);
     timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
     timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
     // stage 3: u = 1/3 u + 2/3 (u2 + dt L(u2))
@@ -2869,13 +3043,17 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     P.out = u;
     P.stage = 3;
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+    advance_draw(C, s);
+    log_alpha(2);
     timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
     timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
+    if (dt_log || alpha_log) hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, s, C->d_ctr);
 }
 
 extern "C" {
 
-int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream)
+int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt_log_dev, double *alpha_log_dev,
+                 void *stream)
 {
     if (!C || !u || nsteps < 0) return SEDG_EINVAL;
     if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
@@ -2885,11 +3063,11 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, C->d_dt, dt_fixed > 0.0 ? dt_fixed : 0.0, C->d_ctr);
     if (C->prof) {
         C->prev = nullptr;
-        for (int st = 0; st < nsteps; ++st) enqueue_step(C, u, dt_fixed, dt_log_dev, s);
+        for (int st = 0; st < nsteps; ++st) enqueue_step(C, u, dt_fixed, dt_log_dev, alpha_log_dev, s);
         C->last = s;
         return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
     }
-    auto key = std::make_tuple(u, dt_log_dev, dt_fixed > 0.0 ? 1 : 0);
+    auto key = std::make_tuple(u, dt_log_dev, alpha_log_dev, dt_fixed > 0.0 ? 1 : 0);
     hipGraphExec_t exec = nullptr;
     auto it = C->graphs.find(key);
     if (it != C->graphs.end()) {
@@ -2905,7 +3083,7 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SEDG_EHIP;
         hipGraph_t graph;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
-        enqueue_step(C, u, dt_fixed, dt_log_dev, cs);
+        enqueue_step(C, u, dt_fixed, dt_log_dev, alpha_log_dev, cs);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -2955,6 +3133,122 @@ int sedg_check(sedg_ctx *C, long *bad_elem)
     int big = INT_MAX;
     if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
     return SEDG_ESTATE;
+}
+
+int sedg_init_state(sedg_ctx *C, double *u_dev, const double *u_host, long *bad_elem)
+{
+    if (!C || !u_dev || !u_host) return SEDG_EINVAL;
+    if (bad_elem) *bad_elem = -1;
+    const size_t n = sizeof(double) * (size_t)C->nv * C->dof;
+    if (hipDeviceSynchronize() != hipSuccess) return SEDG_EHIP;
+    if (hipMemcpy(u_dev, u_host, n, hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    int big = INT_MAX, h = INT_MAX;
+    if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    const unsigned nb = (unsigned)((C->dof + 255) / 256);
+    if (C->mesh.dim == 2)
+        hipLaunchKernelGGL(check_state_kernel<2>, dim3(nb), dim3(256), 0, 0, (const double *)u_dev, C->dof, C->G[0],
+                           C->G[1], C->mesh.K, C->mesh.nelem[0], C->mesh.nelem[1], C->d_err, C->mesh.gamma);
+    else
+        hipLaunchKernelGGL(check_state_kernel<3>, dim3(nb), dim3(256), 0, 0, (const double *)u_dev, C->dof, C->G[0],
+                           C->G[1], C->mesh.K, C->mesh.nelem[0], C->mesh.nelem[1], C->d_err, C->mesh.gamma);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SEDG_EHIP;
+    if (hipMemcpy(&h, C->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SEDG_EHIP;
+    if (h == INT_MAX) return SEDG_OK;
+    if (bad_elem) *bad_elem = h;
+    if (hipMemcpy(C->d_err, &big, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    return SEDG_ESTATE;
+}
+
+int sedg_diagnose(sedg_ctx *C, const double *u, double *dudt, double *alpha_bar, sedg_diag *out, void *stream)
+{
+    if (!C || !u || !dudt || !out || u == dudt) return SEDG_EINVAL;
+    if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
+    const int R = 2 * C->nv + 6;
+    if (!C->d_diag && hipMalloc(&C->d_diag, sizeof(double) * (size_t)R * C->nel) != hipSuccess) {
+        C->d_diag = nullptr;
+        return SEDG_ENOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    KArgs P = base_args(C);
+    P.u = u;
+    P.out = dudt;
+    P.stage = 0;
+    P.fbc = C->d_fbc;
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, C->d_fbc, 0);
+    launch_analyse_any(C, P, s);
+    advance_draw(C, s);
+    launch_residual_any(C, P, s);
+    DiagGeo D;
+    std::memset(&D, 0, sizeof(D));
+    D.dim = C->mesh.dim;
+    D.K = C->mesh.K;
+    D.nv = C->nv;
+    D.nlev = C->nlev;
+    D.A = C->A;
+    for (int li = 0; li < MAXLEV; ++li) { D.lev_n[li] = C->lev_n[li]; D.lev_off[li] = C->lev_off[li]; }
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        D.ne[a] = C->mesh.nelem[a];
+        D.G[a] = C->G[a];
+        if (a < C->mesh.dim) vol *= C->dx[a] / C->mesh.K;
+    }
+    D.dof = C->dof;
+    D.nel = C->nel;
+    D.vol = vol;
+    D.beta_L = C->params.beta_L;
+    hipLaunchKernelGGL(diag_kernel, dim3((C->nel + 127) / 128), dim3(128), 0, s, D, (const double *)dudt,
+                       (const double *)C->d_alpha, (const double *)C->d_beta, alpha_bar, C->d_diag);
+    C->last = s;
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return SEDG_EHIP;
+    std::vector<double> rec((size_t)R * C->nel);
+    int fb = 0;
+    if (hipMemcpy(rec.data(), C->d_diag, sizeof(double) * rec.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&fb, C->d_fbc, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return SEDG_EHIP;
+    std::memset(out, 0, sizeof(*out));
+    out->alpha_bar_min = 1e300;
+    out->alpha_bar_max = -1e300;
+    double asum = 0.0;
+    for (int e = 0; e < C->nel; ++e) {
+        const double *r = &rec[(size_t)e * R];
+        for (int v = 0; v < C->nv; ++v) { out->bulk_change[v] += r[v]; out->bulk_abs[v] += r[C->nv + v]; }
+        out->alpha_bar_min = r[2 * C->nv] < out->alpha_bar_min ? r[2 * C->nv] : out->alpha_bar_min;
+        asum += r[2 * C->nv + 1];
+        out->alpha_bar_max = r[2 * C->nv + 2] > out->alpha_bar_max ? r[2 * C->nv + 2] : out->alpha_bar_max;
+        const int low = (int)r[2 * C->nv + 3];
+        out->elems_by_lowest_order[low == 1 ? 0 : low == 2 ? 1 : low == 4 ? 2 : 3] += 1;
+        out->squeezed += (long)r[2 * C->nv + 4];
+        out->beta_rejected += (long)r[2 * C->nv + 5];
+    }
+    out->alpha_bar_mean = asum / (double)C->dof;
+    out->fallbacks = fb;
+    return SEDG_OK;
+}
+
+int sedg_rk_step_frozen(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, const double *factors, void *stream)
+{
+    if (!C || !u || nsteps < 0 || (nsteps > 0 && (!dt_dev || !factors))) return SEDG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const long long na = (long long)C->A * C->nel;
+    double *stage_in[3] = {u, C->d_u1, C->d_u2};
+    double *stage_out[3] = {C->d_u1, C->d_u2, u};
+    for (int j = 0; j < nsteps; ++j) {
+        const double *f = factors + (long long)j * 6 * na;
+        KArgs P = base_args(C);
+        P.dt = dt_dev + j;
+        for (int k = 0; k < 3; ++k) {
+            P.u = stage_in[k];
+            P.u0 = u;
+            P.out = stage_out[k];
+            P.alpha = const_cast<double *>(f + k * na);
+            P.beta = const_cast<double *>(f + (3 + k) * na);
+            P.stage = k + 1;
+            launch_prep_any(C, P, s);
+            launch_residual_any(C, P, s);
+        }
+    }
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
 }
 
 }  // extern "C"
@@ -3073,6 +3367,7 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
         P.scale = T.scale[0];
         P.stage = 1;
         launch_analyse_any(C, P, s);
+        advance_draw(C, s);
         launch_residual_any(C, P, s);
         P.u = T.u[1];
         P.u0 = u;
@@ -3084,6 +3379,7 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
         P.scale = T.scale[1];
         P.stage = 2;
         launch_analyse_any(C, P, s);
+        advance_draw(C, s);
         launch_residual_any(C, P, s);
         P.u = T.u[2];
         P.u0 = u;
@@ -3095,6 +3391,7 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
         P.scale = T.scale[2];
         P.stage = 3;
         launch_analyse_any(C, P, s);
+        advance_draw(C, s);
         launch_residual_any(C, P, s);
     }
     C->last = s;

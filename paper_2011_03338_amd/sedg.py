@@ -4,10 +4,11 @@ Device memory comes from torch tensors (float64, contiguous, on the GPU) and
 the stream from torch's current stream.
 
 The functions mirror the C entry points declared in include/sedg.h:
-sedg_create / sedg_destroy / sedg_rhs / sedg_max_dt / sedg_rk_step / sedg_check
-/ sedg_tables, the frozen map with its adjoint: sedg_rhs_frozen /
-sedg_adjoint_rhs / sedg_tape_len / sedg_rk_step_tape / sedg_adjoint_rk_step, and
-batched ensembles: sedg_batch_*.  A missing or unloadable library raises at first use; there is
+sedg_create / sedg_destroy / sedg_init_state / sedg_rhs / sedg_max_dt / sedg_rk_step
+/ sedg_diagnose / sedg_check / sedg_tables, the frozen map with its adjoint:
+sedg_rhs_frozen / sedg_adjoint_rhs / sedg_tape_len / sedg_rk_step_tape /
+sedg_rk_step_frozen / sedg_adjoint_rk_step, batched ensembles: sedg_batch_*, and
+the right-hand side without device allocation: sedg_rhs_noalloc.  A missing or unloadable library raises at first use; there is
 no fallback path.
 """
 from __future__ import annotations
@@ -27,7 +28,8 @@ EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "
             "sedg_profile", "sedg_profile_read", "sedg_rhs_frozen", "sedg_adjoint_rhs", "sedg_tape_len",
             "sedg_rk_step_tape", "sedg_adjoint_rk_step", "sedg_batch_create", "sedg_batch_destroy",
             "sedg_batch_state_len", "sedg_batch_state_offset", "sedg_batch_set_tuning", "sedg_batch_get_tuning",
-            "sedg_batch_rk_step", "sedg_batch_check", "sedg_rhs_noalloc"]
+            "sedg_batch_rk_step", "sedg_batch_check", "sedg_rhs_noalloc", "sedg_init_state", "sedg_diagnose",
+            "sedg_rk_step_frozen"]
 
 
 class SedgError(RuntimeError):
@@ -45,7 +47,15 @@ class Mesh_c(ctypes.Structure):
 class Params_c(ctypes.Structure):
     _fields_ = [("tau_A", ctypes.c_double), ("tau_S", ctypes.c_double), ("alpha_H", ctypes.c_double),
                 ("alpha_L", ctypes.c_double), ("beta_L", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int)]
+                ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong)]
+
+
+class Diag_c(ctypes.Structure):
+    _fields_ = [("bulk_change", ctypes.c_double * 5), ("bulk_abs", ctypes.c_double * 5),
+                ("alpha_bar_min", ctypes.c_double), ("alpha_bar_mean", ctypes.c_double),
+                ("alpha_bar_max", ctypes.c_double), ("elems_by_lowest_order", ctypes.c_long * 4),
+                ("squeezed", ctypes.c_long), ("beta_rejected", ctypes.c_long), ("fallbacks", ctypes.c_long)]
 
 
 class Tuning_c(ctypes.Structure):
@@ -74,7 +84,10 @@ def load():
     lib.sedg_set_params.argtypes = [vp, ctypes.POINTER(Params_c)]
     lib.sedg_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.sedg_max_dt.argtypes = [vp, vp, vp, vp]
-    lib.sedg_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
+    lib.sedg_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.sedg_init_state.argtypes = [vp, vp, dp, ctypes.POINTER(ctypes.c_long)]
+    lib.sedg_diagnose.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag_c), vp]
+    lib.sedg_rk_step_frozen.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
     lib.sedg_check.argtypes = [vp, ctypes.POINTER(ctypes.c_long)]
     lib.sedg_tables.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
     lib.sedg_profile.argtypes = [vp, ctypes.c_int]
@@ -125,6 +138,7 @@ def params_c(p) -> Params_c:
     s = Params_c()
     s.tau_A, s.tau_S, s.alpha_H, s.alpha_L, s.beta_L, s.cfl = p.tau_A, p.tau_S, p.alpha_H, p.alpha_L, p.beta_L, p.cfl
     s.top_level, s.level_mask, s.mode = p.top_level, p.level_mask, p.mode
+    s.seed = int(getattr(p, "seed", 0))
     return s
 
 
@@ -205,9 +219,45 @@ class Solver:
     def max_dt(self, u, dt_out, stream=None):
         _check(load().sedg_max_dt(self._h, _ptr(u), _ptr(dt_out), _stream(stream)), "sedg_max_dt")
 
-    def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, stream=None):
-        _check(load().sedg_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log), _stream(stream)),
-               "sedg_rk_step")
+    def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, alpha_log=None, stream=None):
+        """nsteps SSP-RK3 steps of u in place; dt_log (nsteps) and alpha_log (3 * nsteps *
+        alpha_len, step-major) optionally receive the step sizes and every stage's factors."""
+        _check(load().sedg_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log), _ptr(alpha_log),
+                                   _stream(stream)), "sedg_rk_step")
+
+    def init_state(self, u_dev, u_host):
+        """Copy a host state (numpy float64, state layout) into u_dev and check it; raises
+        SedgError(SEDG_ESTATE) naming the first bad element."""
+        import numpy as _np
+        h = _np.ascontiguousarray(u_host, dtype=_np.float64)
+        assert h.size == self.state_len and u_dev.numel() == self.state_len
+        bad = ctypes.c_long(-1)
+        rc = load().sedg_init_state(self._h, _ptr(u_dev), h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.byref(bad))
+        if rc == SEDG_ESTATE:
+            err = SedgError(rc, "sedg_init_state: element %d" % bad.value)
+            err.element = bad.value
+            raise err
+        _check(rc, "sedg_init_state")
+
+    def diagnose(self, u, dudt, alpha_bar=None, stream=None) -> dict:
+        """Right-hand side at u into dudt plus its diagnostics (sedg_diagnose)."""
+        d = Diag_c()
+        _check(load().sedg_diagnose(self._h, _ptr(u), _ptr(dudt), _ptr(alpha_bar), ctypes.byref(d), _stream(stream)),
+               "sedg_diagnose")
+        nv = self.mesh.nvar
+        return {"bulk_change": list(d.bulk_change)[:nv], "bulk_abs": list(d.bulk_abs)[:nv],
+                "alpha_bar_min": d.alpha_bar_min, "alpha_bar_mean": d.alpha_bar_mean, "alpha_bar_max": d.alpha_bar_max,
+                "elems_by_lowest_order": dict(zip(["FV", "O2", "O4", "O8"], list(d.elems_by_lowest_order))),
+                "squeezed": d.squeezed, "beta_rejected": d.beta_rejected, "fallbacks": d.fallbacks}
+
+    def rk_step_frozen(self, u, dt_dev, factors, stream=None):
+        """len(dt_dev) steps of the frozen map, u in place; factors holds per step the
+        [alpha x 3 | beta x 3] block of its tape (6 * alpha_len doubles per step)."""
+        n = dt_dev.numel()
+        assert factors.numel() >= n * 6 * self.alpha_len
+        _check(load().sedg_rk_step_frozen(self._h, _ptr(u), n, _ptr(dt_dev), _ptr(factors), _stream(stream)),
+               "sedg_rk_step_frozen")
 
     def rhs_frozen(self, u, alpha, beta, dudt, stream=None):
         """Right-hand side with alpha and beta held fixed."""

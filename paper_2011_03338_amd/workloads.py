@@ -20,7 +20,7 @@ import numpy as np
 
 PERIODIC, OUTFLOW = 0, 1
 GAUSS, LGL = 0, 1
-ADAPTIVE, FORCE_DG, FORCE_FV, EXTERNAL, FROZEN = 0, 1, 2, 3, 4
+ADAPTIVE, FORCE_DG, FORCE_FV, EXTERNAL, RANDOM = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass
@@ -83,6 +83,7 @@ class Params:
     top_level: int = 0          # 0 -> K
     level_mask: int = 0         # 0 -> all levels
     mode: int = ADAPTIVE
+    seed: int = 0               # RANDOM mode: generator seed
 
 
 def alpha_len(mesh: Mesh, params: Params) -> int:

@@ -1,26 +1,62 @@
 """The HIP path on the Sod shock tube of the 1-D validation runs (Sec. 3.4) at the
-paper's resolution (32 elements of 8 subcells, final time 0.2): the same step
-sizes as the oracle, the final state against the oracle's and the density
-against the exact Riemann solution."""
+paper's resolution (32 elements of 8 subcells, final time 0.2), on the oracle's step
+sizes: the state after 100 steps within the multi-step bar of the oracle's, the final
+state against the oracle's and the density against the exact Riemann solution, and the
+paper's comparison of the multi-level chain with the single-level scheme."""
 import numpy as np
 import pytest
 import torch
 
 from paper_2011_03338_amd import sedg, workloads as W
-from tests.parity import DEV, say
+from tests.parity import DEV, STATE_TOL, rel_err, say
 from tests.test_oracle_sod import exact_density_means, run_to
 
 pytestmark = pytest.mark.gpu
 
+# Over the whole run (861 steps with all levels, 834 with one) rounding tips the
+# indicator at the shock differently: the oracle itself, with its initial state
+# perturbed by 1e-15 relative (random signs), moves by 2.9e-5 (all levels) and 2.1e-5
+# (one level) at the final time, and by 1.0e-10 and 1.3e-10 after 100 steps.  The GPU's
+# rounding differs from the oracle's at every step, not once, and its trajectory ends
+# 1.1e-4 (all levels) from the oracle's, about 4 times that sensitivity: the end-of-run
+# bar is 10 times the sensitivity.  The state after 100 steps is held to 1e-9.
+END_TOL = 3e-4
 
-@pytest.mark.parametrize("mask,bound", [(0, 3e-3), (1 << 3, 4e-3)])
-def test_sod_gpu_matches_oracle_and_exact(mask, bound):
-    """mask 0: all levels O(8) -> O(4) -> O(2) -> FV; 1 << 3: single level O(8) -> FV."""
+
+@pytest.fixture(scope="module")
+def sod_runs():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
-    mesh, u0, info = W.sod_tube(nelem=32, K=8)
-    p = W.Params(level_mask=mask)
-    dts = []
-    u_o = run_to(mesh, p, u0, info["T"], dts)
+    out = {}
+    for mask in (0, 1 << 3):
+        mesh, u0, info = W.sod_tube(nelem=32, K=8)
+        p = W.Params(level_mask=mask)
+        dts = []
+        u_o = run_to(mesh, p, u0, info["T"], dts)
+        out[mask] = (mesh, p, u0, info, dts, u_o)
+    return out
+
+
+@pytest.mark.parametrize("mask", [0, 1 << 3])
+def test_sod_gpu_100_steps(sod_runs, mask):
+    """mask 0: all levels O(8) -> O(4) -> O(2) -> FV; 1 << 3: single level O(8) -> FV.
+    The first 100 of the oracle's step sizes on both sides: states within 1e-9."""
+    from oracle import oracle as O
+    mesh, p, u0, info, dts, _ = sod_runs[mask]
+    u_o = u0
+    for dt in dts[:100]:
+        u_o, _ = O.rk3(mesh, p, u_o, 1, dt_fixed=dt)
+    s = sedg.Solver(mesh, p)
+    ug = torch.from_numpy(u0).to(DEV)
+    for dt in dts[:100]:
+        s.rk_step(ug, 1, dt)
+    s.check()
+    err = rel_err(ug.cpu().numpy(), u_o)
+    s.close()
+    say("  sod mask %d 100 steps rel_err=%.3e" % (mask, err))
+    assert err <= STATE_TOL
+
+
+def _gpu_final(mesh, p, u0, dts):
     s = sedg.Solver(mesh, p)
     ug = torch.from_numpy(u0).to(DEV)
     for dt in dts:
@@ -28,11 +64,22 @@ def test_sod_gpu_matches_oracle_and_exact(mask, bound):
     s.check()
     u_g = ug.cpu().numpy()
     s.close()
-    # rounding can tip the indicator at the shock differently over ~200 steps, so the
-    # two trajectories agree to a small absolute tolerance, not to the one-step bound
-    diff = float(np.max(np.abs(u_g - u_o)))
-    rho = u_g[0, 0].mean(axis=0)
-    l1 = float(np.mean(np.abs(rho - exact_density_means(mesh.edges(0), info["T"]))))
-    say("  sod mask %d %d steps max|gpu-oracle|=%.3e density L1 vs exact=%.3e" % (mask, len(dts), diff, l1))
-    assert diff < 1e-3
-    assert l1 < bound
+    return u_g
+
+
+def test_sod_gpu_final_and_multilevel_vs_single_level(sod_runs):
+    """Final state (T = 0.2) within END_TOL of the oracle's for both level masks, the
+    density L1 error against the exact solution bounded, and the multi-level chain at
+    least 20 % more accurate than the single level on the GPU as in the oracle."""
+    l1 = {}
+    for mask, bound in ((0, 3e-3), (1 << 3, 4e-3)):
+        mesh, p, u0, info, dts, u_o = sod_runs[mask]
+        u_g = _gpu_final(mesh, p, u0, dts)
+        diff = float(np.max(np.abs(u_g - u_o)))
+        rho = u_g[0, 0].mean(axis=0)
+        l1[mask] = float(np.mean(np.abs(rho - exact_density_means(mesh.edges(0), info["T"]))))
+        say("  sod mask %d %d steps max|gpu-oracle|=%.3e density L1 vs exact=%.3e"
+            % (mask, len(dts), diff, l1[mask]))
+        assert diff < END_TOL
+        assert l1[mask] < bound
+    assert l1[0] < 0.8 * l1[1 << 3]
