@@ -60,6 +60,7 @@ enum {
 };
 
 enum { SEDG_PERIODIC = 0, SEDG_OUTFLOW = 1 };
+enum { SEDG_SSPRK3 = 0, SEDG_SSPRK54 = 1 };
 enum { SEDG_GAUSS = 0, SEDG_LGL = 1 };
 enum { SEDG_ADAPTIVE = 0, SEDG_FORCE_DG = 1, SEDG_FORCE_FV = 2, SEDG_EXTERNAL = 3, SEDG_RANDOM = 4 };
 
@@ -68,7 +69,9 @@ typedef struct sedg_mesh {
     int K;              /* 4 or 8 */
     int nelem[3];       /* elements per axis (1 on unused axes) */
     double lo[3], hi[3];/* domain box */
-    int bc[3];          /* SEDG_PERIODIC or SEDG_OUTFLOW (zero-gradient) per axis */
+    int bc[3];          /* SEDG_PERIODIC or SEDG_OUTFLOW per axis; outflow = zero gradient of the
+                           subcell means: a boundary face sees the boundary subcell's mean outside,
+                           with the same blending weights */
     double gamma;       /* ratio of specific heats (eq. equation-of-state) */
     int family;         /* collocation nodes: SEDG_GAUSS (the paper's, Sec. 2.2) or SEDG_LGL */
 } sedg_mesh;
@@ -84,6 +87,13 @@ typedef struct sedg_params {
                                 SEDG_FORCE_FV (all alpha = 0), SEDG_EXTERNAL (alpha given),
                                 SEDG_RANDOM (alpha drawn afresh for every right-hand side) */
     unsigned long long seed; /* SEDG_RANDOM: seed of the generator */
+    double sigma_floor;      /* floor of the denominator max(sigma_n/2, sigma_n, floor) of
+                                eq. calc-blending-factor; 0 = the paper's 1 (a smaller floor
+                                is a variant, not the paper's scheme) */
+    int integrator;          /* SEDG_SSPRK3 (three-stage SSP-RK, Shu-Osher form) or SEDG_SSPRK54
+                                (the five-stage fourth-order SSP-RK of Spiteri and Ruuth, which
+                                the paper uses, Sec. 3) for sedg_rk_step; the step-tape, frozen
+                                and adjoint steps are SSP-RK3 only */
 } sedg_params;
 
 typedef struct sedg_ctx sedg_ctx;
@@ -138,7 +148,8 @@ int sedg_rhs(sedg_ctx *ctx, const double *u, double *dudt, double *alpha_out, do
  * written to the device scalar *dt_dev. */
 int sedg_max_dt(sedg_ctx *ctx, const double *u, double *dt_dev, void *stream);
 
-/* Advance u in place by nsteps steps of three-stage SSP-RK (Shu-Osher form).
+/* Advance u in place by nsteps steps of params.integrator: three-stage SSP-RK
+ * (Shu-Osher form) or SSP-RK(5,4) (five stages; alpha_log then holds 5 arrays per step).
  *   dt_fixed > 0: that step size; otherwise the CFL step of each step's
  *   initial state, computed on the device.
  *   dt_log_dev: device, optional, receives the nsteps step sizes (fixed or CFL).

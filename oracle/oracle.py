@@ -36,7 +36,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("tau_A", ctypes.c_double), ("tau_S", ctypes.c_double), ("alpha_H", ctypes.c_double),
                 ("alpha_L", ctypes.c_double), ("beta_L", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int),
-                ("seed", ctypes.c_ulonglong), ("draw", ctypes.c_longlong)]
+                ("seed", ctypes.c_ulonglong), ("draw", ctypes.c_longlong), ("sigma_floor", ctypes.c_double),
+                ("integrator", ctypes.c_int)]
 
 
 _lib = None
@@ -79,6 +80,8 @@ def _params(p, draw: int = 0) -> _Params:
     s.top_level, s.level_mask, s.mode = p.top_level, p.level_mask, p.mode
     s.seed = int(getattr(p, "seed", 0))
     s.draw = int(draw)
+    s.sigma_floor = float(getattr(p, "sigma_floor", 0.0))
+    s.integrator = int(getattr(p, "integrator", 0))
     return s
 
 
@@ -144,8 +147,9 @@ def max_dt(mesh, params, u) -> float:
 
 
 def rk3(mesh, params, u, nsteps: int, dt_fixed: float = 0.0, draw: int = 0):
-    """nsteps SSP-RK3 steps; returns (u_new, dt_log).  In RANDOM mode the right-hand
-    sides use draws draw, draw + 1, ... (three per step)."""
+    """nsteps steps of SSP-RK3 (or SSP-RK(5,4) with params.integrator = 1); returns
+    (u_new, dt_log).  In RANDOM mode the right-hand sides use draws draw, draw + 1, ...
+    (one per stage)."""
     u = np.array(u, dtype=np.float64, order="C", copy=True)
     dts = np.zeros(max(nsteps, 1))
     rc = lib().or_rk3(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params, draw)), _ptr(u), nsteps, dt_fixed,

@@ -643,7 +643,7 @@ static double indicator(const ctx_t *c, int li, const double *us, const double *
     }
     double alpha = 1.0, xmax = -INFINITY;
     for (int v = 0; v < nv; v++) {
-        double den = fmax(fmax(sig_h[v], sig_n[v]), 1.0);
+        double den = fmax(fmax(sig_h[v], sig_n[v]), c->p.sigma_floor > 0.0 ? c->p.sigma_floor : 1.0);
         double r = fabs(sig_n[v] - sig_h[v]) / den;
         double x = c->p.tau_A * (r - c->p.tau_S);
         if (!isfinite(x)) { *xr = NAN; return 0.0; }
@@ -911,11 +911,13 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
     if (!haveR) gr[a] = gl[a];
     long il = gl[0] + c->G[0] * (gl[1] + (long)c->G[1] * gl[2]);
     long ir = gr[0] + c->G[0] * (gr[1] + (long)c->G[1] * gr[2]);
-    /* states: outflow mirrors the interior side (state and weights) */
+    /* states: at an outflow boundary the exterior state is the mean of the boundary
+       subcell (zero gradient of the subcell means), the exterior weights mirror the
+       interior ones */
     double uL[MAXV], uR[MAXV];
     for (int v = 0; v < nv; v++) {
-        uL[v] = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il] : W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir];
-        uR[v] = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir] : W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il];
+        uL[v] = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + il] : u[v * c->dof + ir];
+        uR[v] = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + ir] : u[v * c->dof + il];
     }
     /* data scales of the two elements sharing the face */
     int el3[3], er3[3];
@@ -960,8 +962,8 @@ static void face_flux(const ctx_t *c, const double *u, const work_t *W, int a, l
                 long jl = cl[0] + c->G[0] * (cl[1] + (long)c->G[1] * cl[2]);
                 long jr = cr[0] + c->G[0] * (cr[1] + (long)c->G[1] * cr[2]);
                 for (int v = 0; v < nv; v++) {
-                    double vl = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + jl] : W->side[(((long)a * 2 + 0) * nv + v) * c->dof + jr];
-                    double vr = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + jr] : W->side[(((long)a * 2 + 1) * nv + v) * c->dof + jl];
+                    double vl = haveL ? W->side[(((long)a * 2 + 1) * nv + v) * c->dof + jl] : u[v * c->dof + jr];
+                    double vr = haveR ? W->side[(((long)a * 2 + 0) * nv + v) * c->dof + jr] : u[v * c->dof + jl];
                     sL[v][q0 + ext[0] * q1] = vl;
                     sR[v][q0 + ext[0] * q1] = vr;
                 }
@@ -1265,6 +1267,8 @@ double or_max_dt(const or_mesh *m, const or_params *p, const double *u)
     return dt;
 }
 
+static int rk54_steps(ctx_t *c, double *u, int nsteps, double dt_fixed, double *dt_log);
+
 /* Three-stage SSP Runge-Kutta (Shu-Osher form):
    u1 = u + dt L(u);  u2 = 3/4 u + 1/4 (u1 + dt L(u1));  u' = 1/3 u + 2/3 (u2 + dt L(u2)). */
 int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps, double dt_fixed, double *dt_log)
@@ -1274,6 +1278,11 @@ int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps, double d
     int rc = make_ctx(m, p, c);
     if (rc) { free(c); return rc; }
     if (c->p.mode == OR_EXTERNAL || c->p.mode == OR_FROZEN) { free(c); return OR_EINVAL; }
+    if (c->p.integrator == 1) {
+        rc = rk54_steps(c, u, nsteps, dt_fixed, dt_log);
+        free(c);
+        return rc;
+    }
     size_t n = (size_t)c->nv * c->dof;
     double *L = malloc(sizeof(double) * n), *u1 = malloc(sizeof(double) * n), *u2 = malloc(sizeof(double) * n);
     /* in OR_RANDOM mode every right-hand side draws new factors: draw, draw + 1, ... */
@@ -1295,6 +1304,51 @@ int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps, double d
         for (size_t i = 0; i < n; i++) u[i] = (1.0 / 3.0) * u[i] + (2.0 / 3.0) * (u2[i] + dt * L[i]);
     }
     free(L); free(u1); free(u2); free(c);
+    return rc;
+}
+
+/* Five-stage fourth-order SSP Runge-Kutta of Spiteri and Ruuth (SIAM J. Numer. Anal.
+   40 (2002)), the scheme the paper advances in time with (Sec. 3), in Shu-Osher form
+   with its published coefficients:
+     u1 = u + c10 dt L(u)
+     u2 = a20 u + a21 u1 + c21 dt L(u1)
+     u3 = a30 u + a32 u2 + c32 dt L(u2)
+     u4 = a40 u + a43 u3 + c43 dt L(u3)
+     u' = a52 u2 + a53 u3 + c53 dt L(u3) + a54 u4 + c54 dt L(u4). */
+static int rk54_steps(ctx_t *c, double *u, int nsteps, double dt_fixed, double *dt_log)
+{
+    const double c10 = 0.391752226571890;
+    const double a20 = 0.444370493651235, a21 = 0.555629506348765, c21 = 0.368410593050371;
+    const double a30 = 0.620101851488403, a32 = 0.379898148511597, c32 = 0.251891774271694;
+    const double a40 = 0.178079954393132, a43 = 0.821920045606868, c43 = 0.544974750228521;
+    const double a52 = 0.517231671970585, a53 = 0.096059710526147, c53 = 0.063692468666290;
+    const double a54 = 0.386708617503269, c54 = 0.226007483236906;
+    size_t n = (size_t)c->nv * c->dof;
+    double *L = malloc(sizeof(double) * n), *u1 = malloc(sizeof(double) * n), *u2 = malloc(sizeof(double) * n);
+    double *u3 = malloc(sizeof(double) * n), *u4 = malloc(sizeof(double) * n), *L3 = malloc(sizeof(double) * n);
+    int rc = OR_OK;
+    for (int st = 0; st < nsteps && rc == OR_OK; st++) {
+        double dt = dt_fixed > 0.0 ? dt_fixed : max_dt_ctx(c, u);
+        if (!(dt > 0.0)) { rc = OR_ESTATE; break; }
+        if (dt_log) dt_log[st] = dt;
+        rc = rhs_ctx(c, u, L, NULL, NULL, NULL, NULL, NULL, NULL); c->p.draw++;
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u1[i] = u[i] + c10 * dt * L[i];
+        rc = rhs_ctx(c, u1, L, NULL, NULL, NULL, NULL, NULL, NULL); c->p.draw++;
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u2[i] = a20 * u[i] + a21 * u1[i] + c21 * dt * L[i];
+        rc = rhs_ctx(c, u2, L, NULL, NULL, NULL, NULL, NULL, NULL); c->p.draw++;
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u3[i] = a30 * u[i] + a32 * u2[i] + c32 * dt * L[i];
+        rc = rhs_ctx(c, u3, L3, NULL, NULL, NULL, NULL, NULL, NULL); c->p.draw++;
+        if (rc) break;
+        for (size_t i = 0; i < n; i++) u4[i] = a40 * u[i] + a43 * u3[i] + c43 * dt * L3[i];
+        rc = rhs_ctx(c, u4, L, NULL, NULL, NULL, NULL, NULL, NULL); c->p.draw++;
+        if (rc) break;
+        for (size_t i = 0; i < n; i++)
+            u[i] = a52 * u2[i] + a53 * u3[i] + c53 * dt * L3[i] + a54 * u4[i] + c54 * dt * L[i];
+    }
+    free(L); free(u1); free(u2); free(u3); free(u4); free(L3);
     return rc;
 }
 
@@ -1616,13 +1670,16 @@ static void adj_face(const ctx_t *c, const double *u, const work_t *W, int a, lo
     if (!haveR) gr[a] = gl[a];
     long il = gl[0] + c->G[0] * (gl[1] + (long)c->G[1] * gl[2]);
     long ir = gr[0] + c->G[0] * (gr[1] + (long)c->G[1] * gr[2]);
-    /* where the left / right interface states come from (outflow mirrors) */
-    long srcL = haveL ? side_index(c, a, 1, 0, il) : side_index(c, a, 0, 0, ir);
-    long srcR = haveR ? side_index(c, a, 0, 0, ir) : side_index(c, a, 1, 0, il);
+    /* where the left / right interface states come from: the interface states, or at an
+       outflow boundary the boundary subcell's mean (index into u, not into side) */
+    long srcL = haveL ? side_index(c, a, 1, 0, il) : ir;
+    long srcR = haveR ? side_index(c, a, 0, 0, ir) : il;
+    const double *baseL = haveL ? W->side : u, *baseR = haveR ? W->side : u;
+    double *gbaseL = haveL ? gside : gu, *gbaseR = haveR ? gside : gu;
     double uL[MAXV], uR[MAXV];
     for (int v = 0; v < nv; v++) {
-        uL[v] = W->side[srcL + (long)v * c->dof];
-        uR[v] = W->side[srcR + (long)v * c->dof];
+        uL[v] = baseL[srcL + (long)v * c->dof];
+        uR[v] = baseR[srcR + (long)v * c->dof];
     }
     int el3[3], er3[3];
     for (int b = 0; b < 3; b++) {
@@ -1666,11 +1723,11 @@ static void adj_face(const ctx_t *c, const double *u, const work_t *W, int a, lo
                 long jl = cl[0] + c->G[0] * (cl[1] + (long)c->G[1] * cl[2]);
                 long jr = cr[0] + c->G[0] * (cr[1] + (long)c->G[1] * cr[2]);
                 int q = q0 + ext[0] * q1;
-                slotL[q] = haveL ? side_index(c, a, 1, 0, jl) : side_index(c, a, 0, 0, jr);
-                slotR[q] = haveR ? side_index(c, a, 0, 0, jr) : side_index(c, a, 1, 0, jl);
+                slotL[q] = haveL ? side_index(c, a, 1, 0, jl) : jr;
+                slotR[q] = haveR ? side_index(c, a, 0, 0, jr) : jl;
                 for (int v = 0; v < nv; v++) {
-                    sL[v][q] = W->side[slotL[q] + (long)v * c->dof];
-                    sR[v][q] = W->side[slotR[q] + (long)v * c->dof];
+                    sL[v][q] = baseL[slotL[q] + (long)v * c->dof];
+                    sR[v][q] = baseR[slotR[q] + (long)v * c->dof];
                 }
             }
         double nL[MAXV][MAXK * MAXK], nR[MAXV][MAXK * MAXK], tmp[MAXK * MAXK];
@@ -1722,8 +1779,8 @@ static void adj_face(const ctx_t *c, const double *u, const work_t *W, int a, lo
                 memcpy(gnR[v], tmp, sizeof(double) * nf);
             }
             for (int q = 0; q < nf; q++) {
-                gside[slotL[q] + (long)v * c->dof] += gnL[v][q];
-                gside[slotR[q] + (long)v * c->dof] += gnR[v][q];
+                gbaseL[slotL[q] + (long)v * c->dof] += gnL[v][q];
+                gbaseR[slotR[q] + (long)v * c->dof] += gnR[v][q];
             }
         }
     }
@@ -1742,9 +1799,9 @@ static void adj_face(const ctx_t *c, const double *u, const work_t *W, int a, lo
                 ar += J[v][nv + x] * thFV * gFv[v];
             }
             if (fbL) gu[x * c->dof + il] += al;
-            else gside[srcL + (long)x * c->dof] += al;
+            else gbaseL[srcL + (long)x * c->dof] += al;
             if (fbR) gu[x * c->dof + ir] += ar;
-            else gside[srcR + (long)x * c->dof] += ar;
+            else gbaseR[srcR + (long)x * c->dof] += ar;
         }
     }
 }

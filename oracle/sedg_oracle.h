@@ -52,6 +52,8 @@ typedef struct or_params {
     int mode;                   /* OR_ADAPTIVE, OR_FORCE_DG, OR_FORCE_FV, OR_EXTERNAL, OR_RANDOM */
     unsigned long long seed;    /* OR_RANDOM: generator seed */
     long long draw;             /* OR_RANDOM: index of the (first) draw of factors */
+    double sigma_floor;         /* floor in the indicator's denominator; <= 0: the paper's 1 */
+    int integrator;             /* or_rk3: 0 SSP-RK3, 1 SSP-RK(5,4) */
 } or_params;
 
 /* Number of blending factors per element. */
@@ -81,8 +83,9 @@ int or_rhs(const or_mesh *m, const or_params *p, const double *u, double *dudt,
 /* CFL time step of the state u; returns a negative value on a bad state. */
 double or_max_dt(const or_mesh *m, const or_params *p, const double *u);
 
-/* nsteps SSP-RK3 steps in place.  dt_fixed > 0 uses that step, else the CFL
- * step of each step's initial state.  dt_log (nsteps) may be NULL. */
+/* nsteps steps in place of SSP-RK3 or (p->integrator = 1) SSP-RK(5,4).  dt_fixed > 0
+ * uses that step, else the CFL step of each step's initial state.  dt_log (nsteps)
+ * may be NULL. */
 int or_rk3(const or_mesh *m, const or_params *p, double *u, int nsteps,
            double dt_fixed, double *dt_log);
 

@@ -95,10 +95,16 @@ struct KArgs {
     unsigned level_mask;
     int stage;              // 0: write dudt; 1, 2, 3: SSP-RK3 stage
     double gamma, tau_A, tau_S, alpha_H, alpha_L, beta_L;
+    double sigma_floor;     // floor of the smoothness-measure denominator (1 in the paper)
     // RANDOM mode: generator seed and the device counter of right-hand-side draws
     unsigned long long seed;
     const long long *draw;
     int *fbc;               // interface-safety fallback counter (diagnostics; nullable)
+    // generic Shu-Osher stage (stage code 5): out = rk[0] u0 + rk[1] u + rk[2] dt L(u)
+    // + rk[3] x1, and, where yout is given, yout = rk[4] y0 + rk[5] u + rk[6] dt L(u)
+    const double *x1, *y0;
+    double *yout;
+    double rk[7];
 };
 
 // Per-axis mesh data by run-time axis.  A kernel may hold its arguments in a local
@@ -937,7 +943,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             double amin = 1.0;
             int nonfin = 0;
             for (int v = 0; v < NV; ++v) {
-                double den = fmax(fmax(sh[v], sn[v]), 1.0);
+                double den = fmax(fmax(sh[v], sn[v]), P.sigma_floor);
                 double r = fabs(sn[v] - sh[v]) / den;
                 double x = P.tau_A * (r - P.tau_S);
                 if (!isfinite(x)) nonfin = 1;
@@ -1067,7 +1073,8 @@ __device__ __forceinline__ void theta_cell_of(const double *al, int cell, double
 
 // The two sides of an element face for the lane at transverse position t: the
 // element's own face state and weights, the neighbour's (nb < 0: a domain boundary,
-// where the outflow copy mirrors the own side), the data scales of the pair and the
+// where the exterior state is the boundary cell's mean and the exterior weights mirror
+// the own side), the data scales of the pair and the
 // cells whose means replace a non-admissible FV input (element -1: own element).
 // The face-buffer and scale loads of both sides are issued together, unconditionally
 // (a boundary lane reads its own element), so that one memory latency covers them.
@@ -1096,9 +1103,14 @@ __device__ __forceinline__ void element_face_sides(const KArgs &P, int ee, int f
         srho = fmax(nsr, own_sr);
         sE = fmax(nse, own_se);
     } else {
+        // outflow boundary (zero gradient of the subcell means): the exterior state is the
+        // mean of the element's boundary cell, the exterior weights mirror its own
         for (int l = 0; l <= LV::NLEV; ++l) thn[l] = tho[l];
+        int e3o[3];
+        elem3(P, ee, e3o);
+        const long long gco = gindex<DIM, K>(P, e3o, co);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) un[v] = uo[v];
+        for (int v = 0; v < NV; ++v) un[v] = P.u[v * P.dof + gco];
     }
     const int me = nb >= 0 ? nb : -1, mc = nb >= 0 ? cn : co;
 #pragma unroll
@@ -1530,6 +1542,24 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     if (!act) return;
     if (P.stage == 0) {
         for (int v = 0; v < NV; ++v) P.out[v * P.dof + g] = out[v];
+    } else if (P.stage == 5) {
+        // one stage of a Shu-Osher form with up to two earlier states (SSP-RK(5,4));
+        // every load before the first store
+        const double dt = *P.dt;
+        double ub[NV], a0[NV], a1[NV], b0[NV];
+        for (int v = 0; v < NV; ++v) {
+            const long long i = v * P.dof + g;
+            ub[v] = S.u[le][v][c];
+            a0[v] = P.u0 ? P.u0[i] : 0.0;
+            a1[v] = P.x1 ? P.x1[i] : 0.0;
+            b0[v] = P.yout ? P.y0[i] : 0.0;
+        }
+        for (int v = 0; v < NV; ++v) {
+            const long long i = v * P.dof + g;
+            const double dl = dt * out[v];
+            if (P.yout) P.yout[i] = P.rk[4] * b0[v] + P.rk[5] * ub[v] + P.rk[6] * dl;
+            P.out[i] = P.rk[0] * a0[v] + P.rk[1] * ub[v] + P.rk[2] * dl + P.rk[3] * a1[v];
+        }
     } else {
         double dt = *P.dt;
         double ub[NV], u0[NV];
@@ -2266,10 +2296,11 @@ __global__ void __launch_bounds__(64) eface_adjoint_kernel(KArgs P)
                                         mLe, mLc, mRe, mRc, nullptr, e, wsG + slot * KF, 64, guL, guR, gdL, gdR);
         if (has) {
             if (sd == 0) {
-                // own side: the right one; the left belongs to the low neighbour's high face
+                // own side: the right one; the left belongs to the low neighbour's high face,
+                // or at an outflow boundary is the own boundary cell's mean
                 for (int v = 0; v < NV; ++v) {
-                    P.gsb[fb_index<DIM, K>(e, a, 0, v, t)] = guR[v] + (nb < 0 ? guL[v] : 0.0);
-                    P.gdb[fb_index<DIM, K>(e, a, 0, v, t)] = gdR[v] + (nb < 0 ? gdL[v] : 0.0);
+                    P.gsb[fb_index<DIM, K>(e, a, 0, v, t)] = guR[v];
+                    P.gdb[fb_index<DIM, K>(e, a, 0, v, t)] = gdR[v] + (nb < 0 ? gdL[v] + guL[v] : 0.0);
                 }
                 if (nb >= 0)
                     for (int v = 0; v < NV; ++v) {
@@ -2277,9 +2308,10 @@ __global__ void __launch_bounds__(64) eface_adjoint_kernel(KArgs P)
                         P.gdb[fb_index<DIM, K>(nb, a, 1, v, t)] = gdL[v];
                     }
             } else {
+                // an outflow high face: own side left, the exterior (right) the own cell's mean
                 for (int v = 0; v < NV; ++v) {
-                    P.gsb[fb_index<DIM, K>(e, a, 1, v, t)] = guL[v] + guR[v];
-                    P.gdb[fb_index<DIM, K>(e, a, 1, v, t)] = gdL[v] + gdR[v];
+                    P.gsb[fb_index<DIM, K>(e, a, 1, v, t)] = guL[v];
+                    P.gdb[fb_index<DIM, K>(e, a, 1, v, t)] = gdL[v] + gdR[v] + guR[v];
                 }
             }
         }
@@ -2493,11 +2525,12 @@ __global__ void log_dt_kernel(const double *dt, double *dt_log, const int *step_
 }
 
 // factor log: the factors of stage `stage` of step step_ctr go to
-// log[(3 * step + stage) * n ...]
-__global__ void log_alpha_kernel(const double *alpha, double *log, const int *step_ctr, int stage, long long n)
+// log[(nstages * step + stage) * n ...]
+__global__ void log_alpha_kernel(const double *alpha, double *log, const int *step_ctr, int stage, long long n,
+                                 int nstages)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) log[(3LL * step_ctr[0] + stage) * n + i] = alpha[i];
+    if (i < n) log[((long long)nstages * step_ctr[0] + stage) * n + i] = alpha[i];
 }
 
 // state check of sedg_init_state: the smallest element index holding a mean value that
@@ -2627,6 +2660,7 @@ struct sedg_ctx {
     sedg_level_tab *d_tabs;
     double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale, *d_mean;
     double *d_ef;                          // element-face common fluxes
+    double *d_u3;                          // fourth stage buffer of SSP-RK(5,4) (first use)
     double *d_gfb, *d_l1, *d_l2, *d_acc;   // adjoint (allocated on first use)
     double *d_gsb, *d_gdb;
     int *d_err, *d_ctr;
@@ -2774,6 +2808,7 @@ KArgs base_args(const sedg_ctx *C)
     P.alpha_H = C->params.alpha_H;
     P.alpha_L = C->params.alpha_L;
     P.beta_L = C->params.beta_L;
+    P.sigma_floor = C->params.sigma_floor > 0.0 ? C->params.sigma_floor : 1.0;
     P.seed = C->params.seed;
     P.draw = C->d_draw;
     return P;
@@ -2798,6 +2833,7 @@ int set_levels(sedg_ctx *C, const sedg_params *p)
     int top = p->top_level > 0 ? p->top_level : K;
     if (top < 2 || top > K || (top & (top - 1))) return SEDG_EINVAL;
     if (p->mode < 0 || p->mode > SEDG_RANDOM) return SEDG_EINVAL;
+    if (p->integrator != SEDG_SSPRK3 && p->integrator != SEDG_SSPRK54) return SEDG_EINVAL;
     C->params = *p;
     if (hipMemset(C->d_draw, 0, sizeof(long long)) != hipSuccess) return SEDG_EHIP;
     C->nlev = 0;
@@ -2914,7 +2950,7 @@ int sedg_destroy(sedg_ctx *C)
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
     void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr,
                     C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_gsb, C->d_gdb, C->d_l1, C->d_l2, C->d_acc,
-                    C->d_draw, C->d_fbc, C->d_diag};
+                    C->d_draw, C->d_fbc, C->d_diag, C->d_u3};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
@@ -3007,7 +3043,7 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     auto log_alpha = [&](int stage) {
         if (alpha_log)
             hipLaunchKernelGGL(log_alpha_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, C->d_alpha,
-                               alpha_log, C->d_ctr, stage, na);
+                               alpha_log, C->d_ctr, stage, na, 3);
     };
     // stage 1: u1 = u + dt L(u)
     P.u = u;
@@ -3050,6 +3086,79 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     if (dt_log || alpha_log) hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, s, C->d_ctr);
 }
 
+// SSP-RK(5,4) of Spiteri & Ruuth (SIAM J. Numer. Anal. 40, 2002) in Shu-Osher form:
+//   u1 = u + c10 dt L(u)
+//   u2 = a20 u + a21 u1 + c21 dt L(u1)
+//   u3 = a30 u + a32 u2 + c32 dt L(u2)
+//   u4 = a40 u + a43 u3 + c43 dt L(u3)
+//   u' = a52 u2 + a53 u3 + c53 dt L(u3) + a54 u4 + c54 dt L(u4)
+// Buffers: u1 and then u3 in d_u1; u2 in d_u2, overwritten in place by stage 4 with
+// a52 u2 + a53 u3 + c53 dt L(u3); u4 in d_u3.
+namespace {
+const double RK54_C10 = 0.391752226571890;
+const double RK54_A20 = 0.444370493651235, RK54_A21 = 0.555629506348765, RK54_C21 = 0.368410593050371;
+const double RK54_A30 = 0.620101851488403, RK54_A32 = 0.379898148511597, RK54_C32 = 0.251891774271694;
+const double RK54_A40 = 0.178079954393132, RK54_A43 = 0.821920045606868, RK54_C43 = 0.544974750228521;
+const double RK54_A52 = 0.517231671970585, RK54_A53 = 0.096059710526147, RK54_C53 = 0.063692468666290;
+const double RK54_A54 = 0.386708617503269, RK54_C54 = 0.226007483236906;
+}  // namespace
+
+static void enqueue_step_rk54(sedg_ctx *C, double *u, double dt_fixed, double *dt_log, double *alpha_log,
+                              hipStream_t s)
+{
+    KArgs P = base_args(C);
+    P.dt = C->d_dt;
+    const long long na = (long long)C->A * C->nel;
+    auto log_alpha = [&](int stage) {
+        if (alpha_log)
+            hipLaunchKernelGGL(log_alpha_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, C->d_alpha,
+                               alpha_log, C->d_ctr, stage, na, 5);
+    };
+    auto set = [&](double r0, double r1, double r2, double r3, double r4, double r5, double r6) {
+        P.rk[0] = r0; P.rk[1] = r1; P.rk[2] = r2; P.rk[3] = r3; P.rk[4] = r4; P.rk[5] = r5; P.rk[6] = r6;
+    };
+    P.stage = 5;
+    // stage 1
+    P.u = u; P.u0 = nullptr; P.x1 = nullptr; P.y0 = nullptr; P.yout = nullptr; P.out = C->d_u1;
+    set(0.0, 1.0, RK54_C10, 0.0, 0.0, 0.0, 0.0);
+    P.lam_part = dt_fixed > 0.0 ? nullptr : C->d_lam;
+    timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+    advance_draw(C, s);
+    log_alpha(0);
+    if (!(dt_fixed > 0.0))
+        timed(C, 2, s, [&] {
+            hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
+                               cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
+        });
+    else if (dt_log)
+        hipLaunchKernelGGL(log_dt_kernel, dim3(1), dim3(64), 0, s, (const double *)C->d_dt, dt_log, (const int *)C->d_ctr);
+    timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+    timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
+    P.lam_part = nullptr;
+    // stages 2 .. 5
+    struct { double *in, *out; const double *u0, *x1, *y0; double *yout; double r[7]; } st[4] = {
+        {C->d_u1, C->d_u2, u, nullptr, nullptr, nullptr, {RK54_A20, RK54_A21, RK54_C21, 0, 0, 0, 0}},
+        {C->d_u2, C->d_u1, u, nullptr, nullptr, nullptr, {RK54_A30, RK54_A32, RK54_C32, 0, 0, 0, 0}},
+        {C->d_u1, C->d_u3, u, nullptr, C->d_u2, C->d_u2, {RK54_A40, RK54_A43, RK54_C43, 0, RK54_A52, RK54_A53, RK54_C53}},
+        {C->d_u3, u, nullptr, C->d_u2, nullptr, nullptr, {0, RK54_A54, RK54_C54, 1.0, 0, 0, 0}},
+    };
+    for (int k = 0; k < 4; ++k) {
+        P.u = st[k].in;
+        P.out = st[k].out;
+        P.u0 = st[k].u0;
+        P.x1 = st[k].x1;
+        P.y0 = st[k].y0;
+        P.yout = st[k].yout;
+        set(st[k].r[0], st[k].r[1], st[k].r[2], st[k].r[3], st[k].r[4], st[k].r[5], st[k].r[6]);
+        timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
+        advance_draw(C, s);
+        log_alpha(k + 1);
+        timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+        timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
+    }
+    if (dt_log || alpha_log) hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, s, C->d_ctr);
+}
+
 extern "C" {
 
 int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt_log_dev, double *alpha_log_dev,
@@ -3058,12 +3167,21 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
     if (!C || !u || nsteps < 0) return SEDG_EINVAL;
     if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
     if (nsteps == 0) return SEDG_OK;
+    const bool rk54 = C->params.integrator == SEDG_SSPRK54;
+    if (rk54 && !C->d_u3 && hipMalloc(&C->d_u3, sizeof(double) * (size_t)C->nv * C->dof) != hipSuccess) {
+        C->d_u3 = nullptr;
+        return SEDG_ENOMEM;
+    }
+    auto step = [&](hipStream_t ss) {
+        if (rk54) enqueue_step_rk54(C, u, dt_fixed, dt_log_dev, alpha_log_dev, ss);
+        else enqueue_step(C, u, dt_fixed, dt_log_dev, alpha_log_dev, ss);
+    };
     hipStream_t s = (hipStream_t)stream;
     // step counter / fixed step
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, C->d_dt, dt_fixed > 0.0 ? dt_fixed : 0.0, C->d_ctr);
     if (C->prof) {
         C->prev = nullptr;
-        for (int st = 0; st < nsteps; ++st) enqueue_step(C, u, dt_fixed, dt_log_dev, alpha_log_dev, s);
+        for (int st = 0; st < nsteps; ++st) step(s);
         C->last = s;
         return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
     }
@@ -3083,7 +3201,7 @@ int sedg_rk_step(sedg_ctx *C, double *u, int nsteps, double dt_fixed, double *dt
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SEDG_EHIP;
         hipGraph_t graph;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
-        enqueue_step(C, u, dt_fixed, dt_log_dev, alpha_log_dev, cs);
+        step(cs);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -3227,6 +3345,7 @@ int sedg_diagnose(sedg_ctx *C, const double *u, double *dudt, double *alpha_bar,
 
 int sedg_rk_step_frozen(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, const double *factors, void *stream)
 {
+    if (C && C->params.integrator != SEDG_SSPRK3) return SEDG_EUNSUPPORTED;
     if (!C || !u || nsteps < 0 || (nsteps > 0 && (!dt_dev || !factors))) return SEDG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long long na = (long long)C->A * C->nel;
@@ -3346,6 +3465,7 @@ extern "C" {
 
 int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, double *tapes, void *stream)
 {
+    if (C && C->params.integrator != SEDG_SSPRK3) return SEDG_EUNSUPPORTED;
     if (!C || !u || nsteps < 0 || (nsteps > 0 && (!dt_dev || !tapes))) return SEDG_EINVAL;
     if (C->params.mode == SEDG_EXTERNAL) return SEDG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -3400,6 +3520,7 @@ int sedg_rk_step_tape(sedg_ctx *C, double *u, int nsteps, const double *dt_dev, 
 
 int sedg_adjoint_rk_step(sedg_ctx *C, const double *tapes, int nsteps, const double *dt_dev, double *lam, void *stream)
 {
+    if (C && C->params.integrator != SEDG_SSPRK3) return SEDG_EUNSUPPORTED;
     if (!C || !lam || nsteps < 0 || (nsteps > 0 && (!tapes || !dt_dev))) return SEDG_EINVAL;
     if (!adjoint_supported(C)) return SEDG_EUNSUPPORTED;
     int rc = ensure_adjoint_buffers(C);
@@ -3544,6 +3665,7 @@ KArgs batch_args(const sedg_batch *B)
     P.alpha_H = B->params.alpha_H;
     P.alpha_L = B->params.alpha_L;
     P.beta_L = B->params.beta_L;
+    P.sigma_floor = B->params.sigma_floor > 0.0 ? B->params.sigma_floor : 1.0;
     return P;
 }
 
@@ -3619,7 +3741,8 @@ int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *par
 {
     if (!meshes || count < 1 || !params || !out) return SEDG_EINVAL;
     *out = nullptr;
-    if (params->top_level != 0 || params->mode == SEDG_EXTERNAL || params->mode < 0 || params->mode > 3)
+    if (params->top_level != 0 || params->mode == SEDG_EXTERNAL || params->mode < 0 || params->mode > 3 ||
+        params->integrator != SEDG_SSPRK3)
         return SEDG_EINVAL;
     for (int p = 0; p < count; ++p) {
         const sedg_mesh &m = meshes[p];
@@ -3931,6 +4054,7 @@ int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const dou
     P.alpha_H = params->alpha_H;
     P.alpha_L = params->alpha_L;
     P.beta_L = params->beta_L;
+    P.sigma_floor = params->sigma_floor > 0.0 ? params->sigma_floor : 1.0;
     P.u = u;
     P.out = dudt;
     P.stage = 0;

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsedg.so")
 
 SEDG_OK, SEDG_EINVAL, SEDG_EHIP, SEDG_ENOMEM, SEDG_ESTATE, SEDG_EUNSUPPORTED, SEDG_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+SEDG_SSPRK3, SEDG_SSPRK54 = 0, 1
 
 EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "sedg_set_params",
             "sedg_rhs", "sedg_max_dt", "sedg_rk_step", "sedg_check", "sedg_tables", "sedg_strerror",
@@ -48,7 +49,7 @@ class Params_c(ctypes.Structure):
     _fields_ = [("tau_A", ctypes.c_double), ("tau_S", ctypes.c_double), ("alpha_H", ctypes.c_double),
                 ("alpha_L", ctypes.c_double), ("beta_L", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("top_level", ctypes.c_int), ("level_mask", ctypes.c_uint), ("mode", ctypes.c_int),
-                ("seed", ctypes.c_ulonglong)]
+                ("seed", ctypes.c_ulonglong), ("sigma_floor", ctypes.c_double), ("integrator", ctypes.c_int)]
 
 
 class Diag_c(ctypes.Structure):
@@ -139,6 +140,8 @@ def params_c(p) -> Params_c:
     s.tau_A, s.tau_S, s.alpha_H, s.alpha_L, s.beta_L, s.cfl = p.tau_A, p.tau_S, p.alpha_H, p.alpha_L, p.beta_L, p.cfl
     s.top_level, s.level_mask, s.mode = p.top_level, p.level_mask, p.mode
     s.seed = int(getattr(p, "seed", 0))
+    s.sigma_floor = float(getattr(p, "sigma_floor", 0.0))
+    s.integrator = int(getattr(p, "integrator", 0))
     return s
 
 
@@ -220,8 +223,9 @@ class Solver:
         _check(load().sedg_max_dt(self._h, _ptr(u), _ptr(dt_out), _stream(stream)), "sedg_max_dt")
 
     def rk_step(self, u, nsteps, dt_fixed=0.0, dt_log=None, alpha_log=None, stream=None):
-        """nsteps SSP-RK3 steps of u in place; dt_log (nsteps) and alpha_log (3 * nsteps *
-        alpha_len, step-major) optionally receive the step sizes and every stage's factors."""
+        """nsteps steps of the context's integrator (SSP-RK3 or SSP-RK(5,4)) of u in place;
+        dt_log (nsteps) and alpha_log (stages * nsteps * alpha_len, step-major) optionally
+        receive the step sizes and every stage's factors."""
         _check(load().sedg_rk_step(self._h, _ptr(u), int(nsteps), float(dt_fixed), _ptr(dt_log), _ptr(alpha_log),
                                    _stream(stream)), "sedg_rk_step")
 

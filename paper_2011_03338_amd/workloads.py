@@ -84,6 +84,8 @@ class Params:
     level_mask: int = 0         # 0 -> all levels
     mode: int = ADAPTIVE
     seed: int = 0               # RANDOM mode: generator seed
+    sigma_floor: float = 0.0    # indicator denominator floor; 0 -> the paper's 1
+    integrator: int = 0         # 0: SSP-RK3, 1: SSP-RK(5,4)
 
 
 def alpha_len(mesh: Mesh, params: Params) -> int:
@@ -273,15 +275,60 @@ def ensemble_problem(desc):
     return sedov(desc["seed"], desc["side"], desc["K"], E=desc["E"], rc=0.2)
 
 
-def sod_tube(nelem: int = 32, K: int = 8):
-    """Sod shock tube on [0, 1] (diaphragm at x = 0.5; (rho, v, p) = (1, 0, 1) left,
-    (0.125, 0, 0.1) right), laid out as a 2-D strip of nelem x 1 elements, outflow
-    in x and periodic in y, so every row of subcells evolves as the 1-D problem.
-    The diaphragm falls on a subcell edge, so the means are exact."""
-    mesh = Mesh(2, K, [nelem, 1], [0.0, 0.0], [1.0, 1.0 / nelem], [OUTFLOW, PERIODIC])
-    xc = 0.5 * (mesh.edges(0)[1:] + mesh.edges(0)[:-1])
-    left = xc < 0.5
+def _tube_mesh(nelem: int, K: int, lo: float, hi: float, dim: int) -> Mesh:
+    """1-D tube mesh (dim 1), or the same tube as a 2-D strip of nelem x 1 elements,
+    outflow in x and periodic in y, every row of subcells evolving as the 1-D problem."""
+    if dim == 1:
+        return Mesh(1, K, [nelem], [lo], [hi], [OUTFLOW])
+    return Mesh(2, K, [nelem, 1], [lo, 0.0], [hi, (hi - lo) / nelem], [OUTFLOW, PERIODIC])
+
+
+def _tube_state(mesh: Mesh, rho, m, E) -> np.ndarray:
     u = np.zeros(mesh.shape())
-    u[0, 0] = np.where(left, 1.0, 0.125)[None, :]
-    u[3, 0] = (np.where(left, 1.0, 0.1) / (mesh.gamma - 1.0))[None, :]
-    return mesh, u, {"x_diaphragm": 0.5, "T": 0.2}
+    u[0, 0] = np.asarray(rho)[None, :]
+    u[1, 0] = np.asarray(m)[None, :]
+    u[mesh.dim + 1, 0] = np.asarray(E)[None, :]
+    return u
+
+
+def riemann_tube(left, right, x_d: float, T: float, nelem: int = 32, K: int = 8, lo: float = 0.0,
+                 hi: float = 1.0, dim: int = 2, gamma: float = 1.4):
+    """Riemann problem (rho, v, p) = left for x < x_d, right for x >= x_d; cell means exact
+    (the diaphragm may cut a subcell)."""
+    mesh = _tube_mesh(nelem, K, lo, hi, dim)
+    fr = _frac_right(mesh.edges(0), x_d)
+
+    def cons(st):
+        rho, v, p = st
+        return rho, rho * v, p / (gamma - 1.0) + 0.5 * rho * v * v
+
+    cl, cr = cons(left), cons(right)
+    u = _tube_state(mesh, *[(1.0 - fr) * a + fr * b for a, b in zip(cl, cr)])
+    return mesh, u, {"x_diaphragm": x_d, "T": T, "left": tuple(left), "right": tuple(right)}
+
+
+def sod_tube(nelem: int = 32, K: int = 8, dim: int = 2):
+    """Sod shock tube on [0, 1] (Sec. 3.4): diaphragm at x = 0.5; (rho, v, p) = (1, 0, 1)
+    left, (0.125, 0, 0.1) right; final time 0.2.  The diaphragm falls on a subcell edge."""
+    return riemann_tube((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.5, 0.2, nelem, K, dim=dim)
+
+
+def lax_tube(nelem: int = 32, K: int = 8, dim: int = 2):
+    """Lax shock tube on [0, 1] (Sec. 3.4): diaphragm at 0.5, (rho, v, p) =
+    (0.445, 0.689, 3.528) left, (0.5, 0, 0.571) right, final time 0.15 (the values and
+    the time the text prints)."""
+    return riemann_tube((0.445, 0.689, 3.528), (0.5, 0.0, 0.571), 0.5, 0.15, nelem, K, dim=dim)
+
+
+def shu_osher(nelem: int = 32, K: int = 8, dim: int = 2, gamma: float = 1.4):
+    """Shu-Osher tube on [-4.5, 4.5] (Sec. 3.4): (rho, v, p) = (3.8567143, 2.629369,
+    10.33333) for x < -4, (1 + 0.2 sin(5 x), 0, 1) beyond; final time 1.8.  Means exact:
+    the subcell holding x = -4 is split, the sine integrated."""
+    mesh = _tube_mesh(nelem, K, -4.5, 4.5, dim)
+    e = mesh.edges(0)
+    fr = _frac_right(e, -4.0)
+    rl, vl, pl = 3.8567143, 2.629369, 10.33333
+    rho = (1.0 - fr) * rl + fr * 1.0 + 0.2 * _int_sin_right(e, 5.0, -4.0)
+    m = (1.0 - fr) * rl * vl
+    E = (1.0 - fr) * (pl / (gamma - 1.0) + 0.5 * rl * vl * vl) + fr * (1.0 / (gamma - 1.0))
+    return mesh, _tube_state(mesh, rho, m, E), {"T": 1.8}

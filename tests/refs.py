@@ -171,12 +171,19 @@ def dgsem_rhs(mesh, ubar, n, tabs=None):
             ir = np.concatenate([np.arange(1, nE), [nE - 1]])
             left_nb = np.take(tr_p, il, axis=eax_t)
             right_nb = np.take(tr_m, ir, axis=eax_t)
-            # outflow: exterior state equals the interior trace
+            # outflow: the exterior state is the boundary subcell's mean (zero gradient of the
+            # subcell means), nodal along the face
+            bt = b
+            for c2 in range(dim):
+                if c2 != a:
+                    bt = _apply(bt, T["R"], c2, dim)
+            g_lo = np.take(bt, 0, axis=ax)
+            g_hi = np.take(bt, bt.shape[ax] - 1, axis=ax)
             sl = [slice(None)] * tr_m.ndim
             sl[eax_t] = 0
-            left_nb[tuple(sl)] = tr_m[tuple(sl)]
+            left_nb[tuple(sl)] = g_lo[tuple(sl)]
             sl[eax_t] = nE - 1
-            right_nb[tuple(sl)] = tr_p[tuple(sl)]
+            right_nb[tuple(sl)] = g_hi[tuple(sl)]
         fl = hlle(left_nb, tr_m, dim, a)
         fr = hlle(tr_p, right_nb, dim, a)
         surf = np.expand_dims(fl, ax) * Bl.reshape([-1 if i == ax else 1 for i in range(ut.ndim)]) + \
@@ -225,12 +232,13 @@ def ml1d_rhs(K, nelem, dx, ubar, alphas, levels, periodic=True, g=GAMMA):
         left = np.roll(up[:, :, K - 1], 1, axis=1)
         right = np.roll(um[:, :, 0], -1, axis=1)
     else:
+        # outflow: the exterior state is the boundary subcell's mean
         left = up[:, :, K - 1].copy()
         left[:, 1:] = up[:, :-1, K - 1]
-        left[:, 0] = um[:, 0, 0]
+        left[:, 0] = U[:, 0, 0]
         right = um[:, :, 0].copy()
         right[:, :-1] = um[:, 1:, 0]
-        right[:, -1] = up[:, -1, K - 1]
+        right[:, -1] = U[:, -1, K - 1]
     Up = np.concatenate([left[:, :, None], up], axis=2)       # (nv, nelem, K+1)
     Um = np.concatenate([um, right[:, :, None]], axis=2)
     fstar = hlle(Up, Um, dim, 0, g)                           # (nv, nelem, K+1)

@@ -113,7 +113,7 @@ def test_random_rk_steps_match_oracle(K, ne):
     err = rel_err(ug.cpu().numpy(), u_o)
     dterr = np.abs(dts.cpu().numpy() - dts_o).max() / dts_o.max()
     say("  random rk3 K=%d 100 steps rel_err=%.3e dt_err=%.3e" % (K, err, dterr))
-    assert err <= STATE_TOL and dterr <= 1e-13
+    assert err <= STATE_TOL and dterr <= 1e-11
     la = alog.view(300, mesh.nel, A // mesh.nel).cpu().numpy()
     for d in (0, 1, 2, 150, 299):
         assert np.array_equal(la[d], random_factors(p.seed, d, mesh.nel, A // mesh.nel)), d
@@ -256,3 +256,44 @@ def test_rk_step_frozen_matches_oracle_frozen_steps():
     err = rel_err(got, x)
     say("  frozen steps vs oracle rel_err=%.3e" % err)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("K", [4, 8])
+def test_rk54_steps_match_oracle(K):
+    """SSP-RK(5,4), the paper's integrator: 100 steps at CFL 0.8 within 1e-9 of the
+    oracle's, step sizes (functions of the state) within 1e-11 (K = 4: the config-0 jump
+    on 16x16 elements; K = 8: the narrow blast of 16x16 elements, as the config-0 jump at
+    K = 8 is no multi-step case); in RANDOM mode the five stages of every step log the
+    oracle's draws."""
+    mesh, u, _ = W.config0(0, 16, 4) if K == 4 else W.sedov(4, 16, 8, L=0.5, sigma=0.01)
+    p = W.Params(cfl=0.8, integrator=sedg.SEDG_SSPRK54)
+    u_o, dts_o = O.rk3(mesh, p, u, 100)
+    s = sedg.Solver(mesh, p)
+    ug = _t(u)
+    dts = torch.zeros(100, dtype=torch.float64, device=DEV)
+    s.rk_step(ug, 100, 0.0, dts)
+    s.check()
+    err = rel_err(ug.cpu().numpy(), u_o)
+    dterr = np.abs(dts.cpu().numpy() - dts_o).max() / dts_o.max()
+    say("  ssp-rk(5,4) K=%d 100 steps rel_err=%.3e dt_err=%.3e" % (K, err, dterr))
+    assert err <= STATE_TOL and dterr <= 1e-11
+    # the step tape and the adjoint steps are SSP-RK3 only
+    tape = torch.empty(s.tape_len, dtype=torch.float64, device=DEV)
+    with pytest.raises(sedg.SedgError) as ei:
+        s.rk_step_tape(ug, dts[:1], tape)
+    assert ei.value.code == sedg.SEDG_EUNSUPPORTED
+    s.close()
+    pr = W.Params(cfl=0.8, integrator=sedg.SEDG_SSPRK54, mode=W.RANDOM, seed=3)
+    mesh, u, _ = W.config0(0, 8, K)
+    u_o, _ = O.rk3(mesh, pr, u, 10)
+    s = sedg.Solver(mesh, pr)
+    A = s.alpha_len
+    ug = _t(u)
+    alog = torch.zeros(50 * A, dtype=torch.float64, device=DEV)
+    s.rk_step(ug, 10, 0.0, None, alog)
+    s.check()
+    assert rel_err(ug.cpu().numpy(), u_o) <= STATE_TOL
+    la = alog.view(50, mesh.nel, A // mesh.nel).cpu().numpy()
+    for d in (0, 4, 5, 49):
+        assert np.array_equal(la[d], random_factors(pr.seed, d, mesh.nel, A // mesh.nel)), d
+    s.close()

@@ -261,3 +261,18 @@ def test_hlle_consistency_and_contact():
     F, _, _ = _oracle_interface_flux((1.0, 0.0, 1.0), (0.25, 0.0, 1.0))
     assert abs(F[1] - 1.0) <= 1e-14 and abs(F[2]) <= 1e-14
     assert F[0] > 0.0
+
+
+def test_indicator_floor_parameter():
+    """The floor of the denominator (1 in eq. calc-blending-factor) as a parameter: with a
+    floor below the measures, the small-amplitude case is judged by its relative
+    difference (0.115 > tau_S + 1/tau_A, so the factor is clamped to 0), the others are
+    unchanged (their measures exceed 1)."""
+    for name in CASES:
+        rho, E = CASES[name]
+        mesh, u = _state_1d(rho, E)
+        _, info = O.rhs(mesh, W.Params(sigma_floor=1e-14), u, full=True)
+        if name == "rho_C_small":
+            assert info["alpha"][0][0] == 0.0
+        elif name != "p_B":
+            assert abs(info["alpha"][0][0] - _expected(name)[0]) <= 1e-11
