@@ -296,6 +296,35 @@ int sedg_batch_rk_step(sedg_batch *batch, double *u, int nsteps, double dt_fixed
  * with the problem index and its element index, else SEDG_OK and -1, -1. */
 int sedg_batch_check(sedg_batch *batch, int *bad_problem, long *bad_elem);
 
+/* ---- refinement and coarsening (App., non-conforming interfaces) ----------------
+ * Blended refinement of every element of the context's mesh into 2^dim children
+ * (eq. 3D-refinement) and its reverse, the blended coarsening of every family of
+ * 2^dim children (eq. 3D-coarsening), as the building blocks of 4:1 non-conforming
+ * meshes.  The fine mesh has twice the elements of the context's mesh along every axis
+ * and the same K: its state (2^dim * sedg_state_len doubles, same layout) is the state
+ * on the doubled global subcell grid.  Written for the multi-level weights of eq.
+ * blending-weights: a fine subcell receives theta_FV times its parent cell's mean (the
+ * expansion E = I (x) 1_2) plus, per DG level n, theta^(n) times the mean over the fine
+ * subcell of the level-n sub-element's nodal polynomial (Z = P^(n->2n) along every
+ * axis); coarsening compresses each child with its own weights (C = 1/2 I (x) 1_2^T,
+ * Q = P^(n->n/2)) and glues the children.  With single-level factors (level mask
+ * {1, K}) these are the paper's formulas.  Both conserve every element's integral for
+ * any factors.
+ *   u, u_fine     device states of the context's mesh and of the fine mesh
+ *   alpha         device, the factors of the context's elements (refine) or of the
+ *                 fine elements (coarsen), A per element in the layout above
+ * Asynchronous; in and out must not alias.  Allocates the context's tables on first
+ * use (SEDG_ENOMEM). */
+int sedg_refine(sedg_ctx *ctx, const double *u, const double *alpha, double *u_fine, void *stream);
+int sedg_coarsen(sedg_ctx *ctx, const double *u_fine, const double *alpha_fine, double *u, void *stream);
+
+/* Host-only: the refinement, coarsening and mortar tables of level n (2, 4, 8) for
+ * node family fam, in the order Z = P^(n->2n) [2n*n], Q = P^(n->n/2) [(n/2)*n],
+ * L_- [n*n], L_+ [n*n] (row-major; (L_+-)_ij = l_i(xi_j/2 +- 1/4) w_j / (2 w_i), the
+ * L2 projection of a fine face's flux onto the coarse face, App. non-conforming
+ * interfaces).  Returns the count written or SEDG_EINVAL. */
+int sedg_nc_tables(int n, int family, double *out, int cap);
+
 /* Host-only: the library's own operator tables of level n (2, 4, 8) for node
  * family fam, in the order xi[n], w[n], Dcal[n*n], D[n*n], bm[n], bp[n],
  * P[n*n], R[n*n], Dhat[n*n], Bhat_left[n], Bhat_right[n], Iplus[n*n],

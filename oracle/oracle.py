@@ -170,6 +170,61 @@ def alpha_bar(mesh, params, alpha):
     return out.reshape(g[2], g[1], g[0])
 
 
+def nc_tables(n: int, family: int = 0) -> dict:
+    """Z = P^(n->2n), Q = P^(n->n/2) and the mortar matrices L_-, L_+ of level n."""
+    L = lib()
+    L.or_nc_tables.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    buf = np.zeros(8 * 64)
+    if L.or_nc_tables(n, family, _ptr(buf), buf.size) < 0:
+        raise OracleError("bad level")
+    h = n // 2
+    o = [0, 2 * n * n, 2 * n * n + h * n, 3 * n * n + h * n, 4 * n * n + h * n]
+    return {"Z": buf[o[0]:o[1]].reshape(2 * n, n).copy(), "Q": buf[o[1]:o[2]].reshape(h, n).copy(),
+            "Lm": buf[o[2]:o[3]].reshape(n, n).copy(), "Lp": buf[o[3]:o[4]].reshape(n, n).copy()}
+
+
+def _setup_rc():
+    L = lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    for f in (L.or_refine, L.or_coarsen):
+        f.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), dp, dp, dp]
+        f.restype = ctypes.c_int
+    return L
+
+
+def fine_mesh(mesh):
+    """The mesh with twice the elements per axis (same box, K and boundaries)."""
+    import dataclasses
+    ne = list(mesh.nelem)
+    return dataclasses.replace(mesh, nelem=[2 * x for x in ne])
+
+
+def refine(mesh, params, u, alpha):
+    """Blended refinement (eq. 3D-refinement) of every element into 2^dim children:
+    the state on fine_mesh(mesh)."""
+    L = _setup_rc()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    fm = fine_mesh(mesh)
+    out = np.zeros(fm.shape())
+    rc = L.or_refine(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(u),
+                     _ptr(np.ascontiguousarray(alpha, dtype=np.float64)), _ptr(out))
+    if rc != 0:
+        raise OracleError("or_refine failed: %d" % rc)
+    return out
+
+
+def coarsen(mesh, params, u_fine, alpha_fine):
+    """Blended coarsening (eq. 3D-coarsening) of the state on fine_mesh(mesh) onto mesh."""
+    L = _setup_rc()
+    uf = np.ascontiguousarray(u_fine, dtype=np.float64)
+    out = np.zeros(mesh.shape())
+    rc = L.or_coarsen(ctypes.byref(_mesh(mesh)), ctypes.byref(_params(params)), _ptr(uf),
+                      _ptr(np.ascontiguousarray(alpha_fine, dtype=np.float64)), _ptr(out))
+    if rc != 0:
+        raise OracleError("or_coarsen failed: %d" % rc)
+    return out
+
+
 def num_threads() -> int:
     return lib().or_num_threads()
 

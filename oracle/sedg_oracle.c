@@ -241,6 +241,51 @@ int or_tables(int n, int fam, double *out, int cap)
     return (int)(o - out);
 }
 
+/* Projection of n nodal values onto m equal subcell means of [-1/2, 1/2] (Sec. 2.3
+   with m subcells): P^(n->m)_ij = m * integral of l_j over subcell i, by the n-point
+   Gauss rule on each subcell (exact: l_j has degree n - 1).  Z = P^(n->2n) and
+   Q = P^(n->n/2) of the non-conforming appendix. */
+static void proj_nm(int n, int m, int fam, double *M)
+{
+    ld x[MAXK], w[MAXK], gx[MAXK], gw[MAXK];
+    if (fam == OR_LGL) lgl_nodes(n, x, w);
+    else gauss_nodes(n, x, w);
+    gauss_nodes(n, gx, gw);
+    for (int i = 0; i < m; i++) {
+        ld a = -0.5L + (ld)i / m, b = -0.5L + (ld)(i + 1) / m;
+        for (int j = 0; j < n; j++) {
+            ld s = 0.0L;
+            for (int q = 0; q < n; q++) s += (b - a) * gw[q] * lagr(n, x, j, 0.5L * (a + b) + (b - a) * gx[q]);
+            M[i * n + j] = (double)((ld)m * s);
+        }
+    }
+}
+
+/* Mortar projection matrices (L_+-)_ij = l_i(xi_j / 2 +- 1/4) w_j / (2 w_i) (App.,
+   L2 projection of the fine faces' fluxes onto the coarse face). */
+static void mortar_mats(int n, int fam, double *Lm, double *Lp)
+{
+    ld x[MAXK], w[MAXK];
+    if (fam == OR_LGL) lgl_nodes(n, x, w);
+    else gauss_nodes(n, x, w);
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            Lm[i * n + j] = (double)(lagr(n, x, i, 0.5L * x[j] - 0.25L) * w[j] / (2.0L * w[i]));
+            Lp[i * n + j] = (double)(lagr(n, x, i, 0.5L * x[j] + 0.25L) * w[j] / (2.0L * w[i]));
+        }
+}
+
+int or_nc_tables(int n, int fam, double *out, int cap)
+{
+    if (n < 2 || n > MAXK || (n & (n - 1))) return OR_EINVAL;
+    int need = 2 * n * n + (n / 2) * n + 2 * n * n;
+    if (cap < need) return OR_EINVAL;
+    proj_nm(n, 2 * n, fam, out);
+    proj_nm(n, n / 2, fam, out + 2 * n * n);
+    mortar_mats(n, fam, out + 2 * n * n + (n / 2) * n, out + 3 * n * n + (n / 2) * n);
+    return need;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Compressible Euler physics (Sec. 3.1)                                      */
 /* ------------------------------------------------------------------------- */
@@ -1930,5 +1975,174 @@ int or_adjoint_rhs(const or_mesh *m, const or_params *p, const double *u, const 
     free(gF); free(gside); free(gu); free(xraw); free(araw);
     free_work(&W);
     free(c);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Blended refinement and coarsening (App., non-conforming interfaces)        */
+/* ------------------------------------------------------------------------- */
+/* Refinement (eq. 3D-refinement) with the multi-level weights: fine subcell f of parent
+   cell c gets theta_FV(c) * ubar_c (the expansion E = I (x) 1_2 repeats the mean) plus
+   sum_n theta_n(c) * (u~_s x_1 Z x_2 Z x_3 Z)_f with u~_s the nodal polynomial of the
+   level-n sub-element holding c and Z = P^(n->2n).  The fine mesh doubles the element
+   count per axis; its state is on the doubled global subcell grid. */
+int or_refine(const or_mesh *m, const or_params *p, const double *u, const double *alpha, double *u_fine)
+{
+    ctx_t *c = malloc(sizeof(ctx_t));
+    if (!c) return OR_EINVAL;
+    int rc = make_ctx(m, p, c);
+    if (rc) { free(c); return rc; }
+    int dim = c->dim, K = c->K, nv = c->nv;
+    long Gf[3];
+    long doff = 1;
+    for (int a = 0; a < 3; a++) { Gf[a] = a < dim ? 2L * c->G[a] : 1; doff *= Gf[a]; }
+    double ub[MAXV * MAXK * MAXK * MAXK], us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK];
+    double Z[MAXLEV][2 * MAXK * MAXK];
+    for (int li = 0; li < c->nlev; li++) proj_nm(c->lev_n[li], 2 * c->lev_n[li], c->m.family, Z[li]);
+#pragma omp parallel for private(ub, us, ut)
+    for (int e = 0; e < c->nel; e++) {
+        int e3[3];
+        elem_coords(c, e, e3);
+        gather_elem(c, u, e, ub);
+        const double *al = alpha + (long)e * c->A;
+        int ky = dim > 1 ? K : 1, kz = dim > 2 ? K : 1;
+        int F = 2 * K, fy = dim > 1 ? F : 1, fz = dim > 2 ? F : 1;
+        for (int v = 0; v < nv; v++) {
+            /* FV part: theta_FV of the parent cell times its mean, on each of its fine cells */
+            double out[2 * MAXK * 2 * MAXK * 2 * MAXK];
+            for (int k = 0; k < fz; k++)
+                for (int j = 0; j < fy; j++)
+                    for (int i = 0; i < F; i++) {
+                        double th[MAXLEV + 1];
+                        theta_cell(c, al, i / 2, j / 2, k / 2, th);
+                        out[i + F * (j + F * k)] = th[0] * ub[v * c->Kd + i / 2 + K * (j / 2 + K * (k / 2))];
+                    }
+            for (int li = 0; li < c->nlev; li++) {
+                int n = c->lev_n[li], ns = K / n;
+                int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+                int ny = dim > 1 ? n : 1, nz = dim > 2 ? n : 1, nd = n * ny * nz;
+                for (int s3 = 0; s3 < sz; s3++)
+                    for (int s2 = 0; s2 < sy; s2++)
+                        for (int s1 = 0; s1 < ns; s1++) {
+                            double th[MAXLEV + 1];
+                            theta_cell(c, al, s1 * n, s2 * n, s3 * n, th);
+                            double thn = th[1 + li];
+                            if (thn == 0.0) continue;
+                            gather_sub(c, ub, n, s1 * n, s2 * n, s3 * n, us);
+                            reconstruct(c, &c->L[li], us, ut);
+                            /* means over the 2n^d fine subcells: Z along every axis */
+                            double fine[2 * MAXK * 2 * MAXK * 2 * MAXK], t1[2 * MAXK * 2 * MAXK * 2 * MAXK];
+                            int ext[3] = {n, ny, nz};
+                            memcpy(fine, ut + v * nd, sizeof(double) * nd);
+                            for (int a = 0; a < dim; a++) {
+                                mode_product(fine, ext, a, Z[li], 2 * n, t1);
+                                ext[a] = 2 * n;
+                                memcpy(fine, t1, sizeof(double) * ext[0] * ext[1] * ext[2]);
+                            }
+                            for (int k = 0; k < ext[2]; k++)
+                                for (int j = 0; j < ext[1]; j++)
+                                    for (int i = 0; i < ext[0]; i++)
+                                        out[(2 * s1 * n + i) + F * ((dim > 1 ? 2 * s2 * n : 0) + j +
+                                                                     F * ((dim > 2 ? 2 * s3 * n : 0) + k))] +=
+                                            thn * fine[i + ext[0] * (j + ext[1] * k)];
+                        }
+            }
+            for (int k = 0; k < fz; k++)
+                for (int j = 0; j < fy; j++)
+                    for (int i = 0; i < F; i++) {
+                        long gx = 2L * e3[0] * K + i, gy = dim > 1 ? 2L * e3[1] * K + j : 0,
+                             gz = dim > 2 ? 2L * e3[2] * K + k : 0;
+                        u_fine[v * doff + gx + Gf[0] * (gy + Gf[1] * gz)] = out[i + F * (j + F * k)];
+                    }
+        }
+    }
+    free(c);
+    return OR_OK;
+}
+
+/* Coarsening (eq. 3D-coarsening) with the multi-level weights, each child r of the fine
+   mesh separately with its own factors: coarse cell q (covering the child's fine cells
+   2q .. 2q+1 per axis) gets theta_FV * (mean of those fine cells: C = 1/2 I (x) 1_2^T)
+   plus sum_n theta_n * (u~_s x_1 Q x_2 Q x_3 Q)_q, Q = P^(n->n/2), the weights those of
+   the fine cell 2q (every level's sub-element holds the pair); then the 2^d children
+   are glued into their parent.  m and p describe the coarse mesh; alpha_fine holds the
+   fine elements' factors. */
+int or_coarsen(const or_mesh *m, const or_params *p, const double *u_fine, const double *alpha_fine, double *u)
+{
+    or_mesh mf = *m;
+    for (int a = 0; a < m->dim; a++) mf.nelem[a] = 2 * m->nelem[a];
+    ctx_t *c = malloc(sizeof(ctx_t)), *cf = malloc(sizeof(ctx_t));
+    if (!c || !cf) { free(c); free(cf); return OR_EINVAL; }
+    int rc = make_ctx(m, p, c);
+    if (!rc) rc = make_ctx(&mf, p, cf);
+    if (rc) { free(c); free(cf); return rc; }
+    int dim = c->dim, K = c->K, nv = c->nv, H = K / 2;
+    double Q[MAXLEV][MAXK * MAXK];
+    for (int li = 0; li < cf->nlev; li++) proj_nm(cf->lev_n[li], cf->lev_n[li] / 2, cf->m.family, Q[li]);
+    double ub[MAXV * MAXK * MAXK * MAXK], us[MAXV * MAXK * MAXK * MAXK], ut[MAXV * MAXK * MAXK * MAXK];
+#pragma omp parallel for private(ub, us, ut)
+    for (int ef = 0; ef < cf->nel; ef++) {
+        int f3[3];
+        elem_coords(cf, ef, f3);
+        gather_elem(cf, u_fine, ef, ub);
+        const double *al = alpha_fine + (long)ef * cf->A;
+        int hy = dim > 1 ? H : 1, hz = dim > 2 ? H : 1;
+        for (int v = 0; v < nv; v++) {
+            double out[MAXK * MAXK * MAXK];
+            for (int k = 0; k < hz; k++)
+                for (int j = 0; j < hy; j++)
+                    for (int i = 0; i < H; i++) {
+                        double th[MAXLEV + 1], s = 0.0;
+                        theta_cell(cf, al, 2 * i, 2 * j, 2 * k, th);
+                        int cnt = 0;
+                        for (int dk = 0; dk < (dim > 2 ? 2 : 1); dk++)
+                            for (int dj = 0; dj < (dim > 1 ? 2 : 1); dj++)
+                                for (int di = 0; di < 2; di++) {
+                                    s += ub[v * cf->Kd + (2 * i + di) + K * ((2 * j + dj) + K * (2 * k + dk))];
+                                    cnt++;
+                                }
+                        out[i + H * (j + H * k)] = th[0] * (s / cnt);
+                    }
+            for (int li = 0; li < cf->nlev; li++) {
+                int n = cf->lev_n[li], ns = K / n, h = n / 2;
+                int sy = dim > 1 ? ns : 1, sz = dim > 2 ? ns : 1;
+                int ny = dim > 1 ? n : 1, nz = dim > 2 ? n : 1, nd = n * ny * nz;
+                for (int s3 = 0; s3 < sz; s3++)
+                    for (int s2 = 0; s2 < sy; s2++)
+                        for (int s1 = 0; s1 < ns; s1++) {
+                            double th[MAXLEV + 1];
+                            theta_cell(cf, al, s1 * n, s2 * n, s3 * n, th);
+                            double thn = th[1 + li];
+                            if (thn == 0.0) continue;
+                            gather_sub(cf, ub, n, s1 * n, s2 * n, s3 * n, us);
+                            reconstruct(cf, &cf->L[li], us, ut);
+                            double a1[MAXK * MAXK * MAXK], a2[MAXK * MAXK * MAXK];
+                            int ext[3] = {n, ny, nz};
+                            memcpy(a1, ut + v * nd, sizeof(double) * nd);
+                            for (int a = 0; a < dim; a++) {
+                                mode_product(a1, ext, a, Q[li], h, a2);
+                                ext[a] = h;
+                                memcpy(a1, a2, sizeof(double) * ext[0] * ext[1] * ext[2]);
+                            }
+                            for (int k = 0; k < ext[2]; k++)
+                                for (int j = 0; j < ext[1]; j++)
+                                    for (int i = 0; i < ext[0]; i++)
+                                        out[(s1 * h + i) + H * ((dim > 1 ? s2 * h : 0) + j + H * ((dim > 2 ? s3 * h : 0) + k))] +=
+                                            thn * a1[i + ext[0] * (j + ext[1] * k)];
+                        }
+            }
+            /* glue: the child's (K/2)^d coarse cells into its parent */
+            for (int k = 0; k < hz; k++)
+                for (int j = 0; j < hy; j++)
+                    for (int i = 0; i < H; i++) {
+                        long gx = (long)(f3[0] / 2) * K + (f3[0] % 2) * H + i;
+                        long gy = dim > 1 ? (long)(f3[1] / 2) * K + (f3[1] % 2) * H + j : 0;
+                        long gz = dim > 2 ? (long)(f3[2] / 2) * K + (f3[2] % 2) * H + k : 0;
+                        u[v * c->dof + gx + c->G[0] * (gy + (long)c->G[1] * gz)] = out[i + H * (j + H * k)];
+                    }
+        }
+    }
+    free(c);
+    free(cf);
     return OR_OK;
 }

@@ -104,6 +104,16 @@ int or_adjoint_rhs(const or_mesh *m, const or_params *p, const double *u, const 
  * factors alpha (nel * A): abar[dof] in the state layout of one variable. */
 int or_alpha_bar(const or_mesh *m, const or_params *p, const double *alpha, double *abar);
 
+/* Tables of the non-conforming appendix for level n: Z = P^(n->2n) [2n*n],
+ * Q = P^(n->n/2) [(n/2)*n], L_- [n*n], L_+ [n*n].  Returns the count or OR_EINVAL. */
+int or_nc_tables(int n, int fam, double *out, int cap);
+
+/* Blended refinement (eq. 3D-refinement) of every element of mesh m into 2^dim
+ * children, and the blended coarsening (eq. 3D-coarsening) of the mesh with twice the
+ * elements per axis back onto m; alpha: factors of the input mesh's elements. */
+int or_refine(const or_mesh *m, const or_params *p, const double *u, const double *alpha, double *u_fine);
+int or_coarsen(const or_mesh *m, const or_params *p, const double *u_fine, const double *alpha_fine, double *u);
+
 /* Number of OpenMP threads the oracle runs with. */
 int or_num_threads(void);
 

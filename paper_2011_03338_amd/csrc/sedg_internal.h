@@ -26,4 +26,17 @@ struct sedg_level_tab {
 
 int sedg_build_level(int n, int family, sedg_level_tab *T);
 
+// Tables of the refinement / coarsening and mortar operators of level n (App.,
+// non-conforming interfaces); matrices row-major.
+struct sedg_nc_tab {
+    int n;
+    int pad;
+    double Z[2 * MAXN * MAXN];   // P^(n -> 2n): n nodal values -> 2n subcell means (2n x n)
+    double Q[MAXN * MAXN / 2];   // P^(n -> n/2): n nodal values -> n/2 subcell means (n/2 x n)
+    double Lm[MAXN * MAXN];      // L_-: l_i(xi_j / 2 - 1/4) w_j / (2 w_i)  (n x n)
+    double Lp[MAXN * MAXN];      // L_+: l_i(xi_j / 2 + 1/4) w_j / (2 w_i)  (n x n)
+};
+
+int sedg_build_nc(int n, int family, sedg_nc_tab *T);
+
 #endif

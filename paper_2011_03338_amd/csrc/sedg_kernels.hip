@@ -2646,6 +2646,198 @@ __global__ void set_scalars_kernel(double *dt, double val, int *step_ctr)
 }
 
 // ---------------------------------------------------------------------------
+// blended refinement and coarsening (App., non-conforming interfaces)
+// ---------------------------------------------------------------------------
+// Refinement of a parent element (eq. 3D-refinement), written for the multi-level
+// weights: every fine subcell takes theta_FV of its parent cell times the parent cell's
+// mean (the expansion E = I (x) 1_2) plus, for each DG level n, theta^(n) times the mean
+// over the fine subcell of the level-n sub-element's nodal polynomial (Z = P^(n -> 2n)
+// along every axis).  Coarsening (eq. 3D-coarsening) compresses each child separately:
+// theta_FV times the mean of the 2^d fine cells (C = 1/2 I (x) 1_2^T) plus theta^(n) times
+// the means over the coarse subcells of the child's level-n polynomials (Q = P^(n -> n/2)),
+// and glues the 2^d children.  With the single-level weights (levels {1, K}) these are the
+// paper's formulas; both conserve every element's total for any factors.
+
+typedef const __attribute__((address_space(4))) sedg_nc_tab CNc;
+
+struct RcArgs {
+    const double *in;       // refine: coarse state; coarsen: fine state
+    const double *alpha;    // factors of the input mesh's elements (A per element)
+    double *out;            // refine: fine state; coarsen: coarse state
+    CTab *tabs;
+    CNc *nc;
+    long long dof_c, dof_f; // subcells of the coarse and the fine mesh
+    int ne[3];              // coarse elements per axis (1 on unused axes)
+    int Gc[3], Gf[3];       // coarse and fine subcell extents
+};
+
+// out = in x_a M within blocks along axis a: the extents of in are ext, those of out ext
+// with ext[a] replaced by ext[a] / n * ro; M is ro x n (row-major), applied to the n
+// inputs of each block of n along a.  Work spread over the workgroup.
+__device__ __forceinline__ void rc_pass(const double *in, double *out, const int *ext, int a, int ro, int n,
+                                        CDbl *M, int tid, int nthr)
+{
+    int eo[3] = {ext[0], ext[1], ext[2]};
+    eo[a] = ext[a] / n * ro;
+    const int total = eo[0] * eo[1] * eo[2];
+    for (int o = tid; o < total; o += nthr) {
+        int oc[3] = {o % eo[0], (o / eo[0]) % eo[1], o / (eo[0] * eo[1])};
+        const int oa = (a == 0) ? oc[0] : (a == 1) ? oc[1] : oc[2];
+        const int b = oa / ro, r = oa - b * ro;
+        const int st = (a == 0) ? 1 : (a == 1) ? ext[0] : ext[0] * ext[1];
+        int ic[3] = {oc[0], oc[1], oc[2]};
+        if (a == 0) ic[0] = b * n; else if (a == 1) ic[1] = b * n; else ic[2] = b * n;
+        const int base = ic[0] + ext[0] * (ic[1] + ext[1] * ic[2]);
+        double acc = 0.0;
+        for (int m = 0; m < n; ++m) acc += M[r * n + m] * in[base + m * st];
+        out[o] = acc;
+    }
+}
+
+template <int DIM, int K, int TOP>
+__global__ void __launch_bounds__((Geo<DIM, K>::KD)) refine_kernel(RcArgs A)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int KD = G::KD, NV = G::NV, ND = 1 << DIM, FD = KD * ND, F = 2 * K;
+    __shared__ double s_al[LV::A];
+    __shared__ double s_u[KD], s_a[FD], s_b[FD];
+    const int e = blockIdx.x, c = threadIdx.x;
+    int e3[3] = {e % A.ne[0], (e / A.ne[0]) % A.ne[1], e / (A.ne[0] * A.ne[1])};
+    const int cx = G::coord(c, 0), cy = G::coord(c, 1), cz = DIM == 3 ? G::coord(c, 2) : 0;
+    const long long gx = (long long)e3[0] * K + cx, gy = (long long)e3[1] * K + cy,
+                    gz = DIM == 3 ? (long long)e3[2] * K + cz : 0;
+    const long long g = gx + A.Gc[0] * (gy + (long long)A.Gc[1] * gz);
+    for (int q = c; q < LV::A; q += KD) s_al[q] = A.alpha[(long long)e * LV::A + q];
+    __syncthreads();
+    int sidx[MAXLEV];
+    subidx_all<DIM, K, LV>(c, sidx);
+    double th[MAXLEV + 1];
+    theta_from_alpha<LV>(s_al, sidx, th);
+    // the parent cell's 2^d fine cells: index inside the element's (2K)^d block and in the fine grid
+    int fl[ND];
+    long long fg[ND];
+    for (int k = 0; k < ND; ++k) {
+        const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+        fl[k] = (2 * cx + dx) + F * ((2 * cy + dy) + F * (DIM == 3 ? 2 * cz + dz : 0));
+        fg[k] = (2 * gx + dx) + A.Gf[0] * ((2 * gy + dy) + (long long)A.Gf[1] * (DIM == 3 ? 2 * gz + dz : 0));
+    }
+    const int ek[3] = {K, K, DIM == 3 ? K : 1};
+    for (int v = 0; v < NV; ++v) {
+        const double ub = A.in[v * A.dof_c + g];
+        double acc[ND];
+        for (int k = 0; k < ND; ++k) acc[k] = th[0] * ub;
+        s_u[c] = ub;
+        __syncthreads();
+#pragma unroll
+        for (int li = 0; li < LV::NLEV; ++li) {
+            if (!block_or<KD>(th[1 + li] != 0.0)) continue;
+            const int n = LV::n(li);
+            CTab &T = A.tabs[li];
+            // nodal polynomial of every level-n sub-element: R along every axis
+            double *src = s_u, *dst = s_a;
+            for (int ax = 0; ax < DIM; ++ax) {
+                rc_pass(src, dst, ek, ax, n, n, T.R, c, KD);
+                __syncthreads();
+                src = dst;
+                dst = (dst == s_a) ? s_b : s_a;
+            }
+            // means over the fine subcells: Z along every axis (extents grow to 2K)
+            int ex[3] = {K, K, DIM == 3 ? K : 1};
+            for (int ax = 0; ax < DIM; ++ax) {
+                rc_pass(src, dst, ex, ax, 2 * n, n, A.nc[li].Z, c, KD);
+                __syncthreads();
+                ex[ax] = F;
+                src = dst;
+                dst = (dst == s_a) ? s_b : s_a;
+            }
+            for (int k = 0; k < ND; ++k) acc[k] += th[1 + li] * src[fl[k]];
+            __syncthreads();
+        }
+        for (int k = 0; k < ND; ++k) A.out[v * A.dof_f + fg[k]] = acc[k];
+        __syncthreads();
+    }
+}
+
+template <int DIM, int K, int TOP>
+__global__ void __launch_bounds__((Geo<DIM, K>::KD)) coarsen_kernel(RcArgs A)
+{
+    typedef Geo<DIM, K> G;
+    typedef Lv<DIM, K, TOP> LV;
+    constexpr int KD = G::KD, NV = G::NV, ND = 1 << DIM, H = K / 2;
+    constexpr int HD = (DIM == 2) ? H * H : H * H * H;
+    __shared__ double s_al[LV::A];
+    __shared__ double s_u[KD], s_a[KD], s_b[KD], s_o[KD];
+    const int e = blockIdx.x, c = threadIdx.x;
+    int e3[3] = {e % A.ne[0], (e / A.ne[0]) % A.ne[1], e / (A.ne[0] * A.ne[1])};
+    const int fne0 = 2 * A.ne[0], fne1 = 2 * A.ne[1];
+    const int ek[3] = {K, K, DIM == 3 ? K : 1};
+    for (int v = 0; v < NV; ++v) {
+        for (int r = 0; r < ND; ++r) {
+            const int rx = r & 1, ry = (r >> 1) & 1, rz = (r >> 2) & 1;
+            const int f3[3] = {2 * e3[0] + rx, 2 * e3[1] + ry, DIM == 3 ? 2 * e3[2] + rz : 0};
+            const long long fe = f3[0] + (long long)fne0 * (f3[1] + (long long)fne1 * f3[2]);
+            // the child's cell c and factors
+            const long long fgx = (long long)f3[0] * K + G::coord(c, 0), fgy = (long long)f3[1] * K + G::coord(c, 1),
+                            fgz = DIM == 3 ? (long long)f3[2] * K + G::coord(c, 2) : 0;
+            s_u[c] = A.in[v * A.dof_f + fgx + A.Gf[0] * (fgy + (long long)A.Gf[1] * fgz)];
+            for (int q = c; q < LV::A; q += KD) s_al[q] = A.alpha[fe * LV::A + q];
+            __syncthreads();
+            // this thread's coarse output inside the child, if any: child position p, whose
+            // fine cells start at 2p (their weights are those of the fine cell 2p)
+            const bool has = c < HD;
+            const int p0 = c % H, p1 = (c / H) % H, p2 = DIM == 3 ? c / (H * H) : 0;
+            const int fc = (2 * p0) + K * ((2 * p1) + K * (DIM == 3 ? 2 * p2 : 0));
+            double th[MAXLEV + 1];
+            {
+                int sidx[MAXLEV];
+                subidx_all<DIM, K, LV>(has ? fc : 0, sidx);
+                theta_from_alpha<LV>(s_al, sidx, th);
+            }
+            double acc = 0.0;
+            if (has) {
+                double m = 0.0;
+                for (int k = 0; k < ND; ++k) {
+                    const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+                    m += s_u[fc + dx + K * (dy + K * dz)];
+                }
+                acc = th[0] * (m / ND);
+            }
+#pragma unroll
+            for (int li = 0; li < LV::NLEV; ++li) {
+                if (!block_or<KD>(has && th[1 + li] != 0.0)) continue;
+                const int n = LV::n(li);
+                CTab &T = A.tabs[li];
+                double *src = s_u, *dst = s_a;
+                for (int ax = 0; ax < DIM; ++ax) {
+                    rc_pass(src, dst, ek, ax, n, n, T.R, c, KD);
+                    __syncthreads();
+                    src = dst;
+                    dst = (dst == s_a) ? s_b : s_a;
+                }
+                int ex[3] = {K, K, DIM == 3 ? K : 1};
+                for (int ax = 0; ax < DIM; ++ax) {
+                    rc_pass(src, dst, ex, ax, n / 2, n, A.nc[li].Q, c, KD);
+                    __syncthreads();
+                    ex[ax] = H;
+                    src = dst;
+                    dst = (dst == s_a) ? s_b : s_a;
+                }
+                if (has) acc += th[1 + li] * src[c];
+                __syncthreads();
+            }
+            // the coarse cell of the parent element this output fills
+            if (has) s_o[(rx * H + p0) + K * ((ry * H + p1) + K * (DIM == 3 ? rz * H + p2 : 0))] = acc;
+            __syncthreads();
+        }
+        const long long gx = (long long)e3[0] * K + G::coord(c, 0), gy = (long long)e3[1] * K + G::coord(c, 1),
+                        gz = DIM == 3 ? (long long)e3[2] * K + G::coord(c, 2) : 0;
+        A.out[v * A.dof_c + gx + A.Gc[0] * (gy + (long long)A.Gc[1] * gz)] = s_o[c];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -2661,6 +2853,7 @@ struct sedg_ctx {
     double *d_alpha, *d_beta, *d_fbuf, *d_lam, *d_dt, *d_u0, *d_u1, *d_u2, *d_scale, *d_mean;
     double *d_ef;                          // element-face common fluxes
     double *d_u3;                          // fourth stage buffer of SSP-RK(5,4) (first use)
+    sedg_nc_tab *d_nc;                     // refinement / coarsening tables (first use)
     double *d_gfb, *d_l1, *d_l2, *d_acc;   // adjoint (allocated on first use)
     double *d_gsb, *d_gdb;
     int *d_err, *d_ctr;
@@ -2853,6 +3046,13 @@ int set_levels(sedg_ctx *C, const sedg_params *p)
     for (int li = 0; li < C->nlev; ++li)
         if (sedg_build_level(C->lev_n[li], C->mesh.family, &h[li])) return SEDG_EINVAL;
     if (hipMemcpy(C->d_tabs, h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    if (C->d_nc) {
+        sedg_nc_tab hn[MAXLEV];
+        std::memset(hn, 0, sizeof(hn));
+        for (int li = 0; li < C->nlev; ++li)
+            if (sedg_build_nc(C->lev_n[li], C->mesh.family, &hn[li])) return SEDG_EINVAL;
+        if (hipMemcpy(C->d_nc, hn, sizeof(hn), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    }
     for (auto &kv : C->graphs) (void)hipGraphExecDestroy(kv.second);
     C->graphs.clear();
     return SEDG_OK;
@@ -2950,7 +3150,7 @@ int sedg_destroy(sedg_ctx *C)
     for (hipEvent_t e : C->pool) (void)hipEventDestroy(e);
     void *ptrs[] = {C->d_tabs, C->d_alpha, C->d_beta, C->d_fbuf, C->d_lam, C->d_dt, C->d_u1, C->d_u2, C->d_err, C->d_ctr,
                     C->d_scale, C->d_mean, C->d_ef, C->d_gfb, C->d_gsb, C->d_gdb, C->d_l1, C->d_l2, C->d_acc,
-                    C->d_draw, C->d_fbc, C->d_diag, C->d_u3};
+                    C->d_draw, C->d_fbc, C->d_diag, C->d_u3, C->d_nc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete C;
@@ -4068,6 +4268,84 @@ int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const dou
     launch_shape(1, d, K, top, nblocks, P, s);
     if (bad_dev) hipLaunchKernelGGL(na_copy_int_kernel, dim3(1), dim3(64), 0, s, P.err, bad_dev);
     return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// refinement / coarsening entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+int ensure_nc(sedg_ctx *C)
+{
+    if (C->d_nc) return SEDG_OK;
+    sedg_nc_tab hn[MAXLEV];
+    std::memset(hn, 0, sizeof(hn));
+    for (int li = 0; li < C->nlev; ++li)
+        if (sedg_build_nc(C->lev_n[li], C->mesh.family, &hn[li])) return SEDG_EINVAL;
+    if (hipMalloc(&C->d_nc, sizeof(hn)) != hipSuccess) { C->d_nc = nullptr; return SEDG_ENOMEM; }
+    if (hipMemcpy(C->d_nc, hn, sizeof(hn), hipMemcpyHostToDevice) != hipSuccess) return SEDG_EHIP;
+    return SEDG_OK;
+}
+
+template <int DIM, int K, int TOP>
+void rc_launch(bool refine, const RcArgs &A, int nel, hipStream_t s)
+{
+    if (refine) hipLaunchKernelGGL((refine_kernel<DIM, K, TOP>), dim3(nel), dim3(Geo<DIM, K>::KD), 0, s, A);
+    else hipLaunchKernelGGL((coarsen_kernel<DIM, K, TOP>), dim3(nel), dim3(Geo<DIM, K>::KD), 0, s, A);
+}
+
+template <int DIM, int K>
+void rc_launch_top(bool refine, int top, const RcArgs &A, int nel, hipStream_t s)
+{
+    if (top == 2) rc_launch<DIM, K, 2>(refine, A, nel, s);
+    else if (top == 4) rc_launch<DIM, K, 4>(refine, A, nel, s);
+    else rc_launch<DIM, K, (K >= 8 ? 8 : 4)>(refine, A, nel, s);
+}
+
+int refine_or_coarsen(sedg_ctx *C, bool refine, const double *in, const double *alpha, double *out, void *stream)
+{
+    if (!C || !in || !alpha || !out || in == out) return SEDG_EINVAL;
+    int rc = ensure_nc(C);
+    if (rc) return rc;
+    RcArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.in = in;
+    A.alpha = alpha;
+    A.out = out;
+    A.tabs = (CTab *)C->d_tabs;
+    A.nc = (CNc *)C->d_nc;
+    A.dof_c = C->dof;
+    A.dof_f = C->dof;
+    for (int a = 0; a < 3; ++a) {
+        A.ne[a] = C->mesh.nelem[a];
+        A.Gc[a] = C->G[a];
+        A.Gf[a] = a < C->mesh.dim ? 2 * C->G[a] : 1;
+        if (a < C->mesh.dim) A.dof_f *= 2;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int d = C->mesh.dim, K = C->mesh.K, top = C->lev_n[0];
+    if (d == 2 && K == 4) rc_launch_top<2, 4>(refine, top, A, C->nel, s);
+    else if (d == 2 && K == 8) rc_launch_top<2, 8>(refine, top, A, C->nel, s);
+    else if (d == 3 && K == 4) rc_launch_top<3, 4>(refine, top, A, C->nel, s);
+    else rc_launch_top<3, 8>(refine, top, A, C->nel, s);
+    C->last = s;
+    return hipGetLastError() == hipSuccess ? SEDG_OK : SEDG_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedg_refine(sedg_ctx *C, const double *u, const double *alpha, double *u_fine, void *stream)
+{
+    return refine_or_coarsen(C, true, u, alpha, u_fine, stream);
+}
+
+int sedg_coarsen(sedg_ctx *C, const double *u_fine, const double *alpha_fine, double *u, void *stream)
+{
+    return refine_or_coarsen(C, false, u_fine, alpha_fine, u, stream);
 }
 
 }  // extern "C"

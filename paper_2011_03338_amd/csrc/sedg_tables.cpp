@@ -257,3 +257,50 @@ extern "C" int sedg_tables(int n, int family, double *out, int cap)
     put(T.Bhl, n); put(T.Bhr, n); put(T.Ip, n * n); put(T.Im, n * n);
     return (int)(o - out);
 }
+
+// Refinement, coarsening and mortar tables of level n (App., non-conforming interfaces):
+// Z = P^(n -> 2n) and Q = P^(n -> n/2), the projections of n nodal values onto 2n and n/2
+// equal subcell means of [-1/2, 1/2] (Sec. 2.3 with other subcell counts), by exact
+// integration of the monomial form of l_j; the L2-projection matrices of the mortar
+// flux, L_+-_ij = l_i(xi_j / 2 +- 1/4) w_j / (2 w_i).
+int sedg_build_nc(int n, int family, sedg_nc_tab *T)
+{
+    if (n < 2 || n > MAXN || (n & (n - 1))) return -1;
+    q x[MAXN], w[MAXN];
+    if (family == 1) lobatto(n, x, w);
+    else gauss(n, x, w);
+    q coef[MAXN][MAXN];
+    for (int j = 0; j < n; ++j) lagrange_monomial(n, x, j, coef[j]);
+    std::memset(T, 0, sizeof(*T));
+    T->n = n;
+    const int nz = 2 * n, nq = n / 2;
+    for (int i = 0; i < nz; ++i)
+        for (int j = 0; j < n; ++j) {
+            q a = -q(1) / 2 + q(i) / nz, b = -q(1) / 2 + q(i + 1) / nz;
+            T->Z[i * n + j] = (double)(nz * polyint(n, coef[j], a, b));
+        }
+    for (int i = 0; i < nq; ++i)
+        for (int j = 0; j < n; ++j) {
+            q a = -q(1) / 2 + q(i) / nq, b = -q(1) / 2 + q(i + 1) / nq;
+            T->Q[i * n + j] = (double)(nq * polyint(n, coef[j], a, b));
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            q f = w[j] / (2 * w[i]);
+            T->Lm[i * n + j] = (double)(polyval(n, coef[i], x[j] / 2 - q(1) / 4) * f);
+            T->Lp[i * n + j] = (double)(polyval(n, coef[i], x[j] / 2 + q(1) / 4) * f);
+        }
+    return 0;
+}
+
+extern "C" int sedg_nc_tables(int n, int family, double *out, int cap)
+{
+    sedg_nc_tab T;
+    if (!out || sedg_build_nc(n, family, &T)) return -1;
+    int need = 2 * n * n + (n / 2) * n + 2 * n * n;
+    if (cap < need) return -1;
+    double *o = out;
+    auto put = [&](const double *a, int cnt) { std::memcpy(o, a, sizeof(double) * cnt); o += cnt; };
+    put(T.Z, 2 * n * n); put(T.Q, (n / 2) * n); put(T.Lm, n * n); put(T.Lp, n * n);
+    return (int)(o - out);
+}

@@ -30,7 +30,7 @@ EXPORTED = ["sedg_create", "sedg_destroy", "sedg_state_len", "sedg_alpha_len", "
             "sedg_rk_step_tape", "sedg_adjoint_rk_step", "sedg_batch_create", "sedg_batch_destroy",
             "sedg_batch_state_len", "sedg_batch_state_offset", "sedg_batch_set_tuning", "sedg_batch_get_tuning",
             "sedg_batch_rk_step", "sedg_batch_check", "sedg_rhs_noalloc", "sedg_init_state", "sedg_diagnose",
-            "sedg_rk_step_frozen"]
+            "sedg_rk_step_frozen", "sedg_refine", "sedg_coarsen", "sedg_nc_tables"]
 
 
 class SedgError(RuntimeError):
@@ -110,6 +110,9 @@ def load():
     lib.sedg_batch_rk_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
     lib.sedg_batch_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_long)]
     lib.sedg_rhs_noalloc.argtypes = [ctypes.POINTER(Mesh_c), ctypes.POINTER(Params_c), vp, vp, vp, vp]
+    lib.sedg_refine.argtypes = [vp, vp, vp, vp, vp]
+    lib.sedg_coarsen.argtypes = [vp, vp, vp, vp, vp]
+    lib.sedg_nc_tables.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
     lib.sedg_strerror.argtypes = [ctypes.c_int]
     lib.sedg_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -159,6 +162,18 @@ def tables(n: int, family: int = 0) -> dict:
         out[name] = buf[o:o + size].reshape(shp).copy()
         o += size
     return out
+
+
+def nc_tables(n: int, family: int = 0) -> dict:
+    """The library's refinement / coarsening / mortar tables of level n (host)."""
+    buf = np.zeros(8 * 64)
+    cnt = load().sedg_nc_tables(n, family, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), buf.size)
+    if cnt < 0:
+        raise SedgError(cnt, "sedg_nc_tables")
+    h = n // 2
+    o = [0, 2 * n * n, 2 * n * n + h * n, 3 * n * n + h * n, 4 * n * n + h * n]
+    return {"Z": buf[o[0]:o[1]].reshape(2 * n, n).copy(), "Q": buf[o[1]:o[2]].reshape(h, n).copy(),
+            "Lm": buf[o[2]:o[3]].reshape(n, n).copy(), "Lp": buf[o[3]:o[4]].reshape(n, n).copy()}
 
 
 def _ptr(t):
@@ -301,6 +316,16 @@ class Solver:
         cnt = (ctypes.c_long * 4)()
         _check(load().sedg_profile_read(self._h, ms, cnt), "sedg_profile_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(["analyse", "residual", "step_size", "faces"])}
+
+    def refine(self, u, alpha, u_fine, stream=None):
+        """Blended refinement of every element into 2^dim children (sedg_refine): u_fine is
+        the state of the mesh with twice the elements per axis."""
+        _check(load().sedg_refine(self._h, _ptr(u), _ptr(alpha), _ptr(u_fine), _stream(stream)), "sedg_refine")
+
+    def coarsen(self, u_fine, alpha_fine, u, stream=None):
+        """Blended coarsening of the doubled mesh's state onto this mesh (sedg_coarsen)."""
+        _check(load().sedg_coarsen(self._h, _ptr(u_fine), _ptr(alpha_fine), _ptr(u), _stream(stream)),
+               "sedg_coarsen")
 
     def check(self):
         """Returns -1, or raises SedgError(SEDG_ESTATE) naming the bad element."""

@@ -51,3 +51,13 @@ def test_two_table_builders_agree(n, fam):
 def test_bad_level_rejected():
     with pytest.raises(sedg.SedgError):
         sedg.tables(3, 0)
+
+
+@pytest.mark.parametrize("n", [2, 4, 8])
+@pytest.mark.parametrize("fam", [0, 1])
+def test_two_nc_table_builders_agree(n, fam):
+    """Refinement, coarsening and mortar tables: library (quad precision) against the
+    oracle (long double), built independently."""
+    a, b = sedg.nc_tables(n, fam), O.nc_tables(n, fam)
+    for k in ("Z", "Q", "Lm", "Lp"):
+        assert np.abs(a[k] - b[k]).max() <= 8 * np.finfo(float).eps * max(1.0, np.abs(b[k]).max()), k
