@@ -254,8 +254,8 @@ int sedg_adjoint_rk_step(sedg_ctx *ctx, const double *tapes, int nsteps, const d
  * not available), the ratio of specific heats and the node family.  Their states
  * sit back to back in one device array: problem p occupies
  * [sedg_batch_state_offset(p), + 4 * its DOF) in the single-problem layout.
- * One step advances every problem by one SSP-RK3 step with one launch of the
- * analyse kernel and one of the residual kernel per stage for the whole
+ * One step advances every problem by one SSP-RK3 step with one launch each of
+ * the analyse, element-face flux and residual kernels per stage for the whole
  * ensemble (plus a per-problem step-size kernel), captured once per
  * (u, dt_log, fixed) into a HIP graph and replayed. */
 typedef struct sedg_batch sedg_batch;

@@ -1,7 +1,7 @@
 // HIP kernels (gfx950) and C-ABI host code of libsedg: the sub-element adaptive
-// blended DG/FV right-hand side of arXiv:2011.03338 and its SSP-RK3 stages.
+// blended DG/FV right-hand side of arXiv:2011.03338 and its SSP Runge-Kutta stages (SSP-RK3, SSP-RK(5,4)).
 //
-// Work decomposition (per RK stage, two launches plus a tiny reduction):
+// Work decomposition (per RK stage, three launches plus a tiny reduction):
 //   analyse  : one thread per subcell, EPB elements per workgroup, all element
 //              data staged in LDS.  Reconstructs every level (eq. reco-*),
 //              computes the squeezing parameters (eq. calc-squeezing-parameter),
@@ -11,16 +11,20 @@
 //              cascade of Sec. 2.6).  Writes alpha, beta and the face buffer
 //              (the only data another element reads), plus per-block maxima of
 //              the CFL eigenvalue estimate (eq. euler-max-eigenvalue).
-//   residual : same decomposition.  Per axis: blended interface states of every
-//              subcell, unique common fluxes at every subcell face (FV
-//              candidate plus per-level DG candidates projected along the face,
-//              App. eq. 3D-blend-interface-fluxes), then the FV and level DG
-//              right-hand sides (eq. multilevel-blending-scheme) blended with
-//              the weights of eq. blending-weights; the SSP-RK3 combination is
-//              fused into the store.
-// Element-face fluxes are computed by both adjacent elements from identical
-// inputs (the face buffer on both sides, the same code), so they agree bit for
-// bit and the scheme stays conservative without atomics.
+//   eface    : one wavefront per element.  The common flux of every element
+//              face (App. eq. 3D-blend-interface-fluxes on the element
+//              boundary) is computed once, by the element whose low face it
+//              is (or by the boundary element at the high end of a
+//              non-periodic axis), and stored in a flux buffer that
+//              both neighbours read, so the scheme is conservative by
+//              construction and without atomics.
+//   residual : same decomposition as analyse.  Per axis: blended interface
+//              states of every interior subcell face, unique common fluxes
+//              there (FV candidate plus per-level DG candidates projected along
+//              the face), then the FV and level DG right-hand sides (eq.
+//              multilevel-blending-scheme) blended with the weights of eq.
+//              blending-weights; the Runge-Kutta combination is fused into the
+//              store.
 #include <hip/hip_runtime.h>
 
 #include <climits>

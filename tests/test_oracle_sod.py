@@ -136,7 +136,7 @@ def test_sod_multilevel_beats_single_level(sod_solutions):
     """Single-level blending (DG of degree 7 straight to FV, level mask {8}) against the
     multi-level chain O(8) -> O(4) -> O(2) -> FV on the same tube: the chain keeps more
     of the high-order solution near the shock and has the smaller density error
-    (1.75e-3 against 2.76e-3 at 32 elements)."""
+    (about 1.9e-3 against 2.8e-3 at 32 elements)."""
     mesh, u0, _ = sod_solutions[32]
     ref = exact_density_means(mesh.edges(0), 0.2)
     multi = float(np.mean(np.abs(sod_solutions[32][2][0, 0].mean(axis=0) - ref)))
