@@ -562,31 +562,66 @@ __device__ __forceinline__ bool block_or(bool pred)
     }
 }
 
-// xor-butterfly reduction over the cells of one level-n sub-element (ln = log2 n;
-// ln = LOGK gives the whole element).  Bits inside a wavefront use lane exchanges,
-// higher bits exchange through LDS; every lane ends with the same value.
-template <int DIM, int K, typename T, typename Op>
-__device__ T subreduce(T v, int ln, T *s_x, Op op)
+// xor-butterfly reduction of NQ values at once over the cells of one level-n
+// sub-element (ln = log2 n; ln = LOGK gives the whole element); every lane ends with
+// the values of its sub-element.  Bits inside a wavefront use lane exchanges.  Bits
+// above them (3-D, K = 8: the bits of the z coordinate, one wavefront per z layer)
+// go through LDS with one barrier pair for all NQ values: one lane per wavefront
+// publishes its partials, and every lane combines those of the wavefronts of its
+// sub-element pairwise in the butterfly's pairing (the operators are commutative, so
+// this is the butterfly's result to the bit).  s_x holds at least NQ x (wavefronts
+// per workgroup) values.
+template <int DIM, int K, int NQ, typename T, typename Op>
+__device__ void subreduce_n(T *v, int ln, T *s_x, Op op)
 {
     constexpr int LOGK = Geo<DIM, K>::LOGK;
-    const int tid = threadIdx.x;
+    constexpr int NB = DIM * LOGK;              // bits of the cell index
 #pragma unroll
-    for (int a = 0; a < DIM; ++a)
+    for (int bit = 0; bit < (NB < 6 ? NB : 6); ++bit) {
+        if (bit % LOGK >= ln) continue;
 #pragma unroll
-        for (int b = 0; b < LOGK; ++b) {
-            if (b >= ln) continue;
-            int bit = a * LOGK + b;
-            int mask = 1 << bit;
-            if (bit < 6) {
-                v = lane_step(v, mask, op);
-            } else {
-                s_x[tid] = v;
-                __syncthreads();
-                T o = s_x[tid ^ mask];
-                __syncthreads();
-                v = op(v, o);
+        for (int q = 0; q < NQ; ++q) v[q] = lane_step(v[q], 1 << bit, op);
+    }
+    if constexpr (NB > 6) {
+        constexpr int NW = 1 << (NB - 6);       // wavefronts of one element
+        int wmask = 0;                          // wavefront bits inside the sub-element
+#pragma unroll
+        for (int bit = 6; bit < NB; ++bit)
+            if (bit % LOGK < ln) wmask |= 1 << (bit - 6);
+        if (wmask == 0) return;
+        const int tid = threadIdx.x, WG = blockDim.x >> 6;
+        const int w = (tid >> 6) & (NW - 1), wbase = (tid >> 6) & ~(NW - 1);
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) s_x[q * WG + (tid >> 6)] = v[q];
+        __syncthreads();
+        const int g0 = w & ~wmask;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i) acc[i] = s_x[q * WG + wbase + i];
+#pragma unroll
+            for (int m = 1; m < NW; m <<= 1) {
+                if (!(wmask & m)) continue;
+#pragma unroll
+                for (int i = 0; i < NW; ++i)
+                    if (!(i & m)) acc[i] = op(acc[i], acc[i | m]);
             }
+            T r = acc[0];                       // acc[g0], by selects (no indexed registers)
+#pragma unroll
+            for (int i = 1; i < NW; ++i)
+                if (i == g0) r = acc[i];
+            v[q] = r;
         }
+        __syncthreads();
+    }
+}
+
+template <int DIM, int K, typename T, typename Op>
+__device__ __forceinline__ T subreduce(T v, int ln, T *s_x, Op op)
+{
+    subreduce_n<DIM, K, 1>(&v, ln, s_x, op);
     return v;
 }
 
@@ -777,11 +812,11 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         }
     }
     {
-        double sr = subreduce<DIM, K>(ub[0], G::LOGK, S.x, OpMax());
-        double se = subreduce<DIM, K>(fabs(ub[NV - 1]), G::LOGK, S.x, OpMax());
+        double sc[2] = {ub[0], fabs(ub[NV - 1])};
+        subreduce_n<DIM, K, 2>(sc, G::LOGK, S.x, OpMax());
         if (act && c == 0) {
-            P.scale[2 * (long long)e] = sr;
-            P.scale[2 * (long long)e + 1] = se;
+            P.scale[2 * (long long)e] = sc[0];
+            P.scale[2 * (long long)e + 1] = sc[1];
         }
     }
     __syncthreads();
@@ -871,10 +906,13 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
         if (block_or<EPB * KD>(visit && !ok)) {
             double nd = (DIM == 2) ? n * n : n * n * n;
-            double mn[NV];
-            for (int v = 0; v < NV; ++v) mn[v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
-            rmin = subreduce<DIM, K>(rmin, ln, S.x, OpMin());
-            pmin = subreduce<DIM, K>(pmin, ln, S.x, OpMin());
+            double mn[NV], mm[2] = {rmin, pmin};
+            for (int v = 0; v < NV; ++v) mn[v] = ub[v];
+            subreduce_n<DIM, K, NV>(mn, ln, S.x, OpSum());
+            for (int v = 0; v < NV; ++v) mn[v] /= nd;
+            subreduce_n<DIM, K, 2>(mm, ln, S.x, OpMin());
+            rmin = mm[0];
+            pmin = mm[1];
             if (!ok) {
                 double rmean = mn[0], pmean = pressure<DIM>(mn, gam);
                 double eps = fmin(1e-20, fmin(rmean, pmean));
@@ -939,9 +977,17 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 }
             }
             __syncthreads();
-            for (int v = 0; v < NV; ++v) {
-                sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
-                sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
+            {
+                double snh[2 * NV];
+                for (int v = 0; v < NV; ++v) {
+                    snh[v] = sn[v];
+                    snh[NV + v] = sh[v];
+                }
+                subreduce_n<DIM, K, 2 * NV>(snh, ln, S.x, OpSum());
+                for (int v = 0; v < NV; ++v) {
+                    sn[v] = snh[v];
+                    sh[v] = snh[NV + v];
+                }
             }
             bad = subreduce<DIM, K>(bad, ln, S.ix, OpOr());
             double amin = 1.0;
@@ -959,8 +1005,9 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         }
         if (!visit) a = 0.0;
         // level decision over the whole element (strict comparisons)
-        int hi = subreduce<DIM, K>((a > P.alpha_H) ? 1 : 0, G::LOGK, S.ix, OpAnd());
-        int lo = subreduce<DIM, K>((a < P.alpha_L) ? 1 : 0, G::LOGK, S.ix, OpAnd());
+        int hl[2] = {(a > P.alpha_H) ? 1 : 0, (a < P.alpha_L) ? 1 : 0};
+        subreduce_n<DIM, K, 2>(hl, G::LOGK, S.ix, OpAnd());
+        const int hi = hl[0], lo = hl[1];
         if (visit) {
             if (hi) { a = 1.0; broke = 1; }
             else if (lo) a = 0.0;
@@ -1758,11 +1805,11 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
     }
     if (act && !(fin && permissible<DIM>(ub, gam))) atomicMin(P.err, P.err_base + e);
     {
-        double sr = subreduce<DIM, K>(ub[0], G::LOGK, S.x, OpMax());
-        double se = subreduce<DIM, K>(fabs(ub[NV - 1]), G::LOGK, S.x, OpMax());
+        double sc[2] = {ub[0], fabs(ub[NV - 1])};
+        subreduce_n<DIM, K, 2>(sc, G::LOGK, S.x, OpMax());
         if (act && c == 0) {
-            P.scale[2 * (long long)e] = sr;
-            P.scale[2 * (long long)e + 1] = se;
+            P.scale[2 * (long long)e] = sc[0];
+            P.scale[2 * (long long)e + 1] = sc[1];
         }
     }
     for (int q = c; q < LV::A; q += KD) {
@@ -1775,7 +1822,9 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
         const int n = LV::n(li), ln = ilog2i(n);
         double nd = (DIM == 2) ? n * n : n * n * n;
         double mn[NV];
-        for (int v = 0; v < NV; ++v) mn[v] = subreduce<DIM, K>(ub[v], ln, S.x, OpSum()) / nd;
+        for (int v = 0; v < NV; ++v) mn[v] = ub[v];
+        subreduce_n<DIM, K, NV>(mn, ln, S.x, OpSum());
+        for (int v = 0; v < NV; ++v) mn[v] /= nd;
         const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
         if (leader)
             for (int v = 0; v < NV; ++v) S.mean[le][v][LV::off(li) + G::subelem(c, n)] = mn[v];
@@ -2094,7 +2143,8 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
         }
         const double nd = (DIM == 2) ? n * n : n * n * n;
         double ms[NV];
-        for (int v = 0; v < NV; ++v) ms[v] = subreduce<DIM, K>(gut[v], ln, S.wsL, OpSum());
+        for (int v = 0; v < NV; ++v) ms[v] = gut[v];
+        subreduce_n<DIM, K, NV>(ms, ln, S.wsL, OpSum());
         if (thn != 0.0)
             for (int v = 0; v < NV; ++v) gu[v] += b * y[v] + (1.0 - b) * ms[v] / nd;
         __syncthreads();
