@@ -267,9 +267,16 @@ typedef struct sedg_batch sedg_batch;
  *                  workgroups per compute unit, each taking a contiguous run of
  *                  tiles (at most 64)
  *   xcd_map        1: workgroups remapped so that each XCD takes a contiguous
- *                  range of tiles (neighbour face data stay in its L2); 0: none */
+ *                  range of tiles (neighbour face data stay in its L2); 0: none
+ *   waves_analyse, waves_residual
+ *                  register budget of the analyse / residual kernel, as the
+ *                  number of wavefronts per SIMD it must leave room for: 3
+ *                  (<= 168 VGPRs) or 4 (<= 128 VGPRs, values may spill to
+ *                  scratch); 0 selects 3
+ * Every shape computes bit-identical results (the same arithmetic in the same order). */
 typedef struct sedg_batch_tuning {
     int epb4, epb8, blocks_per_cu, xcd_map;
+    int waves_analyse, waves_residual;
 } sedg_batch_tuning;
 
 /* Create an ensemble of count problems (meshes[0..count-1], dim 2).  Returns

@@ -1,8 +1,10 @@
 """Autotuner of the batched ensemble's launch shape.
 
 Times a short run of every candidate launch shape (elements per workgroup for
-K = 4 and K = 8, a persistent grid of n workgroups per compute unit or one
-workgroup per tile, XCD-contiguous tile ranges or not) on a scratch copy of the
+K = 4 and K = 8, i.e. the LDS tile of the analyse and residual kernels; a
+persistent grid of n workgroups per compute unit or one workgroup per tile;
+XCD-contiguous tile ranges or not; the register budget of the analyse and the
+residual kernel, 3 or 4 wavefronts per SIMD) on a scratch copy of the
 ensemble state, keeps the fastest and caches the choice as JSON, keyed by the
 device and the ensemble's element counts per K.  The cache file is
 $SEDG_TUNING_CACHE, else ~/.cache/sedg/batch_tuning.json.
@@ -15,16 +17,23 @@ import os
 
 import torch
 
-CANDIDATES = [
-    dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1),
-    dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=0),
-    dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=1),
-    dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=0),
-    dict(epb4=4, epb8=1, blocks_per_cu=4, xcd_map=1),
-    dict(epb4=4, epb8=1, blocks_per_cu=8, xcd_map=1),
-    dict(epb4=8, epb8=2, blocks_per_cu=2, xcd_map=1),
-    dict(epb4=8, epb8=2, blocks_per_cu=4, xcd_map=1),
-]
+def _candidates():
+    """One workgroup per tile: the two element-per-workgroup tiles x XCD remap on/off x
+    the register budgets of the analyse and residual kernels (3 or 4 waves per SIMD);
+    persistent grids of 2-8 workgroups per CU at the default budgets."""
+    out = []
+    for epb4, epb8 in ((4, 1), (8, 2)):
+        for xcd in (1, 0):
+            for wa in (3, 4):
+                for wr in (3, 4):
+                    out.append(dict(epb4=epb4, epb8=epb8, blocks_per_cu=0, xcd_map=xcd, waves_analyse=wa,
+                                    waves_residual=wr))
+    for epb4, epb8, bpc in ((4, 1, 4), (4, 1, 8), (8, 2, 2), (8, 2, 4)):
+        out.append(dict(epb4=epb4, epb8=epb8, blocks_per_cu=bpc, xcd_map=1, waves_analyse=3, waves_residual=3))
+    return out
+
+
+CANDIDATES = _candidates()
 
 
 def cache_path() -> str:
@@ -37,7 +46,7 @@ def signature(batch) -> str:
     counts = {}
     for m in batch.meshes:
         counts[m.K] = counts.get(m.K, 0) + m.nel
-    text = json.dumps([torch.cuda.get_device_name(), sorted(counts.items()), len(batch.meshes)])
+    text = json.dumps([torch.cuda.get_device_name(), sorted(counts.items()), len(batch.meshes), CANDIDATES])
     return hashlib.sha1(text.encode()).hexdigest()[:16]
 
 

@@ -98,7 +98,7 @@ struct KArgs {
     int mode;
     unsigned level_mask;
     int stage;              // 0: write dudt; 1, 2, 3: SSP-RK3 stage
-    double gamma, tau_A, tau_S, alpha_H, alpha_L, beta_L;
+    double gamma, gm1, tau_A, tau_S, alpha_H, alpha_L, beta_L;
     double sigma_floor;     // floor of the smoothness-measure denominator (1 in the paper)
     // RANDOM mode: generator seed and the device counter of right-hand-side draws
     unsigned long long seed;
@@ -158,18 +158,24 @@ __device__ __forceinline__ double pick(const double *x, int a)
     return r;
 }
 
+// the ratio of specific heats and gamma - 1 (the latter a kernel argument, so that it
+// stays in scalar registers instead of a vector register held across the kernel)
+struct Gas {
+    double g, gm1;
+};
+
 template <int DIM>
-__device__ __forceinline__ double pressure(const double *u, double g)
+__device__ __forceinline__ double pressure(const double *u, const Gas &g)
 {
     if (!(u[0] > 0.0)) return -INFINITY;
     double m2 = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) m2 += u[1 + a] * u[1 + a];
-    return (g - 1.0) * (u[DIM + 1] - 0.5 * m2 / u[0]);
+    return g.gm1 * (u[DIM + 1] - 0.5 * m2 / u[0]);
 }
 
 template <int DIM>
-__device__ __forceinline__ bool permissible(const double *u, double g)
+__device__ __forceinline__ bool permissible(const double *u, const Gas &g)
 {
     if (!(u[0] > 0.0)) return false;
     return pressure<DIM>(u, g) > 0.0;
@@ -180,14 +186,14 @@ __device__ __forceinline__ bool permissible(const double *u, double g)
 // rho > 1e-12 srho and p > -1e-10 sE, so that the squeeze's binding point
 // (rho or p = 1e-20 up to rounding) is decided the same way in every rounding order
 template <int DIM>
-__device__ __forceinline__ bool flux_admissible(const double *u, double g, double srho, double sE)
+__device__ __forceinline__ bool flux_admissible(const double *u, const Gas &g, double srho, double sE)
 {
     if (!(u[0] > 1e-12 * srho)) return false;
     return pressure<DIM>(u, g) > -1e-10 * sE;
 }
 
 template <int DIM>
-__device__ __forceinline__ void euler_flux(const double *u, int a, double g, double *f)
+__device__ __forceinline__ void euler_flux(const double *u, int a, const Gas &g, double *f)
 {
     double p = pressure<DIM>(u, g);
     const double ma = pick<DIM>(u + 1, a);
@@ -199,7 +205,7 @@ __device__ __forceinline__ void euler_flux(const double *u, int a, double g, dou
 }
 
 template <int DIM>
-__device__ void hlle(const double *uL, const double *uR, int a, double g, double *fs)
+__device__ void hlle(const double *uL, const double *uR, int a, const Gas &g, double *fs)
 {
     constexpr int NV = DIM + 2;
     double fL[NV], fR[NV];
@@ -207,7 +213,7 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
     euler_flux<DIM>(uR, a, g, fR);
     double pL = pressure<DIM>(uL, g), pR = pressure<DIM>(uR, g);
     double vL = pick<DIM>(uL + 1, a) / uL[0], vR = pick<DIM>(uR + 1, a) / uR[0];
-    double cL = sqrt(fmax(g * pL / uL[0], 0.0)), cR = sqrt(fmax(g * pR / uR[0], 0.0));
+    double cL = sqrt(fmax(g.g * pL / uL[0], 0.0)), cR = sqrt(fmax(g.g * pR / uR[0], 0.0));
     double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
     double HL = (uL[DIM + 1] + pL) / uL[0], HR = (uR[DIM + 1] + pR) / uR[0];
     double vt2 = 0.0, vtn = 0.0;
@@ -218,7 +224,7 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
         if (b == a) vtn = vb;
     }
     double Ht = (sqL * HL + sqR * HR) / (sqL + sqR);
-    double ct = sqrt(fmax((g - 1.0) * (Ht - 0.5 * vt2), 0.0));
+    double ct = sqrt(fmax(g.gm1 * (Ht - 0.5 * vt2), 0.0));
     double SL = fmin(vL - cL, vtn - ct);
     double SR = fmax(vR + cR, vtn + ct);
     double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
@@ -234,23 +240,23 @@ __device__ void hlle(const double *uL, const double *uR, int a, double g, double
 
 // gu = (d f_a / d u)^T gf for the Euler flux of eqn. comp-euler-conservative
 template <int DIM>
-__device__ __forceinline__ void euler_flux_adj(const double *u, int a, double g, const double *gf, double *gu)
+__device__ __forceinline__ void euler_flux_adj(const double *u, int a, const Gas &g, const double *gf, double *gu)
 {
     constexpr int NV = DIM + 2;
     const double ir = 1.0 / u[0];
     double m2 = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) m2 += u[1 + b] * u[1 + b];
-    const double p = (g - 1.0) * (u[DIM + 1] - 0.5 * m2 * ir);
+    const double p = g.gm1 * (u[DIM + 1] - 0.5 * m2 * ir);
     const double ma = pick<DIM>(u + 1, a);
     const double va = ma * ir;
     const double gp = pick<DIM>(gf + 1, a) + gf[NV - 1] * va;
     double gva = gf[NV - 1] * (u[DIM + 1] + p);
 #pragma unroll
     for (int b = 0; b < DIM; ++b) gva += gf[1 + b] * u[1 + b];
-    const double gE = gf[NV - 1] * va + (g - 1.0) * gp;
-    const double gm2 = -0.5 * (g - 1.0) * ir * gp;
-    const double gir = gva * ma - 0.5 * (g - 1.0) * m2 * gp;
+    const double gE = gf[NV - 1] * va + g.gm1 * gp;
+    const double gm2 = -0.5 * g.gm1 * ir * gp;
+    const double gir = gva * ma - 0.5 * g.gm1 * m2 * gp;
     // f_0 = m_a, f_(1+b) = m_b va + delta_ab p, f_E = va (E + p); va = m_a / rho;
     // p = (g - 1)(E - m.m / (2 rho))
 #pragma unroll
@@ -263,7 +269,7 @@ __device__ __forceinline__ void euler_flux_adj(const double *u, int a, double g,
 // (guL, guR) = (d HLLE / d(uL, uR))^T gfs at (uL, uR), branches of every min/max
 // taken as the forward evaluation takes them
 template <int DIM>
-__device__ void hlle_adj(const double *uL, const double *uR, int a, double g, const double *gfs, double *guL, double *guR)
+__device__ void hlle_adj(const double *uL, const double *uR, int a, const Gas &g, const double *gfs, double *guL, double *guR)
 {
     constexpr int NV = DIM + 2;
     double ir[2], m2[2], p[2], va[2], c[2], sq[2], H[2], q[2];
@@ -274,9 +280,9 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
         m2[s] = 0.0;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) m2[s] += w[1 + b] * w[1 + b];
-        p[s] = (g - 1.0) * (w[DIM + 1] - 0.5 * m2[s] * ir[s]);
+        p[s] = g.gm1 * (w[DIM + 1] - 0.5 * m2[s] * ir[s]);
         va[s] = pick<DIM>(w + 1, a) * ir[s];
-        q[s] = g * p[s] * ir[s];
+        q[s] = g.g * p[s] * ir[s];
         c[s] = sqrt(fmax(q[s], 0.0));
         sq[s] = sqrt(w[0]);
         H[s] = (w[DIM + 1] + p[s]) * ir[s];
@@ -290,7 +296,7 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
     }
     const double vta = pick<DIM>(vt, a);
     const double Ht = (sq[0] * H[0] + sq[1] * H[1]) / S;
-    const double ct2 = (g - 1.0) * (Ht - 0.5 * vt2);
+    const double ct2 = g.gm1 * (Ht - 0.5 * vt2);
     const double ct = sqrt(fmax(ct2, 0.0));
     const double aL1 = va[0] - c[0], aL2 = vta - ct;
     const double aR1 = va[1] + c[1], aR2 = vta + ct;
@@ -335,8 +341,8 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
     const double gct = (selR2 ? gSR : 0.0) - (selL2 ? gSL : 0.0);
     // Roe averages
     const double gct2 = (ct > 0.0) ? gct / (2.0 * ct) : 0.0;
-    const double gHt = (g - 1.0) * gct2;
-    const double gvt2 = -0.5 * (g - 1.0) * gct2;
+    const double gHt = g.gm1 * gct2;
+    const double gvt2 = -0.5 * g.gm1 * gct2;
     double gsq[2], gS = -gHt * Ht / S, gH[2];
     gsq[0] = gHt / S * H[0];
     gsq[1] = gHt / S * H[1];
@@ -372,8 +378,8 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
         // c = sqrt(max(q, 0)), q = g p ir
         if (q[s] > 0.0 && c[s] > 0.0) {
             const double gq = gc[s] / (2.0 * c[s]);
-            gp += gq * g * ir[s];
-            gir += gq * g * p[s];
+            gp += gq * g.g * ir[s];
+            gir += gq * g.g * p[s];
         }
         // flux f_a(w) with adjoint fsc * gnum
         const double gfE = fsc * gfs_[NV - 1];
@@ -395,9 +401,9 @@ __device__ void hlle_adj(const double *uL, const double *uR, int a, double g, co
             gir += gvb * w[1 + b];
         }
         // p = (g-1)(E - 0.5 m2 ir)
-        gE += (g - 1.0) * gp;
-        const double gm2 = -0.5 * (g - 1.0) * ir[s] * gp;
-        gir += -0.5 * (g - 1.0) * m2[s] * gp;
+        gE += g.gm1 * gp;
+        const double gm2 = -0.5 * g.gm1 * ir[s] * gp;
+        gir += -0.5 * g.gm1 * m2[s] * gp;
         grho += -gir * ir[s] * ir[s];
         gw[0] += grho;
 #pragma unroll
@@ -779,7 +785,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
     int e3[3];
     elem3(P, ee, e3);
     const long long g = gindex<DIM, K>(P, e3, c);
-    const double gam = P.gamma;
+    const Gas gam = {P.gamma, P.gm1};
 
     double ub[NV];
     for (int v = 0; v < NV; ++v) {
@@ -795,7 +801,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (P.lam_part) {
             double lam = 0.0;
             if (act && ok) {
-                double cs = sqrt(gam * pressure<DIM>(ub, gam) / ub[0]);
+                double cs = sqrt(gam.g * pressure<DIM>(ub, gam) / ub[0]);
                 for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
             }
             #pragma unroll
@@ -977,7 +983,12 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 }
             }
             __syncthreads();
-            {
+            if constexpr (G::KD <= 64) {
+                for (int v = 0; v < NV; ++v) {
+                    sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
+                    sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
+                }
+            } else {
                 double snh[2 * NV];
                 for (int v = 0; v < NV; ++v) {
                     snh[v] = sn[v];
@@ -1006,7 +1017,12 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (!visit) a = 0.0;
         // level decision over the whole element (strict comparisons)
         int hl[2] = {(a > P.alpha_H) ? 1 : 0, (a < P.alpha_L) ? 1 : 0};
-        subreduce_n<DIM, K, 2>(hl, G::LOGK, S.ix, OpAnd());
+        if constexpr (G::KD <= 64) {
+            hl[0] = subreduce<DIM, K>(hl[0], G::LOGK, S.ix, OpAnd());
+            hl[1] = subreduce<DIM, K>(hl[1], G::LOGK, S.ix, OpAnd());
+        } else {
+            subreduce_n<DIM, K, 2>(hl, G::LOGK, S.ix, OpAnd());
+        }
         const int hi = hl[0], lo = hl[1];
         if (visit) {
             if (hi) { a = 1.0; broke = 1; }
@@ -1253,7 +1269,7 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
 {
     typedef Geo<DIM, K> G;
     constexpr int NV = G::NV, KD = G::KD;
-    const double gam = P.gamma;
+    const Gas gam = {P.gamma, P.gm1};
     // DG candidates level by level: R along the face, HLLE at the face nodes, P back
     double thFV = 1.0;
     for (int v = 0; v < NV; ++v) F[v] = 0.0;
@@ -1405,7 +1421,7 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     int e3[3];
     elem3(P, ee, e3);
     const long long g = gindex<DIM, K>(P, e3, c);
-    const double gam = P.gamma;
+    const Gas gam = {P.gamma, P.gm1};
 
     preload_element<DIM, K, LV, false, SM>(P, S, le, c, ee, g);
     int sidx[MAXLEV];
@@ -1792,7 +1808,7 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
     int e3[3];
     elem3(P, ee, e3);
     const long long g = gindex<DIM, K>(P, e3, c);
-    const double gam = P.gamma;
+    const Gas gam = {P.gamma, P.gm1};
     const bool adj = P.lam != nullptr;
 
     double ub[NV];
@@ -1920,7 +1936,7 @@ __device__ __forceinline__ void common_flux_adj(const KArgs &P, double *wsL, dou
 {
     typedef Geo<DIM, K> G;
     constexpr int NV = G::NV, KD = G::KD;
-    const double gam = P.gamma;
+    const Gas gam = {P.gamma, P.gm1};
     double gFv[NV];
     for (int v = 0; v < NV; ++v) gFv[v] = gseg[v * gstride + t];
     for (int v = 0; v < NV; ++v) { guL[v] = 0.0; guR[v] = 0.0; gdL[v] = 0.0; gdR[v] = 0.0; }
@@ -2065,7 +2081,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     int e3[3];
     elem3(P, ee, e3);
     const long long g = gindex<DIM, K>(P, e3, c);
-    const double gam = P.gamma;
+    const Gas gam = {P.gamma, P.gm1};
 
     preload_element<DIM, K, LV, true, AdjointSmem<DIM, K, TOP, EPB>>(P, S, le, c, ee, g);
     int sidx[MAXLEV];
@@ -2454,8 +2470,12 @@ __device__ __forceinline__ KArgs problem_args(const KArgs &P, const ProbDesc &Dm
     return Q;
 }
 
-template <int EPB4, int EPB8, bool PERSIST>
-__global__ void __launch_bounds__(64 * EPB8) analyse_batch_kernel(KArgs P)
+// WA, WR: waves per SIMD the register allocation of the analyse / residual kernel is
+// asked to leave room for (a tuning dimension: more waves hide more latency, fewer
+// registers may spill)
+template <int EPB4, int EPB8, bool PERSIST, int WA>
+__global__ void __launch_bounds__(64 * EPB8)
+__attribute__((amdgpu_waves_per_eu(WA, 8))) analyse_batch_kernel(KArgs P)
 {
     static_assert(16 * EPB4 == 64 * EPB8, "one workgroup size for both K");
     __shared__ union {
@@ -2476,9 +2496,9 @@ __global__ void __launch_bounds__(64 * EPB8) analyse_batch_kernel(KArgs P)
     }
 }
 
-template <int EPB4, int EPB8, bool PERSIST>
+template <int EPB4, int EPB8, bool PERSIST, int WR>
 __global__ void __launch_bounds__(64 * EPB8)
-__attribute__((amdgpu_waves_per_eu(3, 8))) residual_batch_kernel(KArgs P)
+__attribute__((amdgpu_waves_per_eu(WR, 8))) residual_batch_kernel(KArgs P)
 {
     static_assert(16 * EPB4 == 64 * EPB8, "one workgroup size for both K");
     __shared__ union {
@@ -2602,7 +2622,8 @@ __global__ void check_state_kernel(const double *u, long long dof, int G0, int G
         ub[v] = u[v * dof + i];
         fin = fin && isfinite(ub[v]);
     }
-    if (fin && permissible<DIM>(ub, gam)) return;
+    const Gas gs = {gam, gam - 1.0};
+    if (fin && permissible<DIM>(ub, gs)) return;
     const long long gx = i % G0, r = i / G0, gy = r % G1, gz = r / G1;
     const int e = (int)(gx / K + (long long)ne0 * (gy / K + (long long)ne1 * (gz / K)));
     atomicMin(err, e);
@@ -3050,6 +3071,7 @@ KArgs base_args(const sedg_ctx *C)
     P.mode = C->params.mode;
     P.level_mask = C->params.level_mask;
     P.gamma = C->mesh.gamma;
+    P.gm1 = C->mesh.gamma - 1.0;
     P.tau_A = C->params.tau_A;
     P.tau_S = C->params.tau_S;
     P.alpha_H = C->params.alpha_H;
@@ -3914,6 +3936,7 @@ KArgs batch_args(const sedg_batch *B)
     P.mode = B->params.mode;
     P.level_mask = B->params.level_mask;
     P.gamma = B->gamma;
+    P.gm1 = B->gamma - 1.0;
     P.tau_A = B->params.tau_A;
     P.tau_S = B->params.tau_S;
     P.alpha_H = B->params.alpha_H;
@@ -3926,11 +3949,15 @@ KArgs batch_args(const sedg_batch *B)
 template <int EPB4, int EPB8, bool PERSIST>
 void batch_launch_t(int which, const sedg_batch *B, const KArgs &P, hipStream_t s)
 {
-    if (which == 0) hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
-    else {
+    const dim3 grid(B->grid), block(64 * EPB8);
+    if (which == 0) {
+        if (B->tun.waves_analyse == 4) hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST, 4>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST, 3>), grid, block, 0, s, P);
+    } else {
         // the residual reads the element-face fluxes of the face kernel launched before it
         hipLaunchKernelGGL(eface_batch_kernel, dim3(B->nftiles), dim3(64), 0, s, P);
-        hipLaunchKernelGGL((residual_batch_kernel<EPB4, EPB8, PERSIST>), dim3(B->grid), dim3(64 * EPB8), 0, s, P);
+        if (B->tun.waves_residual == 4) hipLaunchKernelGGL((residual_batch_kernel<EPB4, EPB8, PERSIST, 4>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((residual_batch_kernel<EPB4, EPB8, PERSIST, 3>), grid, block, 0, s, P);
     }
 }
 
@@ -4019,6 +4046,8 @@ int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *par
     B->tun.epb8 = 1;
     B->tun.blocks_per_cu = 0;
     B->tun.xcd_map = 1;
+    B->tun.waves_analyse = 3;
+    B->tun.waves_residual = 3;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) { delete B; return SEDG_EHIP; }
@@ -4099,10 +4128,14 @@ int sedg_batch_set_tuning(sedg_batch *B, const sedg_batch_tuning *t)
 {
     if (!B || !t) return SEDG_EINVAL;
     const bool shape_ok = (t->epb4 == 4 && t->epb8 == 1) || (t->epb4 == 8 && t->epb8 == 2);
-    if (!shape_ok || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 || (t->xcd_map != 0 && t->xcd_map != 1))
+    auto waves_ok = [](int w) { return w == 0 || w == 3 || w == 4; };
+    if (!shape_ok || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 || (t->xcd_map != 0 && t->xcd_map != 1) ||
+        !waves_ok(t->waves_analyse) || !waves_ok(t->waves_residual))
         return SEDG_EINVAL;
     if (hipDeviceSynchronize() != hipSuccess) return SEDG_EHIP;
     B->tun = *t;
+    if (B->tun.waves_analyse == 0) B->tun.waves_analyse = 3;
+    if (B->tun.waves_residual == 0) B->tun.waves_residual = 3;
     return batch_layout(B);
 }
 
@@ -4303,6 +4336,7 @@ int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const dou
     P.mode = params->mode;
     P.level_mask = params->level_mask;
     P.gamma = mesh->gamma;
+    P.gm1 = mesh->gamma - 1.0;
     P.tau_A = params->tau_A;
     P.tau_S = params->tau_S;
     P.alpha_H = params->alpha_H;

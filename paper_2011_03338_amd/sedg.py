@@ -61,7 +61,7 @@ class Diag_c(ctypes.Structure):
 
 class Tuning_c(ctypes.Structure):
     _fields_ = [("epb4", ctypes.c_int), ("epb8", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
-                ("xcd_map", ctypes.c_int)]
+                ("xcd_map", ctypes.c_int), ("waves_analyse", ctypes.c_int), ("waves_residual", ctypes.c_int)]
 
 
 _lib = None
@@ -366,14 +366,15 @@ class BatchSolver:
         except Exception:
             pass
 
-    def set_tuning(self, epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1):
-        t = Tuning_c(epb4, epb8, blocks_per_cu, xcd_map)
+    def set_tuning(self, epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1, waves_analyse=3, waves_residual=3):
+        t = Tuning_c(epb4, epb8, blocks_per_cu, xcd_map, waves_analyse, waves_residual)
         _check(load().sedg_batch_set_tuning(self._h, ctypes.byref(t)), "sedg_batch_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning_c()
         _check(load().sedg_batch_get_tuning(self._h, ctypes.byref(t)), "sedg_batch_get_tuning")
-        return {"epb4": t.epb4, "epb8": t.epb8, "blocks_per_cu": t.blocks_per_cu, "xcd_map": t.xcd_map}
+        return {"epb4": t.epb4, "epb8": t.epb8, "blocks_per_cu": t.blocks_per_cu, "xcd_map": t.xcd_map,
+                "waves_analyse": t.waves_analyse, "waves_residual": t.waves_residual}
 
     def pack(self, states):
         """One ensemble state (GPU tensor) from per-problem states (arrays or tensors),
