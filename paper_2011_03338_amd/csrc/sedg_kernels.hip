@@ -913,7 +913,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (block_or<EPB * KD>(visit && !ok)) {
             double nd = (DIM == 2) ? n * n : n * n * n;
             double mn[NV], mm[2] = {rmin, pmin};
-            for (int v = 0; v < NV; ++v) mn[v] = ub[v];
+            for (int v = 0; v < NV; ++v) mn[v] = S.u[le][v][c];   // from LDS: ub need not stay live
             subreduce_n<DIM, K, NV>(mn, ln, S.x, OpSum());
             for (int v = 0; v < NV; ++v) mn[v] /= nd;
             subreduce_n<DIM, K, 2>(mm, ln, S.x, OpMin());
