@@ -268,11 +268,12 @@ typedef struct sedg_batch sedg_batch;
  *                  tiles (at most 64)
  *   xcd_map        1: workgroups remapped so that each XCD takes a contiguous
  *                  range of tiles (neighbour face data stay in its L2); 0: none
- *   waves_analyse, waves_residual
- *                  register budget of the analyse / residual kernel, as the
- *                  number of wavefronts per SIMD it must leave room for: 3
- *                  (<= 168 VGPRs) or 4 (<= 128 VGPRs, values may spill to
- *                  scratch); 0 selects 3
+ *   waves_analyse  register budget of the analyse kernel, as the number of
+ *                  wavefronts per SIMD it must leave room for: 3 (<= 168
+ *                  VGPRs) or 4 (<= 128 VGPRs, values may spill to scratch);
+ *                  0 selects 3
+ *   waves_residual the same for the residual kernel: 3 (or 0); 4 is not built
+ *                  and returns SEDG_EUNSUPPORTED
  * Every shape computes bit-identical results (the same arithmetic in the same order). */
 typedef struct sedg_batch_tuning {
     int epb4, epb8, blocks_per_cu, xcd_map;

@@ -3,8 +3,8 @@
 Times a short run of every candidate launch shape (elements per workgroup for
 K = 4 and K = 8, i.e. the LDS tile of the analyse and residual kernels; a
 persistent grid of n workgroups per compute unit or one workgroup per tile;
-XCD-contiguous tile ranges or not; the register budget of the analyse and the
-residual kernel, 3 or 4 wavefronts per SIMD) on a scratch copy of the
+XCD-contiguous tile ranges or not; the register budget of the analyse kernel,
+3 or 4 wavefronts per SIMD) on a scratch copy of the
 ensemble state, keeps the fastest and caches the choice as JSON, keyed by the
 device and the ensemble's element counts per K.  The cache file is
 $SEDG_TUNING_CACHE, else ~/.cache/sedg/batch_tuning.json.
@@ -19,15 +19,14 @@ import torch
 
 def _candidates():
     """One workgroup per tile: the two element-per-workgroup tiles x XCD remap on/off x
-    the register budgets of the analyse and residual kernels (3 or 4 waves per SIMD);
-    persistent grids of 2-8 workgroups per CU at the default budgets."""
+    the register budget of the analyse kernel (3 or 4 waves per SIMD); persistent grids
+    of 2-8 workgroups per CU at the default budget."""
     out = []
     for epb4, epb8 in ((4, 1), (8, 2)):
         for xcd in (1, 0):
             for wa in (3, 4):
-                for wr in (3, 4):
-                    out.append(dict(epb4=epb4, epb8=epb8, blocks_per_cu=0, xcd_map=xcd, waves_analyse=wa,
-                                    waves_residual=wr))
+                out.append(dict(epb4=epb4, epb8=epb8, blocks_per_cu=0, xcd_map=xcd, waves_analyse=wa,
+                                waves_residual=3))
     for epb4, epb8, bpc in ((4, 1, 4), (4, 1, 8), (8, 2, 2), (8, 2, 4)):
         out.append(dict(epb4=epb4, epb8=epb8, blocks_per_cu=bpc, xcd_map=1, waves_analyse=3, waves_residual=3))
     return out

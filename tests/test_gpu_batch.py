@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 TUNINGS = [dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1), dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=0),
            dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=1), dict(epb4=4, epb8=1, blocks_per_cu=2, xcd_map=1),
            dict(epb4=8, epb8=2, blocks_per_cu=1, xcd_map=0),
-           dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1, waves_analyse=4, waves_residual=4),
+           dict(epb4=4, epb8=1, blocks_per_cu=0, xcd_map=1, waves_analyse=4, waves_residual=3),
            dict(epb4=8, epb8=2, blocks_per_cu=0, xcd_map=1, waves_analyse=4, waves_residual=3)]
 
 
@@ -137,8 +137,11 @@ def test_batch_invalid_arguments():
         B.set_tuning(epb4=8, epb8=1)
     with pytest.raises(sedg.SedgError):
         B.set_tuning(waves_analyse=5)
-    B.set_tuning(waves_analyse=0, waves_residual=4)
-    assert B.get_tuning()["waves_analyse"] == 3 and B.get_tuning()["waves_residual"] == 4
+    with pytest.raises(sedg.SedgError) as ei:
+        B.set_tuning(waves_residual=4)
+    assert ei.value.code == sedg.SEDG_EUNSUPPORTED
+    B.set_tuning(waves_analyse=0, waves_residual=0)
+    assert B.get_tuning()["waves_analyse"] == 3 and B.get_tuning()["waves_residual"] == 3
     B.close()
 
 
