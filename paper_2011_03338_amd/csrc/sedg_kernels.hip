@@ -204,32 +204,53 @@ __device__ __forceinline__ void euler_flux(const double *u, int a, const Gas &g,
     f[DIM + 1] = va * (u[DIM + 1] + p);
 }
 
+// HLL flux with Einfeldt's signal speeds (Roe averages), branch-free in the
+// speeds: F* = (S_R+ f_L - S_L- f_R + S_L- S_R+ (u_R - u_L)) / (S_R+ - S_L-), S_L- =
+// min(S_L, 0), S_R+ = max(S_R, 0).  One reciprocal per density and one for the Roe
+// weights instead of a division per quotient.
 template <int DIM>
 __device__ void hlle(const double *uL, const double *uR, int a, const Gas &g, double *fs)
 {
     constexpr int NV = DIM + 2;
+    const double irL = 1.0 / uL[0], irR = 1.0 / uR[0];
+    double m2L = 0.0, m2R = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        m2L += uL[1 + b] * uL[1 + b];
+        m2R += uR[1 + b] * uR[1 + b];
+    }
+    const double pL = (uL[0] > 0.0) ? g.gm1 * (uL[DIM + 1] - 0.5 * m2L * irL) : -INFINITY;
+    const double pR = (uR[0] > 0.0) ? g.gm1 * (uR[DIM + 1] - 0.5 * m2R * irR) : -INFINITY;
+    const double mL = pick<DIM>(uL + 1, a), mR = pick<DIM>(uR + 1, a);
+    const double vL = mL * irL, vR = mR * irR;
     double fL[NV], fR[NV];
-    euler_flux<DIM>(uL, a, g, fL);
-    euler_flux<DIM>(uR, a, g, fR);
-    double pL = pressure<DIM>(uL, g), pR = pressure<DIM>(uR, g);
-    double vL = pick<DIM>(uL + 1, a) / uL[0], vR = pick<DIM>(uR + 1, a) / uR[0];
-    double cL = sqrt(fmax(g.g * pL / uL[0], 0.0)), cR = sqrt(fmax(g.g * pR / uR[0], 0.0));
-    double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
-    double HL = (uL[DIM + 1] + pL) / uL[0], HR = (uR[DIM + 1] + pR) / uR[0];
+    fL[0] = mL;
+    fR[0] = mR;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        fL[1 + b] = uL[1 + b] * vL + (a == b ? pL : 0.0);
+        fR[1 + b] = uR[1 + b] * vR + (a == b ? pR : 0.0);
+    }
+    fL[DIM + 1] = vL * (uL[DIM + 1] + pL);
+    fR[DIM + 1] = vR * (uR[DIM + 1] + pR);
+    const double cL = sqrt(fmax(g.g * pL * irL, 0.0)), cR = sqrt(fmax(g.g * pR * irR, 0.0));
+    const double sqL = sqrt(uL[0]), sqR = sqrt(uR[0]);
+    const double iS = 1.0 / (sqL + sqR);
+    const double HL = (uL[DIM + 1] + pL) * irL, HR = (uR[DIM + 1] + pR) * irR;
     double vt2 = 0.0, vtn = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        double vb = (sqL * (uL[1 + b] / uL[0]) + sqR * (uR[1 + b] / uR[0])) / (sqL + sqR);
+        const double vb = (sqL * (uL[1 + b] * irL) + sqR * (uR[1 + b] * irR)) * iS;
         vt2 += vb * vb;
         if (b == a) vtn = vb;
     }
-    double Ht = (sqL * HL + sqR * HR) / (sqL + sqR);
-    double ct = sqrt(fmax(g.gm1 * (Ht - 0.5 * vt2), 0.0));
-    double SL = fmin(vL - cL, vtn - ct);
-    double SR = fmax(vR + cR, vtn + ct);
-    double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
-    double den = SRp - SLm;
-    double inv = den > 0.0 ? 1.0 / den : 0.0;
+    const double Ht = (sqL * HL + sqR * HR) * iS;
+    const double ct = sqrt(fmax(g.gm1 * (Ht - 0.5 * vt2), 0.0));
+    const double SL = fmin(vL - cL, vtn - ct);
+    const double SR = fmax(vR + cR, vtn + ct);
+    const double SLm = fmin(SL, 0.0), SRp = fmax(SR, 0.0);
+    const double den = SRp - SLm;
+    const double inv = den > 0.0 ? 1.0 / den : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fs[v] = (SRp * fL[v] - SLm * fR[v] + SLm * SRp * (uR[v] - uL[v])) * inv;
 }
