@@ -192,6 +192,19 @@ __device__ __forceinline__ bool flux_admissible(const double *u, const Gas &g, d
     return pressure<DIM>(u, g) > -1e-10 * sE;
 }
 
+// the Euler flux along axis a from the reciprocal ir of the density and the pressure p
+// (shared by the fluxes along every axis at one node)
+template <int DIM>
+__device__ __forceinline__ void euler_flux_ir(const double *u, double ir, double p, int a, double *f)
+{
+    const double ma = pick<DIM>(u + 1, a);
+    const double va = ma * ir;
+    f[0] = ma;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) f[1 + b] = u[1 + b] * va + (a == b ? p : 0.0);
+    f[DIM + 1] = va * (u[DIM + 1] + p);
+}
+
 template <int DIM>
 __device__ __forceinline__ void euler_flux(const double *u, int a, const Gas &g, double *f)
 {
@@ -1594,10 +1607,14 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
             }
             double lrl[NV];
             for (int v = 0; v < NV; ++v) lrl[v] = 0.0;
+            const double nir = 1.0 / nodal[0];
+            double nm2 = 0.0;
+            for (int d = 0; d < DIM; ++d) nm2 += nodal[1 + d] * nodal[1 + d];
+            const double npr = (nodal[0] > 0.0) ? gam.gm1 * (nodal[DIM + 1] - 0.5 * nm2 * nir) : -INFINITY;
             for (int a = a0; a < a1; ++a) {
                 const int axs = SM::AXO ? 0 : a;
                 double f[NV];
-                euler_flux<DIM>(nodal, a, gam, f);
+                euler_flux_ir<DIM>(nodal, nir, npr, a, f);
                 __syncthreads();
                 for (int v = 0; v < NV; ++v) fst[v * KD + c] = f[v];
                 __syncthreads();
