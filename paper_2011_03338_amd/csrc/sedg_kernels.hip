@@ -83,6 +83,7 @@ struct KArgs {
     const int *tile_prob;   // problem of every tile
     const int *ftile_prob;  // problem of every element-face tile
     int ntiles;             // tiles of the whole ensemble
+    int tile_base;          // first tile of a launch that covers the problems of one K
     int chunk;              // consecutive tiles per workgroup
     int xcd_map;            // remap workgroups to contiguous tile ranges per XCD
     long long dof;
@@ -587,6 +588,39 @@ __device__ __forceinline__ double lane_step(double v, int mask, Op op)
     return op(v, lane_xor(v, mask));
 }
 
+// Sums of 8 values over the 64 lanes of a wavefront (one 2-D K = 8 element), every lane
+// ending with all 8 sums in scalar registers.  A reduce-scatter: one row swap across the
+// 32-lane halves pairs value j (kept by the lower lanes) with value j + 4 (kept by the
+// upper ones), so each lane adds its partner's copy of the value it keeps; the same across
+// 16-lane halves leaves 2 values per lane, an exchange across 8-lane halves 1, value
+// (lane >> 3) & 7; a butterfly over the last three bits completes it, and lane 8q holds
+// sum q.  17 exchanges instead of the 48 of eight butterflies.
+__device__ __forceinline__ void wave_sum8(double *v)
+{
+    double w[4], x[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(__double2loint(v[j]), __double2loint(v[4 + j]), false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(__double2hiint(v[j]), __double2hiint(v[4 + j]), false, false);
+        w[j] = __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const auto rl = __builtin_amdgcn_permlane16_swap(__double2loint(w[j]), __double2loint(w[2 + j]), false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(__double2hiint(w[j]), __double2hiint(w[2 + j]), false, false);
+        x[j] = __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
+    }
+    const bool b3 = (threadIdx.x & 8) != 0;
+    double y = (b3 ? x[1] : x[0]) + lane_xor(b3 ? x[0] : x[1], 8);
+    y += lane_xor(y, 4);
+    y += lane_xor(y, 2);
+    y += lane_xor(y, 1);
+    const int ylo = __double2loint(y), yhi = __double2hiint(y);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        v[q] = __hiloint2double(__builtin_amdgcn_readlane(yhi, 8 * q), __builtin_amdgcn_readlane(ylo, 8 * q));
+}
+
 // OR of a predicate over the workgroup, ordered like a barrier.  A one-wavefront
 // workgroup (every 2-D kernel) takes a wave vote after the barrier; the library's
 // workgroup reduction behind __syncthreads_or keeps an LDS buffer of its own, which
@@ -1017,7 +1051,26 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 }
             }
             __syncthreads();
-            if constexpr (G::KD <= 64) {
+            if constexpr (DIM == 2 && K == 8) {
+                if (ln == G::LOGK) {
+                    // the whole element (one wavefront): reduce-scatter of the 8 sums
+                    double snh[2 * NV];
+                    for (int v = 0; v < NV; ++v) {
+                        snh[v] = sn[v];
+                        snh[NV + v] = sh[v];
+                    }
+                    wave_sum8(snh);
+                    for (int v = 0; v < NV; ++v) {
+                        sn[v] = snh[v];
+                        sh[v] = snh[NV + v];
+                    }
+                } else {
+                    for (int v = 0; v < NV; ++v) {
+                        sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
+                        sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
+                    }
+                }
+            } else if constexpr (G::KD <= 64) {
                 for (int v = 0; v < NV; ++v) {
                     sn[v] = subreduce<DIM, K>(sn[v], ln, S.x, OpSum());
                     sh[v] = subreduce<DIM, K>(sh[v], ln, S.x, OpSum());
@@ -2533,6 +2586,20 @@ __attribute__((amdgpu_waves_per_eu(WA, 8))) analyse_batch_kernel(KArgs P)
     }
 }
 
+// the analysis of the problems of one K: one workgroup per tile of the range
+// [tile_base, tile_base + grid) (which holds that K's tiles only)
+template <int K, int EPB, int WA>
+__global__ void __launch_bounds__((EPB * Geo<2, K>::KD))
+__attribute__((amdgpu_waves_per_eu(WA, 8))) analyse_batch_one_kernel(KArgs P)
+{
+    __shared__ AnalyseSmem<2, K, K, EPB> S;
+    const int t = P.tile_base + (P.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x);
+    const int p = wg_uniform(P.tile_prob[t]);
+    const ProbDesc &D = P.probs[p];
+    const KArgs Q = problem_args(P, D, p);
+    analyse_body<2, K, K, EPB>(Q, t - wg_uniform(D.tile_off), S);
+}
+
 template <int EPB4, int EPB8, bool PERSIST>
 __global__ void __launch_bounds__(64 * EPB8)
 __attribute__((amdgpu_waves_per_eu(3, 8))) residual_batch_kernel(KArgs P)
@@ -3885,7 +3952,7 @@ struct sedg_batch {
     std::vector<ProbDesc> probs;
     long long state_len, alpha_len, fbuf_len, nel;
     sedg_batch_tuning tun;
-    int ntiles, grid, chunk, nftiles;
+    int ntiles, ntiles4, grid, chunk, nftiles;   // ntiles4: the K = 4 tiles, numbered first
     sedg_level_tab *d_tabs;
     ProbDesc *d_probs;
     int *d_tile_prob, *d_ftile_prob;
@@ -3906,15 +3973,23 @@ void batch_drop_graphs(sedg_batch *B)
 // tiles of every problem for the current elements-per-workgroup choice, and the grid
 int batch_layout(sedg_batch *B)
 {
+    // the tiles of the K = 4 problems first, then those of the K = 8 problems, so that
+    // one launch per K can cover each (their analyse kernels then get register
+    // allocations of their own)
     std::vector<int> tp;
     int t = 0;
-    for (int p = 0; p < B->nprob; ++p) {
-        ProbDesc &D = B->probs[p];
-        const int epb = D.K == 4 ? B->tun.epb4 : B->tun.epb8;
-        D.tile_off = t;
-        D.ntiles = (D.nel + epb - 1) / epb;
-        t += D.ntiles;
-        for (int i = 0; i < D.ntiles; ++i) tp.push_back(p);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int Kp = pass == 0 ? 4 : 8;
+        for (int p = 0; p < B->nprob; ++p) {
+            ProbDesc &D = B->probs[p];
+            if (D.K != Kp) continue;
+            const int epb = D.K == 4 ? B->tun.epb4 : B->tun.epb8;
+            D.tile_off = t;
+            D.ntiles = (D.nel + epb - 1) / epb;
+            t += D.ntiles;
+            for (int i = 0; i < D.ntiles; ++i) tp.push_back(p);
+        }
+        if (pass == 0) B->ntiles4 = t;
     }
     B->ntiles = t;
     // element-face tiles: 64 / K tasks (element, axis) each
@@ -3987,9 +4062,27 @@ template <int EPB4, int EPB8, bool PERSIST>
 void batch_launch_t(int which, const sedg_batch *B, const KArgs &P, hipStream_t s)
 {
     const dim3 grid(B->grid), block(64 * EPB8);
-    if (which == 0) {
-        if (B->tun.waves_analyse == 4) hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST, 4>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST, 3>), grid, block, 0, s, P);
+    const bool w4 = B->tun.waves_analyse == 4;
+    if (which == 0 && !PERSIST) {
+        // one analyse launch per K over its own tiles
+        const int n4 = B->ntiles4, n8 = B->ntiles - B->ntiles4;
+        KArgs Q = P;
+        if (n4 > 0) {
+            Q.tile_base = 0;
+            if (w4) hipLaunchKernelGGL((analyse_batch_one_kernel<4, EPB4, 4>), dim3(n4), block, 0, s, Q);
+            else hipLaunchKernelGGL((analyse_batch_one_kernel<4, EPB4, 3>), dim3(n4), block, 0, s, Q);
+        }
+        if (n8 > 0) {
+            Q.tile_base = n4;
+            if (w4) hipLaunchKernelGGL((analyse_batch_one_kernel<8, EPB8, 4>), dim3(n8), block, 0, s, Q);
+            else hipLaunchKernelGGL((analyse_batch_one_kernel<8, EPB8, 3>), dim3(n8), block, 0, s, Q);
+        }
+    } else if (which == 0) {
+        // persistent grid: one launch for both K
+        if constexpr (PERSIST) {
+            if (w4) hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST, 4>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((analyse_batch_kernel<EPB4, EPB8, PERSIST, 3>), grid, block, 0, s, P);
+        }
     } else {
         // the residual reads the element-face fluxes of the face kernel launched before it
         hipLaunchKernelGGL(eface_batch_kernel, dim3(B->nftiles), dim3(64), 0, s, P);
