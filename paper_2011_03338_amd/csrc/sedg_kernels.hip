@@ -148,15 +148,19 @@ __device__ __forceinline__ double splitmix_u01(unsigned long long seed, unsigned
 // ---------------------------------------------------------------------------
 
 // The axis a is a run-time value in the kernels: components along a are picked and
-// scattered with selects over the unrolled component loop, never by indexing a
-// register array with a.
+// scattered over the unrolled component loop, never by indexing a register array with
+// a.  The pick masks the bit patterns of the components (exact for every value): a
+// chain of selects between array elements can be turned by the compiler into one load
+// from a computed address, which puts the array into scratch memory (it did so in 3-D,
+// where the axis differs between the lanes of the element-face kernel).
 template <int DIM>
 __device__ __forceinline__ double pick(const double *x, int a)
 {
-    double r = x[0];
+    unsigned long long r = 0;
 #pragma unroll
-    for (int b = 1; b < DIM; ++b) r = (b == a) ? x[b] : r;
-    return r;
+    for (int b = 0; b < DIM; ++b)
+        r |= (unsigned long long)__double_as_longlong(x[b]) & (0ull - (unsigned long long)(a == b));
+    return __longlong_as_double((long long)r);
 }
 
 // the ratio of specific heats and gamma - 1 (the latter a kernel argument, so that it
@@ -869,8 +873,12 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (P.lam_part) {
             double lam = 0.0;
             if (act && ok) {
-                double cs = sqrt(gam.g * pressure<DIM>(ub, gam) / ub[0]);
-                for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
+                // one reciprocal of the density for the velocities and the sound speed
+                const double ir = 1.0 / ub[0];
+                double m2 = 0.0;
+                for (int a = 0; a < DIM; ++a) m2 += ub[1 + a] * ub[1 + a];
+                const double cs = sqrt(gam.g * gam.gm1 * (ub[NV - 1] - 0.5 * m2 * ir) * ir);
+                for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] * ir) + cs);
             }
             #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) lam = lane_step(lam, off, OpMax());
