@@ -873,12 +873,8 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         if (P.lam_part) {
             double lam = 0.0;
             if (act && ok) {
-                // one reciprocal of the density for the velocities and the sound speed
-                const double ir = 1.0 / ub[0];
-                double m2 = 0.0;
-                for (int a = 0; a < DIM; ++a) m2 += ub[1 + a] * ub[1 + a];
-                const double cs = sqrt(gam.g * gam.gm1 * (ub[NV - 1] - 0.5 * m2 * ir) * ir);
-                for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] * ir) + cs);
+                double cs = sqrt(gam.g * pressure<DIM>(ub, gam) / ub[0]);
+                for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
             }
             #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) lam = lane_step(lam, off, OpMax());
