@@ -1352,7 +1352,7 @@ __device__ __forceinline__ void face_at(int a0, int na, int step, int fidx, int 
 // input (element -1: own element ee, read from uown in LDS when given, else from
 // global memory).  wsL, wsR: LDS exchange buffers of the element's lanes (lane c);
 // every lane of the workgroup (NT threads) calls it with the same face count.
-template <int DIM, int K, class LV, int NT>
+template <int DIM, int K, class LV, int NT, bool WIDE = false>
 __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double *wsR, int c, int sbase, int t, bool has,
                                             int fa, int k, const double *uL, const double *uR, const double *thL,
                                             const double *thR, double srho, double sE, int mLe, int mLc, int mRe,
@@ -1382,6 +1382,65 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
             lo1 = t1 & (n - 1); tb1 = t1 - lo1;
         }
         const int t0 = t - K * (t >> G::LOGK), t1 = t >> G::LOGK;   // 3-D face coordinates
+        if constexpr (WIDE) {
+            // every variable through the exchange buffers at once (NV x NT doubles each):
+            // one LDS round trip per pass instead of one per variable
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                wsL[v * NT + c] = uL[v];
+                wsR[v * NT + c] = uR[v];
+            }
+            __syncthreads();
+            if (DIM == 2) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double sl = 0.0, sr = 0.0;
+                    if (need)
+                        for (int m = 0; m < n; ++m) {
+                            double Rm = T.R[lo0 * n + m];
+                            sl += Rm * wsL[v * NT + sbase + tb0 + m];
+                            sr += Rm * wsR[v * NT + sbase + tb0 + m];
+                        }
+                    nl[v] = sl;
+                    nr[v] = sr;
+                }
+            } else {
+                double al0[NV], ar0[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    al0[v] = 0.0;
+                    ar0[v] = 0.0;
+                    if (need)
+                        for (int m0 = 0; m0 < n; ++m0) {
+                            double Rm = T.R[lo0 * n + m0];
+                            int q = v * NT + sbase + (tb0 + m0) + K * t1;
+                            al0[v] += Rm * wsL[q];
+                            ar0[v] += Rm * wsR[q];
+                        }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    wsL[v * NT + c] = al0[v];
+                    wsR[v * NT + c] = ar0[v];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double sl = 0.0, sr = 0.0;
+                    if (need)
+                        for (int m1 = 0; m1 < n; ++m1) {
+                            double Rm1 = T.R[lo1 * n + m1];
+                            int q = v * NT + sbase + t0 + K * (tb1 + m1);
+                            sl += Rm1 * wsL[q];
+                            sr += Rm1 * wsR[q];
+                        }
+                    nl[v] = sl;
+                    nr[v] = sr;
+                }
+            }
+            __syncthreads();
+        } else
         for (int v = 0; v < NV; ++v) {
             wsL[c] = uL[v];
             wsR[c] = uR[v];
@@ -1440,6 +1499,42 @@ __device__ __forceinline__ void common_flux(const KArgs &P, double *wsL, double 
         double fnod[NV];
         if (need && okf) hlle<DIM>(nl, nr, fa, gam, fnod);
         else for (int v = 0; v < NV; ++v) fnod[v] = 0.0;
+        if constexpr (WIDE) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) wsL[v * NT + c] = fnod[v];
+            __syncthreads();
+            if (DIM == 2) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double sacc = 0.0;
+                    if (need && okf)
+                        for (int m = 0; m < n; ++m) sacc += T.P[lo0 * n + m] * wsL[v * NT + sbase + tb0 + m];
+                    if (need && okf) F[v] += tb * sacc;
+                }
+            } else {
+                double a0s[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    a0s[v] = 0.0;
+                    if (need && okf)
+                        for (int m0 = 0; m0 < n; ++m0)
+                            a0s[v] += T.P[lo0 * n + m0] * wsL[v * NT + sbase + (tb0 + m0) + K * t1];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < NV; ++v) wsL[v * NT + c] = a0s[v];
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double sacc = 0.0;
+                    if (need && okf)
+                        for (int m1 = 0; m1 < n; ++m1)
+                            sacc += T.P[lo1 * n + m1] * wsL[v * NT + sbase + t0 + K * (tb1 + m1)];
+                    if (need && okf) F[v] += tb * sacc;
+                }
+            }
+            __syncthreads();
+        } else
         for (int v = 0; v < NV; ++v) {
             wsL[c] = fnod[v];
             __syncthreads();
@@ -1769,7 +1864,7 @@ __device__ __forceinline__ void eface_body(const KArgs &P, int tile, double *wsL
                                        P.alpha + (long long)(nb >= 0 ? nb : e) * LV::A, own_sr, own_se, uL, uR,
                                        thL, thR, mLe, mLc, mRe, mRc, srho, sE);
         double F[NV];
-        common_flux<DIM, K, LV, 64>(P, wsL, wsR, c, slot * KF, t, has, a, sd ? K : 0, uL, uR, thL, thR, srho, sE, mLe,
+        common_flux<DIM, K, LV, 64, true>(P, wsL, wsR, c, slot * KF, t, has, a, sd ? K : 0, uL, uR, thL, thR, srho, sE, mLe,
                                     mLc, mRe, mRc, nullptr, e, F);
         if (has)
             for (int v = 0; v < NV; ++v) P.ef[fb_index<DIM, K>(e, a, sd, v, t)] = F[v];
@@ -1779,7 +1874,7 @@ __device__ __forceinline__ void eface_body(const KArgs &P, int tile, double *wsL
 template <int DIM, int K, int TOP>
 __global__ void __launch_bounds__(64) eface_kernel(KArgs P)
 {
-    __shared__ double wsL[64], wsR[64];
+    __shared__ double wsL[(DIM + 2) * 64], wsR[(DIM + 2) * 64];
     eface_body<DIM, K, TOP>(P, xcd_tile(blockIdx.x, gridDim.x), wsL, wsR);
 }
 
@@ -2631,7 +2726,7 @@ __attribute__((amdgpu_waves_per_eu(3, 8))) residual_batch_kernel(KArgs P)
 // is one workgroup of 64 lanes
 __global__ void __launch_bounds__(64) eface_batch_kernel(KArgs P)
 {
-    __shared__ double wsL[64], wsR[64];
+    __shared__ double wsL[4 * 64], wsR[4 * 64];
     const int L = P.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int p = wg_uniform(P.ftile_prob[L]);
     const ProbDesc &D = P.probs[p];
