@@ -416,3 +416,14 @@ def test_invalid_arguments():
     with pytest.raises(sedg.SedgError):
         s.rk_step(ug, 1)                        # EXTERNAL cannot step
     s.close()
+    s = sedg.Solver(mesh, W.Params())
+    with pytest.raises(sedg.SedgError) as ei:
+        s.rhs(ug, ug)                           # the output may not alias the state
+    assert ei.value.code == sedg.SEDG_EINVAL
+    with pytest.raises(sedg.SedgError) as ei:
+        s.rk_step(ug, -1)
+    assert ei.value.code == sedg.SEDG_EINVAL
+    before = ug.clone()
+    s.rk_step(ug, 0)                            # zero steps: nothing happens
+    assert torch.equal(ug, before)
+    s.close()

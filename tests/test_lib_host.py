@@ -61,3 +61,31 @@ def test_two_nc_table_builders_agree(n, fam):
     a, b = sedg.nc_tables(n, fam), O.nc_tables(n, fam)
     for k in ("Z", "Q", "Lm", "Lp"):
         assert np.abs(a[k] - b[k]).max() <= 8 * np.finfo(float).eps * max(1.0, np.abs(b[k]).max()), k
+
+
+@pytest.mark.parametrize("case", ["no_elements", "empty_box", "bad_bc", "gamma", "family", "dim", "K"])
+def test_create_rejects_bad_meshes_before_any_device_work(case):
+    """sedg_create validates the mesh before it touches the device (so these run on the
+    CPU): no elements along an axis, an empty box, an unknown boundary condition, gamma
+    <= 1 or an unknown node family give SEDG_EINVAL, an unsupported dimension or K
+    SEDG_EUNSUPPORTED."""
+    from paper_2011_03338_amd import workloads as W
+    mesh = dict(dim=2, K=8, nelem=[4, 4], lo=[0.0, 0.0], hi=[1.0, 1.0], bc=[0, 0])
+    expect = sedg.SEDG_EINVAL
+    if case == "no_elements":
+        mesh["nelem"] = [4, 0]
+    elif case == "empty_box":
+        mesh["hi"] = [1.0, 0.0]
+    elif case == "bad_bc":
+        mesh["bc"] = [0, 7]
+    elif case == "dim":
+        mesh.update(dim=1, nelem=[4], lo=[0.0], hi=[1.0], bc=[0])
+        expect = sedg.SEDG_EUNSUPPORTED
+    elif case == "K":
+        mesh["K"] = 6
+        expect = sedg.SEDG_EUNSUPPORTED
+    m = W.Mesh(mesh["dim"], mesh["K"], mesh["nelem"], mesh["lo"], mesh["hi"], mesh["bc"],
+               gamma=1.0 if case == "gamma" else 1.4, family=5 if case == "family" else 0)
+    with pytest.raises(sedg.SedgError) as ei:
+        sedg.Solver(m, W.Params())
+    assert ei.value.code == expect
