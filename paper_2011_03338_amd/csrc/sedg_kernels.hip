@@ -84,6 +84,13 @@ struct KArgs {
     const int *ftile_prob;  // problem of every element-face tile
     int ntiles;             // tiles of the whole ensemble
     int tile_base;          // first tile of a launch that covers the problems of one K
+    // CFL step size formed by workgroup 0 of the element-face kernel (fin_lam non-null):
+    // the maximum of the per-block eigenvalue maxima, fin_num / it into *dt, and the log
+    double *fin_lam;
+    double fin_num;
+    double *fin_dt;
+    double *fin_dt_log;
+    const int *fin_ctr;
     int chunk;              // consecutive tiles per workgroup
     int xcd_map;            // remap workgroups to contiguous tile ranges per XCD
     long long dof;
@@ -1876,6 +1883,24 @@ __global__ void __launch_bounds__(64) eface_kernel(KArgs P)
 {
     __shared__ double wsL[(DIM + 2) * 64], wsR[(DIM + 2) * 64];
     eface_body<DIM, K, TOP>(P, xcd_tile(blockIdx.x, gridDim.x), wsL, wsR);
+    if (P.fin_lam && blockIdx.x == 0) {
+        // the step size of the stage's residual (launched after this kernel): one launch
+        // less per step than a kernel of its own; maxima are exact in any order
+        const int l = threadIdx.x;
+        double m = 0.0;
+#pragma unroll
+        for (int k = 0; k < LAM_SLOTS / 64; ++k) {
+            m = fmax(m, P.fin_lam[l + 64 * k]);
+            P.fin_lam[l + 64 * k] = 0.0;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m = lane_step(m, off, OpMax());
+        if (l == 0) {
+            const double d = P.fin_num / m;
+            P.fin_dt[0] = d;
+            if (P.fin_dt_log) P.fin_dt_log[P.fin_ctr[0]] = d;
+        }
+    }
 }
 
 template <int DIM, int K, int TOP, int EPB>
@@ -3532,14 +3557,17 @@ static void enqueue_step(sedg_ctx *C, double *u, double dt_fixed, double *dt_log
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
     advance_draw(C, s);
     log_alpha(0);
-    if (!(dt_fixed > 0.0))
-        timed(C, 2, s, [&] {
-            hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
-                               cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
-        });
-    else if (dt_log)
+    if (!(dt_fixed > 0.0)) {
+        // the step size is formed inside the element-face launch that follows
+        P.fin_lam = C->d_lam;
+        P.fin_num = cfl_numerator(C);
+        P.fin_dt = C->d_dt;
+        P.fin_dt_log = dt_log;
+        P.fin_ctr = C->d_ctr;
+    } else if (dt_log)
         hipLaunchKernelGGL(log_dt_kernel, dim3(1), dim3(64), 0, s, (const double *)C->d_dt, dt_log, (const int *)C->d_ctr);
     timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+    P.fin_lam = nullptr;
     timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
     // stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1))
     P.lam_part = nullptr;
