@@ -254,10 +254,12 @@ int sedg_adjoint_rk_step(sedg_ctx *ctx, const double *tapes, int nsteps, const d
  * not available), the ratio of specific heats and the node family.  Their states
  * sit back to back in one device array: problem p occupies
  * [sedg_batch_state_offset(p), + 4 * its DOF) in the single-problem layout.
- * One step advances every problem by one SSP-RK3 step with one launch each of
- * the analyse, element-face flux and residual kernels per stage for the whole
- * ensemble (plus a per-problem step-size kernel), captured once per
- * (u, dt_log, fixed) into a HIP graph and replayed. */
+ * One step advances every problem by one step of params->integrator (SSP-RK3 or
+ * SSP-RK(5,4)) with one launch each of the analyse, element-face flux and
+ * residual kernels per stage for the whole ensemble (plus a per-problem
+ * step-size kernel), captured once per (u, dt_log, fixed) into a HIP graph and
+ * replayed; each problem's result equals, bit for bit, that of a single-problem
+ * context with the same mesh and parameters. */
 typedef struct sedg_batch sedg_batch;
 
 /* Launch shape of the batched kernels (chosen by an autotuner):
@@ -294,10 +296,11 @@ long sedg_batch_state_offset(const sedg_batch *batch, int p);
 int sedg_batch_set_tuning(sedg_batch *batch, const sedg_batch_tuning *tuning);
 int sedg_batch_get_tuning(const sedg_batch *batch, sedg_batch_tuning *tuning);
 
-/* Advance every problem by nsteps SSP-RK3 steps in place.  dt_fixed > 0: that step
- * for all problems; otherwise each problem's own CFL step of each step's initial
- * state.  dt_log_dev (device, optional, CFL steps only) receives nsteps * count
- * step sizes, step-major. */
+/* Advance every problem by nsteps steps of params->integrator in place.  dt_fixed > 0:
+ * that step for all problems; otherwise each problem's own CFL step of each step's
+ * initial state.  dt_log_dev (device, optional, CFL steps only) receives
+ * nsteps * count step sizes, step-major.  SSP-RK(5,4) allocates one more
+ * ensemble-sized state on its first call (SEDG_ENOMEM if that fails). */
 int sedg_batch_rk_step(sedg_batch *batch, double *u, int nsteps, double dt_fixed, double *dt_log_dev, void *stream);
 
 /* Synchronise and report a non-permissible or non-finite mean value: SEDG_ESTATE

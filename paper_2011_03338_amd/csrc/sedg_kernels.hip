@@ -2664,6 +2664,9 @@ __device__ __forceinline__ KArgs problem_args(const KArgs &P, const ProbDesc &Dm
     KArgs Q = P;
     Q.u = P.u + D.state_off;
     Q.u0 = P.u0 ? P.u0 + D.state_off : nullptr;
+    Q.x1 = P.x1 ? P.x1 + D.state_off : nullptr;
+    Q.y0 = P.y0 ? P.y0 + D.state_off : nullptr;
+    Q.yout = P.yout ? P.yout + D.state_off : nullptr;
     Q.out = P.out + D.state_off;
     Q.alpha = P.alpha + D.alpha_off;
     Q.beta = P.beta + D.alpha_off;
@@ -4084,6 +4087,7 @@ struct sedg_batch {
     ProbDesc *d_probs;
     int *d_tile_prob, *d_ftile_prob;
     double *d_alpha, *d_beta, *d_mean, *d_scale, *d_fbuf, *d_ef, *d_u1, *d_u2, *d_dt, *d_lam;
+    double *d_u3;            // SSP-RK(5,4): the fourth stage state (allocated on first use)
     int *d_err, *d_ctr;
     hipStream_t last;
     std::map<std::tuple<double *, double *, int>, hipGraphExec_t> graphs;
@@ -4257,6 +4261,47 @@ void enqueue_batch_step(sedg_batch *B, double *u, bool fixed, double *dt_log, hi
     if (dt_log && !fixed) hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, s, B->d_ctr);
 }
 
+// SSP-RK(5,4) of the ensemble: the stages and buffers of the single-problem form
+// (enqueue_step_rk54), one analyse / element-face / residual launch each for the whole
+// ensemble
+void enqueue_batch_step_rk54(sedg_batch *B, double *u, bool fixed, double *dt_log, hipStream_t s)
+{
+    KArgs P = batch_args(B);
+    auto set = [&](const double *r) { for (int k = 0; k < 7; ++k) P.rk[k] = r[k]; };
+    P.stage = 5;
+    P.u = u;
+    P.u0 = P.x1 = P.y0 = nullptr;
+    P.yout = nullptr;
+    P.out = B->d_u1;
+    const double r1[7] = {0.0, 1.0, RK54_C10, 0.0, 0.0, 0.0, 0.0};
+    set(r1);
+    P.lam_part = fixed ? nullptr : B->d_lam;
+    batch_launch(0, B, P, s);
+    if (!fixed)
+        hipLaunchKernelGGL(finalize_batch_kernel, dim3(B->nprob), dim3(BATCH_SLOTS), 0, s, B->d_lam,
+                           (const ProbDesc *)B->d_probs, B->nprob, B->d_dt, dt_log, (const int *)B->d_ctr);
+    batch_launch(1, B, P, s);
+    P.lam_part = nullptr;
+    struct { double *in, *out; const double *u0, *x1, *y0; double *yout; double r[7]; } st[4] = {
+        {B->d_u1, B->d_u2, u, nullptr, nullptr, nullptr, {RK54_A20, RK54_A21, RK54_C21, 0, 0, 0, 0}},
+        {B->d_u2, B->d_u1, u, nullptr, nullptr, nullptr, {RK54_A30, RK54_A32, RK54_C32, 0, 0, 0, 0}},
+        {B->d_u1, B->d_u3, u, nullptr, B->d_u2, B->d_u2, {RK54_A40, RK54_A43, RK54_C43, 0, RK54_A52, RK54_A53, RK54_C53}},
+        {B->d_u3, u, nullptr, B->d_u2, nullptr, nullptr, {0, RK54_A54, RK54_C54, 1.0, 0, 0, 0}},
+    };
+    for (int k = 0; k < 4; ++k) {
+        P.u = st[k].in;
+        P.out = st[k].out;
+        P.u0 = st[k].u0;
+        P.x1 = st[k].x1;
+        P.y0 = st[k].y0;
+        P.yout = st[k].yout;
+        set(st[k].r);
+        batch_launch(0, B, P, s);
+        batch_launch(1, B, P, s);
+    }
+    if (dt_log && !fixed) hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, s, B->d_ctr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -4267,7 +4312,7 @@ int sedg_batch_destroy(sedg_batch *B)
     (void)hipDeviceSynchronize();
     batch_drop_graphs(B);
     void *ptrs[] = {B->d_tabs, B->d_probs, B->d_tile_prob, B->d_ftile_prob, B->d_alpha, B->d_beta, B->d_mean,
-                    B->d_scale, B->d_fbuf, B->d_ef, B->d_u1, B->d_u2, B->d_dt, B->d_lam, B->d_err, B->d_ctr};
+                    B->d_scale, B->d_fbuf, B->d_ef, B->d_u1, B->d_u2, B->d_u3, B->d_dt, B->d_lam, B->d_err, B->d_ctr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete B;
@@ -4279,7 +4324,7 @@ int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *par
     if (!meshes || count < 1 || !params || !out) return SEDG_EINVAL;
     *out = nullptr;
     if (params->top_level != 0 || params->mode == SEDG_EXTERNAL || params->mode < 0 || params->mode > 3 ||
-        params->integrator != SEDG_SSPRK3)
+        (params->integrator != SEDG_SSPRK3 && params->integrator != SEDG_SSPRK54))
         return SEDG_EINVAL;
     for (int p = 0; p < count; ++p) {
         const sedg_mesh &m = meshes[p];
@@ -4408,6 +4453,11 @@ int sedg_batch_rk_step(sedg_batch *B, double *u, int nsteps, double dt_fixed, do
 {
     if (!B || !u || nsteps < 0) return SEDG_EINVAL;
     if (nsteps == 0) return SEDG_OK;
+    const bool rk54 = B->params.integrator == SEDG_SSPRK54;
+    if (rk54 && !B->d_u3 && hipMalloc(&B->d_u3, sizeof(double) * (size_t)B->state_len) != hipSuccess) {
+        B->d_u3 = nullptr;
+        return SEDG_ENOMEM;
+    }
     hipStream_t s = (hipStream_t)stream;
     const bool fixed = dt_fixed > 0.0;
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, (double *)nullptr, 0.0, B->d_ctr);
@@ -4427,7 +4477,8 @@ int sedg_batch_rk_step(sedg_batch *B, double *u, int nsteps, double dt_fixed, do
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SEDG_EHIP;
         hipGraph_t graph;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
-        enqueue_batch_step(B, u, fixed, dt_log_dev, cs);
+        if (rk54) enqueue_batch_step_rk54(B, u, fixed, dt_log_dev, cs);
+        else enqueue_batch_step(B, u, fixed, dt_log_dev, cs);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess) { (void)hipStreamDestroy(cs); return SEDG_EHIP; }
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);

@@ -1,7 +1,8 @@
 """Batched ensembles: many independent 2-D problems (mixed K, mesh sizes and
 boundary conditions) advanced by one launch per kernel and stage must give, for
-every problem and every launch shape, bit for bit the states and step sizes of
-the single-problem path (the same element arithmetic), and match the oracle."""
+every problem, launch shape and integrator (SSP-RK3, SSP-RK(5,4)), bit for bit the
+states and step sizes of the single-problem path (the same element arithmetic), and
+match the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -102,6 +103,43 @@ def test_batch_matches_oracle():
         say("  batch member %d vs oracle after %d steps: rel_err=%.3e" % (p, nsteps, err))
         assert err <= STATE_TOL
         assert np.abs(logs[:, p] - dto).max() <= 1e-14 * dto.max()
+    B.close()
+
+
+@pytest.mark.parametrize("tuning", [0, 3])
+def test_batch_rk54_matches_single_problem_bitwise(tuning):
+    """SSP-RK(5,4) ensembles (CFL steps, then a fixed step): every member equals the
+    single-problem SSP-RK(5,4) path bit for bit, and one member matches the oracle's
+    SSP-RK(5,4) (state within the state tolerance, steps within 1e-14)."""
+    probs = _problems()
+    prm = W.Params(cfl=0.8, integrator=sedg.SEDG_SSPRK54)
+    nsteps = 3
+    B = sedg.BatchSolver([m for m, _ in probs], prm)
+    B.set_tuning(**TUNINGS[tuning])
+    u = B.pack([x for _, x in probs])
+    log = torch.zeros(nsteps * B.count, dtype=torch.float64, device=DEV)
+    B.rk_step(u, nsteps, 0.0, log)
+    B.rk_step(u, 1, 1e-5)
+    B.check()
+    logs = log.view(nsteps, B.count).cpu().numpy()
+    views = B.views(u)
+    for p, (m, x) in enumerate(probs):
+        s = sedg.Solver(m, prm)
+        ug = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+        rl = torch.zeros(nsteps, dtype=torch.float64, device=DEV)
+        s.rk_step(ug, nsteps, 0.0, rl)
+        s.rk_step(ug, 1, 1e-5)
+        s.check()
+        assert np.array_equal(views[p].cpu().numpy(), ug.cpu().numpy()), (tuning, p)
+        assert np.array_equal(logs[:, p], rl.cpu().numpy()), (tuning, p)
+        s.close()
+    m, x = probs[2]
+    uo, dto = O.rk3(m, prm, x, nsteps)
+    uo, _ = O.rk3(m, prm, uo, 1, dt_fixed=1e-5)
+    err = rel_err(views[2].cpu().numpy(), uo)
+    say("  batch SSP-RK(5,4), tuning %s: %d problems bitwise equal; member 2 vs oracle rel_err=%.3e"
+        % (TUNINGS[tuning], B.count, err))
+    assert err <= STATE_TOL and np.abs(logs[:, 2] - dto).max() <= 1e-14 * dto.max()
     B.close()
 
 
