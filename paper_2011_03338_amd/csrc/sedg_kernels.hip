@@ -647,26 +647,19 @@ __device__ __forceinline__ bool block_or(bool pred)
     }
 }
 
-// xor-butterfly reduction of NQ values at once over the cells of one level-n
-// sub-element (ln = log2 n; ln = LOGK gives the whole element); every lane ends with
-// the values of its sub-element.  Bits inside a wavefront use lane exchanges.  Bits
-// above them (3-D, K = 8: the bits of the z coordinate, one wavefront per z layer)
-// go through LDS with one barrier pair for all NQ values: one lane per wavefront
-// publishes its partials, and every lane combines those of the wavefronts of its
-// sub-element pairwise in the butterfly's pairing (the operators are commutative, so
-// this is the butterfly's result to the bit).  s_x holds at least NQ x (wavefronts
-// per workgroup) values.
+struct OpSum { __device__ double operator()(double a, double b) const { return a + b; } };
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpAnd { __device__ int operator()(int a, int b) const { return a & b; } };
+struct OpOr { __device__ int operator()(int a, int b) const { return a | b; } };
+
+// the part of a sub-element reduction across the wavefronts of one element (3-D, K = 8):
+// each wavefront's partial (already reduced over its lanes) is combined in LDS
 template <int DIM, int K, int NQ, typename T, typename Op>
-__device__ void subreduce_n(T *v, int ln, T *s_x, Op op)
+__device__ void subreduce_xwave(T *v, int ln, T *s_x, Op op)
 {
     constexpr int LOGK = Geo<DIM, K>::LOGK;
     constexpr int NB = DIM * LOGK;              // bits of the cell index
-#pragma unroll
-    for (int bit = 0; bit < (NB < 6 ? NB : 6); ++bit) {
-        if (bit % LOGK >= ln) continue;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = lane_step(v[q], 1 << bit, op);
-    }
     if constexpr (NB > 6) {
         constexpr int NW = 1 << (NB - 6);       // wavefronts of one element
         int wmask = 0;                          // wavefront bits inside the sub-element
@@ -703,18 +696,68 @@ __device__ void subreduce_n(T *v, int ln, T *s_x, Op op)
     }
 }
 
+// xor-butterfly reduction of NQ values at once over the cells of one level-n
+// sub-element (ln = log2 n; ln = LOGK gives the whole element); every lane ends with
+// the values of its sub-element.  Bits inside a wavefront use lane exchanges.  Bits
+// above them (3-D, K = 8: the bits of the z coordinate, one wavefront per z layer)
+// go through LDS with one barrier pair for all NQ values: one lane per wavefront
+// publishes its partials, and every lane combines those of the wavefronts of its
+// sub-element pairwise in the butterfly's pairing (the operators are commutative, so
+// this is the butterfly's result to the bit).  s_x holds at least NQ x (wavefronts
+// per workgroup) values.
+template <int DIM, int K, int NQ, typename T, typename Op>
+__device__ void subreduce_n(T *v, int ln, T *s_x, Op op)
+{
+    constexpr int LOGK = Geo<DIM, K>::LOGK;
+    constexpr int NB = DIM * LOGK;              // bits of the cell index
+#pragma unroll
+    for (int bit = 0; bit < (NB < 6 ? NB : 6); ++bit) {
+        if (bit % LOGK >= ln) continue;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = lane_step(v[q], 1 << bit, op);
+    }
+    subreduce_xwave<DIM, K, NQ>(v, ln, s_x, op);
+}
+
+// AND (ALL) or OR of 0/1 votes over the same groups: inside a wavefront one ballot, each
+// lane testing the bits of its group (the lanes that differ from it only in the varying
+// bits of the cell index), then the cross-wavefront part of subreduce_n
+template <int DIM, int K, int NQ, bool ALL>
+__device__ __forceinline__ void subvote_n(int *v, int ln, int *s_x)
+{
+    constexpr int LOGK = Geo<DIM, K>::LOGK;
+    constexpr int NB = DIM * LOGK;
+    int vary = 0;                               // varying lane bits
+#pragma unroll
+    for (int bit = 0; bit < (NB < 6 ? NB : 6); ++bit)
+        if (bit % LOGK < ln) vary |= 1 << bit;
+    unsigned long long pat = 1;                 // lane offsets inside a group: subsets of vary
+#pragma unroll
+    for (int bit = 0; bit < 6; ++bit)
+        if (vary & (1 << bit)) pat |= pat << (1 << bit);
+    const unsigned long long gm = pat << ((threadIdx.x & 63) & ~vary);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const unsigned long long m = __ballot(v[q] != 0);
+        v[q] = ALL ? ((m & gm) == gm ? 1 : 0) : ((m & gm) != 0 ? 1 : 0);
+    }
+    if constexpr (ALL) subreduce_xwave<DIM, K, NQ>(v, ln, s_x, OpAnd());
+    else subreduce_xwave<DIM, K, NQ>(v, ln, s_x, OpOr());
+}
+
+template <int DIM, int K, bool ALL>
+__device__ __forceinline__ int subvote(int v, int ln, int *s_x)
+{
+    subvote_n<DIM, K, 1, ALL>(&v, ln, s_x);
+    return v;
+}
+
 template <int DIM, int K, typename T, typename Op>
 __device__ __forceinline__ T subreduce(T v, int ln, T *s_x, Op op)
 {
     subreduce_n<DIM, K, 1>(&v, ln, s_x, op);
     return v;
 }
-
-struct OpSum { __device__ double operator()(double a, double b) const { return a + b; } };
-struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
-struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
-struct OpAnd { __device__ int operator()(int a, int b) const { return a & b; } };
-struct OpOr { __device__ int operator()(int a, int b) const { return a | b; } };
 
 // blocked n-mode product: out = sum_m M[lo][m] * src[base + m*stride] along axis a
 // for level n (lo = position of c inside its level-n sub-element along a)
@@ -985,7 +1028,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             rmin = fmin(rmin, pt[0]);
             pmin = fmin(pmin, q);
         }
-        ok = subreduce<DIM, K>(ok, ln, S.ix, OpAnd());
+        ok = subvote<DIM, K, true>(ok, ln, S.ix);
         double b = 1.0;
         const int sub = G::subelem(c, n);
         const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
@@ -1098,7 +1141,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                     sh[v] = snh[NV + v];
                 }
             }
-            bad = subreduce<DIM, K>(bad, ln, S.ix, OpOr());
+            bad = subvote<DIM, K, false>(bad, ln, S.ix);
             double amin = 1.0;
             int nonfin = 0;
             for (int v = 0; v < NV; ++v) {
@@ -1116,10 +1159,10 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         // level decision over the whole element (strict comparisons)
         int hl[2] = {(a > P.alpha_H) ? 1 : 0, (a < P.alpha_L) ? 1 : 0};
         if constexpr (G::KD <= 64) {
-            hl[0] = subreduce<DIM, K>(hl[0], G::LOGK, S.ix, OpAnd());
-            hl[1] = subreduce<DIM, K>(hl[1], G::LOGK, S.ix, OpAnd());
+            hl[0] = subvote<DIM, K, true>(hl[0], G::LOGK, S.ix);
+            hl[1] = subvote<DIM, K, true>(hl[1], G::LOGK, S.ix);
         } else {
-            subreduce_n<DIM, K, 2>(hl, G::LOGK, S.ix, OpAnd());
+            subvote_n<DIM, K, 2, true>(hl, G::LOGK, S.ix);
         }
         const int hi = hl[0], lo = hl[1];
         if (visit) {
