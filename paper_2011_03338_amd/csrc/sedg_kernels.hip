@@ -939,7 +939,19 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             }
         }
     }
-    {
+    if constexpr (KD == 64) {
+        // one element per wavefront: a row swap across the 32-lane halves leaves the lower
+        // lanes the density maxima of both halves and the upper ones the energy maxima,
+        // then a butterfly over the other five bits (maxima are exact in any order)
+        const auto rl = __builtin_amdgcn_permlane32_swap(__double2loint(ub[0]), __double2loint(fabs(ub[NV - 1])),
+                                                         false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(__double2hiint(ub[0]), __double2hiint(fabs(ub[NV - 1])),
+                                                         false, false);
+        double m = fmax(__hiloint2double((int)rh[0], (int)rl[0]), __hiloint2double((int)rh[1], (int)rl[1]));
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) m = lane_step(m, off, OpMax());
+        if (act && (c & 31) == 0) P.scale[2 * (long long)e + (c >> 5)] = m;
+    } else {
         double sc[2] = {ub[0], fabs(ub[NV - 1])};
         subreduce_n<DIM, K, 2>(sc, G::LOGK, S.x, OpMax());
         if (act && c == 0) {
