@@ -27,6 +27,7 @@
 //              store.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -108,6 +109,9 @@ struct KArgs {
     int stage;              // 0: write dudt; 1, 2, 3: SSP-RK3 stage
     double gamma, gm1, tau_A, tau_S, alpha_H, alpha_L, beta_L;
     double sigma_floor;     // floor of the smoothness-measure denominator (1 in the paper)
+    // 0.99 tau_S when tau_A is finite and >= 0 and tau_S > 0, else 0: a relative change of
+    // the smoothness measures below it clamps the blending factor's ramp to 0 for certain
+    double ind_quick;
     // RANDOM mode: generator seed and the device counter of right-hand-side draws
     unsigned long long seed;
     const long long *draw;
@@ -1158,7 +1162,12 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             int nonfin = 0;
             for (int v = 0; v < NV; ++v) {
                 double den = fmax(fmax(sh[v], sn[v]), P.sigma_floor);
-                double r = fabs(sn[v] - sh[v]) / den;
+                const double d = fabs(sn[v] - sh[v]);
+                // below 0.99 tau_S den the rounded quotient lies below tau_S for certain (the
+                // bound's and the quotient's rounding are some 1e-16 relative), so the ramp
+                // clamps to 0 and 1 - 0 leaves amin as it is: the division is skipped
+                if (d < P.ind_quick * den) continue;
+                double r = d / den;
                 double x = P.tau_A * (r - P.tau_S);
                 if (!isfinite(x)) nonfin = 1;
                 double cut = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
@@ -3330,6 +3339,12 @@ int ensure_adjoint_buffers(sedg_ctx *C)
     return SEDG_OK;
 }
 
+// the indicator's quick bound (see KArgs::ind_quick)
+static double ind_quick(const sedg_params &p)
+{
+    return (p.tau_A >= 0.0 && p.tau_A <= DBL_MAX && p.tau_S > 0.0) ? 0.99 * p.tau_S : 0.0;
+}
+
 KArgs base_args(const sedg_ctx *C)
 {
     KArgs P;
@@ -3364,6 +3379,7 @@ KArgs base_args(const sedg_ctx *C)
     P.alpha_L = C->params.alpha_L;
     P.beta_L = C->params.beta_L;
     P.sigma_floor = C->params.sigma_floor > 0.0 ? C->params.sigma_floor : 1.0;
+    P.ind_quick = ind_quick(C->params);
     P.seed = C->params.seed;
     P.draw = C->d_draw;
     return P;
@@ -4241,6 +4257,7 @@ KArgs batch_args(const sedg_batch *B)
     P.alpha_L = B->params.alpha_L;
     P.beta_L = B->params.beta_L;
     P.sigma_floor = B->params.sigma_floor > 0.0 ? B->params.sigma_floor : 1.0;
+    P.ind_quick = ind_quick(B->params);
     return P;
 }
 
@@ -4707,6 +4724,7 @@ int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const dou
     P.alpha_L = params->alpha_L;
     P.beta_L = params->beta_L;
     P.sigma_floor = params->sigma_floor > 0.0 ? params->sigma_floor : 1.0;
+    P.ind_quick = ind_quick(*params);
     P.u = u;
     P.out = dudt;
     P.stage = 0;
