@@ -38,20 +38,21 @@ METRIC = "FP64 DOF-updates/sec on 1 MI355X (fwd, batched, adjoint/fwd cost ratio
 
 def kernel_bytes_per_launch(mesh, A):
     """Algorithmic HBM bytes of one launch of each stage kernel (minimal I/O of the
-    decomposition): the analysis (state in; factors, sub-element means, face states and
-    scales out), the element-face fluxes and the residual (state in and out, stage base
-    state, own factors and means, element-face fluxes, scales)."""
+    decomposition): the analysis (state in; factors, face states and scales out), the
+    element-face fluxes and the residual (state in and out, stage base state, own
+    factors, element-face fluxes, scales).  The sub-element means travel only for
+    squeezed sub-elements (they enter only as (1 - beta) <u>), none in this count."""
     d, K, nv = mesh.dim, mesh.K, mesh.nvar
     nel = mesh.nel
     kd, kf = K ** d, K ** (d - 1)
     per_el = {
-        "analyse": 8 * (nv * kd + 2 * A + nv * A + 2 * d * nv * kf + 2),
+        "analyse": 8 * (nv * kd + 2 * A + 2 * d * nv * kf + 2),
         # element-face fluxes, once per face: the element's d low faces (face states of
         # both sides, both elements' factors and scales in; F* out)
         "faces": 8 * (d * (2 * nv * kf + 2 * A + 4) + d * nv * kf),
-        # state in, out, stage base state (2 of 3 stages), own factors and sub-element
-        # means, the fluxes on its 2d element faces, own scales
-        "residual": 8 * (nv * kd + nv * kd + (2.0 / 3.0) * nv * kd + 2 * A + nv * A + 2 * d * nv * kf + 2),
+        # state in, out, stage base state (2 of 3 stages), own factors, the fluxes on
+        # its 2d element faces, own scales
+        "residual": 8 * (nv * kd + nv * kd + (2.0 / 3.0) * nv * kd + 2 * A + 2 * d * nv * kf + 2),
     }
     return {k: v * nel for k, v in per_el.items()}
 

@@ -1195,12 +1195,16 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
     if (P.mode == SEDG_FORCE_DG)
         for (int q = c; q < LV::off(1 < LV::NLEV ? 1 : 0) + (LV::NLEV > 1 ? 0 : LV::A); q += KD) S.al[le][q] = 1.0;
     __syncthreads();
-    // publish alpha, beta and the sub-element means (coalesced)
+    // publish alpha, beta and the sub-element means (coalesced); a mean enters the
+    // blends only as (1 - beta) <u>_s, so it is stored only for a squeezed sub-element
+    // (beta < 1), and its readers take 0 elsewhere
     if (act)
         for (int q = c; q < LV::A; q += KD) {
+            const double bq = S.be[le][q];
             P.alpha[(long long)e * LV::A + q] = S.al[le][q];
-            P.beta[(long long)e * LV::A + q] = S.be[le][q];
-            for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * LV::A + q] = S.mean[le][v][q];
+            P.beta[(long long)e * LV::A + q] = bq;
+            if (bq < 1.0)
+                for (int v = 0; v < NV; ++v) P.mean[((long long)e * NV + v) * LV::A + q] = S.mean[le][v][q];
         }
     // blended interface states on the element faces: theta_FV * mean + sum_n theta_n *
     // ((1 - beta) <u>_s + beta * (u_s x_a E^{+-})) (cascade of Sec. 2.6, App. eq. 3D-prolongation).
@@ -1360,7 +1364,9 @@ __device__ __forceinline__ void element_face_sides(const KArgs &P, int ee, int f
 // Stage an element's state (and, for the adjoint, its adjoint state), blending
 // factors, squeezing parameters and sub-element means in LDS.  Every global load is
 // issued before the first LDS store, so that one memory latency covers them all (each
-// lane holds at most one entry of the per-element vectors: A <= K^d).
+// lane holds at most one entry of the per-element vectors: A <= K^d).  The means are
+// read only for squeezed sub-elements (beta < 1; only (1 - beta) <u>_s enters the
+// blends, and the analysis stores no others): 0 elsewhere.
 template <int DIM, int K, class LV, bool LAM, class SM>
 __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, int c, int ee, long long g)
 {
@@ -1373,11 +1379,13 @@ __device__ __forceinline__ void preload_element(const KArgs &P, SM &S, int le, i
         if constexpr (LAM) lv[v] = P.lam[v * P.dof + g];
     }
     const bool hq = c < LV::A;
+    for (int v = 0; v < NV; ++v) mv[v] = 0.0;
     if (hq) {
         ao = P.alpha[(long long)ee * LV::A + c];
         bo = P.beta[(long long)ee * LV::A + c];
+        if (bo < 1.0)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) mv[v] = P.mean[((long long)ee * NV + v) * LV::A + c];
+            for (int v = 0; v < NV; ++v) mv[v] = P.mean[((long long)ee * NV + v) * LV::A + c];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
