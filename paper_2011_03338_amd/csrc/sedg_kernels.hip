@@ -657,6 +657,15 @@ struct OpMax { __device__ double operator()(double a, double b) const { return f
 struct OpAnd { __device__ int operator()(int a, int b) const { return a & b; } };
 struct OpOr { __device__ int operator()(int a, int b) const { return a | b; } };
 
+// Maximum over the lanes that differ from this one in bits [B0, B1) of the lane index:
+// one lane exchange per bit with a compile-time mask (maxima are exact in any order)
+template <int B0, int B1>
+__device__ __forceinline__ double lane_max_bits(double v)
+{
+    if constexpr (B0 < B1) return lane_max_bits<B0 + 1, B1>(lane_step(v, 1 << B0, OpMax()));
+    else return v;
+}
+
 // the part of a sub-element reduction across the wavefronts of one element (3-D, K = 8):
 // each wavefront's partial (already reduced over its lanes) is combined in LDS
 template <int DIM, int K, int NQ, typename T, typename Op>
@@ -930,8 +939,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                 double cs = sqrt(gam.g * pressure<DIM>(ub, gam) / ub[0]);
                 for (int a = 0; a < DIM; ++a) lam = fmax(lam, fabs(ub[1 + a] / ub[0]) + cs);
             }
-            #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) lam = lane_step(lam, off, OpMax());
+            lam = lane_max_bits<0, 6>(lam);
             if ((tid & 63) == 0) S.lam[tid >> 6] = lam;
             __syncthreads();
             if (tid == 0) {
@@ -952,8 +960,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
         const auto rh = __builtin_amdgcn_permlane32_swap(__double2hiint(ub[0]), __double2hiint(fabs(ub[NV - 1])),
                                                          false, false);
         double m = fmax(__hiloint2double((int)rh[0], (int)rl[0]), __hiloint2double((int)rh[1], (int)rl[1]));
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) m = lane_step(m, off, OpMax());
+        m = lane_max_bits<0, 5>(m);
         if (act && (c & 31) == 0) P.scale[2 * (long long)e + (c >> 5)] = m;
     } else {
         double sc[2] = {ub[0], fabs(ub[NV - 1])};
@@ -1965,8 +1972,7 @@ __global__ void __launch_bounds__(64) eface_kernel(KArgs P)
             m = fmax(m, P.fin_lam[l + 64 * k]);
             P.fin_lam[l + 64 * k] = 0.0;
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) m = lane_step(m, off, OpMax());
+        m = lane_max_bits<0, 6>(m);
         if (l == 0) {
             const double d = P.fin_num / m;
             P.fin_dt[0] = d;
