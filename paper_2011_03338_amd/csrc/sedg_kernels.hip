@@ -1701,7 +1701,12 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     double th[MAXLEV + 1];
     theta_from_alpha<LV>(P.alpha + (long long)ee * LV::A, sidx, th);
     // active levels of the element (any cell with a nonzero weight)
-    {
+    int actv[MAXLEV + 1];
+    if constexpr (KD == 64) {
+        // one element per wavefront: one ballot per level, no LDS round trip
+#pragma unroll
+        for (int l = 0; l <= MAXLEV; ++l) actv[l] = (l <= LV::NLEV && __ballot(th[l] != 0.0) != 0) ? 1 : 0;
+    } else {
         int flags = 0;
         for (int l = 0; l <= LV::NLEV; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
         flags = subreduce<DIM, K>(flags, G::LOGK, (int *)&S.tmp[0][0][0], OpOr());
@@ -1710,8 +1715,8 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
     }
     const double own_sr = P.scale[2 * (long long)ee], own_se = P.scale[2 * (long long)ee + 1];
     __syncthreads();
-    int actv[MAXLEV + 1];
-    for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
+    if constexpr (KD != 64)
+        for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
     // lane exchange buffers of the face fluxes (the temporary is free then)
     double *const wsx = &S.tmp[0][0][0];
     double *const wsL = &S.tmp[le][0][0], *const wsR = &S.tmp[le][1][0];
