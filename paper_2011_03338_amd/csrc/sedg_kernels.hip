@@ -1018,7 +1018,33 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             // at face node lx, so that one pass covers both axes and both sides, and every
             // trace lies in the sub-element whose reductions below take it
             const int lx = G::coord(c, 0) & (n - 1), ly = G::coord(c, 1) & (n - 1);
-            if (ly < 4) {
+            if (KD == 64 && n == 8) {
+                // the element's 32 traces over all 64 lanes: the lower half (ly < 4) forms
+                // variables 0 and 1 of its trace, the lane 32 above it variables 2 and 3 of
+                // the same trace, which a row swap then hands down (the same sums)
+                const int lt = ly & 3, vb = (ly >> 2) * 2;
+                const int a = lt >> 1;
+                const bool hi = (lt & 1) != 0;
+                const int b0 = c - lx - K * ly;     // low corner of the element (0)
+                const int base = a == 0 ? b0 + K * lx : b0 + lx, st = a == 0 ? 1 : K;
+                double h2[2];
+                for (int j = 0; j < 2; ++j) {
+                    double s = 0.0;
+                    for (int m = 0; m < n; ++m) s += (hi ? T.bp[m] : T.bm[m]) * R0[vb + j][base + m * st];
+                    h2[j] = s;
+                }
+                const double o0 = lane_xor(h2[0], 32), o1 = lane_xor(h2[1], 32);
+                if (ly < 4) {
+                    pt[0] = h2[0];
+                    pt[1] = h2[1];
+                    pt[2] = o0;
+                    pt[3] = o1;
+                    double q = pressure<DIM>(pt, gam);
+                    if (!(pt[0] > 0.0 && q > 0.0)) ok = 0;
+                    rmin = fmin(rmin, pt[0]);
+                    pmin = fmin(pmin, q);
+                }
+            } else if (ly < 4) {
                 const int a = ly >> 1;
                 const bool hi = (ly & 1) != 0;
                 const int b0 = c - lx - K * ly;     // low corner of the sub-element
