@@ -1767,13 +1767,23 @@ __device__ __forceinline__ void residual_body(const KArgs &P, int tile, Residual
         if (actv[0]) step = 1;
         // the element-face fluxes come precomputed (once per face), only interior faces
         // are left to this kernel: copy the element faces' rows of the flux buffer first
-        for (int q = c; q < (a1 - a0) * 2 * KF; q += KD) {
-            const int fa = a0 + q / (2 * KF), sd = (q / KF) & 1, tt = q % KF;
-            const int nb = sd ? neighbour<DIM>(P, e3, fa, 1) : -1;
-            const int src = nb >= 0 ? nb : ee, ssd = nb >= 0 ? 0 : sd;
-            double fv[NV];
-            for (int v = 0; v < NV; ++v) fv[v] = P.ef[fb_index<DIM, K>(src, fa, ssd, v, tt)];
-            for (int v = 0; v < NV; ++v) S.F[le][SM::AXO ? 0 : fa][v][(sd ? K : 0) * KF + tt] = fv[v];
+        {
+            // an element of one wavefront with at least twice as many lanes as rows: the
+            // variables of a row are split over two lanes
+            constexpr int NTR = (SM::AXO ? 1 : DIM) * 2 * KF;
+            constexpr int VS = (KD == 64 && KD >= 2 * NTR) ? 2 : 1, VPL = (NV + VS - 1) / VS;
+            for (int w = c; w < (a1 - a0) * 2 * KF * VS; w += KD) {
+                const int nrow = (a1 - a0) * 2 * KF;
+                const int q = w % nrow, v0 = (w / nrow) * VPL;
+                const int fa = a0 + q / (2 * KF), sd = (q / KF) & 1, tt = q % KF;
+                const int nb = sd ? neighbour<DIM>(P, e3, fa, 1) : -1;
+                const int src = nb >= 0 ? nb : ee, ssd = nb >= 0 ? 0 : sd;
+                double fv[VPL];
+                for (int j = 0; j < VPL; ++j)
+                    if (v0 + j < NV) fv[j] = P.ef[fb_index<DIM, K>(src, fa, ssd, v0 + j, tt)];
+                for (int j = 0; j < VPL; ++j)
+                    if (v0 + j < NV) S.F[le][SM::AXO ? 0 : fa][v0 + j][(sd ? K : 0) * KF + tt] = fv[j];
+            }
         }
         const int nfaces = face_count<K>(a1 - a0, step, true);
         int nfmax = nfaces;
