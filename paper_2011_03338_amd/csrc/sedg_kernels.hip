@@ -2422,7 +2422,12 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     subidx_all<DIM, K, LV>(c, sidx);
     double th[MAXLEV + 1];
     theta_from_alpha<LV>(P.alpha + (long long)ee * LV::A, sidx, th);
-    {
+    int actv[MAXLEV + 1];
+    if constexpr (KD == 64) {
+        // one element per wavefront: one ballot per level, no LDS round trip
+#pragma unroll
+        for (int l = 0; l <= MAXLEV; ++l) actv[l] = (l <= LV::NLEV && __ballot(th[l] != 0.0) != 0) ? 1 : 0;
+    } else {
         int flags = 0;
         for (int l = 0; l <= LV::NLEV; ++l) flags |= (th[l] != 0.0) ? (1 << l) : 0;
         flags = subreduce<DIM, K>(flags, G::LOGK, (int *)S.wsL, OpOr());
@@ -2431,8 +2436,8 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
     }
     const double own_sr = P.scale[2 * (long long)ee], own_se = P.scale[2 * (long long)ee + 1];
     __syncthreads();
-    int actv[MAXLEV + 1];
-    for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
+    if constexpr (KD != 64)
+        for (int l = 0; l <= MAXLEV; ++l) actv[l] = S.act[le][l];
 
     double gu[NV];
     for (int v = 0; v < NV; ++v) gu[v] = 0.0;
