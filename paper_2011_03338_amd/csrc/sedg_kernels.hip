@@ -3766,14 +3766,17 @@ static void enqueue_step_rk54(sedg_ctx *C, double *u, double dt_fixed, double *d
     timed(C, 0, s, [&] { launch_analyse_any(C, P, s); });
     advance_draw(C, s);
     log_alpha(0);
-    if (!(dt_fixed > 0.0))
-        timed(C, 2, s, [&] {
-            hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(LAM_SLOTS), 0, s, C->d_lam, C->nblocks,
-                               cfl_numerator(C), C->d_dt, dt_log, C->d_ctr);
-        });
-    else if (dt_log)
+    if (!(dt_fixed > 0.0)) {
+        // the step size is formed inside the element-face launch that follows
+        P.fin_lam = C->d_lam;
+        P.fin_num = cfl_numerator(C);
+        P.fin_dt = C->d_dt;
+        P.fin_dt_log = dt_log;
+        P.fin_ctr = C->d_ctr;
+    } else if (dt_log)
         hipLaunchKernelGGL(log_dt_kernel, dim3(1), dim3(64), 0, s, (const double *)C->d_dt, dt_log, (const int *)C->d_ctr);
     timed(C, 3, s, [&] { launch_faces_any(C, P, s); });
+    P.fin_lam = nullptr;
     timed(C, 1, s, [&] { launch_residual_only_any(C, P, s); });
     P.lam_part = nullptr;
     // stages 2 .. 5
