@@ -59,6 +59,12 @@ enum {
     SEDG_ESCRATCH = -6     /* problem larger than the static work space of sedg_rhs_noalloc */
 };
 
+/* Largest mesh a context takes: 2^28 - 1 elements (a 2-D K=8 mesh of that size would hold
+ * 2 TB of state, a 3-D one 5 TB), and at most INT_MAX subcells along an axis; larger
+ * requests give SEDG_EINVAL from sedg_create, sedg_batch_create (per member) and
+ * sedg_rhs_noalloc before any device work. */
+#define SEDG_MAX_ELEMENTS 268435455
+
 enum { SEDG_PERIODIC = 0, SEDG_OUTFLOW = 1 };
 enum { SEDG_SSPRK3 = 0, SEDG_SSPRK54 = 1 };
 enum { SEDG_GAUSS = 0, SEDG_LGL = 1 };

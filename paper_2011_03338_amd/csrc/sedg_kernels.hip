@@ -3311,6 +3311,21 @@ int epb_for(int dim, int K)
 
 bool supported(int dim, int K) { return (dim == 2 || dim == 3) && (K == 4 || K == 8); }
 
+// element and subcell counts stay within the int arithmetic of the launches and the
+// per-element indexing: at most SEDG_MAX_ELEMENTS elements (far beyond any mesh whose
+// state fits in device memory) and at most INT_MAX subcells along an axis; counted in
+// 64 bits, so that an oversized request is rejected rather than wrapped
+static bool mesh_extent_ok(int dim, int K, const int *nelem)
+{
+    long long nel = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (nelem[a] < 1 || (long long)nelem[a] * K > INT_MAX) return false;
+        nel *= nelem[a];
+        if (nel > SEDG_MAX_ELEMENTS) return false;
+    }
+    return true;
+}
+
 template <int DIM, int K, int TOP>
 void launch_kernel(int which, const KArgs &P, int nblocks, hipStream_t s)
 {
@@ -3521,6 +3536,7 @@ int sedg_create(const sedg_mesh *mesh, const sedg_params *params, sedg_ctx **out
     if (!supported(mesh->dim, mesh->K)) return SEDG_EUNSUPPORTED;
     if (!(mesh->gamma > 1.0)) return SEDG_EINVAL;
     if (mesh->family != SEDG_GAUSS && mesh->family != SEDG_LGL) return SEDG_EINVAL;
+    if (!mesh_extent_ok(mesh->dim, mesh->K, mesh->nelem)) return SEDG_EINVAL;
     sedg_ctx *C = new sedg_ctx();
     C->mesh = *mesh;
     C->nv = mesh->dim + 2;
@@ -4471,6 +4487,7 @@ int sedg_batch_create(const sedg_mesh *meshes, int count, const sedg_params *par
             if (m.nelem[a] < 1 || !(m.hi[a] > m.lo[a])) return SEDG_EINVAL;
             if (m.bc[a] != SEDG_PERIODIC && m.bc[a] != SEDG_OUTFLOW) return SEDG_EINVAL;
         }
+        if (!mesh_extent_ok(2, m.K, m.nelem)) return SEDG_EINVAL;
     }
     sedg_batch *B = new sedg_batch();
     B->nprob = count;
@@ -4717,6 +4734,7 @@ int sedg_rhs_noalloc(const sedg_mesh *mesh, const sedg_params *params, const dou
     const int d = mesh->dim, K = mesh->K, nv = d + 2;
     const int top = params->top_level > 0 ? params->top_level : K;
     if (top < 2 || top > K || (top & (top - 1))) return SEDG_EINVAL;
+    if (!mesh_extent_ok(d, K, mesh->nelem)) return SEDG_EINVAL;
     // geometry, as sedg_create validates it
     KArgs P;
     std::memset(&P, 0, sizeof(P));

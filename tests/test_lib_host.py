@@ -63,11 +63,14 @@ def test_two_nc_table_builders_agree(n, fam):
         assert np.abs(a[k] - b[k]).max() <= 8 * np.finfo(float).eps * max(1.0, np.abs(b[k]).max()), k
 
 
-@pytest.mark.parametrize("case", ["no_elements", "empty_box", "bad_bc", "gamma", "family", "dim", "K"])
+@pytest.mark.parametrize("case", ["no_elements", "empty_box", "bad_bc", "gamma", "family", "dim", "K",
+                                  "too_many_elements", "axis_subcells_overflow", "element_count_overflow"])
 def test_create_rejects_bad_meshes_before_any_device_work(case):
     """sedg_create validates the mesh before it touches the device (so these run on the
     CPU): no elements along an axis, an empty box, an unknown boundary condition, gamma
-    <= 1 or an unknown node family give SEDG_EINVAL, an unsupported dimension or K
+    <= 1, an unknown node family, more than SEDG_MAX_ELEMENTS = 2^28 - 1 elements, more
+    than INT_MAX subcells along an axis, or an element count beyond 32 bits (which would
+    wrap in 32-bit arithmetic) give SEDG_EINVAL, an unsupported dimension or K
     SEDG_EUNSUPPORTED."""
     from paper_2011_03338_amd import workloads as W
     mesh = dict(dim=2, K=8, nelem=[4, 4], lo=[0.0, 0.0], hi=[1.0, 1.0], bc=[0, 0])
@@ -84,8 +87,35 @@ def test_create_rejects_bad_meshes_before_any_device_work(case):
     elif case == "K":
         mesh["K"] = 6
         expect = sedg.SEDG_EUNSUPPORTED
+    elif case == "too_many_elements":
+        mesh["nelem"] = [16384, 16384]          # 2^28 elements, one above the limit
+    elif case == "axis_subcells_overflow":
+        mesh["nelem"] = [(2 ** 31 - 1) // 8 + 1, 1]
+    elif case == "element_count_overflow":
+        # 2^32 + 2^16 elements: the product wraps to 65536 in 32-bit arithmetic
+        mesh["nelem"] = [65537, 65536]
     m = W.Mesh(mesh["dim"], mesh["K"], mesh["nelem"], mesh["lo"], mesh["hi"], mesh["bc"],
                gamma=1.0 if case == "gamma" else 1.4, family=5 if case == "family" else 0)
     with pytest.raises(sedg.SedgError) as ei:
         sedg.Solver(m, W.Params())
     assert ei.value.code == expect
+
+
+@pytest.mark.parametrize("nelem", [[16384, 16384], [65537, 65536], [(2 ** 31 - 1) // 8 + 1, 1]])
+def test_batch_and_noalloc_reject_oversized_meshes_before_any_device_work(nelem):
+    """sedg_batch_create (per member) and sedg_rhs_noalloc apply the same mesh limits as
+    sedg_create and return SEDG_EINVAL before any device work or use of the state
+    pointers (the pointers passed here are never dereferenced)."""
+    import ctypes
+    from paper_2011_03338_amd import workloads as W
+    lib = sedg.load()
+    ok = W.Mesh(2, 8, [4, 4], [0.0, 0.0], [1.0, 1.0], [0, 0])
+    big = W.Mesh(2, 8, nelem, [0.0, 0.0], [1.0, 1.0], [0, 0])
+    p = sedg.params_c(W.Params())
+    arr = (sedg.Mesh_c * 2)(sedg.mesh_c(ok), sedg.mesh_c(big))
+    h = ctypes.c_void_p()
+    assert lib.sedg_batch_create(arr, 2, ctypes.byref(p), ctypes.byref(h)) == sedg.SEDG_EINVAL
+    assert not h.value
+    rc = lib.sedg_rhs_noalloc(ctypes.byref(sedg.mesh_c(big)), ctypes.byref(p), ctypes.c_void_p(16),
+                              ctypes.c_void_p(32), None, None)
+    assert rc == sedg.SEDG_EINVAL
