@@ -9,8 +9,17 @@
  * once.  Built with -O2 -ffp-contract=off.
  *
  * Where the paper leaves a detail open, the reading taken is stated at the
- * function that implements it.  Parity of those readings against the paper is
- * pinned only through their limits, conservation and reductions (see the tests).
+ * function that implements it.  Pinned against values worked independently of
+ * this file (tests/test_oracle_*.py): operator tables, reconstruction, squeeze,
+ * the blending factor between its clamps (monotone and non-monotone data), the
+ * HLL-Einfeldt flux, free stream, conservation, the DG and FV limits, dimension
+ * reductions, a dense brute force of the 2x2-element scheme, the random factors,
+ * SSP-RK(5,4), the exact Riemann solutions, the non-conforming operators.
+ * Parity unpinned against the paper (readings where the paper defines nothing;
+ * only their limits, conservation and reductions are pinned): the multi-level
+ * blend at partially blended faces in 2-D/3-D, the edge rules at non-positive
+ * density and at ties of the positivity check, the choice of the HLL variant,
+ * the exterior state of the outflow boundary, the interface-safety fallback.
  */
 #include "sedg_oracle.h"
 

@@ -160,6 +160,62 @@ def test_indicator_between_clamps(name, dim):
     assert np.all(a[1:] == 1.0)
 
 
+# A bump (non-monotone cubic): its derivative changes sign between Gauss nodes, so the
+# smoothness measure is the n-point Gauss rule of |q'| on the element's own nodes (the
+# reading of the paper's "appropriate quadrature"), which here differs from the exact L1
+# norm of q'.  The rule's nodes and weights come from numpy, not from any table builder.
+SHAPE_BUMP = [Fr(0), Fr(17, 20), Fr(30, 20), Fr(0)]
+
+
+def _bump_sigmas(scale):
+    c = [float(x) for x in _cubic_from_means(SHAPE_BUMP)]
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    x, w = (xg + 1) / 2, wg / 2                     # the 4-point rule on [0, 1]
+    d = c[1] + 2 * c[2] * x + 3 * c[3] * x * x      # q' at the nodes (element units)
+    s4 = scale * float(np.sum(w * np.abs(d)))
+    # the children's lines through their subcell means vary by 2 |m_b - m_a| each
+    m = [scale * float(v) for v in SHAPE_BUMP]
+    s2 = 2 * abs(m[1] - m[0]) + 2 * abs(m[3] - m[2])
+    # the exact L1 norm of q' (the other reading): 2 max q - q(0) - q(1)
+    roots = np.roots([3 * c[3], 2 * c[2], c[1]])
+    xm = [r.real for r in roots if abs(r.imag) < 1e-14 and 0 < r.real < 1]
+    q = lambda t: c[0] + c[1] * t + c[2] * t * t + c[3] * t ** 3
+    tv = scale * (2 * max(q(t) for t in xm) - q(0.0) - q(1.0))
+    return s4, s2, tv, d
+
+
+def _ramp(s4, s2):
+    return 1.0 - min(max(TAU_A * (abs(s4 - s2) / max(s4, s2, 1.0) - TAU_S), 0.0), 1.0)
+
+
+def test_bump_case_discriminates_the_quadrature():
+    c = _cubic_from_means(SHAPE_BUMP)
+    assert not _monotone(c)
+    s4, s2, tv, d = _bump_sigmas(1.0)
+    assert d.min() < 0 < d.max()                    # the nodes see both signs of q'
+    a_rule, a_exact = _ramp(s4, s2), _ramp(tv, s2)
+    assert 0.01 < a_rule < 0.99
+    assert abs(a_rule - a_exact) > 0.1              # the exact-norm reading gives another factor
+    # densities 3 + bump stay positive at every node and face (no squeeze: the factor is the
+    # indicator's); the cubic's least value on [0, 1] is its end value q(1) = -1.95
+    q = lambda t: float(c[0] + c[1] * t + c[2] * t * t + c[3] * t ** 3)
+    assert 3 + min(q(t) for t in np.linspace(0, 1, 201)) > 1.0
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_indicator_between_clamps_nonmonotone(dim):
+    rho = [3 + x for x in SHAPE_BUMP]
+    mesh, u = (_state_1d if dim == 1 else _state_2d_y_invariant)(rho, [Fr(5, 2)] * 4)
+    _, info = O.rhs(mesh, W.Params(), u, full=True)
+    s4, s2, _, _ = _bump_sigmas(1.0)
+    a_exp = _ramp(s4, s2)
+    x_exp = TAU_A * (abs(s4 - s2) / max(s4, s2, 1.0) - TAU_S)
+    a = info["alpha"][0]
+    assert abs(a[0] - a_exp) <= 1e-11, (a[0], a_exp)
+    assert abs(info["xraw"][0][0] - x_exp) <= 1e-11
+    assert np.all(a[1:] == 1.0)
+
+
 # ---------------------------------------------------------------------------
 # HLL flux with Einfeldt's signal speeds
 # ---------------------------------------------------------------------------
