@@ -348,8 +348,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(multi-GPU sharding is a design note, not a measured path)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the hot path on a single MI355X "
+              "(sharding over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
