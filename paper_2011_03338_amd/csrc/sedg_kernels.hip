@@ -667,31 +667,40 @@ __device__ __forceinline__ double lane_max_bits(double v)
 }
 
 // the part of a sub-element reduction across the wavefronts of one element (3-D, K = 8):
-// each wavefront's partial (already reduced over its lanes) is combined in LDS
+// each wavefront holds the partials of its groups (the lanes of one sub-element in that
+// wavefront: a whole z layer for the element, a quarter of it for a level-4 sub-element,
+// a sixteenth for level 2), already reduced over the group's lanes.  One lane per group
+// publishes them in LDS at a dense group index; s_x has 64 slots per wavefront, so one
+// call exchanges at most 64 / (groups per wavefront) values: 64 for the element, 16
+// for level-4 sub-elements, 4 for level 2 (callers reducing more values at level 2
+// split them, see reduce_means).
 template <int DIM, int K, int NQ, typename T, typename Op>
-__device__ void subreduce_xwave(T *v, int ln, T *s_x, Op op)
+__device__ __forceinline__ void subreduce_xwave(T *v, int ln, T *s_x, Op op)
 {
     constexpr int LOGK = Geo<DIM, K>::LOGK;
     constexpr int NB = DIM * LOGK;              // bits of the cell index
     if constexpr (NB > 6) {
-        constexpr int NW = 1 << (NB - 6);       // wavefronts of one element
-        int wmask = 0;                          // wavefront bits inside the sub-element
-#pragma unroll
-        for (int bit = 6; bit < NB; ++bit)
-            if (bit % LOGK < ln) wmask |= 1 << (bit - 6);
-        if (wmask == 0) return;
+        static_assert(NB == 9 && NQ <= 16, "at most 16 values per exchange at K = 8");
+        constexpr int NW = 8;                   // wavefronts of one element (its z layers)
+        if (ln <= 0) return;
+        const int lnc = ln < 3 ? ln : 3;
+        const int wmask = (1 << lnc) - 1;       // z bits inside the sub-element
         const int tid = threadIdx.x, WG = blockDim.x >> 6;
         const int w = (tid >> 6) & (NW - 1), wbase = (tid >> 6) & ~(NW - 1);
-        if ((tid & 63) == 0)
+        // a wavefront is an 8 x 8 layer (x = lane bits 0-2, y = bits 3-5): the groups are
+        // the (8 >> ln)^2 squares of side n; gi is this lane's square, packed
+        const int lx = tid & 7, ly = (tid >> 3) & 7, low = (1 << lnc) - 1;
+        const int gi = (lx >> lnc) + ((ly >> lnc) << (3 - lnc)), ng = 1 << (2 * (3 - lnc));
+        if (((lx | ly) & low) == 0)             // the group's publishing lane
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) s_x[q * WG + (tid >> 6)] = v[q];
+            for (int q = 0; q < NQ; ++q) s_x[(q * WG + (tid >> 6)) * ng + gi] = v[q];
         __syncthreads();
         const int g0 = w & ~wmask;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             T acc[NW];
 #pragma unroll
-            for (int i = 0; i < NW; ++i) acc[i] = s_x[q * WG + wbase + i];
+            for (int i = 0; i < NW; ++i) acc[i] = s_x[(q * WG + wbase + i) * ng + gi];
 #pragma unroll
             for (int m = 1; m < NW; m <<= 1) {
                 if (!(wmask & m)) continue;
@@ -713,13 +722,13 @@ __device__ void subreduce_xwave(T *v, int ln, T *s_x, Op op)
 // sub-element (ln = log2 n; ln = LOGK gives the whole element); every lane ends with
 // the values of its sub-element.  Bits inside a wavefront use lane exchanges.  Bits
 // above them (3-D, K = 8: the bits of the z coordinate, one wavefront per z layer)
-// go through LDS with one barrier pair for all NQ values: one lane per wavefront
-// publishes its partials, and every lane combines those of the wavefronts of its
-// sub-element pairwise in the butterfly's pairing (the operators are commutative, so
-// this is the butterfly's result to the bit).  s_x holds at least NQ x (wavefronts
-// per workgroup) values.
+// go through LDS with one barrier pair for all NQ values: one lane per group and
+// wavefront publishes the group's partials, and every lane combines those of the
+// wavefronts of its sub-element pairwise in the butterfly's pairing (the operators are
+// commutative, so this is the butterfly's result to the bit).  s_x holds 64 values per
+// wavefront of the workgroup.
 template <int DIM, int K, int NQ, typename T, typename Op>
-__device__ void subreduce_n(T *v, int ln, T *s_x, Op op)
+__device__ __forceinline__ void subreduce_n(T *v, int ln, T *s_x, Op op)
 {
     constexpr int LOGK = Geo<DIM, K>::LOGK;
     constexpr int NB = DIM * LOGK;              // bits of the cell index
@@ -770,6 +779,19 @@ __device__ __forceinline__ T subreduce(T v, int ln, T *s_x, Op op)
 {
     subreduce_n<DIM, K, 1>(&v, ln, s_x, op);
     return v;
+}
+
+// sums of the NV conserved variables over each level-n sub-element; a 3-D K = 8
+// level-2 sub-element takes them in two exchanges (4 + 1 values, see subreduce_xwave)
+template <int DIM, int K, int NV>
+__device__ __forceinline__ void reduce_means(double *mn, int ln, double *s_x)
+{
+    if constexpr (DIM * Geo<DIM, K>::LOGK > 6 && NV > 4) {
+        subreduce_n<DIM, K, 4>(mn, ln, s_x, OpSum());
+        subreduce_n<DIM, K, NV - 4>(mn + 4, ln, s_x, OpSum());
+    } else {
+        subreduce_n<DIM, K, NV>(mn, ln, s_x, OpSum());
+    }
 }
 
 // blocked n-mode product: out = sum_m M[lo][m] * src[base + m*stride] along axis a
@@ -1085,7 +1107,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
             double nd = (DIM == 2) ? n * n : n * n * n;
             double mn[NV], mm[2] = {rmin, pmin};
             for (int v = 0; v < NV; ++v) mn[v] = S.u[le][v][c];   // from LDS: ub need not stay live
-            subreduce_n<DIM, K, NV>(mn, ln, S.x, OpSum());
+            reduce_means<DIM, K, NV>(mn, ln, S.x);
             for (int v = 0; v < NV; ++v) mn[v] /= nd;
             subreduce_n<DIM, K, 2>(mm, ln, S.x, OpMin());
             rmin = mm[0];
@@ -1184,7 +1206,7 @@ __device__ __forceinline__ void analyse_body(const KArgs &P, int tile, AnalyseSm
                     snh[v] = sn[v];
                     snh[NV + v] = sh[v];
                 }
-                subreduce_n<DIM, K, 2 * NV>(snh, ln, S.x, OpSum());
+                subreduce_n<DIM, K, 2 * NV>(snh, ln, S.x, OpSum());   // n >= 4: one exchange
                 for (int v = 0; v < NV; ++v) {
                     sn[v] = snh[v];
                     sh[v] = snh[NV + v];
@@ -2173,7 +2195,7 @@ __global__ void __launch_bounds__((EPB * Geo<DIM, K>::KD)) frozen_prep_kernel(KA
         double nd = (DIM == 2) ? n * n : n * n * n;
         double mn[NV];
         for (int v = 0; v < NV; ++v) mn[v] = ub[v];
-        subreduce_n<DIM, K, NV>(mn, ln, S.x, OpSum());
+        reduce_means<DIM, K, NV>(mn, ln, S.x);
         for (int v = 0; v < NV; ++v) mn[v] /= nd;
         const bool leader = ((G::coord(c, 0) | G::coord(c, 1) | (DIM == 3 ? G::coord(c, 2) : 0)) & (n - 1)) == 0;
         if (leader)
@@ -2499,7 +2521,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) adjoint_kernel(KArgs P)
         const double nd = (DIM == 2) ? n * n : n * n * n;
         double ms[NV];
         for (int v = 0; v < NV; ++v) ms[v] = gut[v];
-        subreduce_n<DIM, K, NV>(ms, ln, S.wsL, OpSum());
+        reduce_means<DIM, K, NV>(ms, ln, S.wsL);
         if (thn != 0.0)
             for (int v = 0; v < NV; ++v) gu[v] += b * y[v] + (1.0 - b) * ms[v] / nd;
         __syncthreads();

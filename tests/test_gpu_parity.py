@@ -190,6 +190,49 @@ def test_rk3_k8_blast_100_steps():
     s.close()
 
 
+def _jump_3d(K, ne):
+    mesh = W.Mesh(3, K, ne, [0, 0, 0], [1, 1, 1], [W.OUTFLOW, W.PERIODIC, W.OUTFLOW])
+    g = mesh.grid
+    x = (np.arange(g[0]) + 0.5) / g[0]
+    u = np.zeros(mesh.shape())
+    u[0] = np.where(x < 0.45, 1.0, 0.2)[None, None, :]
+    u[1] = 0.3 * u[0]
+    u[4] = np.where(x < 0.45, 2.0, 0.3)[None, None, :] / 0.4 + 0.5 * 0.09 * u[0]
+    return mesh, u
+
+
+@pytest.mark.parametrize("case,steps", [("shear K4 4^3", 100), ("shear K8 2^3", 60), ("jump K8 4x2x2 outflow", 50)])
+def test_rk3_3d_multistep(case, steps):
+    """Whole SSP-RK3 steps in 3-D against the oracle: the shear layer on 4^3 K = 4 and
+    2^3 K = 8 elements (at the end every K = 8 element is blended below pure top-level
+    DG) and a moving jump through outflow x and z boundaries on 4x2x2 K = 8 elements.
+    State within 1e-9, step sizes within 1e-11 (the oracle's own trajectories move by
+    at most 1.2e-13 under a 1e-15 relative perturbation of their initial states)."""
+    if case.startswith("shear"):
+        ne, K = (4, 4) if "K4" in case else (2, 8)
+        mesh, u, _ = W.shear_layer_3d(0, ne, K)
+        u = u.numpy()
+    else:
+        mesh, u = _jump_3d(8, [4, 2, 2])
+    p = W.Params(cfl=0.5)
+    u_o, dts_o = O.rk3(mesh, p, u, steps)
+    s = sedg.Solver(mesh, p)
+    ug = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
+    dts = torch.zeros(steps, dtype=torch.float64, device=DEV)
+    s.rk_step(ug, steps, 0.0, dts)
+    s.check()
+    err = rel_err(ug.cpu().numpy(), u_o)
+    dterr = np.abs(dts.cpu().numpy() - dts_o).max() / dts_o.max()
+    _, info = O.rhs(mesh, p, u_o, full=True)
+    nb = int((info["alpha"][:, 0] < 1.0).sum())
+    say("  rk3 3-D %s %d steps rel_err=%.3e dt_err=%.3e; at the end %d of %d elements below pure top-level DG"
+        % (case, steps, err, dterr, nb, mesh.nel))
+    if "K8" in case:
+        assert nb > 0
+    assert err <= STATE_TOL and dterr <= 1e-11
+    s.close()
+
+
 def test_rk3_fixed_dt_and_repeat_bitwise():
     mesh, u, _ = W.config0(1, 8, 8)
     p = W.Params()
