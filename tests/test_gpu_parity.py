@@ -142,6 +142,28 @@ def test_rhs_3d_outflow_jump():
     compare_rhs(mesh, W.Params(), u, "3d outflow jump")
 
 
+def test_rhs_3d_k8_blast_squeezed():
+    """A concentrated 3-D blast (4^3 K = 8 elements over [-1/2, 1/2]^3, outflow, Gaussian
+    energy of width 0.04 over p0 = 1e-5): squeezed sub-elements on every level (8 on the
+    top level, 24 on level 4, 129 on level 2 in the oracle), blended factors and
+    interface-safety fallbacks; one right-hand side, factors and squeezing parameters
+    against the oracle's (the per-level sub-element means and minima of a z layer's
+    level-4 and level-2 sub-elements cross the element's wavefronts)."""
+    mesh = W.Mesh(3, 8, [4, 4, 4], [-0.5] * 3, [0.5] * 3, [W.OUTFLOW] * 3)
+    g = mesh.grid
+    xs = [(-0.5 + (np.arange(g[a]) + 0.5) / g[a]) for a in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    r2 = (X - 0.013) ** 2 + (Y + 0.021) ** 2 + (Z - 0.008) ** 2
+    sig = 0.04
+    u = np.zeros(mesh.shape())
+    u[0] = 1.0
+    u[4] = 1e-5 / 0.4 + 1e-3 / ((2 * np.pi) ** 1.5 * sig ** 3) * np.exp(-r2 / (2 * sig ** 2))
+    _, info = O.rhs(mesh, W.Params(), u, full=True)
+    b = info["beta"]
+    assert (b[:, 0] < 1).sum() > 0 and (b[:, 1:9] < 1).sum() > 0 and (b[:, 9:] < 1).sum() > 0
+    compare_rhs(mesh, W.Params(), u, "3d K8 blast squeezed")
+
+
 def test_rk3_100_steps_config0():
     """100 SSP-RK3 steps at CFL 0.5 on the 16x16, K = 4 case: state within 1e-9,
     step sizes within 1e-14."""
