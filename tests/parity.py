@@ -135,3 +135,19 @@ def compare_rhs(mesh, params, u, label=""):
     say("  parity %-28s rel_err=%.3e exempt=%d" % (label, err, n_exempt))
     assert err <= RHS_TOL, (label, err)
     return err, n_exempt
+
+
+def blast_3d_k8(family=W.GAUSS):
+    """A concentrated 3-D blast on 4^3 K = 8 elements over [-1/2, 1/2]^3 with outflow
+    boundaries: Gaussian energy of width 0.04 over a background pressure of 1e-5, its
+    centre off the element corners; squeezed sub-elements on every level."""
+    mesh = W.Mesh(3, 8, [4, 4, 4], [-0.5] * 3, [0.5] * 3, [W.OUTFLOW] * 3, family=family)
+    g = mesh.grid
+    xs = [(-0.5 + (np.arange(g[a]) + 0.5) / g[a]) for a in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    r2 = (X - 0.013) ** 2 + (Y + 0.021) ** 2 + (Z - 0.008) ** 2
+    sig = 0.04
+    u = np.zeros(mesh.shape())
+    u[0] = 1.0
+    u[4] = 1e-5 / 0.4 + 1e-3 / ((2 * np.pi) ** 1.5 * sig ** 3) * np.exp(-r2 / (2 * sig ** 2))
+    return mesh, u

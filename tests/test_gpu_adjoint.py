@@ -11,7 +11,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_03338_amd import sedg, workloads as W
-from tests.parity import DEV, check_factors, say
+from tests.parity import DEV, blast_3d_k8, check_factors, say
 
 pytestmark = pytest.mark.gpu
 
@@ -67,12 +67,28 @@ def _cases():
     return out
 
 
+def _cases_3d():
+    """3-D cases of the frozen map (the 3-D K = 8 adjoint is not built): the per-level
+    sub-element means of a z layer's level-4 and level-2 sub-elements cross the
+    element's wavefronts at K = 8."""
+    out = []
+    m, u, _ = W.shear_layer_3d(0, 2, 8)
+    out.append(("3-D shear K8 adaptive", m, np.ascontiguousarray(u.numpy()), "adaptive"))
+    out.append(("3-D shear K8 random", m, np.ascontiguousarray(u.numpy()), "random"))
+    m, u = blast_3d_k8()
+    out.append(("3-D blast K8 mid", m, u, "mid"))
+    m, u, _ = W.shear_layer_3d(1, 3, 4)
+    out.append(("3-D shear K4 mid", m, np.ascontiguousarray(u.numpy()), "mid"))
+    return out
+
+
 CASES = _cases()
+FROZEN_CASES = CASES + _cases_3d()
 
 
-@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("case", range(len(FROZEN_CASES)), ids=[c[0] for c in FROZEN_CASES])
 def test_frozen_rhs_matches_oracle(case):
-    label, mesh, u, kind = CASES[case]
+    label, mesh, u, kind = FROZEN_CASES[case]
     al, be = _oracle_frozen_inputs(mesh, u, kind)
     d_o = O.rhs_frozen(mesh, W.Params(), u, al, be)
     s = sedg.Solver(mesh, W.Params())

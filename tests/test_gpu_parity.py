@@ -6,8 +6,8 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_03338_amd import sedg, workloads as W
-from tests.parity import (DEV, RHS_TOL, STATE_TOL, check_factors, compare_rhs, factor_noise, gpu_rhs, rel_err,
-                          say)
+from tests.parity import (DEV, RHS_TOL, STATE_TOL, blast_3d_k8, check_factors, compare_rhs, factor_noise, gpu_rhs,
+                          rel_err, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -142,19 +142,6 @@ def test_rhs_3d_outflow_jump():
     compare_rhs(mesh, W.Params(), u, "3d outflow jump")
 
 
-def _blast_3d_k8(family=W.GAUSS):
-    mesh = W.Mesh(3, 8, [4, 4, 4], [-0.5] * 3, [0.5] * 3, [W.OUTFLOW] * 3, family=family)
-    g = mesh.grid
-    xs = [(-0.5 + (np.arange(g[a]) + 0.5) / g[a]) for a in range(3)]
-    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
-    r2 = (X - 0.013) ** 2 + (Y + 0.021) ** 2 + (Z - 0.008) ** 2
-    sig = 0.04
-    u = np.zeros(mesh.shape())
-    u[0] = 1.0
-    u[4] = 1e-5 / 0.4 + 1e-3 / ((2 * np.pi) ** 1.5 * sig ** 3) * np.exp(-r2 / (2 * sig ** 2))
-    return mesh, u
-
-
 def test_rhs_3d_k8_blast_squeezed():
     """A concentrated 3-D blast (4^3 K = 8 elements over [-1/2, 1/2]^3, outflow, Gaussian
     energy of width 0.04 over p0 = 1e-5): squeezed sub-elements on every level (8 on the
@@ -162,7 +149,7 @@ def test_rhs_3d_k8_blast_squeezed():
     interface-safety fallbacks; one right-hand side, factors and squeezing parameters
     against the oracle's (the per-level sub-element means and minima of a z layer's
     level-4 and level-2 sub-elements cross the element's wavefronts)."""
-    mesh, u = _blast_3d_k8()
+    mesh, u = blast_3d_k8()
     _, info = O.rhs(mesh, W.Params(), u, full=True)
     b = info["beta"]
     assert (b[:, 0] < 1).sum() > 0 and (b[:, 1:9] < 1).sum() > 0 and (b[:, 9:] < 1).sum() > 0
@@ -203,7 +190,7 @@ def test_rhs_3d_k8_variants(state, variant):
         mesh, u, _ = W.shear_layer_3d(0, 2, 8)
         u = u.numpy()
     else:
-        mesh, u = _blast_3d_k8(W.LGL if state == "blast_lgl" else W.GAUSS)
+        mesh, u = blast_3d_k8(W.LGL if state == "blast_lgl" else W.GAUSS)
     u = np.ascontiguousarray(u)
     p = W.Params(**VARIANTS_3D[variant])
     label = "3d K8 %s %s" % (state, variant)
