@@ -787,11 +787,13 @@ template <int DIM, int K, int NV>
 __device__ __forceinline__ void reduce_means(double *mn, int ln, double *s_x)
 {
     if constexpr (DIM * Geo<DIM, K>::LOGK > 6 && NV > 4) {
-        subreduce_n<DIM, K, 4>(mn, ln, s_x, OpSum());
-        subreduce_n<DIM, K, NV - 4>(mn + 4, ln, s_x, OpSum());
-    } else {
-        subreduce_n<DIM, K, NV>(mn, ln, s_x, OpSum());
+        if (ln <= 1) {
+            subreduce_n<DIM, K, 4>(mn, ln, s_x, OpSum());
+            subreduce_n<DIM, K, NV - 4>(mn + 4, ln, s_x, OpSum());
+            return;
+        }
     }
+    subreduce_n<DIM, K, NV>(mn, ln, s_x, OpSum());
 }
 
 // blocked n-mode product: out = sum_m M[lo][m] * src[base + m*stride] along axis a
