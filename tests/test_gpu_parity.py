@@ -266,11 +266,13 @@ def _jump_3d(K, ne):
     return mesh, u
 
 
-@pytest.mark.parametrize("case,steps", [("shear K4 4^3", 100), ("shear K8 2^3", 60), ("jump K8 4x2x2 outflow", 50)])
+@pytest.mark.parametrize("case,steps", [("shear K4 4^3", 100), ("shear K8 2^3", 60), ("jump K8 4x2x2 outflow", 50),
+                                        ("shear K8 2^3 SSP-RK(5,4)", 40)])
 def test_rk3_3d_multistep(case, steps):
     """Whole SSP-RK3 steps in 3-D against the oracle: the shear layer on 4^3 K = 4 and
     2^3 K = 8 elements (at the end every K = 8 element is blended below pure top-level
-    DG) and a moving jump through outflow x and z boundaries on 4x2x2 K = 8 elements.
+    DG) and a moving jump through outflow x and z boundaries on 4x2x2 K = 8 elements;
+    and 40 SSP-RK(5,4) steps of the K = 8 shear layer.
     State within 1e-9, step sizes within 1e-11 (the oracle's own trajectories move by
     at most 1.2e-13 under a 1e-15 relative perturbation of their initial states)."""
     if case.startswith("shear"):
@@ -279,7 +281,7 @@ def test_rk3_3d_multistep(case, steps):
         u = u.numpy()
     else:
         mesh, u = _jump_3d(8, [4, 2, 2])
-    p = W.Params(cfl=0.5)
+    p = W.Params(cfl=0.5, integrator=sedg.SEDG_SSPRK54 if "RK(5,4)" in case else sedg.SEDG_SSPRK3)
     u_o, dts_o = O.rk3(mesh, p, u, steps)
     s = sedg.Solver(mesh, p)
     ug = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
