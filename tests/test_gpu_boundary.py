@@ -10,7 +10,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_03338_amd import adjoint as ADJ, sedg, workloads as W
-from tests.parity import DEV, RHS_TOL, STATE_TOL, rel_err, say
+from tests.parity import DEV, RHS_TOL, STATE_TOL, blast_3d_k8, rel_err, say
 from tests.test_oracle_random import random_factors
 
 pytestmark = pytest.mark.gpu
@@ -169,7 +169,7 @@ def test_conservation_stress_every_stage(dim, K, ne):
     se.close()
 
 
-@pytest.mark.parametrize("case", ["sedov narrow", "config0 K8", "sedov K4"])
+@pytest.mark.parametrize("case", ["sedov narrow", "config0 K8", "sedov K4", "3-D blast K8"])
 def test_diagnose_matches_oracle(case):
     """sedg_diagnose against the oracle's analysis of the same state: fallback count
     (integer, exact), squeezed and rejected sub-elements, elements by lowest order
@@ -177,7 +177,8 @@ def test_diagnose_matches_oracle(case):
     order-estimate, from the oracle's factors)."""
     mesh, u = {"sedov narrow": lambda: W.sedov(4, 16, 8, L=0.5, sigma=0.01)[:2],
                "config0 K8": lambda: W.config0(0, 8, 8)[:2],
-               "sedov K4": lambda: W.sedov(1, 9, 4, L=0.4, sigma=0.02)[:2]}[case]()
+               "sedov K4": lambda: W.sedov(1, 9, 4, L=0.4, sigma=0.02)[:2],
+               "3-D blast K8": blast_3d_k8}[case]()
     p = W.Params()
     s = sedg.Solver(mesh, p)
     ug = _t(u)
@@ -203,18 +204,18 @@ def test_diagnose_matches_oracle(case):
     hist = {"FV": 0, "O2": 0, "O4": 0, "O8": 0}
     for e in range(mesh.nel):
         low = None
-        for j in range(K):
-            for i in range(K):
-                prod, off = 1.0, 0
-                for n in levels:
-                    ns = K // n
-                    a = al[e, off + i // n + ns * (j // n)]
-                    if a * prod != 0.0:
-                        low = n if low is None or n < low else low
-                    prod *= 1.0 - a
-                    off += ns ** dim
-                if prod != 0.0:
-                    low = 1
+        for cell in np.ndindex(*([K] * dim)):     # (.., j, i): i along x
+            prod, off = 1.0, 0
+            for n in levels:
+                ns = K // n
+                q = sum((cell[dim - 1 - a] // n) * ns ** a for a in range(dim))
+                a = al[e, off + q]
+                if a * prod != 0.0:
+                    low = n if low is None or n < low else low
+                prod *= 1.0 - a
+                off += ns ** dim
+            if prod != 0.0:
+                low = 1
         hist["FV" if low == 1 else "O%d" % low] += 1
     say("  diagnose %s: %s, fallbacks %d, squeezed %d, rejected %d, abar mean %.3f"
         % (case, dg["elems_by_lowest_order"], dg["fallbacks"], dg["squeezed"], dg["beta_rejected"], dg["alpha_bar_mean"]))
