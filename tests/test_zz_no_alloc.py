@@ -9,7 +9,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_03338_amd import sedg, workloads as W
-from tests.parity import DEV, RHS_TOL, rel_err, say
+from tests.parity import DEV, RHS_TOL, blast_3d_k8, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +68,8 @@ def test_noalloc_3d_and_oracle():
     u3[2] = -0.1 * u3[0]
     u3[3] = 0.05 * u3[0]
     u3[4] = 2.5 + 0.5 * rng.uniform(size=u3[0].shape)
-    for name, (m, x) in [("3-D K=4 3x2x2", (m3, u3)), ("config0 K=4 4x4", (mesh, u))]:
+    mb, ub = blast_3d_k8()     # squeezed sub-elements on every level of 3-D K = 8
+    for name, (m, x) in [("3-D K=4 3x2x2", (m3, u3)), ("3-D K=8 blast 4^3", (mb, ub)), ("config0 K=4 4x4", (mesh, u))]:
         say("noalloc case", name)
         ug = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
         got, bad = _noalloc_rhs(m, W.Params(), ug)
